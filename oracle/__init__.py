@@ -1,0 +1,332 @@
+"""Python binding of the Link & Code reference oracle (``liblc_oracle.so``).
+
+TEST INFRASTRUCTURE ONLY: this package is loaded by the test-suite, by the
+smoke check and by the CPU-baseline leg of the benchmark, never by the GPU
+library.  It shares no code with ``paper_1804_09996_amd``.
+
+Every function works in float64 (the index stores float32 parameters, which
+are promoted) and follows the paper's definitions:
+
+* PQ training/encoding: Sec. 3.3 and Sec. 4.1 ("Vector approximation").
+* Node levels and the nested graph: Sec. 2 and Sec. 4.1 ("Graph-based
+  structure": upper degree 32, level ratio 30), batched insertion (Sec. 5.1).
+* 0-byte refinement: Sec. 4.2, Eq. (3)-(5); regression codebook: Sec. 4.3,
+  Eq. (6)-(8).
+* Search: greedy descent then best-first walk (Sec. 2), short-list and
+  re-ranking (Sec. 4.1 "Refinement strategy").
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.environ.get("LC_ORACLE_LIB") or os.path.join(_HERE, "liblc_oracle.so")
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            from . import build as _b
+            _b.build()
+        _lib = C.CDLL(LIB_PATH)
+        _declare(_lib)
+    return _lib
+
+
+_p = C.c_void_p
+_i = C.c_int
+_i64 = C.c_int64
+
+
+class OrcIndex(C.Structure):
+    _fields_ = [(n, C.c_int32) for n in ("n", "d", "d_pad", "m", "ksub", "code_stride", "deg0", "deg_up",
+                                          "k_reg", "n_beta", "entry", "max_level")] + \
+               [(n, _p) for n in ("proj", "centroids", "codes", "adj0", "up_base", "adj_up", "beta", "beta_idx")]
+
+
+def _declare(L):
+    L.orc_kmeans.argtypes = [_p, _i64, _i, _i, _p, _i, _i, _p, _p, _p]
+    L.orc_pq_train.argtypes = [_p, _i64, _i, _p, _i, _i, _i, _p, _i, _i, _p, _p]
+    L.orc_pq_encode.argtypes = [_p, _i64, _i, _p, _i, _i, _i, _p, _i, _p, _i]
+    L.orc_levels.argtypes = [_p, _i64, _i, _i, _p]
+    L.orc_levels.restype = _i64
+    L.orc_hnsw_build.argtypes = [_p, _i64, _i, _p, _i, _i, _i, _p, _p, _i, _p, _i, _i, _i, _i, _p, _p, _p, _p, _p]
+    L.orc_lsq_solve.argtypes = [_p, _p, _i, _p]
+    L.orc_beta_train.argtypes = [_p, _p, _i64, _i, _p, _i, _i, _i, _p, _p, _i, _p, _i, _i, _i, _p, _i, _i, _i,
+                                 _p, _p]
+    L.orc_beta_shared.argtypes = [_p, _p, _i64, _i, _p, _i, _i, _i, _p, _p, _i, _p, _i, _i, _p]
+    L.orc_beta_assign.argtypes = [_p, _i64, _i, _p, _i, _i, _i, _p, _p, _i, _p, _i, _i, _i, _p, _i, _p]
+    L.orc_lut.argtypes = [C.POINTER(OrcIndex), _p, _p]
+    L.orc_lut.restype = None
+    L.orc_search.argtypes = [C.POINTER(OrcIndex), _p, _i64, _p, C.c_int32, C.c_int32, _i, _p, _p, _p, _p, _p, _p]
+    L.orc_refined_distance.argtypes = [C.POINTER(OrcIndex), _p, C.c_int32]
+    L.orc_refined_distance.restype = C.c_double
+    L.orc_walk_trace.argtypes = [C.POINTER(OrcIndex), _p, C.c_int32, _p, C.c_int32]
+    L.orc_walk_trace.restype = C.c_int32
+    L.orc_project.argtypes = [_p, _i, _i, _p, _p]
+    L.orc_project.restype = None
+
+
+def _ptr(a: Optional[np.ndarray]):
+    return None if a is None else a.ctypes.data
+
+
+def _c(a, dtype):
+    return np.ascontiguousarray(a, dtype=dtype)
+
+
+def default_threads() -> int:
+    return max(1, min(16, os.cpu_count() or 1))
+
+
+def code_stride_for(m: int) -> int:
+    """Row stride of the code array: the next power of two >= m."""
+    s = 1
+    while s < m:
+        s *= 2
+    return s
+
+
+# ---------------------------------------------------------------------------
+# primitives
+# ---------------------------------------------------------------------------
+def kmeans(x: np.ndarray, k: int, init: np.ndarray, iters: int, nthreads: int = 1):
+    x = _c(x, np.float64)
+    init = _c(init, np.int64)
+    cent = np.empty((k, x.shape[1]), np.float64)
+    assign = np.empty(x.shape[0], np.int32)
+    hist = np.empty(iters + 1, np.float64)
+    rc = _load().orc_kmeans(_ptr(x), x.shape[0], x.shape[1], k, _ptr(init), iters, nthreads, _ptr(cent),
+                            _ptr(assign), _ptr(hist))
+    if rc != 0:
+        raise ValueError(f"orc_kmeans failed ({rc})")
+    return cent, assign, hist
+
+
+def project(proj: Optional[np.ndarray], y: np.ndarray, d_pad: int) -> np.ndarray:
+    y = _c(y, np.float32)
+    out = np.empty(d_pad, np.float64)
+    proj = None if proj is None else _c(proj, np.float32)
+    _load().orc_project(_ptr(proj), d_pad, y.shape[0], _ptr(y), _ptr(out))
+    return out
+
+
+def pq_train(train, proj, d_pad, m, init, iters, nthreads=1, ksub=256):
+    train = _c(train, np.float32)
+    proj = None if proj is None else _c(proj, np.float32)
+    init = _c(init, np.int64)
+    cent = np.empty((m, ksub, d_pad // m), np.float32)
+    hist = np.empty((m, iters + 1), np.float64)
+    rc = _load().orc_pq_train(_ptr(train), train.shape[0], train.shape[1], _ptr(proj), d_pad, m, ksub, _ptr(init),
+                              iters, nthreads, _ptr(cent), _ptr(hist))
+    if rc != 0:
+        raise ValueError(f"orc_pq_train failed ({rc})")
+    return cent, hist
+
+
+def pq_encode(x, proj, d_pad, cent, nthreads=1, code_stride=None):
+    x = _c(x, np.float32)
+    proj = None if proj is None else _c(proj, np.float32)
+    cent = _c(cent, np.float32)
+    m, ksub = cent.shape[0], cent.shape[1]
+    cs = code_stride or code_stride_for(m)
+    codes = np.empty((x.shape[0], cs), np.uint8)
+    rc = _load().orc_pq_encode(_ptr(x), x.shape[0], x.shape[1], _ptr(proj), d_pad, m, ksub, _ptr(cent), nthreads,
+                               _ptr(codes), cs)
+    if rc != 0:
+        raise ValueError(f"orc_pq_encode failed ({rc})")
+    return codes
+
+
+def levels(u: np.ndarray, ratio: int = 30, cap: int = 16):
+    u = _c(u, np.float64)
+    lv = np.empty(u.shape[0], np.int8)
+    rows = _load().orc_levels(_ptr(u), u.shape[0], ratio, cap, _ptr(lv))
+    return lv, int(rows)
+
+
+def hnsw_build(x, proj, d_pad, cent, codes, level, deg0, deg_up, efc, nthreads=1):
+    x = _c(x, np.float32)
+    proj = None if proj is None else _c(proj, np.float32)
+    cent = _c(cent, np.float32)
+    codes = _c(codes, np.uint8)
+    level = _c(level, np.int8)
+    n = x.shape[0]
+    rows = int(level.astype(np.int64).sum())
+    adj0 = np.empty((n, deg0), np.int32)
+    up_base = np.empty(n, np.int32)
+    adj_up = np.empty((max(rows, 1), deg_up), np.int32)
+    entry = C.c_int32()
+    maxl = C.c_int32()
+    rc = _load().orc_hnsw_build(_ptr(x), n, x.shape[1], _ptr(proj), d_pad, cent.shape[0], cent.shape[1], _ptr(cent),
+                                _ptr(codes), codes.shape[1], _ptr(level), deg0, deg_up, efc, nthreads, _ptr(adj0),
+                                _ptr(up_base), _ptr(adj_up), C.byref(entry), C.byref(maxl))
+    if rc != 0:
+        raise ValueError(f"orc_hnsw_build failed ({rc})")
+    if rows == 0:
+        adj_up = adj_up[:0]
+    return adj0, up_base, adj_up, int(entry.value), int(maxl.value)
+
+
+def lsq_solve(a: np.ndarray, c: np.ndarray):
+    a = _c(a, np.float64)
+    c = _c(c, np.float64)
+    beta = np.empty(c.shape[0], np.float64)
+    rc = _load().orc_lsq_solve(_ptr(a), _ptr(c), c.shape[0], _ptr(beta))
+    return beta, int(rc)
+
+
+def beta_train(x, ids, proj, d_pad, cent, codes, adj0, k_reg, n_beta, init, km_iters, em_iters, nthreads=1):
+    x = _c(x, np.float32)
+    ids = _c(ids, np.int64)
+    proj = None if proj is None else _c(proj, np.float32)
+    init = _c(init, np.int64)
+    beta = np.empty((n_beta, k_reg + 1), np.float32)
+    hist = np.empty(em_iters + 1, np.float64)
+    rc = _load().orc_beta_train(_ptr(x), _ptr(ids), ids.shape[0], x.shape[1], _ptr(proj), d_pad, cent.shape[0],
+                                cent.shape[1], _ptr(_c(cent, np.float32)), _ptr(_c(codes, np.uint8)), codes.shape[1],
+                                _ptr(_c(adj0, np.int32)), adj0.shape[1], k_reg, n_beta, _ptr(init), km_iters, em_iters,
+                                nthreads, _ptr(beta), _ptr(hist))
+    if rc != 0:
+        raise ValueError(f"orc_beta_train failed ({rc})")
+    return beta, hist
+
+
+def beta_shared(x, ids, proj, d_pad, cent, codes, adj0, k_reg):
+    x = _c(x, np.float32)
+    ids = _c(ids, np.int64)
+    proj = None if proj is None else _c(proj, np.float32)
+    beta = np.empty(k_reg + 1, np.float64)
+    rc = _load().orc_beta_shared(_ptr(x), _ptr(ids), ids.shape[0], x.shape[1], _ptr(proj), d_pad, cent.shape[0],
+                                 cent.shape[1], _ptr(_c(cent, np.float32)), _ptr(_c(codes, np.uint8)), codes.shape[1],
+                                 _ptr(_c(adj0, np.int32)), adj0.shape[1], k_reg, _ptr(beta))
+    if rc != 0:
+        raise ValueError(f"orc_beta_shared failed ({rc})")
+    return beta
+
+
+def beta_assign(x, proj, d_pad, cent, codes, adj0, k_reg, beta, nthreads=1):
+    x = _c(x, np.float32)
+    proj = None if proj is None else _c(proj, np.float32)
+    beta = _c(beta, np.float32)
+    out = np.empty(x.shape[0], np.uint8)
+    rc = _load().orc_beta_assign(_ptr(x), x.shape[0], x.shape[1], _ptr(proj), d_pad, cent.shape[0], cent.shape[1],
+                                 _ptr(_c(cent, np.float32)), _ptr(_c(codes, np.uint8)), codes.shape[1],
+                                 _ptr(_c(adj0, np.int32)), adj0.shape[1], k_reg, beta.shape[0], _ptr(beta), nthreads,
+                                 _ptr(out))
+    if rc != 0:
+        raise ValueError(f"orc_beta_assign failed ({rc})")
+    return out
+
+
+# ---------------------------------------------------------------------------
+# index
+# ---------------------------------------------------------------------------
+@dataclass
+class Index:
+    """An index in the shared array layout (see ``lc_oracle.h``)."""
+    n: int
+    d: int
+    d_pad: int
+    m: int
+    deg0: int
+    deg_up: int
+    k_reg: int
+    n_beta: int
+    entry: int
+    max_level: int
+    proj: Optional[np.ndarray]
+    centroids: np.ndarray
+    codes: np.ndarray
+    adj0: np.ndarray
+    level: np.ndarray
+    up_base: np.ndarray
+    adj_up: np.ndarray
+    beta: np.ndarray
+    beta_idx: np.ndarray
+    ksub: int = 256
+
+    def arrays(self) -> dict:
+        return {k: getattr(self, k) for k in ("proj", "centroids", "codes", "adj0", "level", "up_base", "adj_up",
+                                              "beta", "beta_idx")}
+
+    def _struct(self) -> OrcIndex:
+        s = OrcIndex()
+        s.n, s.d, s.d_pad, s.m, s.ksub = self.n, self.d, self.d_pad, self.m, self.ksub
+        s.code_stride = self.codes.shape[1]
+        s.deg0, s.deg_up, s.k_reg, s.n_beta = self.deg0, self.deg_up, self.k_reg, self.n_beta
+        s.entry, s.max_level = self.entry, self.max_level
+        for name in ("proj", "centroids", "codes", "adj0", "up_base", "adj_up", "beta", "beta_idx"):
+            a = getattr(self, name)
+            setattr(s, name, None if a is None or a.size == 0 else a.ctypes.data)
+        return s
+
+    def lut(self, y: np.ndarray) -> np.ndarray:
+        out = np.empty((self.m, self.ksub), np.float64)
+        s = self._struct()
+        _load().orc_lut(C.byref(s), _ptr(_c(y, np.float32)), _ptr(out))
+        return out
+
+    def refined_distance(self, y: np.ndarray, i: int) -> float:
+        s = self._struct()
+        return float(_load().orc_refined_distance(C.byref(s), _ptr(_c(y, np.float32)), int(i)))
+
+    def walk_trace(self, y: np.ndarray, ef_eff: int, cap: int = 1 << 20) -> np.ndarray:
+        s = self._struct()
+        out = np.empty(cap, np.int32)
+        nt = _load().orc_walk_trace(C.byref(s), _ptr(_c(y, np.float32)), int(ef_eff), _ptr(out), cap)
+        return out[:nt].copy()
+
+    def search(self, q: np.ndarray, ef, S: int, K: int, nthreads: Optional[int] = None) -> dict:
+        q = _c(q, np.float32)
+        nq = q.shape[0]
+        ef_arr = _c(np.broadcast_to(np.asarray(ef, dtype=np.int32), (nq,)), np.int32)
+        out = {
+            "ids": np.empty((nq, K), np.int32), "d": np.empty((nq, K), np.float64),
+            "cand_ids": np.empty((nq, S), np.int32), "cand_adc": np.empty((nq, S), np.float64),
+            "cand_n": np.empty(nq, np.int32), "stats": np.empty((nq, 2), np.int32),
+        }
+        s = self._struct()
+        rc = _load().orc_search(C.byref(s), _ptr(q), nq, _ptr(ef_arr), S, K, nthreads or default_threads(),
+                                _ptr(out["ids"]), _ptr(out["d"]), _ptr(out["cand_ids"]), _ptr(out["cand_adc"]),
+                                _ptr(out["cand_n"]), _ptr(out["stats"]))
+        if rc != 0:
+            raise ValueError(f"orc_search failed ({rc})")
+        return out
+
+
+def build_index(w, db: np.ndarray, train: np.ndarray, proj: Optional[np.ndarray], level_u: np.ndarray,
+                pq_init: np.ndarray, beta_ids: np.ndarray, beta_init: np.ndarray,
+                nthreads: Optional[int] = None) -> Index:
+    """Whole build from the seeded inputs: PQ, levels, graph, regression codebook."""
+    nt = nthreads or default_threads()
+    cent, _ = pq_train(train, proj, w.d_pad, w.m, pq_init, w.pq_iters, nt)
+    codes = pq_encode(db, proj, w.d_pad, cent, nt)
+    lv, _ = levels(level_u, w.level_ratio, w.max_level_cap)
+    adj0, up_base, adj_up, entry, maxl = hnsw_build(db, proj, w.d_pad, cent, codes, lv, w.deg0, w.deg_up,
+                                                    w.ef_construction, nt)
+    beta, _ = beta_train(db, beta_ids, proj, w.d_pad, cent, codes, adj0, w.k_reg, w.n_beta, beta_init,
+                         w.beta_kmeans_iters, w.em_iters, nt)
+    bidx = beta_assign(db, proj, w.d_pad, cent, codes, adj0, w.k_reg, beta, nt)
+    return Index(n=db.shape[0], d=db.shape[1], d_pad=w.d_pad, m=w.m, deg0=w.deg0, deg_up=w.deg_up, k_reg=w.k_reg,
+                 n_beta=w.n_beta, entry=entry, max_level=maxl, proj=proj, centroids=cent, codes=codes, adj0=adj0,
+                 level=lv, up_base=up_base, adj_up=adj_up, beta=beta, beta_idx=bidx)
+
+
+def build_workload(w, nthreads: Optional[int] = None) -> tuple:
+    """(index, db, queries) for a workload description, all from its seed."""
+    import datagen
+    db = datagen.vectors(w, "db")
+    q = datagen.vectors(w, "query")
+    train = datagen.vectors(w, "train")
+    proj = datagen.projection(w)
+    ix = build_index(w, db, train, proj, datagen.level_uniforms(w), datagen.pq_init_ids(w, train.shape[0]),
+                     datagen.beta_train_ids(w), datagen.beta_init_ids(w, min(w.n, w.n_beta_train)), nthreads)
+    return ix, db, q
