@@ -1,0 +1,154 @@
+/*
+ * liblc — Link & Code search on AMD Instinct MI355X (gfx950).
+ *
+ * Paper: M. Douze, A. Sablayrolles, H. Jegou, "Link and code: Fast indexing
+ * with graphs and compact regression codes", CVPR 2018 (arXiv 1804.09996).
+ *
+ * The search path has three calls, each one or more HIP kernels on the
+ * caller's stream:
+ *   lc_build_lut  per-query product-quantizer distance tables (Sec. 4.1,
+ *                 asymmetric distance computation).
+ *   lc_search     greedy descent on the upper graph levels, then a
+ *                 best-first walk on level 0 whose nodes hold only PQ codes
+ *                 (Sec. 2; Sec. 4.1 "Graph-based structure"); returns the
+ *                 short-list of the first stage (Sec. 4.1 "Refinement
+ *                 strategy").
+ *   lc_refine     re-ranks the short-list with the regression refinement
+ *                 x~ = sum_j beta_j q(g_j(x)) (Sec. 4.2 Eq. 5 with a beta taken
+ *                 from the learned codebook of Sec. 4.3, Eq. 7) and keeps the
+ *                 top K by (squared L2 distance, id).
+ *
+ * Conventions (all calls):
+ *  - Distances are squared Euclidean (Sec. 2 works with d = l2).
+ *  - Ids are int32; -1 marks "no entry".  Keys are ordered by (distance, id).
+ *  - Every data pointer is a DEVICE pointer owned by the caller; the library
+ *    never allocates, frees or copies device memory and never synchronises
+ *    the stream.  `stream` is a hipStream_t (NULL = the null stream).
+ *  - Arguments are validated on the host before anything is launched; a
+ *    failed check returns LC_EINVAL / LC_ENOTSUP / LC_ENOSPC and launches
+ *    nothing.  A launch error returns LC_EHIP; faults inside a kernel surface
+ *    at the caller's next synchronisation.
+ *  - The bound index is immutable, so calls on different streams may run
+ *    concurrently (each with its own workspace).
+ *  - Results do not depend on nq, on the batch a query is in, or on the
+ *    launch schedule.
+ */
+#ifndef LC_H
+#define LC_H
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  LC_OK = 0,
+  LC_EINVAL = 1,  /* a null pointer, a size out of range, inconsistent shapes */
+  LC_ENOSPC = 2,  /* workspace too small                                     */
+  LC_ENOTSUP = 3, /* shape the kernels do not support (e.g. m % 8 != 0)       */
+  LC_EHIP = 4     /* HIP runtime or launch error                              */
+};
+
+enum { LC_LUT_F32 = 0, LC_LUT_F16 = 1 };
+enum { LC_REFINE_F32 = 0, LC_REFINE_BF16_RESCORE = 1 };
+
+/* Borrowed device views of an index (the caller keeps the memory alive).
+ * Layout (row-major, all device memory):
+ *   proj      f32 [d_pad][d]    orthonormal rotation applied before PQ, or
+ *                               NULL when d_pad == d (a rotation ahead of the
+ *                               product quantizer, as OPQ does, Sec. 5.1)
+ *   centroids f32 [m][256][dsub], dsub = d_pad / m (8-bit PQ, Sec. 3.3)
+ *   codes     u8  [n][code_stride], code_stride = next power of two >= m
+ *   adj0      i32 [n][deg0]      level-0 links, -1 padded at the end, each
+ *                               list sorted by increasing distance to its
+ *                               owner (Sec. 4.2 orders g_1..g_k that way)
+ *   up_base   i32 [n]            first upper row of node i, -1 on level 0;
+ *                               the row of level l >= 1 is up_base[i] + l - 1
+ *   adj_up    i32 [n_up_rows][deg_up]  upper-level links, -1 padded
+ *   beta      f32 [n_beta][k_reg + 1]  regression codebook (Sec. 4.3)
+ *   beta_idx  u8  [n]            codebook entry of every vector (1 byte,
+ *                               Sec. 4.3)
+ * entry is the single node of the top level, max_level its level (Sec. 2). */
+typedef struct {
+  int32_t n, d, d_pad, m, ksub, code_stride, deg0, deg_up, k_reg, n_beta;
+  int32_t entry, max_level;
+  int64_t n_up_rows;
+  const float *proj;
+  const float *centroids;
+  const uint8_t *codes;
+  const int32_t *adj0;
+  const int32_t *up_base;
+  const int32_t *adj_up;
+  const float *beta;
+  const uint8_t *beta_idx;
+} lc_index_view;
+
+typedef struct lc_index lc_index;
+
+/* Validate the view and keep a host-side copy of it (host memory only; the
+ * device arrays are borrowed).  Requires ksub == 256, m % 8 == 0, m <= 64,
+ * d_pad % m == 0, dsub <= 16, deg0 <= 32, deg_up <= 32, 1 <= k_reg <= deg0,
+ * 1 <= n_beta <= 256, 0 <= entry < n.  Returns LC_OK and *out, or an error
+ * code and *out = NULL. */
+int lc_index_bind(const lc_index_view *view, lc_index **out);
+void lc_index_release(lc_index *ix);
+
+/* Distance tables, Sec. 4.1 (asymmetric distances):
+ *   LUT[q][s][c] = || (P y_q)^s - C[s][c] ||^2,  s < m, c < 256.
+ * q:   f32 [nq][d] queries.
+ * lut: LC_LUT_F32 -> f32 [nq][m][256];
+ *      LC_LUT_F16 -> f16 [nq][m][256] holding LUT / lut_scale[q], with
+ *      lut_scale f32 [nq] (precision form; NULL for F32).
+ * nq == 0 is a no-op. */
+int lc_build_lut(const lc_index *ix, const float *q, int64_t nq, int lut_dtype, void *lut,
+                 float *lut_scale, void *stream);
+
+/* Bytes of workspace lc_search needs for nq queries with every ef <= ef_max
+ * and short-list S.  The workspace must be zero-filled before its first use;
+ * lc_search leaves it zero-filled again when it returns. */
+size_t lc_search_workspace_bytes(const lc_index *ix, int64_t nq, int32_t ef_max, int32_t S);
+
+/* First stage (Sec. 2 walk + Sec. 4.1 short-list).  For every query q:
+ *   1. greedy descent from `entry` on levels max_level..1: move to the
+ *      neighbour with the smallest key while it beats the current key;
+ *   2. best-first walk on level 0 with a pool W of at most
+ *      ef_eff = max(ef[q], S) keys: repeatedly expand the best
+ *      not-yet-expanded entry of W, evaluate its unvisited links by ADC
+ *      (sum of LUT[s][code[s]]), keep the best ef_eff; stop when every entry
+ *      of W has been expanded;
+ *   3. short-list = the min(S, |W|) best entries of W.
+ * lut:       as written by lc_build_lut (lut_scale for F16, else NULL).
+ * ef:        i32 [nq] per-query efSearch, or NULL for ef_max everywhere;
+ *            a query with ef[q] < 1 or ef[q] > ef_max is not searched and
+ *            gets cand_n[q] = -1.
+ * cand_ids:  i32 [nq][S] short-list ids in key order, -1 padded.
+ * cand_adc:  f32 [nq][S] their ADC distances, +inf padded.
+ * cand_n:    i32 [nq] number of valid short-list entries.
+ * stats:     i32 [nq][2] = (E, D): level-0 expansions and newly visited
+ *            nodes, or NULL.
+ * ws:        workspace of at least lc_search_workspace_bytes(ix, nq, ef_max, S). */
+int lc_search(const lc_index *ix, const void *lut, int lut_dtype, const float *lut_scale,
+              int64_t nq, const int32_t *ef, int32_t ef_max, int32_t S, int32_t *cand_ids,
+              float *cand_adc, int32_t *cand_n, int32_t *stats, void *ws, size_t ws_bytes,
+              void *stream);
+
+/* Second stage (Sec. 4.1 "Refinement strategy"; Sec. 4.2 Eq. 5; Sec. 4.3
+ * Eq. 7).  For each valid short-list id i:
+ *   b = beta_idx[i], g_0 = i, g_j = adj0[i][j-1] (j = 1..k_reg, -1 -> zero),
+ *   x~ = sum_j beta[b][j] * q(g_j),   d~ = || P y - x~ ||^2,
+ * then the K smallest (d~, id) in ascending order.
+ * cand_ids, cand_n: as produced by lc_search (cand_n[q] <= 0 -> no candidates).
+ * precision: LC_REFINE_F32 (fp32 throughout) or LC_REFINE_BF16_RESCORE.
+ * out_ids i32 [nq][K] (-1 padded), out_d f32 [nq][K] (+inf padded).
+ * Requires 1 <= K <= S. */
+int lc_refine(const lc_index *ix, const float *q, int64_t nq, const int32_t *cand_ids,
+              const int32_t *cand_n, int32_t S, int32_t K, int precision, int32_t *out_ids,
+              float *out_d, void *stream);
+
+const char *lc_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,224 @@
+"""Link & Code search on AMD Instinct MI355X.
+
+A thin ctypes binding of ``liblc.so`` (include/lc.h).  PyTorch supplies device
+memory and the current stream; every step of the search runs in the library's
+HIP kernels.  Importing the package does not need a GPU, but every call that
+launches work raises if the native library is missing: there is no CPU
+fallback.
+
+Names follow the paper: ``build_lut`` (Sec. 4.1 asymmetric distances),
+``search`` (Sec. 2 walk and the Sec. 4.1 short-list), ``refine`` (Sec. 4.2 /
+4.3 regression refinement and top-K).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+from typing import Optional, Union
+
+import numpy as np
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "liblc.so")
+
+LC_OK, LC_EINVAL, LC_ENOSPC, LC_ENOTSUP, LC_EHIP = 0, 1, 2, 3, 4
+LC_LUT_F32, LC_LUT_F16 = 0, 1
+LC_REFINE_F32, LC_REFINE_BF16_RESCORE = 0, 1
+
+_lib = None
+
+
+class LCError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        msg = lib().lc_strerror(code).decode() if _lib is not None else str(code)
+        super().__init__(f"{where}: {msg} (code {code})")
+        self.code = code
+
+
+class IndexView(C.Structure):
+    _fields_ = [(n, C.c_int32) for n in ("n", "d", "d_pad", "m", "ksub", "code_stride", "deg0", "deg_up", "k_reg",
+                                          "n_beta", "entry", "max_level")] + \
+               [("n_up_rows", C.c_int64)] + \
+               [(n, C.c_void_p) for n in ("proj", "centroids", "codes", "adj0", "up_base", "adj_up", "beta",
+                                          "beta_idx")]
+
+
+def lib():
+    """The loaded ``liblc.so``; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_1804_09996_amd.build_ext` "
+                              "(or __graft_entry__.build()); there is no CPU fallback")
+        L = C.CDLL(LIB_PATH)
+        p, i32, i64, sz = C.c_void_p, C.c_int32, C.c_int64, C.c_size_t
+        L.lc_strerror.argtypes = [C.c_int]
+        L.lc_strerror.restype = C.c_char_p
+        L.lc_index_bind.argtypes = [C.POINTER(IndexView), C.POINTER(p)]
+        L.lc_index_release.argtypes = [p]
+        L.lc_index_release.restype = None
+        L.lc_build_lut.argtypes = [p, p, i64, C.c_int, p, p, p]
+        L.lc_search_workspace_bytes.argtypes = [p, i64, i32, i32]
+        L.lc_search_workspace_bytes.restype = sz
+        L.lc_search.argtypes = [p, p, C.c_int, p, i64, p, i32, i32, p, p, p, p, p, sz, p]
+        L.lc_refine.argtypes = [p, p, i64, p, p, i32, i32, C.c_int, p, p, p]
+        _lib = L
+    return _lib
+
+
+def exported_symbols():
+    return ["lc_strerror", "lc_index_bind", "lc_index_release", "lc_build_lut", "lc_search_workspace_bytes",
+            "lc_search", "lc_refine"]
+
+
+def _check(rc: int, where: str):
+    if rc != LC_OK:
+        raise LCError(rc, where)
+
+
+def _stream(torch, device):
+    return C.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _ptr(t) -> Optional[int]:
+    return None if t is None else t.data_ptr()
+
+
+@dataclass
+class SearchResult:
+    cand_ids: "object"
+    cand_adc: "object"
+    cand_n: "object"
+    stats: "object"
+
+
+class Index:
+    """An index resident in device memory, bound to ``liblc``.
+
+    ``arrays`` holds numpy arrays in the layout of include/lc.h (keys
+    ``centroids, codes, adj0, up_base, adj_up, beta, beta_idx`` and optional
+    ``proj``); ``meta`` the scalars ``d, d_pad, m, deg0, deg_up, k_reg,
+    entry, max_level``.
+    """
+
+    def __init__(self, arrays: dict, meta: dict, device: Union[str, int] = "cuda"):
+        import torch
+        self.torch = torch
+        self.device = torch.device(device)
+        self.meta = dict(meta)
+        L = lib()
+
+        def up(name, dtype):
+            a = arrays.get(name)
+            if a is None:
+                return None
+            a = np.ascontiguousarray(a, dtype=dtype)
+            if a.size == 0:
+                a = np.zeros(1, dtype=dtype)
+            return torch.from_numpy(a).to(self.device)
+
+        self.t = {
+            "proj": up("proj", np.float32), "centroids": up("centroids", np.float32),
+            "codes": up("codes", np.uint8), "adj0": up("adj0", np.int32), "up_base": up("up_base", np.int32),
+            "adj_up": up("adj_up", np.int32), "beta": up("beta", np.float32), "beta_idx": up("beta_idx", np.uint8),
+        }
+        codes = arrays["codes"]
+        v = IndexView()
+        v.n, v.d, v.d_pad, v.m = codes.shape[0], meta["d"], meta["d_pad"], meta["m"]
+        v.ksub, v.code_stride = 256, codes.shape[1]
+        v.deg0, v.deg_up, v.k_reg = meta["deg0"], meta["deg_up"], meta["k_reg"]
+        v.n_beta = arrays["beta"].shape[0]
+        v.entry, v.max_level = meta["entry"], meta["max_level"]
+        au = arrays.get("adj_up")
+        v.n_up_rows = 0 if au is None else au.shape[0]
+        for name in ("proj", "centroids", "codes", "adj0", "up_base", "adj_up", "beta", "beta_idx"):
+            setattr(v, name, _ptr(self.t[name]))
+        self.view = v
+        h = C.c_void_p()
+        with torch.cuda.device(self.device):
+            _check(L.lc_index_bind(C.byref(v), C.byref(h)), "lc_index_bind")
+        self.handle = h
+        self.n, self.m, self.d, self.d_pad = v.n, v.m, v.d, v.d_pad
+        self.k_reg = v.k_reg
+        self._ws = None
+
+    @classmethod
+    def from_index(cls, ix, device="cuda") -> "Index":
+        """From any object with the index attributes (e.g. a built index)."""
+        arrays = {k: getattr(ix, k) for k in ("proj", "centroids", "codes", "adj0", "up_base", "adj_up", "beta",
+                                              "beta_idx")}
+        meta = {k: int(getattr(ix, k)) for k in ("d", "d_pad", "m", "deg0", "deg_up", "k_reg", "entry",
+                                                 "max_level")}
+        return cls(arrays, meta, device)
+
+    def close(self):
+        if getattr(self, "handle", None) and self.handle.value:
+            lib().lc_index_release(self.handle)
+            self.handle = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- the three calls of the path ---------------------------------------
+    def build_lut(self, q, lut_dtype: int = LC_LUT_F32):
+        torch = self.torch
+        q = q.to(self.device, torch.float32).contiguous()
+        nq = q.shape[0]
+        if lut_dtype == LC_LUT_F32:
+            lut = torch.empty((nq, self.m, 256), dtype=torch.float32, device=self.device)
+            scale = None
+        else:
+            lut = torch.empty((nq, self.m, 256), dtype=torch.float16, device=self.device)
+            scale = torch.empty(nq, dtype=torch.float32, device=self.device)
+        _check(lib().lc_build_lut(self.handle, _ptr(q), nq, lut_dtype, _ptr(lut), _ptr(scale),
+                                  _stream(torch, self.device)), "lc_build_lut")
+        return lut, scale
+
+    def workspace(self, nq: int, ef_max: int, S: int):
+        torch = self.torch
+        need = lib().lc_search_workspace_bytes(self.handle, max(nq, 1), ef_max, S)
+        if self._ws is None or self._ws.numel() < need:
+            self._ws = torch.zeros(max(need, 1), dtype=torch.uint8, device=self.device)
+        return self._ws
+
+    def search(self, lut, scale=None, ef=None, ef_max: int = 64, S: int = 64, stats: bool = True,
+               lut_dtype: Optional[int] = None) -> SearchResult:
+        torch = self.torch
+        nq = lut.shape[0]
+        if lut_dtype is None:
+            lut_dtype = LC_LUT_F16 if lut.dtype == torch.float16 else LC_LUT_F32
+        ef_t = None
+        if ef is not None:
+            ef_t = torch.as_tensor(ef, dtype=torch.int32).to(self.device).contiguous()
+            if ef_t.dim() == 0:
+                ef_t = ef_t.expand(nq).contiguous()
+        cand_ids = torch.empty((nq, S), dtype=torch.int32, device=self.device)
+        cand_adc = torch.empty((nq, S), dtype=torch.float32, device=self.device)
+        cand_n = torch.empty(nq, dtype=torch.int32, device=self.device)
+        st = torch.empty((nq, 2), dtype=torch.int32, device=self.device) if stats else None
+        ws = self.workspace(nq, ef_max, S)
+        _check(lib().lc_search(self.handle, _ptr(lut), lut_dtype, _ptr(scale), nq, _ptr(ef_t), ef_max, S,
+                               _ptr(cand_ids), _ptr(cand_adc), _ptr(cand_n), _ptr(st), _ptr(ws), ws.numel(),
+                               _stream(torch, self.device)), "lc_search")
+        return SearchResult(cand_ids, cand_adc, cand_n, st)
+
+    def refine(self, q, cand_ids, cand_n, K: int, precision: int = LC_REFINE_F32):
+        torch = self.torch
+        q = q.to(self.device, torch.float32).contiguous()
+        nq, S = cand_ids.shape
+        out_ids = torch.empty((nq, K), dtype=torch.int32, device=self.device)
+        out_d = torch.empty((nq, K), dtype=torch.float32, device=self.device)
+        _check(lib().lc_refine(self.handle, _ptr(q), nq, _ptr(cand_ids), _ptr(cand_n), S, K, precision,
+                               _ptr(out_ids), _ptr(out_d), _stream(torch, self.device)), "lc_refine")
+        return out_ids, out_d
+
+    def query(self, q, ef=None, ef_max: int = 64, S: int = 64, K: int = 10, stats: bool = False):
+        """The whole path: tables, walk and short-list, refinement and top-K."""
+        lut, scale = self.build_lut(q)
+        r = self.search(lut, scale, ef=ef, ef_max=ef_max, S=S, stats=stats)
+        ids, d = self.refine(q, r.cand_ids, r.cand_n, K)
+        return ids, d, r

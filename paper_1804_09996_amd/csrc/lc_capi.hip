@@ -1,0 +1,108 @@
+// C-ABI of liblc: argument validation and dispatch to the kernel launchers.
+#include <new>
+
+#include "lc_internal.h"
+
+namespace {
+
+bool pow2(int x) { return x > 0 && (x & (x - 1)) == 0; }
+
+bool supported_dsub(int ds) {
+  return ds == 1 || ds == 2 || ds == 3 || ds == 4 || ds == 6 || ds == 8 || ds == 12 || ds == 16;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *lc_strerror(int code) {
+  switch (code) {
+    case LC_OK: return "ok";
+    case LC_EINVAL: return "invalid argument";
+    case LC_ENOSPC: return "workspace too small";
+    case LC_ENOTSUP: return "unsupported shape or mode";
+    case LC_EHIP: return "HIP runtime error";
+    default: return "unknown error";
+  }
+}
+
+int lc_index_bind(const lc_index_view *v, lc_index **out) {
+  if (!out) return LC_EINVAL;
+  *out = nullptr;
+  if (!v) return LC_EINVAL;
+  if (v->n < 1 || v->d < 1 || v->d_pad < v->d || v->m < 1 || v->ksub != 256) return LC_EINVAL;
+  if (v->d_pad % v->m != 0) return LC_EINVAL;
+  if (!pow2(v->code_stride) || v->code_stride < v->m || (v->code_stride >> 1) >= v->m) return LC_EINVAL;
+  if (v->deg0 < 1 || v->deg_up < 1 || v->k_reg < 1 || v->k_reg > v->deg0) return LC_EINVAL;
+  if (v->n_beta < 1 || v->n_beta > 256) return LC_EINVAL;
+  if (v->entry < 0 || v->entry >= v->n || v->max_level < 0 || v->n_up_rows < 0) return LC_EINVAL;
+  if (v->max_level > 0 && v->n_up_rows < v->max_level) return LC_EINVAL;
+  if (!v->centroids || !v->codes || !v->adj0 || !v->up_base || !v->beta || !v->beta_idx) return LC_EINVAL;
+  if (v->max_level > 0 && !v->adj_up) return LC_EINVAL;
+  if ((v->d_pad != v->d) != (v->proj != nullptr)) return LC_EINVAL;
+  if (v->m % 8 != 0 || v->m > 64 || v->deg0 > 32 || v->deg_up > 32) return LC_ENOTSUP;
+  if (!supported_dsub(v->d_pad / v->m)) return LC_ENOTSUP;
+  lc_index *ix = new (std::nothrow) lc_index;
+  if (!ix) return LC_EINVAL;
+  ix->v = *v;
+  ix->dsub = v->d_pad / v->m;
+  if (hipGetDevice(&ix->device) != hipSuccess) {
+    delete ix;
+    return LC_EHIP;
+  }
+  int cus = 0, lds = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ix->device) != hipSuccess ||
+      hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, ix->device) !=
+          hipSuccess) {
+    delete ix;
+    return LC_EHIP;
+  }
+  ix->num_cus = cus > 0 ? cus : 1;
+  ix->lds_per_cu = lds > 0 ? lds : 65536;
+  *out = ix;
+  return LC_OK;
+}
+
+void lc_index_release(lc_index *ix) { delete ix; }
+
+int lc_build_lut(const lc_index *ix, const float *q, int64_t nq, int lut_dtype, void *lut,
+                 float *lut_scale, void *stream) {
+  if (!ix || nq < 0) return LC_EINVAL;
+  if (lut_dtype != LC_LUT_F32 && lut_dtype != LC_LUT_F16) return LC_EINVAL;
+  if (nq == 0) return LC_OK;
+  if (!q || !lut) return LC_EINVAL;
+  if (lut_dtype == LC_LUT_F16 && !lut_scale) return LC_EINVAL;
+  return lc_launch_lut(ix, q, nq, lut_dtype, lut, lut_scale, static_cast<hipStream_t>(stream));
+}
+
+size_t lc_search_workspace_bytes(const lc_index *ix, int64_t nq, int32_t ef_max, int32_t S) {
+  if (!ix || nq < 1 || ef_max < 1 || S < 1) return 0;
+  return lc_walk_workspace_bytes(ix, nq, ef_max, S);
+}
+
+int lc_search(const lc_index *ix, const void *lut, int lut_dtype, const float *lut_scale, int64_t nq,
+              const int32_t *ef, int32_t ef_max, int32_t S, int32_t *cand_ids, float *cand_adc,
+              int32_t *cand_n, int32_t *stats, void *ws, size_t ws_bytes, void *stream) {
+  if (!ix || nq < 0 || ef_max < 1 || S < 1) return LC_EINVAL;
+  if (ef_max > 4096 || S > 4096) return LC_ENOTSUP;
+  if (lut_dtype != LC_LUT_F32 && lut_dtype != LC_LUT_F16) return LC_EINVAL;
+  if (nq == 0) return LC_OK;
+  if (!lut || !cand_ids || !cand_adc || !cand_n || !ws) return LC_EINVAL;
+  if (lut_dtype == LC_LUT_F16 && !lut_scale) return LC_EINVAL;
+  return lc_launch_walk(ix, lut, lut_dtype, lut_scale, nq, ef, ef_max, S, cand_ids, cand_adc, cand_n, stats,
+                        ws, ws_bytes, static_cast<hipStream_t>(stream));
+}
+
+int lc_refine(const lc_index *ix, const float *q, int64_t nq, const int32_t *cand_ids,
+              const int32_t *cand_n, int32_t S, int32_t K, int precision, int32_t *out_ids, float *out_d,
+              void *stream) {
+  if (!ix || nq < 0 || S < 1 || K < 1 || K > S) return LC_EINVAL;
+  if (S > 4096) return LC_ENOTSUP;
+  if (precision != LC_REFINE_F32 && precision != LC_REFINE_BF16_RESCORE) return LC_EINVAL;
+  if (nq == 0) return LC_OK;
+  if (!q || !cand_ids || !cand_n || !out_ids || !out_d) return LC_EINVAL;
+  return lc_launch_refine(ix, q, nq, cand_ids, cand_n, S, K, precision, out_ids, out_d,
+                          static_cast<hipStream_t>(stream));
+}
+
+}  // extern "C"

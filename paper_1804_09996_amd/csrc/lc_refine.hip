@@ -1,0 +1,335 @@
+// Second stage of the search (Sec. 4.1 "Refinement strategy"): every
+// short-list entry i is rebuilt from its own code and the codes of its first
+// k graph links, weighted by its regression vector (Sec. 4.2 Eq. 5 with the
+// codebook entry of Sec. 4.3 Eq. 7):
+//
+//   x~_i = sum_{j=0..k} beta[b_i][j] * q(g_j(i)),  g_0 = i, g_j = adj0[i][j-1]
+//   d~   = || P y - x~_i ||^2
+//
+// and the K smallest (d~, id) are kept.  A block stages the centroids of all
+// sub-spaces in LDS once; each wavefront then owns one query at a time.  Four
+// lanes share a candidate, lane part p accumulating the sub-spaces s = p mod 4
+// in registers; the candidate's distance is the sum of the four partial sums
+// in a fixed order.  The short-list keys are sorted in LDS by a bitonic
+// network and the first K written out.
+#include "lc_internal.h"
+
+namespace {
+
+using namespace lc;
+
+struct RefineArgs {
+  const float *q;
+  int64_t nq;
+  int d, d_pad;
+  const float *proj, *cent;
+  const uint8_t *codes;
+  int code_stride;
+  const int32_t *adj0;
+  int n, n_beta, deg0, k_reg;
+  const float *beta;
+  const uint8_t *beta_idx;
+  const int32_t *cand_ids, *cand_n;
+  int S, K, S_pad, wpb;
+  int32_t *out_ids;
+  float *out_d;
+};
+
+template <int CS>
+struct CodeRow {
+  static constexpr int NV = CS >= 16 ? CS / 16 : 1;
+  uint32_t w[CS >= 16 ? CS / 4 : 4];
+  __device__ __forceinline__ void load(const uint8_t *p) {
+    if constexpr (CS >= 16) {
+#pragma unroll
+      for (int i = 0; i < CS / 16; ++i) {
+        const uint4 v = reinterpret_cast<const uint4 *>(p)[i];
+        w[4 * i] = v.x;
+        w[4 * i + 1] = v.y;
+        w[4 * i + 2] = v.z;
+        w[4 * i + 3] = v.w;
+      }
+    } else {
+      const uint2 v = *reinterpret_cast<const uint2 *>(p);
+      w[0] = v.x;
+      w[1] = v.y;
+    }
+  }
+  __device__ __forceinline__ uint32_t byte(int s) const { return (w[s >> 2] >> (8 * (s & 3))) & 0xFFu; }
+};
+
+template <int M, int DSUB, int CS>
+__global__ __launch_bounds__(1024) void refine_f32_kernel(RefineArgs a) {
+  constexpr int DP = M * DSUB;
+  constexpr int U = M / 4;  // sub-spaces per lane part
+  extern __shared__ __align__(16) unsigned char smem[];
+  float *C = reinterpret_cast<float *>(smem);  // [M][256][DSUB]
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  unsigned char *wbase = smem + size_t(M) * 256 * DSUB * 4 + size_t(wave) * (DP * 4 + a.S_pad * 8);
+  float *yv = reinterpret_cast<float *>(wbase);
+  uint64_t *keys = reinterpret_cast<uint64_t *>(wbase + DP * 4);
+
+  for (int i = threadIdx.x; i < M * 256 * DSUB / 4; i += blockDim.x)
+    reinterpret_cast<float4 *>(C)[i] = reinterpret_cast<const float4 *>(a.cent)[i];
+  __syncthreads();
+
+  const int part = lane & 3, grp = lane >> 2;
+  for (int64_t q = int64_t(blockIdx.x) * a.wpb + wave; q < a.nq; q += int64_t(gridDim.x) * a.wpb) {
+    const float *y = a.q + q * a.d;
+    for (int r = lane; r < DP; r += 64) {
+      float v;
+      if (a.proj) {
+        const float *pr = a.proj + size_t(r) * a.d;
+        v = 0.f;
+        for (int u = 0; u < a.d; ++u) v += pr[u] * y[u];
+      } else {
+        v = y[r];
+      }
+      yv[r] = v;
+    }
+    wave_sync();
+    const int cn = a.cand_n[q];
+    for (int c0 = 0; c0 < a.S_pad; c0 += 16) {
+      const int c = c0 + grp;
+      int32_t id = -1;
+      if (c < a.S && c < cn) id = a.cand_ids[q * a.S + c];
+      if (id >= a.n || (id >= 0 && a.beta_idx[id] >= a.n_beta)) id = -1;  // malformed input: no candidate
+      float acc[U * DSUB];
+#pragma unroll
+      for (int t = 0; t < U * DSUB; ++t) acc[t] = 0.f;
+      if (id >= 0) {
+        const float *bw = a.beta + size_t(a.beta_idx[id]) * (a.k_reg + 1);
+        const int32_t *links = a.adj0 + int64_t(id) * a.deg0;
+        for (int j = 0; j <= a.k_reg; ++j) {
+          const int32_t g = j == 0 ? id : links[j - 1];
+          if (g < 0 || g >= a.n) continue;  // a missing link is a zero vector
+          const float w = bw[j];
+          CodeRow<CS> row;
+          row.load(a.codes + size_t(g) * CS);
+#pragma unroll
+          for (int u = 0; u < U; ++u) {
+            const int s = part + 4 * u;
+            const float *cr = C + (s * 256 + int(row.byte(s))) * DSUB;
+#pragma unroll
+            for (int t = 0; t < DSUB; ++t) acc[u * DSUB + t] += w * cr[t];
+          }
+        }
+      }
+      float e = 0.f;
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int s = part + 4 * u;
+#pragma unroll
+        for (int t = 0; t < DSUB; ++t) {
+          const float df = yv[s * DSUB + t] - acc[u * DSUB + t];
+          e += df * df;
+        }
+      }
+      // (p0 + p1) + (p2 + p3)
+      e += __shfl_xor(e, 1);
+      e += __shfl_xor(e, 2);
+      if (part == 0 && c < a.S_pad) keys[c] = id >= 0 ? make_key(e, id) : kKeyMax;
+    }
+    wave_sync();
+    // bitonic sort of S_pad keys, ascending
+    for (int k = 2; k <= a.S_pad; k <<= 1) {
+      for (int j = k >> 1; j > 0; j >>= 1) {
+        for (int i = lane; i < a.S_pad; i += 64) {
+          const int ixj = i ^ j;
+          if (ixj > i) {
+            const uint64_t x = keys[i], z = keys[ixj];
+            const bool asc = (i & k) == 0;
+            if ((x > z) == asc) {
+              keys[i] = z;
+              keys[ixj] = x;
+            }
+          }
+        }
+        wave_sync();
+      }
+    }
+    for (int r = lane; r < a.K; r += 64) {
+      const uint64_t v = keys[r];
+      a.out_ids[q * a.K + r] = v == kKeyMax ? -1 : key_id(v);
+      a.out_d[q * a.K + r] = v == kKeyMax ? __builtin_inff() : key_dist(v);
+    }
+    wave_sync();
+  }
+}
+
+
+// Any (m, dsub) without a specialised kernel: a lane part walks its
+// sub-spaces one at a time and re-reads the code byte of each neighbour.
+__global__ __launch_bounds__(1024) void refine_f32_generic(RefineArgs a, int m, int dsub) {
+  const int DP = m * dsub;
+  extern __shared__ __align__(16) unsigned char smem[];
+  float *C = reinterpret_cast<float *>(smem);
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  unsigned char *wbase = smem + size_t(m) * 256 * dsub * 4 + size_t(wave) * (DP * 4 + a.S_pad * 8);
+  float *yv = reinterpret_cast<float *>(wbase);
+  uint64_t *keys = reinterpret_cast<uint64_t *>(wbase + DP * 4);
+  for (int i = threadIdx.x; i < m * 256 * dsub; i += blockDim.x) C[i] = a.cent[i];
+  __syncthreads();
+  const int part = lane & 3, grp = lane >> 2;
+  for (int64_t q = int64_t(blockIdx.x) * a.wpb + wave; q < a.nq; q += int64_t(gridDim.x) * a.wpb) {
+    const float *y = a.q + q * a.d;
+    for (int r = lane; r < DP; r += 64) {
+      float v;
+      if (a.proj) {
+        const float *pr = a.proj + size_t(r) * a.d;
+        v = 0.f;
+        for (int u = 0; u < a.d; ++u) v += pr[u] * y[u];
+      } else {
+        v = y[r];
+      }
+      yv[r] = v;
+    }
+    wave_sync();
+    const int cn = a.cand_n[q];
+    for (int c0 = 0; c0 < a.S_pad; c0 += 16) {
+      const int c = c0 + grp;
+      int32_t id = -1;
+      if (c < a.S && c < cn) id = a.cand_ids[q * a.S + c];
+      if (id >= a.n || (id >= 0 && a.beta_idx[id] >= a.n_beta)) id = -1;
+      float e = 0.f;
+      if (id >= 0) {
+        const float *bw = a.beta + size_t(a.beta_idx[id]) * (a.k_reg + 1);
+        const int32_t *links = a.adj0 + int64_t(id) * a.deg0;
+        for (int s = part; s < m; s += 4) {
+          float acc[16];
+          for (int t = 0; t < 16; ++t) acc[t] = 0.f;
+          for (int j = 0; j <= a.k_reg; ++j) {
+            const int32_t g = j == 0 ? id : links[j - 1];
+            if (g < 0 || g >= a.n) continue;
+            const float w = bw[j];
+            const float *cr = C + (s * 256 + int(a.codes[size_t(g) * a.code_stride + s])) * dsub;
+            for (int t = 0; t < dsub; ++t) acc[t] += w * cr[t];
+          }
+          for (int t = 0; t < dsub; ++t) {
+            const float df = yv[s * dsub + t] - acc[t];
+            e += df * df;
+          }
+        }
+      }
+      e += __shfl_xor(e, 1);
+      e += __shfl_xor(e, 2);
+      if (part == 0 && c < a.S_pad) keys[c] = id >= 0 ? make_key(e, id) : kKeyMax;
+    }
+    wave_sync();
+    for (int k = 2; k <= a.S_pad; k <<= 1) {
+      for (int j = k >> 1; j > 0; j >>= 1) {
+        for (int i = lane; i < a.S_pad; i += 64) {
+          const int ixj = i ^ j;
+          if (ixj > i) {
+            const uint64_t x = keys[i], z = keys[ixj];
+            const bool asc = (i & k) == 0;
+            if ((x > z) == asc) {
+              keys[i] = z;
+              keys[ixj] = x;
+            }
+          }
+        }
+        wave_sync();
+      }
+    }
+    for (int r = lane; r < a.K; r += 64) {
+      const uint64_t v = keys[r];
+      a.out_ids[q * a.K + r] = v == kKeyMax ? -1 : key_id(v);
+      a.out_d[q * a.K + r] = v == kKeyMax ? __builtin_inff() : key_dist(v);
+    }
+    wave_sync();
+  }
+}
+
+int next_pow2(int x) {
+  int p = 1;
+  while (p < x) p <<= 1;
+  return p;
+}
+
+RefineArgs make_args(const lc_index *ix, const float *q, int64_t nq, const int32_t *cand_ids,
+                     const int32_t *cand_n, int32_t S, int32_t K, int32_t *out_ids, float *out_d) {
+  RefineArgs a;
+  a.q = q;
+  a.nq = nq;
+  a.d = ix->v.d;
+  a.d_pad = ix->v.d_pad;
+  a.proj = ix->v.proj;
+  a.cent = ix->v.centroids;
+  a.codes = ix->v.codes;
+  a.code_stride = ix->v.code_stride;
+  a.adj0 = ix->v.adj0;
+  a.n = ix->v.n;
+  a.n_beta = ix->v.n_beta;
+  a.deg0 = ix->v.deg0;
+  a.k_reg = ix->v.k_reg;
+  a.beta = ix->v.beta;
+  a.beta_idx = ix->v.beta_idx;
+  a.cand_ids = cand_ids;
+  a.cand_n = cand_n;
+  a.S = S;
+  a.K = K;
+  a.S_pad = next_pow2(S < 16 ? 16 : S);
+  a.out_ids = out_ids;
+  a.out_d = out_d;
+  a.wpb = 0;
+  return a;
+}
+
+// Waves per block and LDS bytes for the centroids plus per-wave buffers.
+bool plan_blocks(const lc_index *ix, RefineArgs &a, int *lds, int64_t *blocks) {
+  const int cent_bytes = ix->v.m * 256 * ix->dsub * 4;
+  const int per_wave = ix->v.d_pad * 4 + a.S_pad * 8;
+  int wpb = (ix->lds_per_cu - cent_bytes) / per_wave;
+  if (wpb > 16) wpb = 16;
+  if (wpb < 1) return false;
+  a.wpb = wpb;
+  *lds = cent_bytes + wpb * per_wave;
+  int64_t b = (a.nq + wpb - 1) / wpb;
+  if (b > ix->num_cus) b = ix->num_cus;
+  *blocks = b < 1 ? 1 : b;
+  return true;
+}
+
+template <int M, int DSUB, int CS>
+int launch_f32(const lc_index *ix, RefineArgs a, hipStream_t st) {
+  int lds;
+  int64_t blocks;
+  if (!plan_blocks(ix, a, &lds, &blocks)) return LC_ENOTSUP;
+  if (hipFuncSetAttribute(reinterpret_cast<const void *>(&refine_f32_kernel<M, DSUB, CS>),
+                          hipFuncAttributeMaxDynamicSharedMemorySize, lds) != hipSuccess)
+    return LC_EHIP;
+  hipLaunchKernelGGL((refine_f32_kernel<M, DSUB, CS>), dim3(int(blocks)), dim3(64 * a.wpb), lds, st, a);
+  return hipGetLastError() == hipSuccess ? LC_OK : LC_EHIP;
+}
+
+int launch_generic(const lc_index *ix, RefineArgs a, hipStream_t st) {
+  int lds;
+  int64_t blocks;
+  if (ix->dsub > 16 || !plan_blocks(ix, a, &lds, &blocks)) return LC_ENOTSUP;
+  if (hipFuncSetAttribute(reinterpret_cast<const void *>(&refine_f32_generic),
+                          hipFuncAttributeMaxDynamicSharedMemorySize, lds) != hipSuccess)
+    return LC_EHIP;
+  hipLaunchKernelGGL(refine_f32_generic, dim3(int(blocks)), dim3(64 * a.wpb), lds, st, a, ix->v.m, ix->dsub);
+  return hipGetLastError() == hipSuccess ? LC_OK : LC_EHIP;
+}
+
+}  // namespace
+
+// Shapes with kernels: (m, dsub) of the supported workloads; code stride is
+// the next power of two >= m.
+int lc_launch_refine(const lc_index *ix, const float *q, int64_t nq, const int32_t *cand_ids,
+                     const int32_t *cand_n, int32_t S, int32_t K, int precision, int32_t *out_ids,
+                     float *out_d, hipStream_t st) {
+  if (precision != LC_REFINE_F32) return LC_ENOTSUP;
+  const RefineArgs a = make_args(ix, q, nq, cand_ids, cand_n, S, K, out_ids, out_d);
+  const int m = ix->v.m, ds = ix->dsub;
+#define SHAPE(MM, DS, CSS) \
+  if (m == MM && ds == DS) return launch_f32<MM, DS, CSS>(ix, a, st);
+  SHAPE(8, 12, 8)
+  SHAPE(16, 6, 16)
+  SHAPE(32, 4, 32)
+  SHAPE(56, 2, 64)
+#undef SHAPE
+  return launch_generic(ix, a, st);
+}

@@ -1,0 +1,183 @@
+"""GPU path against the oracle, element by element, through the C-ABI.
+
+Indexes here are built by the oracle from seeded inputs; the GPU library only
+searches them.  Bars: integer outputs (ids, E, D, short-list) bit-exact;
+float32 distances within 1e-5 relative of the oracle's float64 values; top-K
+ids EXACT in the sense of tests/parity.py on every query.
+"""
+import dataclasses
+
+import numpy as np
+import pytest
+
+import datagen
+import oracle
+from tests import parity
+
+pytestmark = pytest.mark.gpu
+
+F32_EPS = 2.0 ** -24
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    assert t.cuda.is_available(), "GPU tests need a GPU"
+    return t
+
+
+@pytest.fixture(scope="module")
+def c1(c1_build, torch):
+    import paper_1804_09996_amd as lc
+    w, ix, db, q = c1_build
+    return w, ix, lc.Index.from_index(ix), db, q
+
+
+@pytest.fixture(scope="module")
+def c1_oracle(c1):
+    w, ix, gix, db, q = c1
+    return ix.search(q, w.ef, w.shortlist, w.topk)
+
+
+def _lut_bound(ix, q):
+    dsub = ix.d_pad // ix.m
+    mu = ix.centroids.astype(np.float64).mean(1)  # [m][dsub]
+    nc = ((ix.centroids.astype(np.float64) - mu[:, None, :]) ** 2).sum(-1)  # [m][256]
+    out = []
+    for y in q:
+        yp = oracle.project(ix.proj, y, ix.d_pad).reshape(ix.m, dsub)
+        ny = ((yp - mu) ** 2).sum(-1)
+        out.append(16 * F32_EPS * (ny[:, None] + nc) + 1e-30)
+    return np.stack(out)
+
+
+def test_lut_matches_oracle_within_bound(c1, torch):
+    w, ix, gix, db, q = c1
+    lut, _ = gix.build_lut(torch.from_numpy(q))
+    got = lut.cpu().numpy().astype(np.float64)
+    ref = np.stack([ix.lut(y) for y in q])
+    bound = _lut_bound(ix, q)
+    assert got.shape == ref.shape
+    assert np.all(np.abs(got - ref) <= bound), float(np.max(np.abs(got - ref) / bound))
+    assert np.all(got >= 0) and not np.any(np.signbit(got))
+
+
+def test_walk_matches_oracle(c1, c1_oracle, torch):
+    w, ix, gix, db, q = c1
+    lut, _ = gix.build_lut(torch.from_numpy(q))
+    r = gix.search(lut, ef=w.ef, ef_max=w.ef, S=w.shortlist)
+    ids = r.cand_ids.cpu().numpy()
+    adc = r.cand_adc.cpu().numpy()
+    n = r.cand_n.cpu().numpy()
+    st = r.stats.cpu().numpy()
+    o = c1_oracle
+    same = [(np.array_equal(ids[i], o["cand_ids"][i]) and n[i] == o["cand_n"][i]
+             and np.array_equal(st[i], o["stats"][i])) for i in range(w.nq)]
+    print(f"walk identical (short-list, E, D) on {sum(same)}/{w.nq} queries")
+    assert np.mean(same) >= 0.99
+    for i in np.flatnonzero(same):
+        k = n[i]
+        np.testing.assert_allclose(adc[i, :k], o["cand_adc"][i, :k], rtol=1e-5)
+        assert np.all(ids[i, k:] == -1) and np.all(np.isinf(adc[i, k:]))
+
+
+def test_full_path_parity(c1, c1_oracle, torch):
+    w, ix, gix, db, q = c1
+    ids, d, _ = gix.query(torch.from_numpy(q), ef=w.ef, ef_max=w.ef, S=w.shortlist, K=w.topk)
+    ids, d = ids.cpu().numpy(), d.cpu().numpy()
+    s = parity.summarize(ix, q, ids, d, c1_oracle)
+    print(f"EXACT {s['exact_frac']:.4f} strict {s['strict_frac']:.4f} max rel err {s['max_rel_err']:.2e}")
+    assert s["exact_frac"] == 1.0
+    assert s["max_rel_err"] <= 1e-5
+
+
+def test_per_query_ef_and_rejected_queries(c1, torch):
+    w, ix, gix, db, q = c1
+    qq = q[:9]
+    ef = np.array([1, 5, 16, 64, 0, 65, 33, 2, 64], np.int32)
+    lut, _ = gix.build_lut(torch.from_numpy(qq))
+    r = gix.search(lut, ef=torch.from_numpy(ef), ef_max=64, S=8)
+    ids, n, st = r.cand_ids.cpu().numpy(), r.cand_n.cpu().numpy(), r.stats.cpu().numpy()
+    for i in range(9):
+        if ef[i] < 1 or ef[i] > 64:
+            assert n[i] == -1 and np.all(ids[i] == -1)
+            continue
+        o = ix.search(qq[i:i + 1], int(ef[i]), 8, 1)
+        assert np.array_equal(ids[i], o["cand_ids"][0]) and n[i] == o["cand_n"][0]
+        assert np.array_equal(st[i], o["stats"][0])
+
+
+def test_ragged_batches_and_batch_independence(c1, torch):
+    w, ix, gix, db, q = c1
+    full_ids, full_d, full_r = gix.query(torch.from_numpy(q), ef=w.ef, ef_max=w.ef, S=w.shortlist, K=w.topk,
+                                         stats=True)
+    full_ids, full_d = full_ids.cpu().numpy(), full_d.cpu().numpy()
+    for lo, hi in ((0, 1), (3, 20), (37, 100)):
+        ids, d, _ = gix.query(torch.from_numpy(q[lo:hi]), ef=w.ef, ef_max=w.ef, S=w.shortlist, K=w.topk)
+        assert np.array_equal(ids.cpu().numpy(), full_ids[lo:hi])
+        assert np.array_equal(d.cpu().numpy().view(np.uint32), full_d[lo:hi].view(np.uint32))
+    again_ids, again_d, _ = gix.query(torch.from_numpy(q), ef=w.ef, ef_max=w.ef, S=w.shortlist, K=w.topk)
+    assert np.array_equal(again_ids.cpu().numpy(), full_ids)
+    assert np.array_equal(again_d.cpu().numpy().view(np.uint32), full_d.view(np.uint32))
+    # the empty batch is a no-op
+    e_ids, e_d, _ = gix.query(torch.zeros((0, w.d)), ef=w.ef, ef_max=w.ef, S=w.shortlist, K=w.topk)
+    assert e_ids.shape == (0, w.topk)
+
+
+def test_exhaustive_walk_and_short_graph(torch):
+    # ef >= N makes the walk visit the whole (connected) graph; S > |W| pads
+    import paper_1804_09996_amd as lc
+    w = datagen.small(name="gpu-small", n=600, nq=21, d=32, m=8, n_train=1024, n_beta=16, n_beta_train=600, k_reg=8)
+    ix, db, q = oracle.build_workload(w, nthreads=4)
+    gix = lc.Index.from_index(ix)
+    for ef, S, K in ((600, 640, 640), (17, 9, 9), (3, 40, 7)):
+        o = ix.search(q, ef, S, K)
+        ids, d, r = gix.query(torch.from_numpy(q), ef=ef, ef_max=ef, S=S, K=K, stats=True)
+        assert np.array_equal(r.cand_ids.cpu().numpy(), o["cand_ids"])
+        assert np.array_equal(r.stats.cpu().numpy(), o["stats"])
+        s = parity.summarize(ix, q, ids.cpu().numpy(), d.cpu().numpy(), o)
+        assert s["exact_frac"] == 1.0 and s["max_rel_err"] <= 1e-5
+
+
+def test_lossless_case_returns_exact_knn(torch):
+    import paper_1804_09996_amd as lc
+    rs = np.random.default_rng(11)
+    n, d, m = 256, 16, 8
+    db = rs.standard_normal((n, d)).astype(np.float32)
+    cent, _ = oracle.pq_train(db, None, d, m, np.stack([rs.permutation(n) for _ in range(m)]), 2)
+    codes = oracle.pq_encode(db, None, d, cent)
+    lv, _ = oracle.levels(1.0 - rs.random(n))
+    adj0, up_base, adj_up, entry, maxl = oracle.hnsw_build(db, None, d, cent, codes, lv, 32, 32, 64)
+    beta = np.zeros((1, 5), np.float32)
+    beta[0, 0] = 1
+    ix = oracle.Index(n=n, d=d, d_pad=d, m=m, deg0=32, deg_up=32, k_reg=4, n_beta=1, entry=entry, max_level=maxl,
+                      proj=None, centroids=cent, codes=codes, adj0=adj0, level=lv, up_base=up_base, adj_up=adj_up,
+                      beta=beta, beta_idx=np.zeros(n, np.uint8))
+    gix = lc.Index.from_index(ix)
+    q = rs.standard_normal((33, d)).astype(np.float32)
+    ids, dist, _ = gix.query(torch.from_numpy(q), ef=n, ef_max=n, S=n, K=10)
+    dd = ((q[:, None, :].astype(np.float64) - db[None]) ** 2).sum(-1)
+    gt = np.argsort(dd, axis=1, kind="stable")[:, :10]
+    ids = ids.cpu().numpy()
+    for i in range(33):
+        for r in range(10):
+            assert ids[i, r] == gt[i, r] or abs(dd[i, ids[i, r]] - dd[i, gt[i, r]]) <= 1e-5 * dd[i, gt[i, r]]
+    np.testing.assert_allclose(dist.cpu().numpy(), np.take_along_axis(dd, ids.astype(np.int64), 1), rtol=1e-5)
+
+
+def test_single_node_index(torch):
+    import paper_1804_09996_amd as lc
+    rs = np.random.default_rng(12)
+    cent = rs.standard_normal((8, 256, 2)).astype(np.float32)
+    ix = oracle.Index(n=1, d=16, d_pad=16, m=8, deg0=32, deg_up=32, k_reg=2, n_beta=1, entry=0, max_level=0,
+                      proj=None, centroids=cent, codes=rs.integers(0, 256, (1, 8)).astype(np.uint8),
+                      adj0=np.full((1, 32), -1, np.int32), level=np.zeros(1, np.int8),
+                      up_base=np.full(1, -1, np.int32), adj_up=np.zeros((0, 32), np.int32),
+                      beta=np.array([[0.9, 0.1, 0.2]], np.float32), beta_idx=np.zeros(1, np.uint8))
+    gix = lc.Index.from_index(ix)
+    q = rs.standard_normal((3, 16)).astype(np.float32)
+    ids, d, r = gix.query(torch.from_numpy(q), ef=4, ef_max=4, S=4, K=3, stats=True)
+    o = ix.search(q, 4, 4, 3)
+    assert np.array_equal(ids.cpu().numpy(), o["ids"])
+    assert np.array_equal(r.stats.cpu().numpy(), o["stats"])
+    np.testing.assert_allclose(d.cpu().numpy()[:, 0], o["d"][:, 0], rtol=1e-5)
