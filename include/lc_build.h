@@ -1,0 +1,74 @@
+/*
+ * liblc_build — host-side construction of a Link & Code index in the layout
+ * that include/lc.h binds (codes, adj0, up_base/adj_up, beta, beta_idx).
+ *
+ * Paper: Douze, Sablayrolles, Jegou, "Link and code: Fast indexing with graphs
+ * and compact regression codes", CVPR 2018 (arXiv 1804.09996).
+ *
+ * All pointers are HOST pointers owned by the caller; outputs are written in
+ * place.  Functions return 0 on success, a negative value on invalid
+ * arguments (-1) or allocation failure (-2).  `nthreads` worker threads are
+ * used; every result is independent of the thread count.  Random draws
+ * (k-means seeds, level uniforms, training subsets) are inputs.
+ */
+#ifndef LC_BUILD_H
+#define LC_BUILD_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Product quantizer (Sec. 3.3; Sec. 4.1 "Vector approximation"): per
+ * sub-space k-means with 256 centroids on the (projected) training vectors,
+ * seeded with the rows init[s][0..255], `iters` Lloyd iterations; an empty
+ * cluster is re-seeded with the point of largest error.
+ * centroids: f32 [m][256][d_pad/m]. */
+int lcb_pq_train(const float *train, int64_t n, int d, const float *proj, int d_pad, int m,
+                 const int64_t *init, int iters, int nthreads, float *centroids);
+
+/* PQ codes (nearest centroid per sub-space, lowest index on ties):
+ * codes u8 [n][code_stride]. */
+int lcb_pq_encode(const float *x, int64_t n, int d, const float *proj, int d_pad, int m,
+                  const float *centroids, int nthreads, uint8_t *codes, int code_stride);
+
+/* Node levels (Sec. 2 geometric layers, Sec. 4.1 ratio between levels):
+ * level_i = min(cap, floor(-ln(u_i) / ln(ratio))).  Returns sum_i level_i,
+ * the number of upper-level rows. */
+int64_t lcb_levels(const double *u, int64_t n, int ratio, int cap, int8_t *level);
+
+/* Nested graph over the coded vectors (Sec. 2; Sec. 4.1 "Graph-based
+ * structure"; Sec. 5.1): nodes are inserted by level (descending) then id, in
+ * batches of clamp(inserted / 16, 1, 4096) searched against the graph as it
+ * stood before the batch, with asymmetric distances from the raw vector; the
+ * links of a node are chosen by the shrinking heuristic and filled up to the
+ * degree with the nearest rejected candidates; reverse links re-shrink a full
+ * list from its owner's raw vector.  Level-0 lists are sorted by increasing
+ * distance to their owner (Sec. 4.2).  Outputs: adj0 i32 [n][deg0], up_base
+ * i32 [n], adj_up i32 [rows][deg_up], *entry, *max_level. */
+int lcb_graph_build(const float *x, int64_t n, int d, const float *proj, int d_pad, int m,
+                    const float *centroids, const uint8_t *codes, int code_stride,
+                    const int8_t *level, int deg0, int deg_up, int ef_construction, int nthreads,
+                    int32_t *adj0, int32_t *up_base, int32_t *adj_up, int32_t *entry,
+                    int32_t *max_level);
+
+/* Regression codebook (Sec. 4.3, Eq. 6-8) in float64 on the training ids:
+ * per-vector least squares initialises a k-means (km_iters), then em_iters
+ * rounds of assignment (Eq. 7) and per-cluster least squares (Eq. 8).
+ * beta: f32 [n_beta][k_reg+1]; loss_hist (optional) em_iters+1 values. */
+int lcb_beta_train(const float *x, const int64_t *ids, int64_t n_sub, int d, const float *proj,
+                   int d_pad, int m, const float *centroids, const uint8_t *codes, int code_stride,
+                   const int32_t *adj0, int deg0, int k_reg, int n_beta, const int64_t *init,
+                   int km_iters, int em_iters, int nthreads, float *beta, double *loss_hist);
+
+/* Codebook entry of every vector (Sec. 4.3, Eq. 7) with the f32 codebook:
+ * beta_idx u8 [n]. */
+int lcb_beta_assign(const float *x, int64_t n, int d, const float *proj, int d_pad, int m,
+                    const float *centroids, const uint8_t *codes, int code_stride,
+                    const int32_t *adj0, int deg0, int k_reg, int n_beta, const float *beta,
+                    int nthreads, uint8_t *beta_idx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

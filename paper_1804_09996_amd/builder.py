@@ -1,0 +1,167 @@
+"""Binding of ``liblc_build.so`` (include/lc_build.h): builds an index on the
+host from seeded inputs, in the array layout that :class:`Index` binds.
+
+The random draws the build consumes (k-means seeds, level uniforms, the
+regression training subset) come from ``datagen``; the arithmetic is all in
+the native builder.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import time
+from dataclasses import dataclass, fields
+from typing import Optional
+
+import numpy as np
+
+from . import PKG
+
+LIB_PATH = os.path.join(PKG, "liblc_build.so")
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_1804_09996_amd.build_ext`")
+        L = C.CDLL(LIB_PATH)
+        p, i, i64 = C.c_void_p, C.c_int, C.c_int64
+        L.lcb_pq_train.argtypes = [p, i64, i, p, i, i, p, i, i, p]
+        L.lcb_pq_encode.argtypes = [p, i64, i, p, i, i, p, i, p, i]
+        L.lcb_levels.argtypes = [p, i64, i, i, p]
+        L.lcb_levels.restype = i64
+        L.lcb_graph_build.argtypes = [p, i64, i, p, i, i, p, p, i, p, i, i, i, i, p, p, p, p, p]
+        L.lcb_beta_train.argtypes = [p, p, i64, i, p, i, i, p, p, i, p, i, i, i, p, i, i, i, p, p]
+        L.lcb_beta_assign.argtypes = [p, i64, i, p, i, i, p, p, i, p, i, i, i, p, i, p]
+        _lib = L
+    return _lib
+
+
+def _c(a, dt):
+    return None if a is None else np.ascontiguousarray(a, dtype=dt)
+
+
+def _p(a):
+    return None if a is None else a.ctypes.data
+
+
+def _ok(rc, what):
+    if rc != 0:
+        raise RuntimeError(f"{what} failed ({rc})")
+
+
+def threads() -> int:
+    return max(1, min(16, os.cpu_count() or 1))
+
+
+def code_stride_for(m: int) -> int:
+    s = 1
+    while s < m:
+        s *= 2
+    return s
+
+
+@dataclass
+class BuiltIndex:
+    n: int
+    d: int
+    d_pad: int
+    m: int
+    deg0: int
+    deg_up: int
+    k_reg: int
+    n_beta: int
+    entry: int
+    max_level: int
+    proj: Optional[np.ndarray]
+    centroids: np.ndarray
+    codes: np.ndarray
+    adj0: np.ndarray
+    level: np.ndarray
+    up_base: np.ndarray
+    adj_up: np.ndarray
+    beta: np.ndarray
+    beta_idx: np.ndarray
+
+    def save(self, path: str):
+        arrays = {f.name: getattr(self, f.name) for f in fields(self) if isinstance(getattr(self, f.name), np.ndarray)}
+        scalars = {f.name: getattr(self, f.name) for f in fields(self) if isinstance(getattr(self, f.name), int)}
+        np.savez(path, **arrays, **{"_" + k: np.int64(v) for k, v in scalars.items()})
+
+    @classmethod
+    def load(cls, path: str) -> "BuiltIndex":
+        z = np.load(path, allow_pickle=False)
+        kw = {}
+        for f in fields(cls):
+            if f.name in z.files:
+                kw[f.name] = z[f.name]
+            elif "_" + f.name in z.files:
+                kw[f.name] = int(z["_" + f.name])
+            else:
+                kw[f.name] = None
+        return cls(**kw)
+
+
+def build_index(w, db, train, proj, level_u, pq_init, beta_ids, beta_init, nthreads: Optional[int] = None,
+                log=None) -> BuiltIndex:
+    L = lib()
+    nt = nthreads or threads()
+    db, train, proj = _c(db, np.float32), _c(train, np.float32), _c(proj, np.float32)
+    n, d = db.shape
+    t0 = time.time()
+    cent = np.empty((w.m, 256, w.d_pad // w.m), np.float32)
+    _ok(L.lcb_pq_train(_p(train), train.shape[0], d, _p(proj), w.d_pad, w.m, _p(_c(pq_init, np.int64)), w.pq_iters,
+                       nt, _p(cent)), "lcb_pq_train")
+    cs = code_stride_for(w.m)
+    codes = np.empty((n, cs), np.uint8)
+    _ok(L.lcb_pq_encode(_p(db), n, d, _p(proj), w.d_pad, w.m, _p(cent), nt, _p(codes), cs), "lcb_pq_encode")
+    t1 = time.time()
+    level = np.empty(n, np.int8)
+    rows = int(L.lcb_levels(_p(_c(level_u, np.float64)), n, w.level_ratio, w.max_level_cap, _p(level)))
+    adj0 = np.empty((n, w.deg0), np.int32)
+    up_base = np.empty(n, np.int32)
+    adj_up = np.empty((max(rows, 1), w.deg_up), np.int32)
+    entry, maxl = C.c_int32(), C.c_int32()
+    _ok(L.lcb_graph_build(_p(db), n, d, _p(proj), w.d_pad, w.m, _p(cent), _p(codes), cs, _p(level), w.deg0,
+                          w.deg_up, w.ef_construction, nt, _p(adj0), _p(up_base), _p(adj_up), C.byref(entry),
+                          C.byref(maxl)), "lcb_graph_build")
+    adj_up = adj_up[:rows]
+    t2 = time.time()
+    beta = np.empty((w.n_beta, w.k_reg + 1), np.float32)
+    bids = _c(beta_ids, np.int64)
+    _ok(L.lcb_beta_train(_p(db), _p(bids), bids.shape[0], d, _p(proj), w.d_pad, w.m, _p(cent), _p(codes), cs,
+                         _p(adj0), w.deg0, w.k_reg, w.n_beta, _p(_c(beta_init, np.int64)), w.beta_kmeans_iters,
+                         w.em_iters, nt, _p(beta), None), "lcb_beta_train")
+    bidx = np.empty(n, np.uint8)
+    _ok(L.lcb_beta_assign(_p(db), n, d, _p(proj), w.d_pad, w.m, _p(cent), _p(codes), cs, _p(adj0), w.deg0, w.k_reg,
+                          w.n_beta, _p(beta), nt, _p(bidx)), "lcb_beta_assign")
+    t3 = time.time()
+    if log:
+        log(f"index build: pq {t1 - t0:.1f}s graph {t2 - t1:.1f}s beta {t3 - t2:.1f}s ({nt} threads)")
+    return BuiltIndex(n=n, d=d, d_pad=w.d_pad, m=w.m, deg0=w.deg0, deg_up=w.deg_up, k_reg=w.k_reg, n_beta=w.n_beta,
+                      entry=int(entry.value), max_level=int(maxl.value), proj=proj, centroids=cent, codes=codes,
+                      adj0=adj0, level=level, up_base=up_base, adj_up=adj_up, beta=beta, beta_idx=bidx)
+
+
+def build_workload(w, nthreads: Optional[int] = None, cache_dir: Optional[str] = None, log=None):
+    """(index, db, queries) for a workload, built from its seed (cached on disk
+    under ``cache_dir`` keyed by every field of the workload)."""
+    import datagen
+    db = datagen.vectors(w, "db")
+    q = datagen.vectors(w, "query")
+    path = None
+    if cache_dir:
+        os.makedirs(cache_dir, exist_ok=True)
+        path = os.path.join(cache_dir, f"{w.name}-{w.key()}.npz")
+        if os.path.exists(path):
+            return BuiltIndex.load(path), db, q
+    train = datagen.vectors(w, "train")
+    ix = build_index(w, db, train, datagen.projection(w), datagen.level_uniforms(w),
+                     datagen.pq_init_ids(w, train.shape[0]), datagen.beta_train_ids(w),
+                     datagen.beta_init_ids(w, min(w.n, w.n_beta_train)), nthreads, log)
+    if path:
+        ix.save(path + ".tmp.npz")
+        os.replace(path + ".tmp.npz", path)
+    return ix, db, q
