@@ -98,8 +98,10 @@ void lc_index_release(lc_index *ix);
  *   LUT[q][s][c] = || (P y_q)^s - C[s][c] ||^2,  s < m, c < 256.
  * q:   f32 [nq][d] queries.
  * lut: LC_LUT_F32 -> f32 [nq][m][256];
- *      LC_LUT_F16 -> f16 [nq][m][256] holding LUT / lut_scale[q], with
- *      lut_scale f32 [nq] (precision form; NULL for F32).
+ *      LC_LUT_F16 -> f16 [nq][m][256] holding LUT[q][s][c] / lut_scale[q][s]
+ *      rounded to nearest, with lut_scale f32 [nq][m] a power of two per
+ *      (query, sub-space) that maps the largest entry of the row to at most
+ *      2^15 (precision form; lut_scale is NULL for F32).
  * nq == 0 is a no-op. */
 int lc_build_lut(const lc_index *ix, const float *q, int64_t nq, int lut_dtype, void *lut,
                  float *lut_scale, void *stream);
@@ -132,6 +134,44 @@ int lc_search(const lc_index *ix, const void *lut, int lut_dtype, const float *l
               int64_t nq, const int32_t *ef, int32_t ef_max, int32_t S, int32_t *cand_ids,
               float *cand_adc, int32_t *cand_n, int32_t *stats, void *ws, size_t ws_bytes,
               void *stream);
+
+/* Launch schedule of the walk.  Every schedule returns exactly the same
+ * short-lists, distances and (E, D) counts; only speed changes.
+ *   hash_bits     log2 capacity of the per-query LDS table of the visited set
+ *                 (9..14; 0 = chosen from ef).
+ *   prefetch      1 = load the adjacency row of the predicted next candidate
+ *                 while the current one is processed (used only when the
+ *                 prediction is confirmed), 0 = off.
+ *   waves_per_cu  cap on resident query slots per compute unit (0 = as many as
+ *                 LDS allows).
+ *   queue         1 = slots take queries from an atomic counter in the
+ *                 workspace (load balance for uneven walk lengths), 0 = each
+ *                 slot strides over the batch.
+ *   visited       0 = the LDS table holds the visited ids (open addressing);
+ *                 past half full the query continues on the slot's bitset in
+ *                 the workspace.
+ *                 1 = the slot's bitset in the workspace is the visited set;
+ *                 the LDS table is a direct-mapped cache of recently visited
+ *                 ids, and a miss tests-and-sets the bit while the node's
+ *                 code is fetched speculatively (less LDS per query, so more
+ *                 queries resident). */
+typedef struct {
+  int32_t hash_bits, prefetch, waves_per_cu, queue, visited;
+} lc_schedule;
+
+/* Workspace bytes for lc_search_sched with schedule `sched` (NULL = default). */
+size_t lc_search_workspace_bytes_sched(const lc_index *ix, int64_t nq, int32_t ef_max, int32_t S,
+                                       const lc_schedule *sched);
+
+/* lc_search with an explicit schedule (NULL = the default of lc_search) and an
+ * optional processing order: order i32 [nq] is a permutation of 0..nq-1 (or
+ * NULL for 0..nq-1); slots take queries in that order (e.g. longest ef first),
+ * and every output still lands in the query's own row.  An entry outside
+ * 0..nq-1 is skipped. */
+int lc_search_sched(const lc_index *ix, const void *lut, int lut_dtype, const float *lut_scale,
+                    int64_t nq, const int32_t *ef, int32_t ef_max, int32_t S, const int32_t *order,
+                    int32_t *cand_ids, float *cand_adc, int32_t *cand_n, int32_t *stats, void *ws,
+                    size_t ws_bytes, const lc_schedule *sched, void *stream);
 
 /* Second stage (Sec. 4.1 "Refinement strategy"; Sec. 4.2 Eq. 5; Sec. 4.3
  * Eq. 7).  For each valid short-list id i:

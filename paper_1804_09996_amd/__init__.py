@@ -44,6 +44,24 @@ class IndexView(C.Structure):
                                           "beta_idx")]
 
 
+class Schedule(C.Structure):
+    """Launch schedule of the walk (lc_schedule); every schedule gives the
+    same results."""
+    _fields_ = [("hash_bits", C.c_int32), ("prefetch", C.c_int32), ("waves_per_cu", C.c_int32),
+                ("queue", C.c_int32), ("visited", C.c_int32)]
+
+    def __repr__(self):
+        return (f"Schedule(hash_bits={self.hash_bits}, prefetch={self.prefetch}, "
+                f"waves_per_cu={self.waves_per_cu}, queue={self.queue}, visited={self.visited})")
+
+    def as_dict(self):
+        return {k: int(getattr(self, k)) for k, _ in self._fields_}
+
+
+def schedule(hash_bits=0, prefetch=0, waves_per_cu=0, queue=1, visited=0) -> Schedule:
+    return Schedule(hash_bits, prefetch, waves_per_cu, queue, visited)
+
+
 def lib():
     """The loaded ``liblc.so``; raises if it has not been built."""
     global _lib
@@ -62,6 +80,9 @@ def lib():
         L.lc_search_workspace_bytes.argtypes = [p, i64, i32, i32]
         L.lc_search_workspace_bytes.restype = sz
         L.lc_search.argtypes = [p, p, C.c_int, p, i64, p, i32, i32, p, p, p, p, p, sz, p]
+        L.lc_search_workspace_bytes_sched.argtypes = [p, i64, i32, i32, C.POINTER(Schedule)]
+        L.lc_search_workspace_bytes_sched.restype = sz
+        L.lc_search_sched.argtypes = [p, p, C.c_int, p, i64, p, i32, i32, p, p, p, p, p, p, sz, C.POINTER(Schedule), p]
         L.lc_refine.argtypes = [p, p, i64, p, p, i32, i32, C.c_int, p, p, p]
         _lib = L
     return _lib
@@ -69,7 +90,7 @@ def lib():
 
 def exported_symbols():
     return ["lc_strerror", "lc_index_bind", "lc_index_release", "lc_build_lut", "lc_search_workspace_bytes",
-            "lc_search", "lc_refine"]
+            "lc_search", "lc_refine", "lc_search_workspace_bytes_sched", "lc_search_sched"]
 
 
 def _check(rc: int, where: str):
@@ -173,20 +194,22 @@ class Index:
             scale = None
         else:
             lut = torch.empty((nq, self.m, 256), dtype=torch.float16, device=self.device)
-            scale = torch.empty(nq, dtype=torch.float32, device=self.device)
+            scale = torch.empty((nq, self.m), dtype=torch.float32, device=self.device)
         _check(lib().lc_build_lut(self.handle, _ptr(q), nq, lut_dtype, _ptr(lut), _ptr(scale),
                                   _stream(torch, self.device)), "lc_build_lut")
         return lut, scale
 
-    def workspace(self, nq: int, ef_max: int, S: int):
+    def workspace(self, nq: int, ef_max: int, S: int, sched: Optional[Schedule] = None):
         torch = self.torch
-        need = lib().lc_search_workspace_bytes(self.handle, max(nq, 1), ef_max, S)
+        need = lib().lc_search_workspace_bytes_sched(self.handle, max(nq, 1), ef_max, S,
+                                                     None if sched is None else C.byref(sched))
         if self._ws is None or self._ws.numel() < need:
             self._ws = torch.zeros(max(need, 1), dtype=torch.uint8, device=self.device)
         return self._ws
 
     def search(self, lut, scale=None, ef=None, ef_max: int = 64, S: int = 64, stats: bool = True,
-               lut_dtype: Optional[int] = None) -> SearchResult:
+               lut_dtype: Optional[int] = None, sched: Optional[Schedule] = None, order=None,
+               out: Optional[SearchResult] = None) -> SearchResult:
         torch = self.torch
         nq = lut.shape[0]
         if lut_dtype is None:
@@ -196,14 +219,24 @@ class Index:
             ef_t = torch.as_tensor(ef, dtype=torch.int32).to(self.device).contiguous()
             if ef_t.dim() == 0:
                 ef_t = ef_t.expand(nq).contiguous()
-        cand_ids = torch.empty((nq, S), dtype=torch.int32, device=self.device)
-        cand_adc = torch.empty((nq, S), dtype=torch.float32, device=self.device)
-        cand_n = torch.empty(nq, dtype=torch.int32, device=self.device)
-        st = torch.empty((nq, 2), dtype=torch.int32, device=self.device) if stats else None
-        ws = self.workspace(nq, ef_max, S)
-        _check(lib().lc_search(self.handle, _ptr(lut), lut_dtype, _ptr(scale), nq, _ptr(ef_t), ef_max, S,
-                               _ptr(cand_ids), _ptr(cand_adc), _ptr(cand_n), _ptr(st), _ptr(ws), ws.numel(),
-                               _stream(torch, self.device)), "lc_search")
+        if out is not None:
+            cand_ids, cand_adc, cand_n, st = out.cand_ids, out.cand_adc, out.cand_n, out.stats
+        else:
+            cand_ids = torch.empty((nq, S), dtype=torch.int32, device=self.device)
+            cand_adc = torch.empty((nq, S), dtype=torch.float32, device=self.device)
+            cand_n = torch.empty(nq, dtype=torch.int32, device=self.device)
+            st = torch.empty((nq, 2), dtype=torch.int32, device=self.device) if stats else None
+        ws = self.workspace(nq, ef_max, S, sched)
+        if sched is None and order is None:
+            rc = lib().lc_search(self.handle, _ptr(lut), lut_dtype, _ptr(scale), nq, _ptr(ef_t), ef_max, S,
+                                 _ptr(cand_ids), _ptr(cand_adc), _ptr(cand_n), _ptr(st), _ptr(ws), ws.numel(),
+                                 _stream(torch, self.device))
+        else:
+            rc = lib().lc_search_sched(self.handle, _ptr(lut), lut_dtype, _ptr(scale), nq, _ptr(ef_t), ef_max, S,
+                                       _ptr(order), _ptr(cand_ids), _ptr(cand_adc), _ptr(cand_n), _ptr(st), _ptr(ws),
+                                       ws.numel(), None if sched is None else C.byref(sched),
+                                       _stream(torch, self.device))
+        _check(rc, "lc_search")
         return SearchResult(cand_ids, cand_adc, cand_n, st)
 
     def refine(self, q, cand_ids, cand_n, K: int, precision: int = LC_REFINE_F32):
@@ -216,9 +249,13 @@ class Index:
                                _ptr(out_ids), _ptr(out_d), _stream(torch, self.device)), "lc_refine")
         return out_ids, out_d
 
-    def query(self, q, ef=None, ef_max: int = 64, S: int = 64, K: int = 10, stats: bool = False):
-        """The whole path: tables, walk and short-list, refinement and top-K."""
-        lut, scale = self.build_lut(q)
-        r = self.search(lut, scale, ef=ef, ef_max=ef_max, S=S, stats=stats)
-        ids, d = self.refine(q, r.cand_ids, r.cand_n, K)
+    def query(self, q, ef=None, ef_max: int = 64, S: int = 64, K: int = 10, stats: bool = False,
+              sched: Optional[Schedule] = None, precision: str = "f32"):
+        """The whole path: tables, walk and short-list, refinement and top-K.
+        ``precision="f16"`` selects the fp16 table and the bf16 refinement
+        with exact fp32 re-scoring of the final candidates."""
+        lp = precision == "f16"
+        lut, scale = self.build_lut(q, LC_LUT_F16 if lp else LC_LUT_F32)
+        r = self.search(lut, scale, ef=ef, ef_max=ef_max, S=S, stats=stats, sched=sched)
+        ids, d = self.refine(q, r.cand_ids, r.cand_n, K, LC_REFINE_BF16_RESCORE if lp else LC_REFINE_F32)
         return ids, d, r

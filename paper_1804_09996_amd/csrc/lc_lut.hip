@@ -10,17 +10,24 @@
 //
 // One wavefront per (16 queries, sub-space); the write of the table (m*256
 // floats per query) dominates, so the kernel is bound by HBM writes.
+#include <hip/hip_fp16.h>
+
+#include <type_traits>
+
 #include "lc_internal.h"
 
 namespace {
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 
-template <int DSUB>
-__global__ __launch_bounds__(64) void lut_f32_kernel(const float *__restrict__ q, int64_t nq, int d,
-                                                      const float *__restrict__ proj, int m,
-                                                      const float *__restrict__ cent,
-                                                      float *__restrict__ lut) {
+// OUT = float: the table itself.  OUT = __half: the table divided by a
+// power-of-two scale per (query, sub-space) row that maps the row's largest
+// entry to at most 2^15 (scale written to `scale`).
+template <int DSUB, typename OUT>
+__global__ __launch_bounds__(64) void lut_kernel(const float *__restrict__ q, int64_t nq, int d,
+                                                  const float *__restrict__ proj, int m,
+                                                  const float *__restrict__ cent, OUT *__restrict__ lut,
+                                                  float *__restrict__ scale) {
   constexpr int KS = (DSUB + 3) / 4;  // MFMA K steps
   constexpr int DP = KS * 4;          // sub-dimension padded to the MFMA K
   __shared__ float cc[256 * DP];      // centred centroids, zero padded
@@ -84,26 +91,70 @@ __global__ __launch_bounds__(64) void lut_f32_kernel(const float *__restrict__ q
   float a[KS];
 #pragma unroll
   for (int ks = 0; ks < KS; ++ks) a[ks] = ya[col * DP + ks * 4 + kg];
-  for (int tile = 0; tile < 16; ++tile) {
-    floatx4 acc = {0.f, 0.f, 0.f, 0.f};
-    const int c = tile * 16 + col;
+  if constexpr (std::is_same<OUT, float>::value) {
+    for (int tile = 0; tile < 16; ++tile) {
+      floatx4 acc = {0.f, 0.f, 0.f, 0.f};
+      const int c = tile * 16 + col;
 #pragma unroll
-    for (int ks = 0; ks < KS; ++ks)
-      acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[ks], cc[c * DP + ks * 4 + kg], acc, 0, 0, 0);
+      for (int ks = 0; ks < KS; ++ks)
+        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[ks], cc[c * DP + ks * 4 + kg], acc, 0, 0, 0);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = kg * 4 + r;
+        const int64_t qi = q0 + i;
+        if (qi < nq) lut[(qi * m + s) * 256 + c] = lc::clamp0(ny[i] + nc[c] - 2.f * acc[r]);
+      }
+    }
+  } else {
+    float vals[16][4];
+    float mx[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int tile = 0; tile < 16; ++tile) {
+      floatx4 acc = {0.f, 0.f, 0.f, 0.f};
+      const int c = tile * 16 + col;
+#pragma unroll
+      for (int ks = 0; ks < KS; ++ks)
+        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[ks], cc[c * DP + ks * 4 + kg], acc, 0, 0, 0);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        vals[tile][r] = lc::clamp0(ny[kg * 4 + r] + nc[c] - 2.f * acc[r]);
+        mx[r] = fmaxf(mx[r], vals[tile][r]);
+      }
+    }
+    // row maxima across the 16 lanes that share a row group
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+      for (int o = 1; o < 16; o <<= 1) mx[r] = fmaxf(mx[r], __shfl_xor(mx[r], o));
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int i = kg * 4 + r;
       const int64_t qi = q0 + i;
-      if (qi < nq) lut[(qi * m + s) * 256 + c] = lc::clamp0(ny[i] + nc[c] - 2.f * acc[r]);
+      if (qi >= nq) continue;
+      int e = 0;
+      if (mx[r] > 0.f) {
+        frexpf(mx[r] * (1.f / 32768.f), &e);  // mx / 2^15 = f * 2^e, f in [0.5, 1)
+        e = e < -100 ? -100 : (e > 100 ? 100 : e);
+      }
+      const float sc = ldexpf(1.f, e);
+      const float inv = ldexpf(1.f, -e);
+      if (col == 0) scale[qi * m + s] = sc;
+#pragma unroll
+      for (int tile = 0; tile < 16; ++tile)
+        lut[(qi * m + s) * 256 + tile * 16 + col] = __float2half_rn(vals[tile][r] * inv);
     }
   }
 }
 
 template <int DSUB>
-hipError_t launch_dsub(const lc_index *ix, const float *q, int64_t nq, float *lut, hipStream_t st) {
+hipError_t launch_dsub(const lc_index *ix, const float *q, int64_t nq, int dtype, void *lut, float *scale,
+                       hipStream_t st) {
   dim3 grid(lc::ceil_div(nq, 16), ix->v.m);
-  hipLaunchKernelGGL(lut_f32_kernel<DSUB>, grid, dim3(64), 0, st, q, nq, ix->v.d, ix->v.proj, ix->v.m,
-                     ix->v.centroids, lut);
+  if (dtype == LC_LUT_F32)
+    hipLaunchKernelGGL((lut_kernel<DSUB, float>), grid, dim3(64), 0, st, q, nq, ix->v.d, ix->v.proj, ix->v.m,
+                       ix->v.centroids, static_cast<float *>(lut), scale);
+  else
+    hipLaunchKernelGGL((lut_kernel<DSUB, __half>), grid, dim3(64), 0, st, q, nq, ix->v.d, ix->v.proj, ix->v.m,
+                       ix->v.centroids, static_cast<__half *>(lut), scale);
   return hipGetLastError();
 }
 
@@ -111,19 +162,14 @@ hipError_t launch_dsub(const lc_index *ix, const float *q, int64_t nq, float *lu
 
 int lc_launch_lut(const lc_index *ix, const float *q, int64_t nq, int dtype, void *lut, float *scale,
                   hipStream_t st) {
-  (void)scale;
-  if (dtype != LC_LUT_F32) return LC_ENOTSUP;
-  if (nq > int64_t(65535) * 16 * 1024) return LC_EINVAL;
+  if (dtype != LC_LUT_F32 && dtype != LC_LUT_F16) return LC_ENOTSUP;
+  if (nq > int64_t(0x7FFFFFFF) * 16) return LC_EINVAL;
   hipError_t e;
   switch (ix->dsub) {
-    case 1: e = launch_dsub<1>(ix, q, nq, (float *)lut, st); break;
-    case 2: e = launch_dsub<2>(ix, q, nq, (float *)lut, st); break;
-    case 3: e = launch_dsub<3>(ix, q, nq, (float *)lut, st); break;
-    case 4: e = launch_dsub<4>(ix, q, nq, (float *)lut, st); break;
-    case 6: e = launch_dsub<6>(ix, q, nq, (float *)lut, st); break;
-    case 8: e = launch_dsub<8>(ix, q, nq, (float *)lut, st); break;
-    case 12: e = launch_dsub<12>(ix, q, nq, (float *)lut, st); break;
-    case 16: e = launch_dsub<16>(ix, q, nq, (float *)lut, st); break;
+#define CASE(DS) \
+  case DS: e = launch_dsub<DS>(ix, q, nq, dtype, lut, scale, st); break;
+    CASE(1) CASE(2) CASE(3) CASE(4) CASE(6) CASE(8) CASE(12) CASE(16)
+#undef CASE
     default: return LC_ENOTSUP;
   }
   return e == hipSuccess ? LC_OK : LC_EHIP;

@@ -12,6 +12,12 @@
 // in registers; the candidate's distance is the sum of the four partial sums
 // in a fixed order.  The short-list keys are sorted in LDS by a bitonic
 // network and the first K written out.
+//
+// Precision form: the centroids are staged in LDS as bfloat16 and the beta
+// weights rounded to bfloat16, products accumulated in float32; the best
+// K' = min(S, 2K) candidates of that pass are then re-scored with exactly the
+// float32 arithmetic of the plain kernel (float32 centroids read from global
+// memory) and re-sorted, so every returned distance is the plain one.
 #include "lc_internal.h"
 
 namespace {
@@ -30,15 +36,14 @@ struct RefineArgs {
   const float *beta;
   const uint8_t *beta_idx;
   const int32_t *cand_ids, *cand_n;
-  int S, K, S_pad, wpb;
+  int S, K, S_pad, K2, K2_pad, wpb;
   int32_t *out_ids;
   float *out_d;
 };
 
 template <int CS>
 struct CodeRow {
-  static constexpr int NV = CS >= 16 ? CS / 16 : 1;
-  uint32_t w[CS >= 16 ? CS / 4 : 4];
+  uint32_t w[CS >= 16 ? CS / 4 : 2];
   __device__ __forceinline__ void load(const uint8_t *p) {
     if constexpr (CS >= 16) {
 #pragma unroll
@@ -58,139 +63,190 @@ struct CodeRow {
   __device__ __forceinline__ uint32_t byte(int s) const { return (w[s >> 2] >> (8 * (s & 3))) & 0xFFu; }
 };
 
-template <int M, int DSUB, int CS>
-__global__ __launch_bounds__(1024) void refine_f32_kernel(RefineArgs a) {
+// Centroid element as float32: float32 storage, or bfloat16 (top 16 bits).
+__device__ __forceinline__ float cval(const float *C, int i) { return C[i]; }
+__device__ __forceinline__ float cval(const uint16_t *C, int i) { return __uint_as_float(uint32_t(C[i]) << 16); }
+
+// Round a float32 to the nearest bfloat16 (ties to even), returned as float32.
+__device__ __forceinline__ float round_bf16(float x) {
+  uint32_t u = __float_as_uint(x);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return __uint_as_float(u & 0xFFFF0000u);
+}
+
+// This lane part's share of || y' - x~_id ||^2 (sub-spaces s = part mod 4).
+template <int M, int DSUB, int CS, typename CT, bool BF16W>
+__device__ __forceinline__ float part_dist(const RefineArgs &a, const CT *C, const float *yv, int32_t id,
+                                           int part) {
+  constexpr int U = M / 4;
+  float acc[U * DSUB];
+#pragma unroll
+  for (int t = 0; t < U * DSUB; ++t) acc[t] = 0.f;
+  const float *bw = a.beta + size_t(a.beta_idx[id]) * (a.k_reg + 1);
+  const int32_t *links = a.adj0 + int64_t(id) * a.deg0;
+  for (int j = 0; j <= a.k_reg; ++j) {
+    const int32_t g = j == 0 ? id : links[j - 1];
+    if (g < 0 || g >= a.n) continue;  // a missing link is a zero vector
+    const float w = BF16W ? round_bf16(bw[j]) : bw[j];
+    CodeRow<CS> row;
+    row.load(a.codes + size_t(g) * CS);
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int s = part + 4 * u;
+      const int base = (s * 256 + int(row.byte(s))) * DSUB;
+#pragma unroll
+      for (int t = 0; t < DSUB; ++t) acc[u * DSUB + t] += w * cval(C, base + t);
+    }
+  }
+  float e = 0.f;
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int s = part + 4 * u;
+#pragma unroll
+    for (int t = 0; t < DSUB; ++t) {
+      const float df = yv[s * DSUB + t] - acc[u * DSUB + t];
+      e += df * df;
+    }
+  }
+  return e;
+}
+
+// (p0 + p1) + (p2 + p3) over the four lanes of a candidate group.
+__device__ __forceinline__ float group_sum(float e) {
+  e += __shfl_xor(e, 1);
+  e += __shfl_xor(e, 2);
+  return e;
+}
+
+// Ascending bitonic sort of n (a power of two) keys in LDS by one wavefront.
+__device__ __forceinline__ void wave_sort(uint64_t *keys, int n, int lane) {
+  for (int k = 2; k <= n; k <<= 1) {
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      for (int i = lane; i < n; i += 64) {
+        const int ixj = i ^ j;
+        if (ixj > i) {
+          const uint64_t x = keys[i], z = keys[ixj];
+          const bool asc = (i & k) == 0;
+          if ((x > z) == asc) {
+            keys[i] = z;
+            keys[ixj] = x;
+          }
+        }
+      }
+      wave_sync();
+    }
+  }
+}
+
+__device__ __forceinline__ void project_query(const RefineArgs &a, int64_t q, float *yv, int lane) {
+  const float *y = a.q + q * a.d;
+  for (int r = lane; r < a.d_pad; r += 64) {
+    float v;
+    if (a.proj) {
+      const float *pr = a.proj + size_t(r) * a.d;
+      v = 0.f;
+      for (int u = 0; u < a.d; ++u) v += pr[u] * y[u];
+    } else {
+      v = y[r];
+    }
+    yv[r] = v;
+  }
+}
+
+__device__ __forceinline__ int32_t candidate(const RefineArgs &a, int64_t q, int c, int cn) {
+  int32_t id = -1;
+  if (c < a.S && c < cn) id = a.cand_ids[q * a.S + c];
+  if (id >= a.n || (id >= 0 && a.beta_idx[id] >= a.n_beta)) id = -1;  // malformed input: no candidate
+  return id;
+}
+
+__device__ __forceinline__ void write_topk(const RefineArgs &a, int64_t q, const uint64_t *keys, int lane) {
+  for (int r = lane; r < a.K; r += 64) {
+    const uint64_t v = keys[r];
+    a.out_ids[q * a.K + r] = v == kKeyMax ? -1 : key_id(v);
+    a.out_d[q * a.K + r] = v == kKeyMax ? __builtin_inff() : key_dist(v);
+  }
+}
+
+// CT = float: plain float32 refinement.  CT = uint16_t: bfloat16 first pass
+// plus exact float32 re-score of the best K2 candidates.
+template <int M, int DSUB, int CS, typename CT>
+__global__ __launch_bounds__(1024) void refine_kernel(RefineArgs a) {
   constexpr int DP = M * DSUB;
-  constexpr int U = M / 4;  // sub-spaces per lane part
+  constexpr bool kBF16 = sizeof(CT) == 2;
   extern __shared__ __align__(16) unsigned char smem[];
-  float *C = reinterpret_cast<float *>(smem);  // [M][256][DSUB]
+  CT *C = reinterpret_cast<CT *>(smem);  // [M][256][DSUB]
+  constexpr int kCentBytes = (M * 256 * DSUB * int(sizeof(CT)) + 15) / 16 * 16;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  unsigned char *wbase = smem + size_t(M) * 256 * DSUB * 4 + size_t(wave) * (DP * 4 + a.S_pad * 8);
+  unsigned char *wbase = smem + kCentBytes + size_t(wave) * (DP * 4 + a.S_pad * 8);
   float *yv = reinterpret_cast<float *>(wbase);
   uint64_t *keys = reinterpret_cast<uint64_t *>(wbase + DP * 4);
 
-  for (int i = threadIdx.x; i < M * 256 * DSUB / 4; i += blockDim.x)
-    reinterpret_cast<float4 *>(C)[i] = reinterpret_cast<const float4 *>(a.cent)[i];
+  if constexpr (kBF16) {
+    for (int i = threadIdx.x; i < M * 256 * DSUB; i += blockDim.x)
+      C[i] = uint16_t(__float_as_uint(round_bf16(a.cent[i])) >> 16);
+  } else {
+    for (int i = threadIdx.x; i < M * 256 * DSUB / 4; i += blockDim.x)
+      reinterpret_cast<float4 *>(C)[i] = reinterpret_cast<const float4 *>(a.cent)[i];
+  }
   __syncthreads();
 
   const int part = lane & 3, grp = lane >> 2;
   for (int64_t q = int64_t(blockIdx.x) * a.wpb + wave; q < a.nq; q += int64_t(gridDim.x) * a.wpb) {
-    const float *y = a.q + q * a.d;
-    for (int r = lane; r < DP; r += 64) {
-      float v;
-      if (a.proj) {
-        const float *pr = a.proj + size_t(r) * a.d;
-        v = 0.f;
-        for (int u = 0; u < a.d; ++u) v += pr[u] * y[u];
-      } else {
-        v = y[r];
-      }
-      yv[r] = v;
-    }
+    project_query(a, q, yv, lane);
     wave_sync();
     const int cn = a.cand_n[q];
     for (int c0 = 0; c0 < a.S_pad; c0 += 16) {
       const int c = c0 + grp;
-      int32_t id = -1;
-      if (c < a.S && c < cn) id = a.cand_ids[q * a.S + c];
-      if (id >= a.n || (id >= 0 && a.beta_idx[id] >= a.n_beta)) id = -1;  // malformed input: no candidate
-      float acc[U * DSUB];
-#pragma unroll
-      for (int t = 0; t < U * DSUB; ++t) acc[t] = 0.f;
-      if (id >= 0) {
-        const float *bw = a.beta + size_t(a.beta_idx[id]) * (a.k_reg + 1);
-        const int32_t *links = a.adj0 + int64_t(id) * a.deg0;
-        for (int j = 0; j <= a.k_reg; ++j) {
-          const int32_t g = j == 0 ? id : links[j - 1];
-          if (g < 0 || g >= a.n) continue;  // a missing link is a zero vector
-          const float w = bw[j];
-          CodeRow<CS> row;
-          row.load(a.codes + size_t(g) * CS);
-#pragma unroll
-          for (int u = 0; u < U; ++u) {
-            const int s = part + 4 * u;
-            const float *cr = C + (s * 256 + int(row.byte(s))) * DSUB;
-#pragma unroll
-            for (int t = 0; t < DSUB; ++t) acc[u * DSUB + t] += w * cr[t];
-          }
-        }
-      }
+      const int32_t id = candidate(a, q, c, cn);
       float e = 0.f;
-#pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const int s = part + 4 * u;
-#pragma unroll
-        for (int t = 0; t < DSUB; ++t) {
-          const float df = yv[s * DSUB + t] - acc[u * DSUB + t];
-          e += df * df;
-        }
-      }
-      // (p0 + p1) + (p2 + p3)
-      e += __shfl_xor(e, 1);
-      e += __shfl_xor(e, 2);
-      if (part == 0 && c < a.S_pad) keys[c] = id >= 0 ? make_key(e, id) : kKeyMax;
+      if (id >= 0) e = part_dist<M, DSUB, CS, CT, kBF16>(a, C, yv, id, part);
+      e = group_sum(e);
+      if (part == 0) keys[c] = id >= 0 ? make_key(e, id) : kKeyMax;
     }
     wave_sync();
-    // bitonic sort of S_pad keys, ascending
-    for (int k = 2; k <= a.S_pad; k <<= 1) {
-      for (int j = k >> 1; j > 0; j >>= 1) {
-        for (int i = lane; i < a.S_pad; i += 64) {
-          const int ixj = i ^ j;
-          if (ixj > i) {
-            const uint64_t x = keys[i], z = keys[ixj];
-            const bool asc = (i & k) == 0;
-            if ((x > z) == asc) {
-              keys[i] = z;
-              keys[ixj] = x;
-            }
-          }
-        }
+    wave_sort(keys, a.S_pad, lane);
+    if constexpr (kBF16) {
+      // exact float32 re-score of the best K2, then re-sort those
+      for (int c0 = 0; c0 < a.K2_pad; c0 += 16) {
+        const int c = c0 + grp;
+        const uint64_t v = c < a.K2 ? keys[c] : kKeyMax;
+        const int32_t id = v == kKeyMax ? -1 : key_id(v);
+        float e = 0.f;
+        if (id >= 0) e = part_dist<M, DSUB, CS, float, false>(a, a.cent, yv, id, part);
+        e = group_sum(e);
+        wave_sync();
+        if (part == 0) keys[c] = id >= 0 ? make_key(e, id) : kKeyMax;
         wave_sync();
       }
+      wave_sort(keys, a.K2_pad, lane);
     }
-    for (int r = lane; r < a.K; r += 64) {
-      const uint64_t v = keys[r];
-      a.out_ids[q * a.K + r] = v == kKeyMax ? -1 : key_id(v);
-      a.out_d[q * a.K + r] = v == kKeyMax ? __builtin_inff() : key_dist(v);
-    }
+    write_topk(a, q, keys, lane);
     wave_sync();
   }
 }
 
-
-// Any (m, dsub) without a specialised kernel: a lane part walks its
-// sub-spaces one at a time and re-reads the code byte of each neighbour.
+// Any (m, dsub) without a specialised kernel (float32 only): a lane part walks
+// its sub-spaces one at a time and re-reads the code byte of each neighbour.
 __global__ __launch_bounds__(1024) void refine_f32_generic(RefineArgs a, int m, int dsub) {
   const int DP = m * dsub;
   extern __shared__ __align__(16) unsigned char smem[];
   float *C = reinterpret_cast<float *>(smem);
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  unsigned char *wbase = smem + size_t(m) * 256 * dsub * 4 + size_t(wave) * (DP * 4 + a.S_pad * 8);
+  unsigned char *wbase =
+      smem + (size_t(m) * 256 * dsub * 4 + 15) / 16 * 16 + size_t(wave) * (DP * 4 + a.S_pad * 8);
   float *yv = reinterpret_cast<float *>(wbase);
   uint64_t *keys = reinterpret_cast<uint64_t *>(wbase + DP * 4);
   for (int i = threadIdx.x; i < m * 256 * dsub; i += blockDim.x) C[i] = a.cent[i];
   __syncthreads();
   const int part = lane & 3, grp = lane >> 2;
   for (int64_t q = int64_t(blockIdx.x) * a.wpb + wave; q < a.nq; q += int64_t(gridDim.x) * a.wpb) {
-    const float *y = a.q + q * a.d;
-    for (int r = lane; r < DP; r += 64) {
-      float v;
-      if (a.proj) {
-        const float *pr = a.proj + size_t(r) * a.d;
-        v = 0.f;
-        for (int u = 0; u < a.d; ++u) v += pr[u] * y[u];
-      } else {
-        v = y[r];
-      }
-      yv[r] = v;
-    }
+    project_query(a, q, yv, lane);
     wave_sync();
     const int cn = a.cand_n[q];
     for (int c0 = 0; c0 < a.S_pad; c0 += 16) {
       const int c = c0 + grp;
-      int32_t id = -1;
-      if (c < a.S && c < cn) id = a.cand_ids[q * a.S + c];
-      if (id >= a.n || (id >= 0 && a.beta_idx[id] >= a.n_beta)) id = -1;
+      const int32_t id = candidate(a, q, c, cn);
       float e = 0.f;
       if (id >= 0) {
         const float *bw = a.beta + size_t(a.beta_idx[id]) * (a.k_reg + 1);
@@ -211,32 +267,12 @@ __global__ __launch_bounds__(1024) void refine_f32_generic(RefineArgs a, int m, 
           }
         }
       }
-      e += __shfl_xor(e, 1);
-      e += __shfl_xor(e, 2);
-      if (part == 0 && c < a.S_pad) keys[c] = id >= 0 ? make_key(e, id) : kKeyMax;
+      e = group_sum(e);
+      if (part == 0) keys[c] = id >= 0 ? make_key(e, id) : kKeyMax;
     }
     wave_sync();
-    for (int k = 2; k <= a.S_pad; k <<= 1) {
-      for (int j = k >> 1; j > 0; j >>= 1) {
-        for (int i = lane; i < a.S_pad; i += 64) {
-          const int ixj = i ^ j;
-          if (ixj > i) {
-            const uint64_t x = keys[i], z = keys[ixj];
-            const bool asc = (i & k) == 0;
-            if ((x > z) == asc) {
-              keys[i] = z;
-              keys[ixj] = x;
-            }
-          }
-        }
-        wave_sync();
-      }
-    }
-    for (int r = lane; r < a.K; r += 64) {
-      const uint64_t v = keys[r];
-      a.out_ids[q * a.K + r] = v == kKeyMax ? -1 : key_id(v);
-      a.out_d[q * a.K + r] = v == kKeyMax ? __builtin_inff() : key_dist(v);
-    }
+    wave_sort(keys, a.S_pad, lane);
+    write_topk(a, q, keys, lane);
     wave_sync();
   }
 }
@@ -270,15 +306,17 @@ RefineArgs make_args(const lc_index *ix, const float *q, int64_t nq, const int32
   a.S = S;
   a.K = K;
   a.S_pad = next_pow2(S < 16 ? 16 : S);
+  a.K2 = 2 * K < S ? 2 * K : S;
+  a.K2_pad = next_pow2(a.K2 < 16 ? 16 : a.K2);
   a.out_ids = out_ids;
   a.out_d = out_d;
   a.wpb = 0;
   return a;
 }
 
-// Waves per block and LDS bytes for the centroids plus per-wave buffers.
-bool plan_blocks(const lc_index *ix, RefineArgs &a, int *lds, int64_t *blocks) {
-  const int cent_bytes = ix->v.m * 256 * ix->dsub * 4;
+// Waves per block and LDS bytes for the staged centroids plus per-wave buffers.
+bool plan_blocks(const lc_index *ix, RefineArgs &a, int cent_elem_bytes, int *lds, int64_t *blocks) {
+  const int cent_bytes = (ix->v.m * 256 * ix->dsub * cent_elem_bytes + 15) / 16 * 16;
   const int per_wave = ix->v.d_pad * 4 + a.S_pad * 8;
   int wpb = (ix->lds_per_cu - cent_bytes) / per_wave;
   if (wpb > 16) wpb = 16;
@@ -291,22 +329,22 @@ bool plan_blocks(const lc_index *ix, RefineArgs &a, int *lds, int64_t *blocks) {
   return true;
 }
 
-template <int M, int DSUB, int CS>
-int launch_f32(const lc_index *ix, RefineArgs a, hipStream_t st) {
+template <int M, int DSUB, int CS, typename CT>
+int launch_spec(const lc_index *ix, RefineArgs a, hipStream_t st) {
   int lds;
   int64_t blocks;
-  if (!plan_blocks(ix, a, &lds, &blocks)) return LC_ENOTSUP;
-  if (hipFuncSetAttribute(reinterpret_cast<const void *>(&refine_f32_kernel<M, DSUB, CS>),
+  if (!plan_blocks(ix, a, int(sizeof(CT)), &lds, &blocks)) return LC_ENOTSUP;
+  if (hipFuncSetAttribute(reinterpret_cast<const void *>(&refine_kernel<M, DSUB, CS, CT>),
                           hipFuncAttributeMaxDynamicSharedMemorySize, lds) != hipSuccess)
     return LC_EHIP;
-  hipLaunchKernelGGL((refine_f32_kernel<M, DSUB, CS>), dim3(int(blocks)), dim3(64 * a.wpb), lds, st, a);
+  hipLaunchKernelGGL((refine_kernel<M, DSUB, CS, CT>), dim3(int(blocks)), dim3(64 * a.wpb), lds, st, a);
   return hipGetLastError() == hipSuccess ? LC_OK : LC_EHIP;
 }
 
 int launch_generic(const lc_index *ix, RefineArgs a, hipStream_t st) {
   int lds;
   int64_t blocks;
-  if (ix->dsub > 16 || !plan_blocks(ix, a, &lds, &blocks)) return LC_ENOTSUP;
+  if (ix->dsub > 16 || !plan_blocks(ix, a, 4, &lds, &blocks)) return LC_ENOTSUP;
   if (hipFuncSetAttribute(reinterpret_cast<const void *>(&refine_f32_generic),
                           hipFuncAttributeMaxDynamicSharedMemorySize, lds) != hipSuccess)
     return LC_EHIP;
@@ -316,20 +354,24 @@ int launch_generic(const lc_index *ix, RefineArgs a, hipStream_t st) {
 
 }  // namespace
 
-// Shapes with kernels: (m, dsub) of the supported workloads; code stride is
-// the next power of two >= m.
+// Specialised shapes (m, dsub, code stride); other shapes take the generic
+// float32 kernel, and the precision form needs a specialised shape.
 int lc_launch_refine(const lc_index *ix, const float *q, int64_t nq, const int32_t *cand_ids,
                      const int32_t *cand_n, int32_t S, int32_t K, int precision, int32_t *out_ids,
                      float *out_d, hipStream_t st) {
-  if (precision != LC_REFINE_F32) return LC_ENOTSUP;
   const RefineArgs a = make_args(ix, q, nq, cand_ids, cand_n, S, K, out_ids, out_d);
   const int m = ix->v.m, ds = ix->dsub;
-#define SHAPE(MM, DS, CSS) \
-  if (m == MM && ds == DS) return launch_f32<MM, DS, CSS>(ix, a, st);
+  const bool bf = precision == LC_REFINE_BF16_RESCORE;
+#define SHAPE(MM, DS, CSS)                                                                              \
+  if (m == MM && ds == DS)                                                                              \
+    return bf ? launch_spec<MM, DS, CSS, uint16_t>(ix, a, st) : launch_spec<MM, DS, CSS, float>(ix, a, st);
+  SHAPE(8, 2, 8)
+  SHAPE(8, 4, 8)
   SHAPE(8, 12, 8)
   SHAPE(16, 6, 16)
   SHAPE(32, 4, 32)
   SHAPE(56, 2, 64)
 #undef SHAPE
+  if (bf) return LC_ENOTSUP;
   return launch_generic(ix, a, st);
 }

@@ -181,3 +181,151 @@ def test_single_node_index(torch):
     assert np.array_equal(ids.cpu().numpy(), o["ids"])
     assert np.array_equal(r.stats.cpu().numpy(), o["stats"])
     np.testing.assert_allclose(d.cpu().numpy()[:, 0], o["d"][:, 0], rtol=1e-5)
+
+
+SCHEDULES = [dict(hash_bits=9, prefetch=0, waves_per_cu=0, queue=0),   # small table: bitset overflow path
+             dict(hash_bits=9, prefetch=1, waves_per_cu=1, queue=1),
+             dict(hash_bits=14, prefetch=1, waves_per_cu=0, queue=1),
+             dict(hash_bits=0, prefetch=0, waves_per_cu=2, queue=1),
+             dict(hash_bits=11, prefetch=1, waves_per_cu=0, queue=0),
+             dict(hash_bits=9, prefetch=0, waves_per_cu=0, queue=1, visited=1),   # bitset + LDS cache
+             dict(hash_bits=10, prefetch=1, waves_per_cu=0, queue=0, visited=1)]
+
+
+def test_every_schedule_gives_identical_results(c1, c1_oracle, torch):
+    import paper_1804_09996_amd as lc
+    w, ix, gix, db, q = c1
+    lut, _ = gix.build_lut(torch.from_numpy(q))
+    ref = None
+    for sd in SCHEDULES:
+        sc = lc.schedule(**sd)
+        for _ in range(2):  # twice: the workspace must come back clean
+            r = gix.search(lut, ef=w.ef, ef_max=w.ef, S=w.shortlist, sched=sc)
+            got = (r.cand_ids.cpu().numpy(), r.cand_adc.cpu().numpy().view(np.uint32), r.cand_n.cpu().numpy(),
+                   r.stats.cpu().numpy())
+            if ref is None:
+                ref = got
+                assert np.array_equal(got[0], c1_oracle["cand_ids"]) and np.array_equal(got[3], c1_oracle["stats"])
+            for a, b in zip(got, ref):
+                assert np.array_equal(a, b), sd
+            ws = gix.workspace(q.shape[0], w.ef, w.shortlist, sc)
+            assert int(ws.count_nonzero().item()) == 0, f"workspace not left zeroed: {sd}"
+
+
+def test_overflow_path_with_large_pool(torch):
+    # ef = N on a graph of 2400 nodes with a 512-slot table: most of the walk
+    # runs on the workspace bitset
+    import paper_1804_09996_amd as lc
+    w = datagen.small(name="ovf", n=2400, nq=12, d=32, m=8, n_train=1024, n_beta=16, n_beta_train=2400, k_reg=8)
+    ix, db, q = oracle.build_workload(w, nthreads=4)
+    gix = lc.Index.from_index(ix)
+    o = ix.search(q, 2400, 64, 10)
+    for sd in (dict(hash_bits=9, prefetch=1, waves_per_cu=0, queue=1),
+               dict(hash_bits=14, prefetch=0, waves_per_cu=0, queue=0),
+               dict(hash_bits=9, prefetch=0, waves_per_cu=0, queue=1, visited=1)):
+        sc = lc.schedule(**sd)
+        ids, d, r = gix.query(torch.from_numpy(q), ef=2400, ef_max=2400, S=64, K=10, stats=True, sched=sc)
+        assert np.array_equal(r.cand_ids.cpu().numpy(), o["cand_ids"])
+        assert np.array_equal(r.stats.cpu().numpy(), o["stats"])
+        assert np.all(r.stats.cpu().numpy()[:, 1] == 2399)
+        assert int(gix.workspace(12, 2400, 64, sc).count_nonzero().item()) == 0
+
+
+# ---------------------------------------------------------------------------
+# precision form: fp16 tables, bf16 refinement, exact fp32 re-score
+# ---------------------------------------------------------------------------
+def test_fp16_lut_is_the_scaled_table(c1, torch):
+    import paper_1804_09996_amd as lc
+    w, ix, gix, db, q = c1
+    lut, sc = gix.build_lut(torch.from_numpy(q), lc.LC_LUT_F16)
+    h = lut.cpu().numpy().astype(np.float64)
+    sc = sc.cpu().numpy().astype(np.float64)
+    ref = np.stack([ix.lut(y) for y in q])
+    mant, _ = np.frexp(sc)
+    assert np.all(mant == 0.5), "scales are powers of two"
+    assert np.all(h.max(-1) <= 32768.0)
+    got = h * sc[:, :, None]
+    # fp16 rounding of LUT/scale (half an ulp, at most 2^-11 relative) plus the fp32 table bound
+    bound = 2.0 ** -11 * np.abs(ref) + 2.0 ** -24 * sc[:, :, None] + _lut_bound(ix, q)
+    assert np.all(np.abs(got - ref) <= bound)
+
+
+def test_precision_refine_rescores_exactly(c1, torch):
+    import paper_1804_09996_amd as lc
+    w, ix, gix, db, q = c1
+    qt = torch.from_numpy(q)
+    lut, _ = gix.build_lut(qt)
+    r = gix.search(lut, ef=w.ef, ef_max=w.ef, S=w.shortlist)
+    ids32, d32 = gix.refine(qt, r.cand_ids, r.cand_n, w.topk, lc.LC_REFINE_F32)
+    ids16, d16 = gix.refine(qt, r.cand_ids, r.cand_n, w.topk, lc.LC_REFINE_BF16_RESCORE)
+    ids32, d32, ids16, d16 = (t.cpu().numpy() for t in (ids32, d32, ids16, d16))
+    same = 0
+    for i in range(w.nq):
+        plain = {int(a): float(b) for a, b in zip(ids32[i], d32[i]) if a >= 0}
+        for a, b in zip(ids16[i], d16[i]):
+            if a in plain:
+                assert np.float32(b).view(np.uint32) == np.float32(plain[a]).view(np.uint32)
+        same += np.array_equal(ids16[i], ids32[i])
+        keys = list(zip(d16[i].tolist(), ids16[i].tolist()))
+        assert keys == sorted(keys)
+    print(f"bf16+rescore top-{w.topk} identical to fp32 on {same}/{w.nq} queries")
+    assert same >= 0.95 * w.nq
+
+
+def test_precision_path_recall_close_to_plain(c1, torch):
+    w, ix, gix, db, q = c1
+    qt = torch.from_numpy(q)
+    gt = np.argmin(((q[:, None, :].astype(np.float64) - db[None].astype(np.float64)) ** 2).sum(-1), 1)
+    i32, _, _ = gix.query(qt, ef=w.ef, ef_max=w.ef, S=w.shortlist, K=w.topk)
+    i16, d16, _ = gix.query(qt, ef=w.ef, ef_max=w.ef, S=w.shortlist, K=w.topk, precision="f16")
+    r32 = parity.recall_at(i32.cpu().numpy(), gt, 10)
+    r16 = parity.recall_at(i16.cpu().numpy(), gt, 10)
+    print(f"R@10 fp32 {r32:.3f} fp16/bf16 {r16:.3f}")
+    assert r16 >= r32 - 0.03
+    err = parity.distance_errors(ix, q, i16.cpu().numpy(), d16.cpu().numpy())
+    assert np.nanmax(err) <= 1e-5  # every returned distance is an exact fp32 re-score
+
+
+# ---------------------------------------------------------------------------
+# batched form: per-query ef, longest-first order, graph replay
+# ---------------------------------------------------------------------------
+def test_processing_order_does_not_change_results(c1, torch):
+    w, ix, gix, db, q = c1
+    ef = np.random.default_rng(21).integers(8, 65, w.nq).astype(np.int32)
+    lut, _ = gix.build_lut(torch.from_numpy(q))
+    a = gix.search(lut, ef=torch.from_numpy(ef), ef_max=64, S=16)
+    perm = np.argsort(-ef, kind="stable").astype(np.int32)
+    b = gix.search(lut, ef=torch.from_numpy(ef), ef_max=64, S=16, order=torch.from_numpy(perm).cuda())
+    for x, y in ((a.cand_ids, b.cand_ids), (a.cand_n, b.cand_n), (a.stats, b.stats)):
+        assert torch.equal(x, y)
+    o = ix.search(q, ef, 16, 10)
+    assert np.array_equal(b.cand_ids.cpu().numpy(), o["cand_ids"])
+    assert np.array_equal(b.stats.cpu().numpy(), o["stats"])
+
+
+@pytest.mark.parametrize("precision", ["f32", "f16"])
+def test_graph_replays_match_eager(c1, torch, precision):
+    from paper_1804_09996_amd.batched import BatchedSearcher
+    w, ix, gix, db, q = c1
+    ef = np.random.default_rng(22).integers(8, 65, w.nq).astype(np.int32)
+    bs = BatchedSearcher(gix, w.nq, ef_max=64, S=32, K=10, precision=precision)
+    bs.set_inputs(q, ef)
+    eager_ids, eager_d = (t.clone() for t in bs.run())
+    bs.capture()
+    for rep in range(4):
+        # other eager work between replays, on the same device
+        gix.query(torch.from_numpy(q[:7]), ef=16, ef_max=16, S=16, K=5)
+        torch.cuda.synchronize()
+        ids, d = bs.run()
+        torch.cuda.synchronize()
+        assert torch.equal(ids, eager_ids), rep
+        assert torch.equal(d.view(torch.int32), eager_d.view(torch.int32)), rep
+        ws = gix.workspace(w.nq, 64, 32, bs.sched)
+        assert int(ws.count_nonzero().item()) == 0
+    # a new batch through the same graph
+    q2 = np.ascontiguousarray(q[::-1])
+    bs.set_inputs(q2, ef[::-1].copy())
+    ids2, d2 = bs.run()
+    ref_ids, ref_d, _ = gix.query(torch.from_numpy(q2), ef=torch.from_numpy(ef[::-1].copy()), ef_max=64, S=32, K=10,
+                                  precision=precision)
+    assert torch.equal(ids2, ref_ids)

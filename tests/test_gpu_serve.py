@@ -1,0 +1,31 @@
+"""Serving loop on the GPU: every request's result is the same alone and in
+the mix (bitwise), in both precision forms."""
+import numpy as np
+import pytest
+
+from paper_1804_09996_amd import serve
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("precision", ["f16", "f32"])
+def test_results_same_alone_and_in_the_mix(c1_build, precision):
+    import torch
+
+    import paper_1804_09996_amd as lc
+    w, ix, db, q = c1_build
+    gix = lc.Index.from_index(ix)
+    S, K, ef_max = 32, 10, 64
+    reqs = serve.poisson_requests(w.d, q, rate_rps=4000.0, n_requests=40, seed=5, efs=(16, 32, 64), max_batch=48)
+    eng = serve.GpuEngine(gix, n_slots=3, slot_queries=128, ef_max=ef_max, S=S, K=K, precision=precision)
+    sch = serve.Scheduler(3, 128, mem_budget=200 * serve.query_bytes(w.m, S, K, w.d), bytes_per_query=
+                          serve.query_bytes(w.m, S, K, w.d))
+    stats = serve.serve(eng, sch, reqs)
+    torch.cuda.synchronize()
+    assert stats["requests"] == 40
+    assert len({r.slot for r in reqs}) > 1
+    for r in reqs:
+        ids, d, _ = gix.query(torch.from_numpy(r.queries), ef=r.ef, ef_max=ef_max, S=S, K=K, precision=precision)
+        assert np.array_equal(r.ids, ids.cpu().numpy()), r.rid
+        assert np.array_equal(r.dist.view(np.uint32), d.cpu().numpy().view(np.uint32)), r.rid
+    print(f"{precision}: {stats}")
