@@ -384,11 +384,14 @@ __global__ __launch_bounds__(64) void walk_kernel(WalkArgs a) {
         }
       } else {
         __threadfence();  // the recorded ids are visible to every lane
+        const int nl = vcount < a.list_cap ? vcount : a.list_cap;
         if (vcount > a.list_cap) {
           for (int64_t i = lane; i < a.words; i += 64) bits[i] = 0u;
         } else {
-          for (int i = lane; i < vcount; i += 64) bits[uint32_t(vlist[i]) >> 5] = 0u;
+          for (int i = lane; i < nl; i += 64) bits[uint32_t(vlist[i]) >> 5] = 0u;
         }
+        __threadfence();
+        for (int i = lane; i < nl; i += 64) vlist[i] = 0;  // the workspace is left zero-filled
         __threadfence();
       }
       wave_sync();
