@@ -138,7 +138,8 @@ int lc_search(const lc_index *ix, const void *lut, int lut_dtype, const float *l
 /* Launch schedule of the walk.  Every schedule returns exactly the same
  * short-lists, distances and (E, D) counts; only speed changes.
  *   hash_bits     log2 capacity of the per-query LDS table of the visited set
- *                 (9..14; 0 = chosen from ef).
+ *                 (9..14; 0 = automatic: 9 for visited mode 1, else chosen
+ *                 from ef).
  *   prefetch      1 = load the adjacency row of the predicted next candidate
  *                 while the current one is processed (used only when the
  *                 prediction is confirmed), 0 = off.
@@ -154,7 +155,8 @@ int lc_search(const lc_index *ix, const void *lut, int lut_dtype, const float *l
  *                 the LDS table is a direct-mapped cache of recently visited
  *                 ids, and a miss tests-and-sets the bit while the node's
  *                 code is fetched speculatively (less LDS per query, so more
- *                 queries resident). */
+ *                 queries resident).
+ * The default schedule (sched = NULL, and lc_search) is {0, 0, 0, 1, 1}. */
 typedef struct {
   int32_t hash_bits, prefetch, waves_per_cu, queue, visited;
 } lc_schedule;

@@ -58,7 +58,7 @@ class Schedule(C.Structure):
         return {k: int(getattr(self, k)) for k, _ in self._fields_}
 
 
-def schedule(hash_bits=0, prefetch=0, waves_per_cu=0, queue=1, visited=0) -> Schedule:
+def schedule(hash_bits=0, prefetch=0, waves_per_cu=0, queue=1, visited=1) -> Schedule:
     return Schedule(hash_bits, prefetch, waves_per_cu, queue, visited)
 
 

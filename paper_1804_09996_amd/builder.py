@@ -111,6 +111,8 @@ def build_index(w, db, train, proj, level_u, pq_init, beta_ids, beta_init, nthre
     db, train, proj = _c(db, np.float32), _c(train, np.float32), _c(proj, np.float32)
     n, d = db.shape
     t0 = time.time()
+    if log:
+        log(f"index build: {n} vectors, m={w.m}, {nt} threads")
     cent = np.empty((w.m, 256, w.d_pad // w.m), np.float32)
     _ok(L.lcb_pq_train(_p(train), train.shape[0], d, _p(proj), w.d_pad, w.m, _p(_c(pq_init, np.int64)), w.pq_iters,
                        nt, _p(cent)), "lcb_pq_train")
@@ -118,6 +120,8 @@ def build_index(w, db, train, proj, level_u, pq_init, beta_ids, beta_init, nthre
     codes = np.empty((n, cs), np.uint8)
     _ok(L.lcb_pq_encode(_p(db), n, d, _p(proj), w.d_pad, w.m, _p(cent), nt, _p(codes), cs), "lcb_pq_encode")
     t1 = time.time()
+    if log:
+        log(f"index build: product quantizer done ({t1 - t0:.1f}s)")
     level = np.empty(n, np.int8)
     rows = int(L.lcb_levels(_p(_c(level_u, np.float64)), n, w.level_ratio, w.max_level_cap, _p(level)))
     adj0 = np.empty((n, w.deg0), np.int32)
@@ -129,6 +133,8 @@ def build_index(w, db, train, proj, level_u, pq_init, beta_ids, beta_init, nthre
                           C.byref(maxl)), "lcb_graph_build")
     adj_up = adj_up[:rows]
     t2 = time.time()
+    if log:
+        log(f"index build: graph done ({t2 - t1:.1f}s)")
     beta = np.empty((w.n_beta, w.k_reg + 1), np.float32)
     bids = _c(beta_ids, np.int64)
     _ok(L.lcb_beta_train(_p(db), _p(bids), bids.shape[0], d, _p(proj), w.d_pad, w.m, _p(cent), _p(codes), cs,

@@ -7,6 +7,9 @@
 
 #include <algorithm>
 #include <atomic>
+#include <chrono>
+#include <cstdio>
+#include <cstdlib>
 #include <cfloat>
 #include <cmath>
 #include <cstring>
@@ -16,6 +19,25 @@
 #include <vector>
 
 namespace {
+
+// Progress lines on stderr every ~15 s when LCB_PROGRESS is set (long builds).
+struct Progress {
+  const char *what;
+  bool on;
+  std::chrono::steady_clock::time_point last, start;
+  explicit Progress(const char *w) : what(w), on(std::getenv("LCB_PROGRESS") != nullptr) {
+    last = start = std::chrono::steady_clock::now();
+  }
+  void tick(int64_t done, int64_t total) {
+    if (!on) return;
+    auto now = std::chrono::steady_clock::now();
+    if (std::chrono::duration<double>(now - last).count() < 15.0) return;
+    last = now;
+    std::fprintf(stderr, "[lc_build] %s: %lld / %lld (%.0f s)\n", what, (long long)done, (long long)total,
+                 std::chrono::duration<double>(now - start).count());
+    std::fflush(stderr);
+  }
+};
 
 // ---------------------------------------------------------------------------
 // threads
@@ -484,8 +506,10 @@ int lcb_graph_build(const float *x, int64_t n, int d, const float *proj, int d_p
   std::vector<RL> rl;
   std::vector<int64_t> goff;
 
+  Progress prog("graph");
   int64_t pos = 1;
   while (pos < n) {
+    prog.tick(pos, n);
     int64_t bs = std::max<int64_t>(1, std::min<int64_t>(bmax, pos / 16));
     if (pos + bs > n) bs = n - pos;
     const int32_t *batch = order.data() + pos;
@@ -702,7 +726,9 @@ int lcb_beta_train(const float *x, const int64_t *ids, int64_t n_sub, int d, con
   }
   // EM: assignment (Eq. 7), per-cluster least squares (Eq. 8)
   std::vector<double> ls(n_sub);
+  Progress prog("beta EM");
   for (int it = 0;; ++it) {
+    prog.tick(it, em_iters);
     parallel_for(n_sub, nthreads, [&](int64_t r, int) { as[r] = best_beta(g, r, B.data(), n_beta, &ls[r]); },
                  256);
     if (loss_hist) {
@@ -737,7 +763,9 @@ int lcb_beta_assign(const float *x, int64_t n, int d, const float *proj, int d_p
   for (size_t t = 0; t < B.size(); ++t) B[t] = beta[t];
   const int64_t chunk = 1 << 17;
   std::vector<int64_t> ids(chunk);
+  Progress prog("beta assignment");
   for (int64_t c0 = 0; c0 < n; c0 += chunk) {
+    prog.tick(c0, n);
     const int64_t c1 = std::min(n, c0 + chunk);
     for (int64_t i = c0; i < c1; ++i) ids[i - c0] = i;
     Gram g;

@@ -439,7 +439,8 @@ WalkPlan plan_for(const lc_index *ix, int64_t nq, int32_t ef_max, int32_t S, con
   WalkPlan p;
   int ef_eff = ef_max > S ? ef_max : S;
   p.w_cap = (ef_eff + 63) / 64 * 64;
-  p.hash_bits = (sc && sc->hash_bits) ? sc->hash_bits : auto_hash_bits(p.w_cap);
+  // visited mode 1 keeps only a small LDS cache; mode 0 sizes its table from the pool
+  p.hash_bits = (sc && sc->hash_bits) ? sc->hash_bits : (sc && sc->visited == 1 ? 9 : auto_hash_bits(p.w_cap));
   p.lds_bytes = lds_bytes_for<M>(p.w_cap, p.hash_bits, lut_bytes);
   int per_cu = ix->lds_per_cu / p.lds_bytes;
   if (sc && sc->waves_per_cu > 0 && sc->waves_per_cu < per_cu) per_cu = sc->waves_per_cu;
@@ -460,7 +461,7 @@ bool valid_schedule(const lc_schedule *sc) {
   return true;
 }
 
-const lc_schedule kDefaultSchedule = {0, 0, 0, 1, 0};
+const lc_schedule kDefaultSchedule = {0, 0, 0, 1, 1};
 
 int list_cap_for(int w_cap) { return 16 * w_cap > 4096 ? 16 * w_cap : 4096; }
 
