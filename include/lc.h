@@ -137,28 +137,37 @@ int lc_search(const lc_index *ix, const void *lut, int lut_dtype, const float *l
 
 /* Launch schedule of the walk.  Every schedule returns exactly the same
  * short-lists, distances and (E, D) counts; only speed changes.
- *   hash_bits     log2 capacity of the per-query LDS table of the visited set
- *                 (9..14; 0 = automatic: 9 for visited mode 1, else chosen
- *                 from ef).
- *   prefetch      1 = load the adjacency row of the predicted next candidate
- *                 while the current one is processed (used only when the
- *                 prediction is confirmed), 0 = off.
+ *   hash_bits     log2 of the per-query LDS table of the visited set, in
+ *                 4-byte words (9..14; 0 = automatic: 9 for visited mode 1,
+ *                 else a table of about 8 ef_eff ids).
+ *   prefetch      visited mode 0 only: 1 = at the start of every step, load
+ *                 the adjacency rows of the two unexpanded entries that follow
+ *                 the two being expanded (used at the next step when they
+ *                 are still the next two), 0 = load each row when it is
+ *                 needed.
  *   waves_per_cu  cap on resident query slots per compute unit (0 = as many as
  *                 LDS allows).
  *   queue         1 = slots take queries from an atomic counter in the
  *                 workspace (load balance for uneven walk lengths), 0 = each
  *                 slot strides over the batch.
- *   visited       0 = the LDS table holds the visited ids (open addressing);
- *                 past half full the query continues on the slot's bitset in
- *                 the workspace.
+ *   visited       0 = the LDS table holds the visited ids: each id has a home
+ *                 bucket of 16 bytes and is kept there while the bucket has
+ *                 room, else in the slot's bitset in the workspace.  Each
+ *                 step expands the best unexpanded entry and, when the
+ *                 sequential walk would expand it next, the second one too
+ *                 (same results, half the dependent steps).
  *                 1 = the slot's bitset in the workspace is the visited set;
  *                 the LDS table is a direct-mapped cache of recently visited
  *                 ids, and a miss tests-and-sets the bit while the node's
  *                 code is fetched speculatively (less LDS per query, so more
  *                 queries resident).
- * The default schedule (sched = NULL, and lc_search) is {0, 0, 0, 1, 1}. */
+ *   wide          visited mode 0 only: 1 = the table holds 32-bit ids (four
+ *                 per bucket); 0 = 16-bit tags (eight per bucket, twice the
+ *                 ids in the same LDS) whenever ids below n fit a tag, which
+ *                 is when n <= 2^(hash_bits + 13).
+ * The default schedule (sched = NULL, and lc_search) is {0, 1, 0, 1, 0, 0}. */
 typedef struct {
-  int32_t hash_bits, prefetch, waves_per_cu, queue, visited;
+  int32_t hash_bits, prefetch, waves_per_cu, queue, visited, wide;
 } lc_schedule;
 
 /* Workspace bytes for lc_search_sched with schedule `sched` (NULL = default). */

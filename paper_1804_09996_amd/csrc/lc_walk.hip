@@ -2,23 +2,35 @@
 // levels, then a best-first walk on level 0 over nodes that hold only PQ codes,
 // scored by asymmetric distances from the per-query table.
 //
-// One wavefront owns one query at a time (grid-stride over queries):
-//  * the query's table (m x 256 float32) is staged in LDS;
+// One wavefront owns one query at a time (slots take queries from an atomic
+// counter or stride over the batch):
+//  * the query's table (m x 256, float32 or fp16 with per-row scales) is
+//    staged in LDS;
 //  * the pool W (<= ef_eff keys, sorted, "expanded" flag in bit 31) is an LDS
 //    array;
-//  * the visited set is exact: an LDS open-addressing table of node ids, and
-//    once that table is half full, a per-wave bitset in the workspace (cleared
-//    again before the next query);
-//  * each expansion reads one 32-link row of adj0 (lanes 0..31), tests and
-//    marks the links as visited, gathers the codes of the fresh ones (lanes L
-//    and L+32 each sum half of the sub-spaces, in a fixed order), and merges
-//    the keys that can enter W.
+//  * the visited set is exact, in one of two forms (the schedule's choice):
+//    an LDS open-addressing table of ids that continues on a per-slot bitset
+//    in the workspace once half full (walk_kernel), or the per-slot bitset
+//    behind a direct-mapped LDS cache (walk_cache_kernel).
 //
 // Expanding the best unexpanded entry of W, evaluating all its fresh links,
 // and merging them at once leaves W, the expansion count E and the evaluation
 // count D exactly as in the textbook two-heap form: keys are unique, keeping
 // the best ef_eff of a union is associative, and a candidate that is no longer
 // in W is worse than every entry of W, so it would end the two-heap loop.
+//
+// walk_kernel also expands the second unexpanded entry p of W in the same
+// step, on lanes 32..63, whenever that is what the sequential walk would do
+// next: after the first expansion c, the next one is p exactly when none of
+// c's fresh keys is below key(p).  Both expansions' links are probed against
+// the visited table together (p's only looked up), their codes fetched and
+// scored together; once every fresh key of c is known to be above key(p), p's
+// absent links are inserted for real and the kept keys of both are merged at
+// once.  Merging c's keys and then p's keys (each time keeping the best
+// ef_eff) equals merging their union, so W, E and D stay those of the
+// sequential walk.  The adjacency rows of the two entries that follow p are
+// loaded at the start of each step and used at the next one when they are
+// still the next two unexpanded entries.
 #include <hip/hip_fp16.h>
 
 #include "lc_internal.h"
@@ -38,6 +50,7 @@ struct WalkArgs {
   int64_t nq, n_up_rows;
   int32_t n, code_stride, deg0, deg_up, entry, max_level;
   int32_t w_cap, hash_bits, prefetch, queue, vmode, list_cap;
+  int32_t tag_bits;    // walk_kernel's table: 16-bit tags of this many bits, 0 = 32-bit ids
   uint32_t *counters;  // [0] next query, [1] finished slots (queue mode)
   uint32_t *bits;
   int32_t *vlists;     // [slots][list_cap] ids whose bit is set (visited mode 1)
@@ -122,45 +135,293 @@ __device__ __forceinline__ uint64_t readlane64(uint64_t v, int l) {
   return (uint64_t(hi) << 32) | lo;
 }
 
-// Test-and-set of `id` in the visited set; true when `id` was not there.
-__device__ __forceinline__ bool visit(uint32_t *hash, uint32_t hmask, int hshift, int32_t id, bool ovf,
-                                      uint32_t *bits) {
-  uint32_t h = (uint32_t(id) * 0x9E3779B1u) >> hshift;
-  if (!ovf) {
-    for (;;) {
-      const uint32_t old = atomicCAS(&hash[h], kEmpty, uint32_t(id));
-      if (old == kEmpty) return true;
-      if (old == uint32_t(id)) return false;
-      h = (h + 1) & hmask;
-    }
-  }
-  for (;;) {
-    const uint32_t v = hash[h];
-    if (v == uint32_t(id)) return false;
-    if (v == kEmpty) break;
-    h = (h + 1) & hmask;
-  }
-  const uint32_t bit = 1u << (uint32_t(id) & 31u);
-  const uint32_t old = atomicOr(&bits[uint32_t(id) >> 5], bit);
-  return (old & bit) == 0;
+__device__ __forceinline__ uint32_t hash_slot(int32_t id, int hshift) {
+  return (uint32_t(id) * 0x9E3779B1u) >> hshift;
 }
 
+// Merges the kept keys (one per lane with `keep`, all unique, none in W, each
+// below the largest key of W when W is full) into the sorted pool W[0..nw),
+// keeping the best efe; nw is updated.  Without sorting the kept keys: each is
+// broadcast in turn; its rank among the kept keys plus its count of smaller W
+// entries is its slot, and every W entry moves up by the number of kept keys
+// below it (chunks of 64 from the top, stopping below the smallest kept key).
+// Returns the slot of the smallest kept key; before_ck = kept keys below ck.
+__device__ __forceinline__ int merge_kept(uint64_t *W, int &nw, int efe, uint64_t k, bool keep, uint64_t km,
+                                          uint64_t ck, int lane, int &before_ck) {
+  const int nn = __popcll(km);
+  uint64_t kmin = kKeyMax;
+  int rank = 0;
+  before_ck = 0;
+  for (uint64_t mm = km; mm; mm &= mm - 1) {
+    const int j = __ffsll((unsigned long long)mm) - 1;
+    const uint64_t kj = readlane64(k, j);
+    kmin = kj < kmin ? kj : kmin;
+    rank += (keep && kj < k) ? 1 : 0;
+    before_ck += kj < ck ? 1 : 0;
+  }
+  int mypos = 0;
+  int c = (nw - 1) >> 6;
+  for (; c >= 0; --c) {
+    const int idx = (c << 6) + lane;
+    const bool in = idx < nw;
+    const uint64_t v = in ? W[idx] : kKeyMax;
+    const uint64_t pv = pure_key(v);
+    int cnt = 0;
+    for (uint64_t mm = km; mm; mm &= mm - 1) {
+      const int j = __ffsll((unsigned long long)mm) - 1;
+      const uint64_t kj = readlane64(k, j);
+      cnt += (in && kj < pv) ? 1 : 0;
+      const int below = __popcll(__ballot(in && pv < kj));
+      if (lane == j) mypos += below;
+    }
+    wave_sync();  // the whole chunk is in registers before anything moves
+    if (in && cnt > 0 && idx + cnt < efe) W[idx + cnt] = v;
+    wave_sync();
+    if (readlane64(pv, 0) < kmin) {  // lower chunks lie entirely below every kept key
+      --c;
+      break;
+    }
+  }
+  mypos += (c + 1) << 6;
+  if (keep && mypos + rank < efe) W[mypos + rank] = k;
+  const int jmin = __ffsll((unsigned long long)__ballot(keep && rank == 0)) - 1;
+  const int pos_min = __builtin_amdgcn_readlane(mypos, jmin);
+  nw = nw + nn < efe ? nw + nn : efe;
+  wave_sync();
+  return pos_min;
+}
+
+// The visited table of walk_kernel: 2^(hash_bits-2) buckets of 16 bytes in
+// LDS.  An id has one home bucket; it is stored there while the bucket has a
+// free slot, and otherwise in the slot's bitset in the workspace (so an id is
+// in exactly one of the two, and only a full bucket sends a look-up on to the
+// bitset).  Narrow tables hold eight 16-bit tags per bucket: with
+// h = id * 0x9E3779B1 mod 2^id_bits (a bijection), the bucket is the top bits
+// of h and the tag the rest, so (bucket, tag) identifies the id.  Wide tables
+// hold four ids per bucket (bucket from the top bits of the 32-bit product).
+struct VTable {
+  uint32_t *t;
+  int bshift;       // wide: 32 - bucket bits
+  int tbits;        // narrow: tag bits (<= 15)
+  uint32_t hmask;   // narrow: 2^id_bits - 1
+  bool narrow;
+};
+
+constexpr uint32_t kTagEmpty = 0xFFFFu;
+
+__device__ __forceinline__ void vt_locate(const VTable &v, int32_t id, uint32_t &b, uint32_t &tag) {
+  const uint32_t p = uint32_t(id) * 0x9E3779B1u;
+  if (v.narrow) {
+    const uint32_t h = p & v.hmask;
+    b = h >> v.tbits;
+    tag = h & ((1u << v.tbits) - 1u);
+  } else {
+    b = p >> v.bshift;
+    tag = uint32_t(id);
+  }
+}
+
+__device__ __forceinline__ uint32_t dword_of(const uint4 &s, int i) {
+  return i == 0 ? s.x : i == 1 ? s.y : i == 2 ? s.z : s.w;
+}
+
+// hit: the tag is in the bucket; e: its first free slot (-1: full)
+__device__ __forceinline__ void vt_inspect(const VTable &v, const uint4 &s, uint32_t tag, bool &hit, int &e) {
+  uint32_t hm, em;
+  if (v.narrow) {
+    const uint32_t w[4] = {s.x, s.y, s.z, s.w};
+    hm = em = 0u;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const uint32_t l16 = w[i] & 0xFFFFu, h16 = w[i] >> 16;
+      hm |= (uint32_t(l16 == tag) | (uint32_t(h16 == tag) << 1)) << (2 * i);
+      em |= (uint32_t(l16 == kTagEmpty) | (uint32_t(h16 == kTagEmpty) << 1)) << (2 * i);
+    }
+  } else {
+    hm = uint32_t(s.x == tag) | (uint32_t(s.y == tag) << 1) | (uint32_t(s.z == tag) << 2) |
+         (uint32_t(s.w == tag) << 3);
+    em = uint32_t(s.x == kEmpty) | (uint32_t(s.y == kEmpty) << 1) | (uint32_t(s.z == kEmpty) << 2) |
+         (uint32_t(s.w == kEmpty) << 3);
+  }
+  hit = hm != 0u;
+  e = em ? __builtin_ctz(em) : -1;
+}
+
+// One CAS that stores the tag in free slot e of bucket b, given the bucket as
+// read; false when another lane changed that word first.
+__device__ __forceinline__ bool vt_try_store(const VTable &v, uint32_t b, int e, uint32_t tag, const uint4 &s) {
+  if (v.narrow) {
+    const uint32_t seen = dword_of(s, e >> 1);
+    const int sh = (e & 1) * 16;
+    const uint32_t want = (seen & ~(0xFFFFu << sh)) | (tag << sh);
+    return atomicCAS(&v.t[4 * b + (e >> 1)], seen, want) == seen;
+  }
+  return atomicCAS(&v.t[4 * b + e], kEmpty, tag) == kEmpty;
+}
+
+// Test-and-set of the bitset bit of id: true when it was clear.
+__device__ __forceinline__ bool bit_set(uint32_t *bits, int32_t id) {
+  const uint32_t bit = 1u << (uint32_t(id) & 31u);
+  return (atomicOr(&bits[uint32_t(id) >> 5], bit) & bit) == 0u;
+}
+
+// Test of the bitset bit of id (device-coherent read): true when it is clear.
+__device__ __forceinline__ bool bit_clear(uint32_t *bits, int32_t id) {
+  const uint32_t w = __hip_atomic_load(&bits[uint32_t(id) >> 5], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return (w & (1u << (uint32_t(id) & 31u))) == 0u;
+}
+
+// General test-and-set of id: true when id was not visited; set_bit tells
+// that it went to the bitset.
+__device__ __forceinline__ bool vt_insert(const VTable &v, uint32_t b, uint32_t tag, int32_t id, uint32_t *bits,
+                                          bool &set_bit) {
+  set_bit = false;
+  for (;;) {
+    const uint4 s = reinterpret_cast<const uint4 *>(v.t)[b];
+    bool hit;
+    int e;
+    vt_inspect(v, s, tag, hit, e);
+    if (hit) return false;
+    if (e < 0) {
+      const bool f = bit_set(bits, id);
+      set_bit = f;
+      return f;
+    }
+    if (vt_try_store(v, b, e, tag, s)) return true;
+  }
+}
+
+// Values every lane of the wave holds alike, made visibly uniform to the
+// compiler (scalar registers and scalar branches).
+__device__ __forceinline__ int uni(int x) { return __builtin_amdgcn_readfirstlane(x); }
+__device__ __forceinline__ uint64_t uni64(uint64_t x) {
+  const uint32_t lo = uint32_t(__builtin_amdgcn_readfirstlane(int(uint32_t(x))));
+  const uint32_t hi = uint32_t(__builtin_amdgcn_readfirstlane(int(uint32_t(x >> 32))));
+  return (uint64_t(hi) << 32) | lo;
+}
+
+// Lowest set bits of a 128-bit lane mask, one at a time (-1 once empty).
+struct Pick2 {
+  uint64_t lo, hi;
+  __device__ __forceinline__ int next() {
+    const bool l = lo != 0;
+    const uint64_t m = l ? lo : hi;
+    const int r = m ? __ffsll((unsigned long long)m) - 1 + (l ? 0 : 64) : -1;
+    const uint64_t m2 = m & (m - 1);
+    lo = l ? m2 : lo;
+    hi = l ? hi : m2;
+    return r;
+  }
+};
+
+// Insertion of a single kept key k (held by lane j): entries above it move up
+// by one, chunk by chunk from the top.  Returns its slot.
+__device__ __forceinline__ int merge_one(uint64_t *W, int &nw, int efe, uint64_t k, int j, int lane) {
+  const uint64_t kk = readlane64(k, j);
+  int pos = 0;
+  for (int c = (nw - 1) >> 6; c >= 0; --c) {
+    const int idx = (c << 6) + lane;
+    const bool in = idx < nw;
+    const uint64_t v = in ? W[idx] : kKeyMax;
+    const bool up = in && pure_key(v) > kk;
+    wave_sync();
+    if (up && idx + 1 < efe) W[idx + 1] = v;
+    const uint64_t below = __ballot(in && !up);
+    if (below) {  // the slot is in this chunk, right above its last entry below kk
+      pos = (c << 6) + 64 - __clzll((long long)below);
+      break;
+    }
+  }
+  if (lane == 0 && pos < efe) W[pos] = kk;
+  nw = nw + 1 < efe ? nw + 1 : efe;
+  wave_sync();
+  return pos;
+}
+
+// Merge of at most 8 kept keys (see merge_kept for the general case), with
+// VALU counting against the sorted kept keys broadcast from LDS.  Entries move
+// up by the number of kept keys below them; the kept keys of ranks
+// [kept below W[i-1], kept below W[i]) land just below entry i (or below the
+// end of W).  Returns the slot of the smallest kept key.
+__device__ __forceinline__ int merge_few(uint64_t *W, uint64_t *Ks, int &nw, int efe, uint64_t k, bool keep,
+                                         uint64_t km, uint64_t ck, int lane, int &before_ck) {
+  const int nn = __popcll(km);
+  // rank of each kept key among the kept keys, then the kept keys sorted in Ks
+  int rank = 0;
+  for (uint64_t mm = km; mm; mm &= mm - 1) {
+    const uint64_t kj = readlane64(k, __ffsll((unsigned long long)mm) - 1);
+    rank += kj < k ? 1 : 0;
+  }
+  if (lane < 8) Ks[lane] = kKeyMax;
+  wave_sync();
+  if (keep) Ks[rank] = k;
+  wave_sync();
+  uint64_t kv[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) kv[j] = Ks[j];
+  int bc = 0;
+#pragma unroll
+  for (int j = 0; j < 8; ++j) bc += kv[j] < ck ? 1 : 0;
+  before_ck = __builtin_amdgcn_readfirstlane(bc);
+
+  int pos_min = efe;
+  for (int c = nw >> 6; c >= 0; --c) {
+    const int base = c << 6;
+    const int idx = base + lane;
+    // idx == nw is a sentinel above every kept key
+    const uint64_t v = idx < nw ? W[idx] : kKeyMax;
+    const uint64_t pv = idx < nw ? pure_key(v) : kKeyMax;
+    const uint64_t pp = (idx >= 1 && idx <= nw) ? pure_key(W[idx - 1]) : 0ull;
+    int cnt = 0, cprev = 0;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      cnt += kv[j] < pv ? 1 : 0;
+      cprev += kv[j] < pp ? 1 : 0;
+    }
+    if (idx > nw) cnt = cprev = 0;
+    wave_sync();  // the chunk and its lower neighbours are in registers before anything moves
+    if (idx < nw && cnt > 0 && idx + cnt < efe) W[idx + cnt] = v;
+    for (int t = cprev; t < cnt; ++t)
+      if (idx + t < efe) W[idx + t] = Ks[t];
+    const uint64_t m0 = __ballot(cprev == 0 && cnt > 0);
+    wave_sync();
+    if (__builtin_amdgcn_readfirstlane(cprev) == 0) {  // nothing below this chunk moves
+      if (m0) pos_min = base + __ffsll((unsigned long long)m0) - 1;
+      break;
+    }
+  }
+  nw = nw + nn < efe ? nw + nn : efe;
+  return pos_min;
+}
+
+// Level-0 walk with the visited set in an LDS table (and the bitset for ids
+// whose home bucket is full), two expansions per step when the sequential
+// order allows it.
 template <int M, typename T>
 __global__ __launch_bounds__(64) void walk_kernel(WalkArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int lane = threadIdx.x;
   const int l32 = lane & 31;
+  const bool lo = lane < 32;
   constexpr int kLutBytes = M * 256 * int(sizeof(T));
   constexpr int kScaleBytes = sizeof(T) == 2 ? (M * 4 + 15) / 16 * 16 : 0;
   T *lut = reinterpret_cast<T *>(smem);
   float *sc = reinterpret_cast<float *>(smem + kLutBytes);
   uint64_t *W = reinterpret_cast<uint64_t *>(smem + kLutBytes + kScaleBytes);
-  uint32_t *hash = reinterpret_cast<uint32_t *>(W + a.w_cap);
-  const int H = 1 << a.hash_bits;
-  const uint32_t hmask = uint32_t(H - 1);
-  const int hshift = 32 - a.hash_bits;
-  const int hlimit = H / 2;
+  uint64_t *Ks = W + a.w_cap;  // merge scratch: the kept keys, sorted
+  uint32_t *hash = reinterpret_cast<uint32_t *>(Ks + 16);
+  const int H = 1 << a.hash_bits;  // table words
+  VTable vt;
+  vt.t = hash;
+  vt.bshift = 32 - (a.hash_bits - 2);
+  vt.tbits = a.tag_bits;
+  vt.hmask = a.tag_bits ? uint32_t((1ull << (a.tag_bits + a.hash_bits - 2)) - 1ull) : 0u;
+  vt.narrow = a.tag_bits != 0;
   uint32_t *bits = a.bits + int64_t(blockIdx.x) * a.words;
+  int32_t *vlist = a.vlists + int64_t(blockIdx.x) * a.list_cap;
+  // every row load reads a valid column, so that loads need no branch around them
+  const int lcol = l32 < a.deg0 ? l32 : a.deg0 - 1;
+  const bool col_ok = l32 < a.deg0;
 
   int64_t pos = blockIdx.x;
   if (a.queue) {
@@ -219,143 +480,195 @@ __global__ __launch_bounds__(64) void walk_kernel(WalkArgs a) {
       }
 
       // best-first walk on level 0
-      int32_t *vlist = a.vlists + int64_t(blockIdx.x) * a.list_cap;
       if (lane == 0) {
         W[0] = curkey;
-        if (a.vmode == 0) {
-          visit(hash, hmask, hshift, cur, false, bits);
-        } else {
-          atomicOr(&bits[uint32_t(cur) >> 5], 1u << (uint32_t(cur) & 31u));
-          hash[(uint32_t(cur) * 0x9E3779B1u) >> hshift] = uint32_t(cur);
-          vlist[0] = cur;
-        }
+        uint32_t b0, t0;
+        vt_locate(vt, cur, b0, t0);
+        hash[4 * b0] = vt.narrow ? (t0 | 0xFFFF0000u) : t0;
       }
-      int vcount = 1;  // ids recorded in vlist (visited mode 1)
-      int nw = 1, fu = 0, E = 0, D = 0, hcount = 1;
-      bool ovf = false;
-      uint64_t ck = curkey;                            // key of W[fu]
-      uint64_t wmax = efe == 1 ? curkey : kKeyMax;     // largest key of W once W is full
-      int pidx = -1;                                   // second unexpanded entry (prefetch guess)
-      int32_t nb = l32 < a.deg0 ? a.adj0[int64_t(cur) * a.deg0 + l32] : -1;
+      int nw = 1, fu = 0, pidx = -1, E = 0, D = 0, vcount = 0;
+      uint64_t ck = curkey;                         // key of W[fu], the next expansion
+      uint64_t pk = kKeyMax;                        // key of W[pidx], the unexpanded entry after it
+      uint64_t wmax = efe == 1 ? curkey : kKeyMax;  // largest key of W once W is full
+      int32_t pre0 = -1, pre1 = -1;                 // ids whose rows `nxt` holds (lanes 0..31, 32..63)
+      int32_t row = a.adj0[int64_t(cur) * a.deg0 + lcol];
+      if (row >= a.n) row = -1;  // a malformed link is ignored rather than followed
       wave_sync();
       while (fu < nw) {
-        int32_t pred = -1, pnb = -1;
-        if (a.prefetch && pidx >= 0) {
-          pred = key_id(W[pidx]);
-          pnb = l32 < a.deg0 ? a.adj0[int64_t(pred) * a.deg0 + l32] : -1;
+        const int32_t cid = key_id(ck);
+        // rows of the entries likely to come next; every lane loads, from the
+        // expanded node's own row when there is no guess
+        int32_t nxt = 0;
+        if (a.prefetch) {
+          const int32_t g = lo ? pre0 : pre1;
+          nxt = a.adj0[int64_t(g >= 0 ? g : cid) * a.deg0 + lcol];
         }
+        const bool two = pidx >= 0;
         if (lane == 0) W[fu] = ck | kExpanded;
-        wave_sync();
-        ++E;
-        if (nb >= a.n) nb = -1;  // a malformed link is ignored rather than followed
-        bool fresh = false;
-        uint64_t k = kKeyMax;
-        if (a.vmode == 0) {
-          if (!ovf && hcount + a.deg0 > hlimit) ovf = true;
-          if (lane < 32 && nb >= 0) fresh = visit(hash, hmask, hshift, nb, ovf, bits);
-          const int nf = __popcll(__ballot(fresh));
-          D += nf;
-          if (!ovf) hcount += nf;
-          if (fresh) k = make_key(adc_full<M, T>(lut, sc, a.codes, a.code_stride, nb), nb);
-        } else {
-          // cache hit: visited; miss: test-and-set the bit, fetching the code meanwhile
-          CodeRegs<M> row;
-          if (lane < 32 && nb >= 0) {
-            const uint32_t h = (uint32_t(nb) * 0x9E3779B1u) >> hshift;
-            if (hash[h] != uint32_t(nb)) {
-              const uint32_t bit = 1u << (uint32_t(nb) & 31u);
-              const uint32_t old = atomicOr(&bits[uint32_t(nb) >> 5], bit);
-              row.load(a.codes, a.code_stride, nb);
-              fresh = (old & bit) == 0;
-              hash[h] = uint32_t(nb);
-            }
+        const int32_t nb = col_ok && (lo || two) ? row : -1;
+
+        // lanes 0..31 test-and-set c's links; lanes 32..63 look p's links up.
+        // One bucket read and at most one CAS settle almost every link; a
+        // full bucket or a lost CAS goes round the general path.
+        const bool act = nb >= 0;
+        uint32_t b, tag;
+        vt_locate(vt, act ? nb : 0, b, tag);
+        const uint4 s4 = reinterpret_cast<const uint4 *>(hash)[b];
+        bool hit;
+        int e;
+        vt_inspect(vt, s4, tag, hit, e);
+        hit = hit & act;
+        const bool ins = act & lo & !hit & (e >= 0);
+        bool ok = false;
+        if (ins) ok = vt_try_store(vt, b, e, tag, s4);
+        bool cand = lo ? ok : (act & !hit & (e >= 0));  // lanes 32..63: absent before this step
+        bool set_bit = false;
+        const bool rest = act & !hit & ((e < 0) | (ins & !ok));
+        if (__ballot(rest)) {
+          if (rest) {
+            if (lo) cand = vt_insert(vt, b, tag, nb, bits, set_bit);
+            else cand = bit_clear(bits, nb);  // the bucket is full: the bitset decides
           }
-          const uint64_t fm = __ballot(fresh);
-          const int nf = __popcll(fm);
-          if (fresh) {
-            const int at = vcount + __popcll(fm & ((1ull << lane) - 1ull));
-            if (at < a.list_cap) vlist[at] = nb;
-            k = make_key(row.adc(lut, sc), nb);
-          }
-          vcount += nf;
-          D += nf;
         }
+        const uint64_t fc = __ballot(lo && cand);
+        D += __popcll(fc);
+        // codes and ADC keys of both halves' candidates
+        uint64_t k = kKeyMax;
+        if (cand) {
+          CodeRegs<M> cr;
+          cr.load(a.codes, a.code_stride, nb);
+          k = make_key(cr.adc(lut, sc), nb);
+        }
+
+        // p is the next expansion of the sequential walk iff no fresh key of c is below it
+        const bool dual = two && __ballot(lo && cand && k < pk) == 0ull;
+        bool fresh = lo && cand;
+        if (dual) {
+          // p's absent links, inserted for real: one CAS at the slot the look-up
+          // saw free, the general path otherwise (a full bucket: the bitset)
+          const bool ins2 = !lo & cand & (e >= 0);
+          bool ok2 = false;
+          if (ins2) ok2 = vt_try_store(vt, b, e, tag, s4);
+          if (!lo) fresh = ok2;
+          const bool rest2 = !lo & cand & !ok2;
+          if (__ballot(rest2)) {
+            if (rest2) fresh = vt_insert(vt, b, tag, nb, bits, set_bit);
+          }
+          const int nfp = __popcll(__ballot(!lo && fresh));
+          D += nfp;
+          E += 2;
+          if (lane == 0) W[pidx] = pk | kExpanded;
+        } else {
+          E += 1;
+        }
+        {
+          // ids that went to the bitset, listed for clearing at the end of the query
+          const uint64_t sb = __ballot(set_bit);
+          if (sb) {
+            const int at = vcount + __popcll(sb & ((1ull << lane) - 1ull));
+            if (set_bit && at < a.list_cap) vlist[at] = nb;
+            vcount += __popcll(sb);
+          }
+        }
+        wave_sync();
+
         const bool keep = fresh && k < wmax;
         const uint64_t km = __ballot(keep);
         int p0 = fu;
         if (km) {
-          // Merge the kept keys into W without sorting them: every kept key is
-          // broadcast in turn; its rank among the kept keys and its count of
-          // smaller W entries give its slot, and every W entry moves up by the
-          // number of kept keys below it.
+          int before_ck = 0;
           const int nn = __popcll(km);
-          uint64_t kmin = kKeyMax;
-          int rank = 0, before_ck = 0;
-          for (uint64_t mm = km; mm; mm &= mm - 1) {
-            const int j = __ffsll((unsigned long long)mm) - 1;
-            const uint64_t kj = readlane64(k, j);
-            kmin = kj < kmin ? kj : kmin;
-            rank += (keep && kj < k) ? 1 : 0;
-            before_ck += kj < ck ? 1 : 0;
+          int pos_min;
+          if (nn == 1) {
+            const int j = __ffsll((unsigned long long)km) - 1;
+            pos_min = merge_one(W, nw, efe, k, j, lane);
+            before_ck = readlane64(k, j) < ck ? 1 : 0;
+          } else if (nn <= 8) {
+            pos_min = merge_few(W, Ks, nw, efe, k, keep, km, ck, lane, before_ck);
+          } else {
+            pos_min = merge_kept(W, nw, efe, k, keep, km, ck, lane, before_ck);
           }
-          int mypos = 0;
-          int c = (nw - 1) >> 6;
-          for (; c >= 0; --c) {
-            const int idx = (c << 6) + lane;
-            const bool in = idx < nw;
-            const uint64_t v = in ? W[idx] : kKeyMax;
-            const uint64_t pv = pure_key(v);
-            int cnt = 0;
-            for (uint64_t mm = km; mm; mm &= mm - 1) {
-              const int j = __ffsll((unsigned long long)mm) - 1;
-              const uint64_t kj = readlane64(k, j);
-              cnt += (in && kj < pv) ? 1 : 0;
-              const int below = __popcll(__ballot(in && pv < kj));
-              if (lane == j) mypos += below;
-            }
-            wave_sync();  // the whole chunk is in registers before anything moves
-            if (in && cnt > 0 && idx + cnt < efe) W[idx + cnt] = v;
-            wave_sync();
-            if (readlane64(pv, 0) < kmin) {  // lower chunks lie entirely below every kept key
-              --c;
-              break;
-            }
-          }
-          mypos += (c + 1) << 6;
-          if (keep && mypos + rank < efe) W[mypos + rank] = k;
-          const int jmin = __ffsll((unsigned long long)__ballot(keep && rank == 0)) - 1;
-          const int pos_min = __builtin_amdgcn_readlane(mypos, jmin);
           const int fu_new = fu + before_ck;
           p0 = fu_new < pos_min ? fu_new : pos_min;
-          nw = nw + nn < efe ? nw + nn : efe;
           wave_sync();
           wmax = nw == efe ? pure_key(W[nw - 1]) : kKeyMax;
         }
-        wave_sync();
-        // first and second unexpanded entries at or after p0 (all before are expanded)
-        int nfu = nw;
-        uint64_t nck = 0;
-        pidx = -1;
-        for (int base = p0; base < nw; base += 64) {
-          const int idx = base + lane;
-          const uint64_t v = idx < nw ? W[idx] : kExpanded;
-          uint64_t bm = __ballot((v & kExpanded) == 0);
-          if (bm) {
-            const int l0 = __ffsll((unsigned long long)bm) - 1;
-            nfu = base + l0;
-            nck = readlane64(v, l0);
-            bm &= bm - 1;
-            if (bm) pidx = base + __ffsll((unsigned long long)bm) - 1;
-            break;
+
+        // the first four unexpanded entries at or after p0 (all before are expanded),
+        // from two chunks at a time
+        int i0 = nw, i1 = -1;
+        uint64_t k0 = 0, k1 = kKeyMax;
+        int32_t g2 = -1, g3 = -1;
+        {
+          const int ia = p0 + lane, ib = p0 + 64 + lane;
+          const uint64_t va = ia < nw ? W[ia] : kExpanded;
+          const uint64_t vb = ib < nw ? W[ib] : kExpanded;
+          Pick2 pm;
+          pm.lo = __ballot((va & kExpanded) == 0);
+          pm.hi = __ballot((vb & kExpanded) == 0);
+          const int r0 = pm.next(), r1 = pm.next(), r2 = pm.next(), r3 = pm.next();
+          const uint64_t x0 = readlane64(r0 < 64 ? va : vb, r0 & 63);
+          const uint64_t x1 = readlane64(r1 < 64 ? va : vb, r1 & 63);
+          const int32_t y2 = __builtin_amdgcn_readlane(int(uint32_t(r2 < 64 ? va : vb)), r2 & 63) & 0x7FFFFFFF;
+          const int32_t y3 = __builtin_amdgcn_readlane(int(uint32_t(r3 < 64 ? va : vb)), r3 & 63) & 0x7FFFFFFF;
+          if (r0 >= 0) {
+            i0 = p0 + r0;
+            k0 = x0;
+          }
+          if (r1 >= 0) {
+            i1 = p0 + r1;
+            k1 = x1;
+          }
+          g2 = r2 >= 0 ? y2 : -1;
+          g3 = r3 >= 0 ? y3 : -1;
+          if (r3 < 0 && p0 + 128 < nw) {
+            // fewer than four in these two chunks: look further (rare)
+            int found = r0 < 0 ? 0 : r1 < 0 ? 1 : r2 < 0 ? 2 : 3;
+            for (int base = p0 + 128; base < nw && found < 4; base += 64) {
+              const int idx = base + lane;
+              const uint64_t v = idx < nw ? W[idx] : kExpanded;
+              uint64_t bm = __ballot((v & kExpanded) == 0);
+              while (bm && found < 4) {
+                const int l = __ffsll((unsigned long long)bm) - 1;
+                const uint64_t x = readlane64(v, l);
+                if (found == 0) {
+                  i0 = base + l;
+                  k0 = x;
+                } else if (found == 1) {
+                  i1 = base + l;
+                  k1 = x;
+                } else if (found == 2) {
+                  g2 = key_id(x);
+                } else {
+                  g3 = key_id(x);
+                }
+                ++found;
+                bm &= bm - 1;
+              }
+            }
           }
         }
-        fu = nfu;
+        const int32_t pid = key_id(pk);
+        fu = i0;
+        pidx = i1;
         if (fu < nw) {
-          ck = nck;
-          const int32_t nc = key_id(ck);
-          if (nc == pred) nb = pnb;
-          else nb = l32 < a.deg0 ? a.adj0[int64_t(nc) * a.deg0 + l32] : -1;
+          ck = k0;
+          pk = k1;
+          const int32_t nc = key_id(k0);
+          const int32_t np = i1 >= 0 ? key_id(k1) : -1;
+          if (a.prefetch && dual && nc == pre0 && (np < 0 || np == pre1)) {
+            row = nxt;  // the guessed pair came next
+          } else if (a.prefetch && !dual && nc == pid && (np < 0 || np == pre0)) {
+            row = __shfl_xor(lo ? nxt : row, 32);  // p came next: its row moves down, the guess's up
+          } else {
+            row = a.adj0[int64_t(lo || np < 0 ? nc : np) * a.deg0 + lcol];
+          }
+          if (row >= a.n) row = -1;
+          pre0 = g2;
+          pre1 = g3;
         }
+        // nothing is in flight across steps: the next step's loads are the only ones to wait for
+        __builtin_amdgcn_s_waitcnt(0);
       }
 
       // short-list = the first min(S, |W|) entries of W
@@ -377,12 +690,7 @@ __global__ __launch_bounds__(64) void walk_kernel(WalkArgs a) {
           a.stats[2 * q + 1] = D;
         }
       }
-      if (a.vmode == 0) {
-        if (ovf) {
-          for (int64_t i = lane; i < a.words; i += 64) bits[i] = 0u;
-          __threadfence();
-        }
-      } else {
+      if (vcount > 0) {
         __threadfence();  // the recorded ids are visible to every lane
         const int nl = vcount < a.list_cap ? vcount : a.list_cap;
         if (vcount > a.list_cap) {
@@ -414,6 +722,195 @@ __global__ __launch_bounds__(64) void walk_kernel(WalkArgs a) {
   }
 }
 
+// Level-0 walk with the visited set in the slot's bitset behind a
+// direct-mapped LDS cache; one expansion per step.
+template <int M, typename T>
+__global__ __launch_bounds__(64) void walk_cache_kernel(WalkArgs a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int lane = threadIdx.x;
+  const int l32 = lane & 31;
+  constexpr int kLutBytes = M * 256 * int(sizeof(T));
+  constexpr int kScaleBytes = sizeof(T) == 2 ? (M * 4 + 15) / 16 * 16 : 0;
+  T *lut = reinterpret_cast<T *>(smem);
+  float *sc = reinterpret_cast<float *>(smem + kLutBytes);
+  uint64_t *W = reinterpret_cast<uint64_t *>(smem + kLutBytes + kScaleBytes);
+  uint32_t *hash = reinterpret_cast<uint32_t *>(W + a.w_cap + 16);  // after the merge scratch
+  const int H = 1 << a.hash_bits;
+  const int hshift = 32 - a.hash_bits;
+  uint32_t *bits = a.bits + int64_t(blockIdx.x) * a.words;
+  int32_t *vlist = a.vlists + int64_t(blockIdx.x) * a.list_cap;
+
+  int64_t pos = blockIdx.x;
+  if (a.queue) {
+    int64_t t = 0;
+    if (lane == 0) t = int64_t(atomicAdd(a.counters, 1u));
+    pos = __shfl(t, 0);
+  }
+  while (pos < a.nq) {
+    const int64_t q = a.order ? int64_t(a.order[pos]) : pos;
+    if (q < 0 || q >= a.nq) {
+      // not a query of this batch: nothing to do
+    } else {
+    const int32_t efq = a.ef ? a.ef[q] : a.ef_max;
+    if (efq < 1 || efq > a.ef_max) {
+      for (int i = lane; i < a.S; i += 64) {
+        a.cand_ids[q * a.S + i] = -1;
+        a.cand_adc[q * a.S + i] = __builtin_inff();
+      }
+      if (lane == 0) {
+        a.cand_n[q] = -1;
+        if (a.stats) {
+          a.stats[2 * q] = 0;
+          a.stats[2 * q + 1] = 0;
+        }
+      }
+    } else {
+      const int efe = efq > a.S ? efq : a.S;
+
+      const float4 *src = reinterpret_cast<const float4 *>(static_cast<const T *>(a.lut) + q * (M * 256));
+      for (int i = lane; i < kLutBytes / 16; i += 64) reinterpret_cast<float4 *>(lut)[i] = src[i];
+      if (sizeof(T) == 2)
+        for (int i = lane; i < M; i += 64) sc[i] = a.scale[q * M + i];
+      for (int i = lane; i < H; i += 64) hash[i] = kEmpty;
+      wave_sync();
+
+      int32_t cur = a.entry;
+      uint64_t curkey = make_key(adc_full<M, T>(lut, sc, a.codes, a.code_stride, cur), cur);
+      for (int l = a.max_level; l >= 1; --l) {
+        for (;;) {
+          const int64_t row = int64_t(a.up_base[cur]) + l - 1;
+          int32_t nb = -1;
+          if (lane < a.deg_up && row >= 0 && row < a.n_up_rows) nb = a.adj_up[row * a.deg_up + lane];
+          if (nb >= a.n) nb = -1;
+          const uint64_t k = nb >= 0 ? make_key(adc_full<M, T>(lut, sc, a.codes, a.code_stride, nb), nb) : kKeyMax;
+          const uint64_t mn = wave_min64(k);
+          if (mn < curkey) {
+            curkey = mn;
+            cur = key_id(mn);
+          } else {
+            break;
+          }
+        }
+      }
+
+      if (lane == 0) {
+        W[0] = curkey;
+        atomicOr(&bits[uint32_t(cur) >> 5], 1u << (uint32_t(cur) & 31u));
+        hash[hash_slot(cur, hshift)] = uint32_t(cur);
+        vlist[0] = cur;
+      }
+      int vcount = 1;  // ids recorded in vlist
+      int nw = 1, fu = 0, E = 0, D = 0;
+      uint64_t ck = curkey;
+      uint64_t wmax = efe == 1 ? curkey : kKeyMax;
+      int32_t nb = l32 < a.deg0 ? a.adj0[int64_t(cur) * a.deg0 + l32] : -1;
+      wave_sync();
+      while (fu < nw) {
+        if (lane == 0) W[fu] = ck | kExpanded;
+        wave_sync();
+        ++E;
+        if (nb >= a.n) nb = -1;
+        bool fresh = false;
+        uint64_t k = kKeyMax;
+        // cache hit: visited; miss: test-and-set the bit, fetching the code meanwhile
+        CodeRegs<M> cr;
+        if (lane < 32 && nb >= 0) {
+          const uint32_t h = hash_slot(nb, hshift);
+          if (hash[h] != uint32_t(nb)) {
+            const uint32_t bit = 1u << (uint32_t(nb) & 31u);
+            const uint32_t old = atomicOr(&bits[uint32_t(nb) >> 5], bit);
+            cr.load(a.codes, a.code_stride, nb);
+            fresh = (old & bit) == 0;
+            hash[h] = uint32_t(nb);
+          }
+        }
+        const uint64_t fm = __ballot(fresh);
+        const int nf = __popcll(fm);
+        if (fresh) {
+          k = make_key(cr.adc(lut, sc), nb);
+          const int at = vcount + __popcll(fm & ((1ull << lane) - 1ull));
+          if (at < a.list_cap) vlist[at] = nb;  // after the scoring, so that nothing waits on this store
+        }
+        vcount += nf;
+        D += nf;
+        const bool keep = fresh && k < wmax;
+        const uint64_t km = __ballot(keep);
+        int p0 = fu;
+        if (km) {
+          int before_ck = 0;
+          const int pos_min = merge_kept(W, nw, efe, k, keep, km, ck, lane, before_ck);
+          const int fu_new = fu + before_ck;
+          p0 = fu_new < pos_min ? fu_new : pos_min;
+          wmax = nw == efe ? pure_key(W[nw - 1]) : kKeyMax;
+        }
+        wave_sync();
+        int nfu = nw;
+        uint64_t nck = 0;
+        for (int base = p0; base < nw; base += 64) {
+          const int idx = base + lane;
+          const uint64_t v = idx < nw ? W[idx] : kExpanded;
+          const uint64_t bm = __ballot((v & kExpanded) == 0);
+          if (bm) {
+            const int l0 = __ffsll((unsigned long long)bm) - 1;
+            nfu = base + l0;
+            nck = readlane64(v, l0);
+            break;
+          }
+        }
+        fu = nfu;
+        if (fu < nw) {
+          ck = nck;
+          nb = l32 < a.deg0 ? a.adj0[int64_t(key_id(ck)) * a.deg0 + l32] : -1;
+        }
+      }
+
+      const int ns = a.S < nw ? a.S : nw;
+      for (int i = lane; i < a.S; i += 64) {
+        if (i < ns) {
+          const uint64_t v = W[i];
+          a.cand_ids[q * a.S + i] = key_id(v);
+          a.cand_adc[q * a.S + i] = key_dist(v);
+        } else {
+          a.cand_ids[q * a.S + i] = -1;
+          a.cand_adc[q * a.S + i] = __builtin_inff();
+        }
+      }
+      if (lane == 0) {
+        a.cand_n[q] = ns;
+        if (a.stats) {
+          a.stats[2 * q] = E;
+          a.stats[2 * q + 1] = D;
+        }
+      }
+      __threadfence();  // the recorded ids are visible to every lane
+      const int nl = vcount < a.list_cap ? vcount : a.list_cap;
+      if (vcount > a.list_cap) {
+        for (int64_t i = lane; i < a.words; i += 64) bits[i] = 0u;
+      } else {
+        for (int i = lane; i < nl; i += 64) bits[uint32_t(vlist[i]) >> 5] = 0u;
+      }
+      __threadfence();
+      for (int i = lane; i < nl; i += 64) vlist[i] = 0;  // the workspace is left zero-filled
+      __threadfence();
+      wave_sync();
+    }
+    }
+    if (a.queue) {
+      int64_t t = 0;
+      if (lane == 0) t = int64_t(atomicAdd(a.counters, 1u));
+      pos = __shfl(t, 0);
+    } else {
+      pos += gridDim.x;
+    }
+  }
+  if (a.queue && lane == 0) {
+    if (atomicAdd(a.counters + 1, 1u) == gridDim.x - 1) {
+      atomicExch(a.counters, 0u);
+      atomicExch(a.counters + 1, 0u);
+    }
+  }
+}
+
 struct WalkPlan {
   int w_cap, hash_bits, lds_bytes, grid;
 };
@@ -423,13 +920,27 @@ constexpr size_t kHeaderBytes = 256;  // two queue counters, padded
 template <int M>
 int lds_bytes_for(int w_cap, int hash_bits, int lut_bytes) {
   const int scale_bytes = lut_bytes == 2 ? (M * 4 + 15) / 16 * 16 : 0;
-  return M * 256 * lut_bytes + scale_bytes + w_cap * 8 + (1 << hash_bits) * 4;
+  return M * 256 * lut_bytes + scale_bytes + w_cap * 8 + 16 * 8 + (1 << hash_bits) * 4;
 }
 
-int auto_hash_bits(int w_cap) {
-  // about 8 table slots per pool slot: half of them before the bitset takes over
+// Tag width of a narrow visited table with 2^(hash_bits-2) buckets for ids
+// below n, or 0 when 16-bit tags cannot tell every id apart.
+int table_tag_bits(int32_t n, int hash_bits) {
+  int id_bits = 0;
+  while (id_bits < 31 && (int64_t(1) << id_bits) < int64_t(n)) ++id_bits;
+  const int bb = hash_bits - 2;
+  const int t = id_bits > bb ? id_bits - bb : 1;
+  return t <= 15 ? t : 0;
+}
+
+// About 8 ids of table per pool slot (walks visit ~3-6 ef_eff nodes): narrow
+// tables hold two ids per word, wide ones one.
+int auto_hash_bits(int w_cap, int32_t n) {
   int bits = 9;
-  while ((1 << bits) < 8 * w_cap && bits < 14) ++bits;
+  while ((1 << bits) < 4 * w_cap && bits < 13) ++bits;  // narrow: 8 w_cap ids
+  if (table_tag_bits(n, bits)) return bits;
+  bits = 9;
+  while ((1 << bits) < 8 * w_cap && bits < 14) ++bits;  // wide
   return bits;
 }
 
@@ -440,7 +951,8 @@ WalkPlan plan_for(const lc_index *ix, int64_t nq, int32_t ef_max, int32_t S, con
   int ef_eff = ef_max > S ? ef_max : S;
   p.w_cap = (ef_eff + 63) / 64 * 64;
   // visited mode 1 keeps only a small LDS cache; mode 0 sizes its table from the pool
-  p.hash_bits = (sc && sc->hash_bits) ? sc->hash_bits : (sc && sc->visited == 1 ? 9 : auto_hash_bits(p.w_cap));
+  p.hash_bits = (sc && sc->hash_bits) ? sc->hash_bits
+              : (sc && sc->visited == 1 ? 9 : auto_hash_bits(p.w_cap, sc && sc->wide ? INT32_MAX : ix->v.n));
   p.lds_bytes = lds_bytes_for<M>(p.w_cap, p.hash_bits, lut_bytes);
   int per_cu = ix->lds_per_cu / p.lds_bytes;
   if (sc && sc->waves_per_cu > 0 && sc->waves_per_cu < per_cu) per_cu = sc->waves_per_cu;
@@ -457,19 +969,17 @@ bool valid_schedule(const lc_schedule *sc) {
   if (!sc) return true;
   if (sc->hash_bits != 0 && (sc->hash_bits < 9 || sc->hash_bits > 14)) return false;
   if (sc->prefetch < 0 || sc->prefetch > 1 || sc->queue < 0 || sc->queue > 1 || sc->waves_per_cu < 0) return false;
-  if (sc->visited < 0 || sc->visited > 1) return false;
+  if (sc->visited < 0 || sc->visited > 1 || sc->wide < 0 || sc->wide > 1) return false;
   return true;
 }
 
-const lc_schedule kDefaultSchedule = {0, 0, 0, 1, 1};
+const lc_schedule kDefaultSchedule = {0, 1, 0, 1, 0, 0};
 
 int list_cap_for(int w_cap) { return 16 * w_cap > 4096 ? 16 * w_cap : 4096; }
 
-// header, then per slot its bitset, then (visited mode 1) per slot its id list
-size_t ws_need(const WalkPlan &p, int64_t words, int vmode) {
-  size_t b = kHeaderBytes + size_t(p.grid) * size_t(words) * 4;
-  if (vmode == 1) b += size_t(p.grid) * size_t(list_cap_for(p.w_cap)) * 4;
-  return b;
+// header, then per slot its bitset, then per slot its id list
+size_t ws_need(const WalkPlan &p, int64_t words) {
+  return kHeaderBytes + size_t(p.grid) * size_t(words) * 4 + size_t(p.grid) * size_t(list_cap_for(p.w_cap)) * 4;
 }
 
 template <int M>
@@ -477,7 +987,7 @@ size_t ws_bytes_m(const lc_index *ix, int64_t nq, int32_t ef_max, int32_t S, con
   // sized for the smaller (fp16) table, which admits the most slots
   WalkPlan p = plan_for<M>(ix, nq, ef_max, S, sc, 2);
   const int64_t words = (int64_t(ix->v.n) + 31) / 32;
-  return ws_need(p, words, sc->visited);
+  return ws_need(p, words);
 }
 
 template <int M, typename T>
@@ -486,7 +996,7 @@ int launch_m(const lc_index *ix, const void *lut, const float *scale, int64_t nq
              int32_t *stats, void *ws, size_t ws_bytes, const lc_schedule *sc, hipStream_t st) {
   WalkPlan p = plan_for<M>(ix, nq, ef_max, S, sc, int(sizeof(T)));
   const int64_t words = (int64_t(ix->v.n) + 31) / 32;
-  if (ws_bytes < ws_need(p, words, sc->visited)) return LC_ENOSPC;
+  if (ws_bytes < ws_need(p, words)) return LC_ENOSPC;
   if (p.lds_bytes > ix->lds_per_cu) return LC_ENOTSUP;
   WalkArgs a;
   a.codes = ix->v.codes;
@@ -513,6 +1023,7 @@ int launch_m(const lc_index *ix, const void *lut, const float *scale, int64_t nq
   a.queue = sc->queue;
   a.vmode = sc->visited;
   a.list_cap = list_cap_for(p.w_cap);
+  a.tag_bits = sc->wide ? 0 : table_tag_bits(ix->v.n, p.hash_bits);
   a.counters = static_cast<uint32_t *>(ws);
   a.bits = reinterpret_cast<uint32_t *>(static_cast<char *>(ws) + kHeaderBytes);
   a.vlists = reinterpret_cast<int32_t *>(static_cast<char *>(ws) + kHeaderBytes +
@@ -522,10 +1033,14 @@ int launch_m(const lc_index *ix, const void *lut, const float *scale, int64_t nq
   a.cand_adc = cand_adc;
   a.cand_n = cand_n;
   a.stats = stats;
-  if (hipFuncSetAttribute(reinterpret_cast<const void *>(&walk_kernel<M, T>),
-                          hipFuncAttributeMaxDynamicSharedMemorySize, p.lds_bytes) != hipSuccess)
+  const void *fn = sc->visited == 1 ? reinterpret_cast<const void *>(&walk_cache_kernel<M, T>)
+                                    : reinterpret_cast<const void *>(&walk_kernel<M, T>);
+  if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, p.lds_bytes) != hipSuccess)
     return LC_EHIP;
-  hipLaunchKernelGGL((walk_kernel<M, T>), dim3(p.grid), dim3(64), p.lds_bytes, st, a);
+  if (sc->visited == 1)
+    hipLaunchKernelGGL((walk_cache_kernel<M, T>), dim3(p.grid), dim3(64), p.lds_bytes, st, a);
+  else
+    hipLaunchKernelGGL((walk_kernel<M, T>), dim3(p.grid), dim3(64), p.lds_bytes, st, a);
   return hipGetLastError() == hipSuccess ? LC_OK : LC_EHIP;
 }
 

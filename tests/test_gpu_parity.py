@@ -183,11 +183,11 @@ def test_single_node_index(torch):
     np.testing.assert_allclose(d.cpu().numpy()[:, 0], o["d"][:, 0], rtol=1e-5)
 
 
-SCHEDULES = [dict(hash_bits=9, prefetch=0, waves_per_cu=0, queue=0),   # small table: bitset overflow path
-             dict(hash_bits=9, prefetch=1, waves_per_cu=1, queue=1),
-             dict(hash_bits=14, prefetch=1, waves_per_cu=0, queue=1),
-             dict(hash_bits=0, prefetch=0, waves_per_cu=2, queue=1),
-             dict(hash_bits=11, prefetch=1, waves_per_cu=0, queue=0),
+SCHEDULES = [dict(hash_bits=9, prefetch=0, waves_per_cu=0, queue=0, visited=0),   # small table: full buckets
+             dict(hash_bits=9, prefetch=1, waves_per_cu=1, queue=1, visited=0, wide=1),
+             dict(hash_bits=14, prefetch=1, waves_per_cu=0, queue=1, visited=0),
+             dict(hash_bits=0, prefetch=0, waves_per_cu=2, queue=1, visited=0),
+             dict(hash_bits=11, prefetch=1, waves_per_cu=0, queue=0, visited=0, wide=1),
              dict(hash_bits=9, prefetch=0, waves_per_cu=0, queue=1, visited=1),   # bitset + LDS cache
              dict(hash_bits=10, prefetch=1, waves_per_cu=0, queue=0, visited=1)]
 
@@ -220,8 +220,9 @@ def test_overflow_path_with_large_pool(torch):
     ix, db, q = oracle.build_workload(w, nthreads=4)
     gix = lc.Index.from_index(ix)
     o = ix.search(q, 2400, 64, 10)
-    for sd in (dict(hash_bits=9, prefetch=1, waves_per_cu=0, queue=1),
-               dict(hash_bits=14, prefetch=0, waves_per_cu=0, queue=0),
+    for sd in (dict(hash_bits=9, prefetch=1, waves_per_cu=0, queue=1, visited=0),
+               dict(hash_bits=9, prefetch=1, waves_per_cu=0, queue=1, visited=0, wide=1),
+               dict(hash_bits=14, prefetch=0, waves_per_cu=0, queue=0, visited=0),
                dict(hash_bits=9, prefetch=0, waves_per_cu=0, queue=1, visited=1)):
         sc = lc.schedule(**sd)
         ids, d, r = gix.query(torch.from_numpy(q), ef=2400, ef_max=2400, S=64, K=10, stats=True, sched=sc)
