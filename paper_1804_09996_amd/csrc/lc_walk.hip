@@ -39,6 +39,8 @@ namespace {
 
 using namespace lc;
 
+constexpr int kMergeScratch = 34;  // keys of merge scratch: up to 32 kept keys and a pad, 16-byte multiple
+
 struct WalkArgs {
   const uint8_t *codes;
   const int32_t *adj0, *up_base, *adj_up;
@@ -291,15 +293,6 @@ __device__ __forceinline__ bool vt_insert(const VTable &v, uint32_t b, uint32_t 
   }
 }
 
-// Values every lane of the wave holds alike, made visibly uniform to the
-// compiler (scalar registers and scalar branches).
-__device__ __forceinline__ int uni(int x) { return __builtin_amdgcn_readfirstlane(x); }
-__device__ __forceinline__ uint64_t uni64(uint64_t x) {
-  const uint32_t lo = uint32_t(__builtin_amdgcn_readfirstlane(int(uint32_t(x))));
-  const uint32_t hi = uint32_t(__builtin_amdgcn_readfirstlane(int(uint32_t(x >> 32))));
-  return (uint64_t(hi) << 32) | lo;
-}
-
 // Lowest set bits of a 128-bit lane mask, one at a time (-1 once empty).
 struct Pick2 {
   uint64_t lo, hi;
@@ -394,6 +387,143 @@ __device__ __forceinline__ int merge_few(uint64_t *W, uint64_t *Ks, int &nw, int
   return pos_min;
 }
 
+// Number of the first n entries of the sorted array A that are below x.
+__device__ __forceinline__ int count_below(const uint64_t *A, int n, int steps, uint64_t x) {
+  int lo = 0, len = n;
+  for (int i = 0; i < steps; ++i) {  // steps = bit length of n, the same on every lane
+    const int half = len >> 1;
+    const int mid = lo + half;
+    const bool go = len > 0 && A[mid < n ? mid : n - 1] < x;
+    lo = go ? mid + 1 : lo;
+    len = go ? len - half - 1 : half;
+  }
+  return lo;
+}
+
+// Merge of 9..32 kept keys: the same moves as merge_few, with the kept keys
+// ranked through a compacted copy in LDS (then overwritten by the sorted
+// keys) and counted by binary search.
+__device__ __forceinline__ int merge_many(uint64_t *W, uint64_t *Ks, int &nw, int efe, uint64_t k, bool keep,
+                                          uint64_t km, uint64_t ck, int lane, int &before_ck) {
+  const int nn = __popcll(km);
+  uint64_t *Kc = Ks;  // compacted, unsorted; read whole before the sorted keys replace it
+  const int ci = __builtin_amdgcn_mbcnt_hi(uint32_t(km >> 32), __builtin_amdgcn_mbcnt_lo(uint32_t(km), 0u));
+  if (keep) Kc[ci] = k;
+  if (lane == 0) Kc[nn] = kKeyMax;  // pads an odd count for the pairwise reads
+  wave_sync();
+  int rank = 0;
+  for (int i = 0; i < nn; i += 2) {
+    const uint64_t a0 = Kc[i], a1 = Kc[i + 1];
+    rank += (a0 < k ? 1 : 0) + (a1 < k ? 1 : 0);
+  }
+  wave_sync();
+  if (keep) Ks[rank] = k;
+  wave_sync();
+  const int steps = 32 - __clz(nn);
+  before_ck = __builtin_amdgcn_readfirstlane(count_below(Ks, nn, steps, ck));
+
+  int pos_min = efe;
+  for (int c = nw >> 6; c >= 0; --c) {
+    const int base = c << 6;
+    const int idx = base + lane;
+    const uint64_t v = idx < nw ? W[idx] : kKeyMax;
+    const uint64_t pv = idx < nw ? pure_key(v) : kKeyMax;
+    const uint64_t pp = (idx >= 1 && idx <= nw) ? pure_key(W[idx - 1]) : 0ull;
+    int cnt = count_below(Ks, nn, steps, pv);
+    int cprev = count_below(Ks, nn, steps, pp);
+    if (idx > nw) cnt = cprev = 0;
+    wave_sync();
+    if (idx < nw && cnt > 0 && idx + cnt < efe) W[idx + cnt] = v;
+    for (int t = cprev; t < cnt; ++t)
+      if (idx + t < efe) W[idx + t] = Ks[t];
+    const uint64_t m0 = __ballot(cprev == 0 && cnt > 0);
+    wave_sync();
+    if (__builtin_amdgcn_readfirstlane(cprev) == 0) {
+      if (m0) pos_min = base + __ffsll((unsigned long long)m0) - 1;
+      break;
+    }
+  }
+  nw = nw + nn < efe ? nw + nn : efe;
+  return pos_min;
+}
+
+// Links of the expanded entry c (lanes 0..31, nb) and of the next unexpanded
+// entry p (lanes 32..63 when `two`): test-and-set against the visited set,
+// codes and ADC keys, and whether p's expansion is the sequential walk's next
+// step (dual).  D, E and the bitset id list are updated; `fresh` marks the
+// keys that enter the merge (subject to the wmax filter).
+struct StepOut {
+  uint64_t k;
+  bool fresh, dual;
+};
+
+template <int M, typename T>
+__device__ __forceinline__ StepOut expand_links(const WalkArgs &a, const VTable &vt, uint32_t *bits, int32_t *vlist,
+                                                const T *lut, const float *sc, int32_t nb, bool lo, bool two,
+                                                uint64_t pk, int lane, int &D, int &E, int &vcount) {
+  // lanes 0..31 test-and-set c's links; lanes 32..63 look p's links up.
+  // One bucket read and at most one CAS settle almost every link; a full
+  // bucket or a lost CAS goes round the general path.
+  const bool act = nb >= 0;
+  uint32_t b, tag;
+  vt_locate(vt, act ? nb : 0, b, tag);
+  const uint4 s4 = reinterpret_cast<const uint4 *>(vt.t)[b];
+  bool hit;
+  int e;
+  vt_inspect(vt, s4, tag, hit, e);
+  hit = hit & act;
+  const bool ins = act & lo & !hit & (e >= 0);
+  bool ok = false;
+  if (ins) ok = vt_try_store(vt, b, e, tag, s4);
+  bool cand = lo ? ok : (act & !hit & (e >= 0));  // lanes 32..63: absent before this step
+  bool set_bit = false;
+  const bool rest = act & !hit & ((e < 0) | (ins & !ok));
+  if (__ballot(rest)) {
+    if (rest) {
+      if (lo) cand = vt_insert(vt, b, tag, nb, bits, set_bit);
+      else cand = bit_clear(bits, nb);  // the bucket is full: the bitset decides
+    }
+  }
+  D += __popcll(__ballot(lo && cand));
+
+  // codes and ADC keys of both halves' candidates
+  StepOut o;
+  o.k = kKeyMax;
+  if (cand) {
+    CodeRegs<M> cr;
+    cr.load(a.codes, a.code_stride, nb);
+    o.k = make_key(cr.adc(lut, sc), nb);
+  }
+
+  // p is the next expansion of the sequential walk iff no fresh key of c is below it
+  o.dual = two && __ballot(lo && cand && o.k < pk) == 0ull;
+  o.fresh = lo && cand;
+  if (o.dual) {
+    // p's absent links, inserted for real: one CAS at the slot the look-up
+    // saw free, the general path otherwise (a full bucket: the bitset)
+    const bool ins2 = !lo & cand & (e >= 0);
+    bool ok2 = false;
+    if (ins2) ok2 = vt_try_store(vt, b, e, tag, s4);
+    if (!lo) o.fresh = ok2;
+    const bool rest2 = !lo & cand & !ok2;
+    if (__ballot(rest2)) {
+      if (rest2) o.fresh = vt_insert(vt, b, tag, nb, bits, set_bit);
+    }
+    D += __popcll(__ballot(!lo && o.fresh));
+    E += 2;
+  } else {
+    E += 1;
+  }
+  // ids that went to the bitset, listed for clearing at the end of the query
+  const uint64_t sb = __ballot(set_bit);
+  if (sb) {
+    const int at = vcount + __popcll(sb & ((1ull << lane) - 1ull));
+    if (set_bit && at < a.list_cap) vlist[at] = nb;
+    vcount += __popcll(sb);
+  }
+  return o;
+}
+
 // Level-0 walk with the visited set in an LDS table (and the bitset for ids
 // whose home bucket is full), two expansions per step when the sequential
 // order allows it.
@@ -408,8 +538,8 @@ __global__ __launch_bounds__(64) void walk_kernel(WalkArgs a) {
   T *lut = reinterpret_cast<T *>(smem);
   float *sc = reinterpret_cast<float *>(smem + kLutBytes);
   uint64_t *W = reinterpret_cast<uint64_t *>(smem + kLutBytes + kScaleBytes);
-  uint64_t *Ks = W + a.w_cap;  // merge scratch: the kept keys, sorted
-  uint32_t *hash = reinterpret_cast<uint32_t *>(Ks + 16);
+  uint64_t *Ks = W + a.w_cap;  // merge scratch: the kept keys (compacted, then sorted)
+  uint32_t *hash = reinterpret_cast<uint32_t *>(Ks + kMergeScratch);
   const int H = 1 << a.hash_bits;  // table words
   VTable vt;
   vt.t = hash;
@@ -507,69 +637,11 @@ __global__ __launch_bounds__(64) void walk_kernel(WalkArgs a) {
         if (lane == 0) W[fu] = ck | kExpanded;
         const int32_t nb = col_ok && (lo || two) ? row : -1;
 
-        // lanes 0..31 test-and-set c's links; lanes 32..63 look p's links up.
-        // One bucket read and at most one CAS settle almost every link; a
-        // full bucket or a lost CAS goes round the general path.
-        const bool act = nb >= 0;
-        uint32_t b, tag;
-        vt_locate(vt, act ? nb : 0, b, tag);
-        const uint4 s4 = reinterpret_cast<const uint4 *>(hash)[b];
-        bool hit;
-        int e;
-        vt_inspect(vt, s4, tag, hit, e);
-        hit = hit & act;
-        const bool ins = act & lo & !hit & (e >= 0);
-        bool ok = false;
-        if (ins) ok = vt_try_store(vt, b, e, tag, s4);
-        bool cand = lo ? ok : (act & !hit & (e >= 0));  // lanes 32..63: absent before this step
-        bool set_bit = false;
-        const bool rest = act & !hit & ((e < 0) | (ins & !ok));
-        if (__ballot(rest)) {
-          if (rest) {
-            if (lo) cand = vt_insert(vt, b, tag, nb, bits, set_bit);
-            else cand = bit_clear(bits, nb);  // the bucket is full: the bitset decides
-          }
-        }
-        const uint64_t fc = __ballot(lo && cand);
-        D += __popcll(fc);
-        // codes and ADC keys of both halves' candidates
-        uint64_t k = kKeyMax;
-        if (cand) {
-          CodeRegs<M> cr;
-          cr.load(a.codes, a.code_stride, nb);
-          k = make_key(cr.adc(lut, sc), nb);
-        }
-
-        // p is the next expansion of the sequential walk iff no fresh key of c is below it
-        const bool dual = two && __ballot(lo && cand && k < pk) == 0ull;
-        bool fresh = lo && cand;
-        if (dual) {
-          // p's absent links, inserted for real: one CAS at the slot the look-up
-          // saw free, the general path otherwise (a full bucket: the bitset)
-          const bool ins2 = !lo & cand & (e >= 0);
-          bool ok2 = false;
-          if (ins2) ok2 = vt_try_store(vt, b, e, tag, s4);
-          if (!lo) fresh = ok2;
-          const bool rest2 = !lo & cand & !ok2;
-          if (__ballot(rest2)) {
-            if (rest2) fresh = vt_insert(vt, b, tag, nb, bits, set_bit);
-          }
-          const int nfp = __popcll(__ballot(!lo && fresh));
-          D += nfp;
-          E += 2;
-          if (lane == 0) W[pidx] = pk | kExpanded;
-        } else {
-          E += 1;
-        }
-        {
-          // ids that went to the bitset, listed for clearing at the end of the query
-          const uint64_t sb = __ballot(set_bit);
-          if (sb) {
-            const int at = vcount + __popcll(sb & ((1ull << lane) - 1ull));
-            if (set_bit && at < a.list_cap) vlist[at] = nb;
-            vcount += __popcll(sb);
-          }
-        }
+        const StepOut o = expand_links<M, T>(a, vt, bits, vlist, lut, sc, nb, lo, two, pk, lane, D, E, vcount);
+        const bool dual = o.dual;
+        const bool fresh = o.fresh;
+        const uint64_t k = o.k;
+        if (dual && lane == 0) W[pidx] = pk | kExpanded;
         wave_sync();
 
         const bool keep = fresh && k < wmax;
@@ -585,6 +657,8 @@ __global__ __launch_bounds__(64) void walk_kernel(WalkArgs a) {
             before_ck = readlane64(k, j) < ck ? 1 : 0;
           } else if (nn <= 8) {
             pos_min = merge_few(W, Ks, nw, efe, k, keep, km, ck, lane, before_ck);
+          } else if (nn <= 32) {
+            pos_min = merge_many(W, Ks, nw, efe, k, keep, km, ck, lane, before_ck);
           } else {
             pos_min = merge_kept(W, nw, efe, k, keep, km, ck, lane, before_ck);
           }
@@ -734,7 +808,7 @@ __global__ __launch_bounds__(64) void walk_cache_kernel(WalkArgs a) {
   T *lut = reinterpret_cast<T *>(smem);
   float *sc = reinterpret_cast<float *>(smem + kLutBytes);
   uint64_t *W = reinterpret_cast<uint64_t *>(smem + kLutBytes + kScaleBytes);
-  uint32_t *hash = reinterpret_cast<uint32_t *>(W + a.w_cap + 16);  // after the merge scratch
+  uint32_t *hash = reinterpret_cast<uint32_t *>(W + a.w_cap + kMergeScratch);  // after the merge scratch
   const int H = 1 << a.hash_bits;
   const int hshift = 32 - a.hash_bits;
   uint32_t *bits = a.bits + int64_t(blockIdx.x) * a.words;
@@ -920,7 +994,7 @@ constexpr size_t kHeaderBytes = 256;  // two queue counters, padded
 template <int M>
 int lds_bytes_for(int w_cap, int hash_bits, int lut_bytes) {
   const int scale_bytes = lut_bytes == 2 ? (M * 4 + 15) / 16 * 16 : 0;
-  return M * 256 * lut_bytes + scale_bytes + w_cap * 8 + 16 * 8 + (1 << hash_bits) * 4;
+  return M * 256 * lut_bytes + scale_bytes + w_cap * 8 + kMergeScratch * 8 + (1 << hash_bits) * 4;
 }
 
 // Tag width of a narrow visited table with 2^(hash_bits-2) buckets for ids
