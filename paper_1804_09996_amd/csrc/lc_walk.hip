@@ -331,117 +331,97 @@ __device__ __forceinline__ int merge_one(uint64_t *W, int &nw, int efe, uint64_t
   return pos;
 }
 
-// Merge of at most 8 kept keys (see merge_kept for the general case), with
-// VALU counting against the sorted kept keys broadcast from LDS.  Entries move
-// up by the number of kept keys below them; the kept keys of ranks
-// [kept below W[i-1], kept below W[i]) land just below entry i (or below the
-// end of W).  Returns the slot of the smallest kept key.
-__device__ __forceinline__ int merge_few(uint64_t *W, uint64_t *Ks, int &nw, int efe, uint64_t k, bool keep,
-                                         uint64_t km, uint64_t ck, int lane, int &before_ck) {
+// v moved up one lane across the whole wave; lane 0 receives `fill`.
+__device__ __forceinline__ int shr1(int v, int fill) {
+  return __builtin_amdgcn_update_dpp(fill, v, 0x138, 0xf, 0xf, false);  // wave_shr:1
+}
+
+// Merge of 2..32 kept keys (one per lane with `keep` in km, all unique, none
+// in W, each below the largest key of W when W is full) into the sorted pool
+// W[0..nw), keeping the best efe; nw is updated.  The kept keys are ranked
+// (broadcast one by one) and stored sorted in Ks.  Chunks of 64 entries move
+// from the top down: an entry moves up by the number of kept keys below it,
+// and the kept keys of ranks [below entry i-1, below entry i) land just
+// below entry i (slot nw acts as +inf).  Each chunk's counts come with the
+// next-lower chunk read one step ahead, whose top lane gives lane 0 its
+// predecessor's count; the walk stops below the smallest kept key.
+// Returns the slot of the smallest kept key.
+__device__ __forceinline__ int merge_keys(uint64_t *W, uint64_t *Ks, int &nw, int efe, uint64_t k, bool keep,
+                                          uint64_t km, int lane) {
   const int nn = __popcll(km);
-  // rank of each kept key among the kept keys, then the kept keys sorted in Ks
   int rank = 0;
   for (uint64_t mm = km; mm; mm &= mm - 1) {
     const uint64_t kj = readlane64(k, __ffsll((unsigned long long)mm) - 1);
     rank += kj < k ? 1 : 0;
   }
-  if (lane < 8) Ks[lane] = kKeyMax;
+  if (lane < 32) Ks[lane] = kKeyMax;
   wave_sync();
   if (keep) Ks[rank] = k;
   wave_sync();
-  uint64_t kv[8];
+  uint64_t kv[16];
 #pragma unroll
-  for (int j = 0; j < 8; ++j) kv[j] = Ks[j];
-  int bc = 0;
+  for (int j = 0; j < 16; ++j) kv[j] = Ks[j];
+  const bool mid = nn > 8, more = nn > 16;
+  // number of kept keys below x (the padding never counts), in four
+  // independent sums so that the compares overlap
+  auto below = [&](uint64_t x) {
+    int n0 = 0, n1 = 0, n2 = 0, n3 = 0;
 #pragma unroll
-  for (int j = 0; j < 8; ++j) bc += kv[j] < ck ? 1 : 0;
-  before_ck = __builtin_amdgcn_readfirstlane(bc);
-
-  int pos_min = efe;
-  for (int c = nw >> 6; c >= 0; --c) {
-    const int base = c << 6;
-    const int idx = base + lane;
-    // idx == nw is a sentinel above every kept key
-    const uint64_t v = idx < nw ? W[idx] : kKeyMax;
-    const uint64_t pv = idx < nw ? pure_key(v) : kKeyMax;
-    const uint64_t pp = (idx >= 1 && idx <= nw) ? pure_key(W[idx - 1]) : 0ull;
-    int cnt = 0, cprev = 0;
-#pragma unroll
-    for (int j = 0; j < 8; ++j) {
-      cnt += kv[j] < pv ? 1 : 0;
-      cprev += kv[j] < pp ? 1 : 0;
+    for (int j = 0; j < 8; j += 4) {
+      n0 += kv[j] < x ? 1 : 0;
+      n1 += kv[j + 1] < x ? 1 : 0;
+      n2 += kv[j + 2] < x ? 1 : 0;
+      n3 += kv[j + 3] < x ? 1 : 0;
     }
-    if (idx > nw) cnt = cprev = 0;
-    wave_sync();  // the chunk and its lower neighbours are in registers before anything moves
+    if (mid) {
+#pragma unroll
+      for (int j = 8; j < 16; j += 4) {
+        n0 += kv[j] < x ? 1 : 0;
+        n1 += kv[j + 1] < x ? 1 : 0;
+        n2 += kv[j + 2] < x ? 1 : 0;
+        n3 += kv[j + 3] < x ? 1 : 0;
+      }
+    }
+    if (more) {
+#pragma unroll
+      for (int j = 16; j < 32; j += 4) {
+        n0 += Ks[j] < x ? 1 : 0;
+        n1 += Ks[j + 1] < x ? 1 : 0;
+        n2 += Ks[j + 2] < x ? 1 : 0;
+        n3 += Ks[j + 3] < x ? 1 : 0;
+      }
+    }
+    return (n0 + n1) + (n2 + n3);
+  };
+  int c = nw >> 6;
+  int idx = (c << 6) + lane;
+  uint64_t v = idx < nw ? W[idx] : kKeyMax;
+  int cnt = idx < nw ? below(pure_key(v)) : nn;
+  int pos_min = efe;
+  for (; c >= 0; --c) {
+    // the next-lower chunk lies wholly below nw, and this chunk's writes never reach it
+    int cl = 0;
+    uint64_t vl = 0;
+    const int il = ((c - 1) << 6) + lane;
+    if (c > 0) {
+      vl = W[il];
+      cl = below(pure_key(vl));
+    }
+    const int fill = c > 0 ? __builtin_amdgcn_readlane(cl, 63) : 0;
+    const int cprev = shr1(cnt, fill);
+    wave_sync();  // reads of this chunk and the one below come before any write
     if (idx < nw && cnt > 0 && idx + cnt < efe) W[idx + cnt] = v;
     for (int t = cprev; t < cnt; ++t)
       if (idx + t < efe) W[idx + t] = Ks[t];
-    const uint64_t m0 = __ballot(cprev == 0 && cnt > 0);
+    const uint64_t m0 = __ballot(cprev == 0 && cnt > 0 && idx <= nw);
     wave_sync();
-    if (__builtin_amdgcn_readfirstlane(cprev) == 0) {  // nothing below this chunk moves
-      if (m0) pos_min = base + __ffsll((unsigned long long)m0) - 1;
+    if (fill == 0) {  // nothing below this chunk moves
+      if (m0) pos_min = (c << 6) + __ffsll((unsigned long long)m0) - 1;
       break;
     }
-  }
-  nw = nw + nn < efe ? nw + nn : efe;
-  return pos_min;
-}
-
-// Number of the first n entries of the sorted array A that are below x.
-__device__ __forceinline__ int count_below(const uint64_t *A, int n, int steps, uint64_t x) {
-  int lo = 0, len = n;
-  for (int i = 0; i < steps; ++i) {  // steps = bit length of n, the same on every lane
-    const int half = len >> 1;
-    const int mid = lo + half;
-    const bool go = len > 0 && A[mid < n ? mid : n - 1] < x;
-    lo = go ? mid + 1 : lo;
-    len = go ? len - half - 1 : half;
-  }
-  return lo;
-}
-
-// Merge of 9..32 kept keys: the same moves as merge_few, with the kept keys
-// ranked through a compacted copy in LDS (then overwritten by the sorted
-// keys) and counted by binary search.
-__device__ __forceinline__ int merge_many(uint64_t *W, uint64_t *Ks, int &nw, int efe, uint64_t k, bool keep,
-                                          uint64_t km, uint64_t ck, int lane, int &before_ck) {
-  const int nn = __popcll(km);
-  uint64_t *Kc = Ks;  // compacted, unsorted; read whole before the sorted keys replace it
-  const int ci = __builtin_amdgcn_mbcnt_hi(uint32_t(km >> 32), __builtin_amdgcn_mbcnt_lo(uint32_t(km), 0u));
-  if (keep) Kc[ci] = k;
-  if (lane == 0) Kc[nn] = kKeyMax;  // pads an odd count for the pairwise reads
-  wave_sync();
-  int rank = 0;
-  for (int i = 0; i < nn; i += 2) {
-    const uint64_t a0 = Kc[i], a1 = Kc[i + 1];
-    rank += (a0 < k ? 1 : 0) + (a1 < k ? 1 : 0);
-  }
-  wave_sync();
-  if (keep) Ks[rank] = k;
-  wave_sync();
-  const int steps = 32 - __clz(nn);
-  before_ck = __builtin_amdgcn_readfirstlane(count_below(Ks, nn, steps, ck));
-
-  int pos_min = efe;
-  for (int c = nw >> 6; c >= 0; --c) {
-    const int base = c << 6;
-    const int idx = base + lane;
-    const uint64_t v = idx < nw ? W[idx] : kKeyMax;
-    const uint64_t pv = idx < nw ? pure_key(v) : kKeyMax;
-    const uint64_t pp = (idx >= 1 && idx <= nw) ? pure_key(W[idx - 1]) : 0ull;
-    int cnt = count_below(Ks, nn, steps, pv);
-    int cprev = count_below(Ks, nn, steps, pp);
-    if (idx > nw) cnt = cprev = 0;
-    wave_sync();
-    if (idx < nw && cnt > 0 && idx + cnt < efe) W[idx + cnt] = v;
-    for (int t = cprev; t < cnt; ++t)
-      if (idx + t < efe) W[idx + t] = Ks[t];
-    const uint64_t m0 = __ballot(cprev == 0 && cnt > 0);
-    wave_sync();
-    if (__builtin_amdgcn_readfirstlane(cprev) == 0) {
-      if (m0) pos_min = base + __ffsll((unsigned long long)m0) - 1;
-      break;
-    }
+    idx = il;
+    v = vl;
+    cnt = cl;
   }
   nw = nw + nn < efe ? nw + nn : efe;
   return pos_min;
@@ -459,8 +439,9 @@ struct StepOut {
 
 template <int M, typename T>
 __device__ __forceinline__ StepOut expand_links(const WalkArgs &a, const VTable &vt, uint32_t *bits, int32_t *vlist,
-                                                const T *lut, const float *sc, int32_t nb, bool lo, bool two,
-                                                uint64_t pk, int lane, int &D, int &E, int &vcount) {
+                                                const T *lut, const float *sc, int32_t nb, const CodeRegs<M> &cr,
+                                                bool lo, bool two, uint64_t pk, int lane, int &D, int &E,
+                                                int &vcount) {
   // lanes 0..31 test-and-set c's links; lanes 32..63 look p's links up.
   // One bucket read and at most one CAS settle almost every link; a full
   // bucket or a lost CAS goes round the general path.
@@ -486,14 +467,10 @@ __device__ __forceinline__ StepOut expand_links(const WalkArgs &a, const VTable 
   }
   D += __popcll(__ballot(lo && cand));
 
-  // codes and ADC keys of both halves' candidates
+  // ADC keys of both halves' candidates, from the codes loaded at the start of the step
   StepOut o;
   o.k = kKeyMax;
-  if (cand) {
-    CodeRegs<M> cr;
-    cr.load(a.codes, a.code_stride, nb);
-    o.k = make_key(cr.adc(lut, sc), nb);
-  }
+  if (cand) o.k = make_key(cr.adc(lut, sc), nb);
 
   // p is the next expansion of the sequential walk iff no fresh key of c is below it
   o.dual = two && __ballot(lo && cand && o.k < pk) == 0ull;
@@ -636,8 +613,12 @@ __global__ __launch_bounds__(64) void walk_kernel(WalkArgs a) {
         const bool two = pidx >= 0;
         if (lane == 0) W[fu] = ck | kExpanded;
         const int32_t nb = col_ok && (lo || two) ? row : -1;
+        // the codes of every link, fetched while the visited set is probed (a
+        // link that is not fresh reads its code for nothing)
+        CodeRegs<M> cr;
+        cr.load(a.codes, a.code_stride, nb >= 0 ? nb : cid);
 
-        const StepOut o = expand_links<M, T>(a, vt, bits, vlist, lut, sc, nb, lo, two, pk, lane, D, E, vcount);
+        const StepOut o = expand_links<M, T>(a, vt, bits, vlist, lut, sc, nb, cr, lo, two, pk, lane, D, E, vcount);
         const bool dual = o.dual;
         const bool fresh = o.fresh;
         const uint64_t k = o.k;
@@ -648,22 +629,18 @@ __global__ __launch_bounds__(64) void walk_kernel(WalkArgs a) {
         const uint64_t km = __ballot(keep);
         int p0 = fu;
         if (km) {
-          int before_ck = 0;
           const int nn = __popcll(km);
           int pos_min;
           if (nn == 1) {
-            const int j = __ffsll((unsigned long long)km) - 1;
-            pos_min = merge_one(W, nw, efe, k, j, lane);
-            before_ck = readlane64(k, j) < ck ? 1 : 0;
-          } else if (nn <= 8) {
-            pos_min = merge_few(W, Ks, nw, efe, k, keep, km, ck, lane, before_ck);
+            pos_min = merge_one(W, nw, efe, k, __ffsll((unsigned long long)km) - 1, lane);
           } else if (nn <= 32) {
-            pos_min = merge_many(W, Ks, nw, efe, k, keep, km, ck, lane, before_ck);
+            pos_min = merge_keys(W, Ks, nw, efe, k, keep, km, lane);
           } else {
+            int before_ck = 0;
             pos_min = merge_kept(W, nw, efe, k, keep, km, ck, lane, before_ck);
           }
-          const int fu_new = fu + before_ck;
-          p0 = fu_new < pos_min ? fu_new : pos_min;
+          // unexpanded entries were at or above fu and only move up; new ones sit at or above pos_min
+          p0 = fu < pos_min ? fu : pos_min;
           wave_sync();
           wmax = nw == efe ? pure_key(W[nw - 1]) : kKeyMax;
         }
