@@ -139,7 +139,8 @@ int lc_search(const lc_index *ix, const void *lut, int lut_dtype, const float *l
  * short-lists, distances and (E, D) counts; only speed changes.
  *   hash_bits     log2 of the per-query LDS table of the visited set, in
  *                 4-byte words (9..14; 0 = automatic: 9 for visited mode 1,
- *                 else a table of about 8 ef_eff ids).
+ *                 else the largest table of 2^10..2^12 words that leaves 8
+ *                 query slots per compute unit, or 2^10).
  *   prefetch      visited mode 0 only: 1 = at the start of every step, load
  *                 the adjacency rows of the two unexpanded entries that follow
  *                 the two being expanded (used at the next step when they

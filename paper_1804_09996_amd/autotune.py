@@ -23,13 +23,11 @@ def candidates(ef_max: int, S: int) -> list:
     """Grid of schedules: where the visited set lives (LDS table, or workspace
     bitset behind an LDS cache), the LDS table size and id width, prefetch;
     always the queue."""
-    w_cap = (max(ef_max, S) + 63) // 64 * 64
-    base_bits = max(9, min(13, (4 * w_cap - 1).bit_length()))  # a table of ~8 ef_eff ids (16-bit tags)
-    out = []
-    for hb in sorted({max(9, base_bits - 1), base_bits, min(14, base_bits + 1)}):
+    out = [schedule(hash_bits=0, prefetch=1, waves_per_cu=0, queue=1, visited=0)]  # the library's own choice
+    for hb in (9, 10, 11, 12):
         out.append(schedule(hash_bits=hb, prefetch=1, waves_per_cu=0, queue=1, visited=0))
-    out.append(schedule(hash_bits=base_bits, prefetch=0, waves_per_cu=0, queue=1, visited=0))
-    out.append(schedule(hash_bits=min(14, base_bits + 1), prefetch=1, waves_per_cu=0, queue=1, visited=0, wide=1))
+    out.append(schedule(hash_bits=11, prefetch=0, waves_per_cu=0, queue=1, visited=0))
+    out.append(schedule(hash_bits=12, prefetch=1, waves_per_cu=0, queue=1, visited=0, wide=1))
     out.append(schedule(hash_bits=9, prefetch=0, waves_per_cu=0, queue=1, visited=1))
     return out
 

@@ -984,15 +984,15 @@ int table_tag_bits(int32_t n, int hash_bits) {
   return t <= 15 ? t : 0;
 }
 
-// About 8 ids of table per pool slot (walks visit ~3-6 ef_eff nodes): narrow
-// tables hold two ids per word, wide ones one.
-int auto_hash_bits(int w_cap, int32_t n) {
-  int bits = 9;
-  while ((1 << bits) < 4 * w_cap && bits < 13) ++bits;  // narrow: 8 w_cap ids
-  if (table_tag_bits(n, bits)) return bits;
-  bits = 9;
-  while ((1 << bits) < 8 * w_cap && bits < 14) ++bits;  // wide
-  return bits;
+// The visited table is sized by LDS: the largest narrow table of 2^10..2^12
+// words that leaves 8 query slots per CU (a full bucket sends ids to the
+// global bitset, which the longest walks pay for at every step, so capacity
+// beats residency down to about 8 slots); else 2^10 words.
+template <int M>
+int auto_hash_bits(int w_cap, int32_t n, int lut_bytes, int lds_per_cu) {
+  for (int hb = 12; hb >= 10; --hb)
+    if (table_tag_bits(n, hb) && lds_per_cu / lds_bytes_for<M>(w_cap, hb, lut_bytes) >= 8) return hb;
+  return table_tag_bits(n, 10) || !table_tag_bits(n, 11) ? 10 : 11;
 }
 
 template <int M>
@@ -1003,7 +1003,9 @@ WalkPlan plan_for(const lc_index *ix, int64_t nq, int32_t ef_max, int32_t S, con
   p.w_cap = (ef_eff + 63) / 64 * 64;
   // visited mode 1 keeps only a small LDS cache; mode 0 sizes its table from the pool
   p.hash_bits = (sc && sc->hash_bits) ? sc->hash_bits
-              : (sc && sc->visited == 1 ? 9 : auto_hash_bits(p.w_cap, sc && sc->wide ? INT32_MAX : ix->v.n));
+              : (sc && sc->visited == 1 ? 9
+                                        : auto_hash_bits<M>(p.w_cap, sc && sc->wide ? INT32_MAX : ix->v.n, lut_bytes,
+                                                            ix->lds_per_cu));
   p.lds_bytes = lds_bytes_for<M>(p.w_cap, p.hash_bits, lut_bytes);
   int per_cu = ix->lds_per_cu / p.lds_bytes;
   if (sc && sc->waves_per_cu > 0 && sc->waves_per_cu < per_cu) per_cu = sc->waves_per_cu;
@@ -1035,10 +1037,11 @@ size_t ws_need(const WalkPlan &p, int64_t words) {
 
 template <int M>
 size_t ws_bytes_m(const lc_index *ix, int64_t nq, int32_t ef_max, int32_t S, const lc_schedule *sc) {
-  // sized for the smaller (fp16) table, which admits the most slots
-  WalkPlan p = plan_for<M>(ix, nq, ef_max, S, sc, 2);
+  // enough for either table type
   const int64_t words = (int64_t(ix->v.n) + 31) / 32;
-  return ws_need(p, words);
+  const size_t a = ws_need(plan_for<M>(ix, nq, ef_max, S, sc, 2), words);
+  const size_t b = ws_need(plan_for<M>(ix, nq, ef_max, S, sc, 4), words);
+  return a > b ? a : b;
 }
 
 template <int M, typename T>
