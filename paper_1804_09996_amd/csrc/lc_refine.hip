@@ -79,23 +79,36 @@ template <int M, int DSUB, int CS, typename CT, bool BF16W>
 __device__ __forceinline__ float part_dist(const RefineArgs &a, const CT *C, const float *yv, int32_t id,
                                            int part) {
   constexpr int U = M / 4;
+  constexpr int B = CS >= 64 ? 3 : CS >= 32 ? 4 : 6;  // rows in flight: their ids, then their code rows, then the sums
   float acc[U * DSUB];
 #pragma unroll
   for (int t = 0; t < U * DSUB; ++t) acc[t] = 0.f;
   const float *bw = a.beta + size_t(a.beta_idx[id]) * (a.k_reg + 1);
   const int32_t *links = a.adj0 + int64_t(id) * a.deg0;
-  for (int j = 0; j <= a.k_reg; ++j) {
-    const int32_t g = j == 0 ? id : links[j - 1];
-    if (g < 0 || g >= a.n) continue;  // a missing link is a zero vector
-    const float w = BF16W ? round_bf16(bw[j]) : bw[j];
-    CodeRow<CS> row;
-    row.load(a.codes + size_t(g) * CS);
+  for (int j0 = 0; j0 <= a.k_reg; j0 += B) {
+    int32_t g[B];
+    float wj[B];
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int s = part + 4 * u;
-      const int base = (s * 256 + int(row.byte(s))) * DSUB;
+    for (int t = 0; t < B; ++t) {
+      const int j = j0 + t;
+      const int32_t gj = j == 0 ? id : (j <= a.k_reg ? links[j - 1] : -1);
+      const bool ok = j <= a.k_reg && gj >= 0 && gj < a.n;  // a missing link is a zero vector
+      g[t] = ok ? gj : id;
+      wj[t] = ok ? (BF16W ? round_bf16(bw[j]) : bw[j]) : 0.f;
+    }
+    CodeRow<CS> row[B];
 #pragma unroll
-      for (int t = 0; t < DSUB; ++t) acc[u * DSUB + t] += w * cval(C, base + t);
+    for (int t = 0; t < B; ++t) row[t].load(a.codes + size_t(g[t]) * CS);
+    // a row past k or a missing link has weight 0: it adds exact zeros
+#pragma unroll
+    for (int t = 0; t < B; ++t) {
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int s = part + 4 * u;
+        const int base = (s * 256 + int(row[t].byte(s))) * DSUB;
+#pragma unroll
+        for (int q = 0; q < DSUB; ++q) acc[u * DSUB + q] += wj[t] * cval(C, base + q);
+      }
     }
   }
   float e = 0.f;
@@ -362,9 +375,12 @@ int lc_launch_refine(const lc_index *ix, const float *q, int64_t nq, const int32
   const RefineArgs a = make_args(ix, q, nq, cand_ids, cand_n, S, K, out_ids, out_d);
   const int m = ix->v.m, ds = ix->dsub;
   const bool bf = precision == LC_REFINE_BF16_RESCORE;
+  // when the re-score covers the whole short-list (2K >= S) the first pass decides nothing: every
+  // candidate's distance is the float32 one and all are sorted by it, which is the plain kernel
+  const bool bf_pass = bf && a.K2 < S;
 #define SHAPE(MM, DS, CSS)                                                                              \
   if (m == MM && ds == DS)                                                                              \
-    return bf ? launch_spec<MM, DS, CSS, uint16_t>(ix, a, st) : launch_spec<MM, DS, CSS, float>(ix, a, st);
+    return bf_pass ? launch_spec<MM, DS, CSS, uint16_t>(ix, a, st) : launch_spec<MM, DS, CSS, float>(ix, a, st);
   SHAPE(8, 2, 8)
   SHAPE(8, 4, 8)
   SHAPE(8, 12, 8)
