@@ -265,6 +265,8 @@ def main():
     ap.add_argument("--loads", default="0.5,0.8", help="offered loads as fractions of saturation (serving form)")
     ap.add_argument("--cache", default=os.environ.get("LC_INDEX_CACHE", os.path.join("/tmp", "lc_index_cache")))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--streams", type=int, default=3,
+                    help="streams that consecutive steps alternate on (1 = each step runs alone)")
     ap.add_argument("--precision", choices=("f32", "f16", "f16+bf16"), default="f32",
                     help="form timed by --form plain (default: the plain fp32 path)")
     ap.add_argument("--ef", type=int, default=0, help="efSearch for --form plain (default: the workload's)")
@@ -309,42 +311,64 @@ def main():
     FORMS = {"f32": (lc.LC_LUT_F32, lc.LC_REFINE_F32), "f16": (lc.LC_LUT_F16, lc.LC_REFINE_F32),
              "f16+bf16": (lc.LC_LUT_F16, lc.LC_REFINE_BF16_RESCORE)}
 
-    def run(form, ef, S, steps, warmup):
+    def run(form, ef, S, steps, warmup, streams=None):
+        """Time `steps` steps.  With several streams, step k runs on stream
+        k mod streams with its own workspace and outputs, so consecutive
+        batches overlap on the device (a batch's walk tail is filled by the
+        next batch's walk, as in continuous batching); per-kernel times then
+        come from a separate one-stream run, in which launches do not overlap."""
+        streams = streams or args.streams
         lut_dt, ref_p = FORMS[form]
-        gix.workspace(nq, max(ef, S), S)
+        if streams == 1:
+            lanes = [(torch.cuda.current_stream(dev), gix.workspace(nq, max(ef, S), S))]
+        else:
+            nb = gix.workspace_bytes(nq, max(ef, S), S)
+            lanes = [(torch.cuda.Stream(device=dev), torch.zeros(nb, dtype=torch.uint8, device=dev))
+                     for _ in range(streams)]
+        torch.cuda.synchronize()
 
-        def step(ev=None):
-            if ev is not None:
-                ev[0].record()
-            lut, scale = gix.build_lut(qd, lut_dt)
-            if ev is not None:
-                ev[1].record()
-            r = gix.search(lut, scale, ef=None, ef_max=ef, S=S, stats=True)
-            if ev is not None:
-                ev[2].record()
-            ids, d = gix.refine(qd, r.cand_ids, r.cand_n, K, ref_p)
-            if ev is not None:
-                ev[3].record()
+        def step(k, ev=None):
+            st_, ws = lanes[k % len(lanes)]
+            with torch.cuda.stream(st_):
+                if ev is not None:
+                    ev[0].record()
+                lut, scale = gix.build_lut(qd, lut_dt)
+                if ev is not None:
+                    ev[1].record()
+                r = gix.search(lut, scale, ef=None, ef_max=ef, S=S, stats=True, ws=ws)
+                if ev is not None:
+                    ev[2].record()
+                ids, d = gix.refine(qd, r.cand_ids, r.cand_n, K, ref_p)
+                if ev is not None:
+                    ev[3].record()
             return ids, d, r
 
-        for _ in range(warmup):
-            step()
+        for k in range(max(warmup, streams)):  # every stream's buffers exist before the timed steps
+            step(k)
         evs = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(steps)]
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for k in range(steps):
-            ids, d, r = step(evs[k])
+            ids, d, r = step(k, evs[k])
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
         kern = np.array([[evs[k][j].elapsed_time(evs[k][j + 1]) for j in range(3)] for k in range(steps)])
         step_ms = np.array([evs[k][0].elapsed_time(evs[k][3]) for k in range(steps)])
         ids_np = ids.cpu().numpy()
         st = r.stats.cpu().numpy()
-        return {"precision": form, "ef": ef, "S": S, "qps": nq * steps / wall, "ms_per_step": wall / steps * 1e3,
-                "kernels_ms": dict(zip(("build_lut", "walk", "refine"), kern.mean(0).tolist())),
-                "step_ms_p50": float(np.percentile(step_ms, 50)), "step_ms_p99": float(np.percentile(step_ms, 99)),
-                "recall": {f"R@{r_}": recall(ids_np, gt, r_) for r_ in (1, 10, 100) if r_ <= K},
-                "ids": ids_np, "d": d.cpu().numpy(), "stats": st, "cand_n": r.cand_n.cpu().numpy()}
+        out = {"precision": form, "ef": ef, "S": S, "streams": streams, "qps": nq * steps / wall,
+               "ms_per_step": wall / steps * 1e3,
+               "step_ms_p50": float(np.percentile(step_ms, 50)), "step_ms_p99": float(np.percentile(step_ms, 99)),
+               "recall": {f"R@{r_}": recall(ids_np, gt, r_) for r_ in (1, 10, 100) if r_ <= K},
+               "ids": ids_np, "d": d.cpu().numpy(), "stats": st, "cand_n": r.cand_n.cpu().numpy()}
+        if streams == 1:
+            out["kernels_ms"] = dict(zip(("build_lut", "walk", "refine"), kern.mean(0).tolist()))
+        else:
+            one = run(form, ef, S, max(3, steps // 2), 1, streams=1)
+            assert np.array_equal(one["ids"], ids_np) and np.array_equal(one["stats"], st)
+            out["kernels_ms"] = one["kernels_ms"]
+            out["one_stream"] = {k_: one[k_] for k_ in ("qps", "ms_per_step", "step_ms_p50", "step_ms_p99")}
+        return out
 
     # the plain path at the workload's own operating point defines the target recall
     plain = run("f32", w.ef, w.shortlist, args.steps, args.warmup)
@@ -403,8 +427,11 @@ def main():
         "config": {"workload": f"{w.name}: N={w.n} d={w.d} Gaussian mixture ({w.n_comp} components, "
                                f"L2-normalised), PQ {w.m}x256, level-0 degree {w.deg0}, k={w.k_reg}, "
                                f"beta codebook {w.n_beta}, top-{K}, {nq} queries per step; {form}; "
-                               f"efSearch {head['ef']}, shortlist {S_h}",
-                   "queries_per_step": nq, "ef": head["ef"], "shortlist": S_h,
+                               f"efSearch {head['ef']}, shortlist {S_h}; " +
+                               (f"consecutive steps alternate over {args.streams} streams (each with its own workspace "
+                                f"and outputs), so one batch's walk tail overlaps the next batch" if args.streams > 1
+                                else "each step runs alone"),
+                   "queries_per_step": nq, "ef": head["ef"], "shortlist": S_h, "streams": args.streams,
                    "index": f"built on the host by liblc_build from seed {w.seed}"},
         "roofline": {"bound": "hbm", "achieved": wb / (wm * 1e-3) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": wb / (wm * 1e-3) / 1e9 / HBM_PEAK_GBS, "traffic": traffic,
@@ -415,15 +442,18 @@ def main():
                                      "walk": wb / (wm * 1e-3) / 1e9,
                                      "refine": rb / (head["kernels_ms"]["refine"] * 1e-3) / 1e9},
         "recall": head["recall"], "batch_latency_ms": {"p50": head["step_ms_p50"], "p99": head["step_ms_p99"]},
+        "one_stream": head.get("one_stream"),
         "walk_mean_E": float(E.mean()), "walk_mean_D": float(D.mean()),
         "plain_fp32": {"qps": plain["qps"], "recall": plain["recall"], "ef": plain["ef"], "S": plain["S"],
-                       "kernels_ms": plain["kernels_ms"]},
+                       "kernels_ms": plain["kernels_ms"], "one_stream": plain.get("one_stream")},
     }
     if curves:
         out["target_R@1"] = r_target
         out["curves"] = {f: [{"ef": c["ef"], "S": c["S"], "qps": c["qps"], "R@1": c["recall"]["R@1"],
                               "R@10": c["recall"].get("R@10"), "walk_ms": c["kernels_ms"]["walk"],
-                              "refine_ms": c["kernels_ms"]["refine"]} for c in cs] for f, cs in curves.items()}
+                              "refine_ms": c["kernels_ms"]["refine"],
+                              "qps_one_stream": (c.get("one_stream") or {}).get("qps")} for c in cs]
+                         for f, cs in curves.items()}
         out["qps_at_target_R@1"] = {f: (max((c["qps"] for c in cs if c["recall"]["R@1"] >= r_target), default=None))
                                     for f, cs in curves.items()}
     if not args.no_cpu_baseline:

@@ -200,6 +200,11 @@ int lc_refine(const lc_index *ix, const float *q, int64_t nq, const int32_t *can
 
 const char *lc_strerror(int code);
 
+/* Identity of the build: a hex sha1 over this header and the library's
+ * sources, fixed at compile time, so that a binding can refuse a library
+ * built from other sources (e.g. with another layout of lc_index_view). */
+const char *lc_build_id(void);
+
 #ifdef __cplusplus
 }
 #endif

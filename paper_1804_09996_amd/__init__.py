@@ -70,6 +70,12 @@ def lib():
             raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_1804_09996_amd.build_ext` "
                               "(or __graft_entry__.build()); there is no CPU fallback")
         L = C.CDLL(LIB_PATH)
+        L.lc_build_id.restype = C.c_char_p
+        from .build_ext import source_id
+        built, here = L.lc_build_id().decode(), source_id()
+        if built != here:
+            raise ImportError(f"{LIB_PATH} was built from other sources (build {built[:12]}, sources {here[:12]}): "
+                              "rebuild it with `python -m paper_1804_09996_amd.build_ext`")
         p, i32, i64, sz = C.c_void_p, C.c_int32, C.c_int64, C.c_size_t
         L.lc_strerror.argtypes = [C.c_int]
         L.lc_strerror.restype = C.c_char_p
@@ -89,7 +95,7 @@ def lib():
 
 
 def exported_symbols():
-    return ["lc_strerror", "lc_index_bind", "lc_index_release", "lc_build_lut", "lc_search_workspace_bytes",
+    return ["lc_build_id", "lc_strerror", "lc_index_bind", "lc_index_release", "lc_build_lut", "lc_search_workspace_bytes",
             "lc_search", "lc_refine", "lc_search_workspace_bytes_sched", "lc_search_sched"]
 
 
@@ -199,17 +205,23 @@ class Index:
                                   _stream(torch, self.device)), "lc_build_lut")
         return lut, scale
 
+    def workspace_bytes(self, nq: int, ef_max: int, S: int, sched: Optional[Schedule] = None) -> int:
+        return int(lib().lc_search_workspace_bytes_sched(self.handle, max(nq, 1), ef_max, S,
+                                                         None if sched is None else C.byref(sched)))
+
     def workspace(self, nq: int, ef_max: int, S: int, sched: Optional[Schedule] = None):
         torch = self.torch
-        need = lib().lc_search_workspace_bytes_sched(self.handle, max(nq, 1), ef_max, S,
-                                                     None if sched is None else C.byref(sched))
+        need = self.workspace_bytes(nq, ef_max, S, sched)
         if self._ws is None or self._ws.numel() < need:
             self._ws = torch.zeros(max(need, 1), dtype=torch.uint8, device=self.device)
         return self._ws
 
     def search(self, lut, scale=None, ef=None, ef_max: int = 64, S: int = 64, stats: bool = True,
                lut_dtype: Optional[int] = None, sched: Optional[Schedule] = None, order=None,
-               out: Optional[SearchResult] = None) -> SearchResult:
+               out: Optional[SearchResult] = None, ws=None) -> SearchResult:
+        """``ws``: a zero-filled uint8 device tensor of at least
+        ``workspace_bytes(...)`` bytes, or None for the index's own (searches
+        that may overlap on different streams need one each)."""
         torch = self.torch
         nq = lut.shape[0]
         if lut_dtype is None:
@@ -226,7 +238,10 @@ class Index:
             cand_adc = torch.empty((nq, S), dtype=torch.float32, device=self.device)
             cand_n = torch.empty(nq, dtype=torch.int32, device=self.device)
             st = torch.empty((nq, 2), dtype=torch.int32, device=self.device) if stats else None
-        ws = self.workspace(nq, ef_max, S, sched)
+        if ws is None:
+            ws = self.workspace(nq, ef_max, S, sched)
+        elif ws.numel() < self.workspace_bytes(nq, ef_max, S, sched):
+            raise LCError(LC_ENOSPC, "lc_search")
         if sched is None and order is None:
             rc = lib().lc_search(self.handle, _ptr(lut), lut_dtype, _ptr(scale), nq, _ptr(ef_t), ef_max, S,
                                  _ptr(cand_ids), _ptr(cand_adc), _ptr(cand_n), _ptr(st), _ptr(ws), ws.numel(),

@@ -5,6 +5,7 @@
 * ``liblc_build.so`` — the host-side index builder declared in
                        include/lc_build.h (g++, no GPU code).
 """
+import hashlib
 import os
 import subprocess
 import sys
@@ -21,6 +22,19 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("LC_OFFLOAD_ARCH", "gfx950")
 
 
+def source_id() -> str:
+    """sha1 over the sources liblc.so is built from (include/lc.h and every
+    file under csrc/ except the host builder), in name order."""
+    h = hashlib.sha1()
+    files = [os.path.join(INCLUDE, "lc.h")] + sorted(
+        os.path.join(CSRC, f) for f in os.listdir(CSRC)
+        if f.endswith((".hip", ".h")) and f not in BUILD_SOURCES)
+    for f in files:
+        h.update(os.path.basename(f).encode())
+        h.update(open(f, "rb").read())
+    return h.hexdigest()
+
+
 def _run(cmd, verbose):
     if verbose:
         print(" ".join(cmd), flush=True)
@@ -33,7 +47,7 @@ def build_hip(verbose: bool = False, jobs: int = 4) -> str:
     os.makedirs(objdir, exist_ok=True)
     common = [HIPCC, "-O3", "-std=c++17", f"--offload-arch={ARCH}", "-fPIC", "-Wall",
               "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-              "-I", INCLUDE, "-I", CSRC]
+              "-I", INCLUDE, "-I", CSRC, f'-DLC_SOURCE_ID="{source_id()}"']
     objs, procs = [], []
     for src in HIP_SOURCES:
         obj = os.path.join(objdir, src.replace(".hip", ".o"))

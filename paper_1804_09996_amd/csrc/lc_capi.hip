@@ -15,6 +15,12 @@ bool supported_dsub(int ds) {
 
 extern "C" {
 
+#ifndef LC_SOURCE_ID
+#define LC_SOURCE_ID "unknown"
+#endif
+
+const char *lc_build_id(void) { return LC_SOURCE_ID; }
+
 const char *lc_strerror(int code) {
   switch (code) {
     case LC_OK: return "ok";

@@ -699,7 +699,6 @@ __global__ __launch_bounds__(64) void walk_kernel(WalkArgs a) {
             }
           }
         }
-        const int32_t pid = key_id(pk);
         fu = i0;
         pidx = i1;
         if (fu < nw) {
@@ -707,10 +706,10 @@ __global__ __launch_bounds__(64) void walk_kernel(WalkArgs a) {
           pk = k1;
           const int32_t nc = key_id(k0);
           const int32_t np = i1 >= 0 ? key_id(k1) : -1;
+          // only a dual step can meet the guess: when p was not expanded, a
+          // kept key of c lies below key(p) and comes next
           if (a.prefetch && dual && nc == pre0 && (np < 0 || np == pre1)) {
             row = nxt;  // the guessed pair came next
-          } else if (a.prefetch && !dual && nc == pid && (np < 0 || np == pre0)) {
-            row = __shfl_xor(lo ? nxt : row, 32);  // p came next: its row moves down, the guess's up
           } else {
             row = a.adj0[int64_t(lo || np < 0 ? nc : np) * a.deg0 + lcol];
           }

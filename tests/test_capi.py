@@ -91,3 +91,10 @@ def test_calls_reject_bad_arguments_before_launch(L):
     assert L.lc_search(None, p, 0, None, 1, None, 8, 8, p, p, p, None, p, 1, None) == lc.LC_EINVAL
     assert L.lc_refine(None, p, 1, p, p, 8, 8, 0, p, p, None) == lc.LC_EINVAL
     assert L.lc_search_workspace_bytes(None, 1, 8, 8) == 0
+
+
+def test_library_is_built_from_these_sources(L):
+    # a library built from other sources (another lc_index_view layout, an
+    # older kernel) must never be loaded
+    from paper_1804_09996_amd import build_ext
+    assert L.lc_build_id().decode() == build_ext.source_id()
