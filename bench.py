@@ -34,6 +34,14 @@ def walk_bytes(w, E, D, S):
     return float(nq * (4 * w.m * 256 + 8 * S + 12) + 4 * w.deg0 * E.sum() + w.m * D.sum())
 
 
+def walk_kernel_name(m, precision, ef, S):
+    """The walk kernel the default schedule launches: the pool in registers up
+    to 128 entries, in LDS beyond."""
+    t = "half" if precision != "f32" else "float"
+    w_cap = -(-max(ef, S) // 64) * 64
+    return f"walk_reg_kernel<{m},{t},2>" if w_cap <= 128 else f"walk_kernel<{m},{t}>"
+
+
 def refine_bytes(w, cand_n, K):
     """Per candidate: its beta index (1), k links (4k), k+1 codes (m(k+1));
     per query the output (8K)."""
@@ -435,7 +443,7 @@ def main():
                    "index": f"built on the host by liblc_build from seed {w.seed}"},
         "roofline": {"bound": "hbm", "achieved": wb / (wm * 1e-3) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": wb / (wm * 1e-3) / 1e9 / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": f"walk_kernel<{w.m},{'half' if f16 else 'float'}>",
+                     "kernel": walk_kernel_name(w.m, head["precision"], head["ef"], S_h),
                      "algorithmic_bytes_per_launch": wb},
         "kernels_ms": head["kernels_ms"],
         "kernels_GBps_algorithmic": {"build_lut": lb / (head["kernels_ms"]["build_lut"] * 1e-3) / 1e9,

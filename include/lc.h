@@ -166,9 +166,13 @@ int lc_search(const lc_index *ix, const void *lut, int lut_dtype, const float *l
  *                 per bucket); 0 = 16-bit tags (eight per bucket, twice the
  *                 ids in the same LDS) whenever ids below n fit a tag, which
  *                 is when n <= 2^(hash_bits + 13).
- * The default schedule (sched = NULL, and lc_search) is {0, 1, 0, 1, 0, 0}. */
+ *   pool          visited mode 0 only: 0 = the pool W lives in registers when
+ *                 it has at most 128 entries (max(ef_max, S) <= 128; the scan
+ *                 is a ballot, kept keys are merged by bitonic networks), in
+ *                 LDS otherwise; 1 = always in LDS.
+ * The default schedule (sched = NULL, and lc_search) is {0, 1, 0, 1, 0, 0, 0}. */
 typedef struct {
-  int32_t hash_bits, prefetch, waves_per_cu, queue, visited, wide;
+  int32_t hash_bits, prefetch, waves_per_cu, queue, visited, wide, pool;
 } lc_schedule;
 
 /* Workspace bytes for lc_search_sched with schedule `sched` (NULL = default). */

@@ -48,18 +48,19 @@ class Schedule(C.Structure):
     """Launch schedule of the walk (lc_schedule); every schedule gives the
     same results."""
     _fields_ = [("hash_bits", C.c_int32), ("prefetch", C.c_int32), ("waves_per_cu", C.c_int32),
-                ("queue", C.c_int32), ("visited", C.c_int32), ("wide", C.c_int32)]
+                ("queue", C.c_int32), ("visited", C.c_int32), ("wide", C.c_int32), ("pool", C.c_int32)]
 
     def __repr__(self):
         return (f"Schedule(hash_bits={self.hash_bits}, prefetch={self.prefetch}, "
-                f"waves_per_cu={self.waves_per_cu}, queue={self.queue}, visited={self.visited}, wide={self.wide})")
+                f"waves_per_cu={self.waves_per_cu}, queue={self.queue}, visited={self.visited}, wide={self.wide}, "
+                f"pool={self.pool})")
 
     def as_dict(self):
         return {k: int(getattr(self, k)) for k, _ in self._fields_}
 
 
-def schedule(hash_bits=0, prefetch=1, waves_per_cu=0, queue=1, visited=0, wide=0) -> Schedule:
-    return Schedule(hash_bits, prefetch, waves_per_cu, queue, visited, wide)
+def schedule(hash_bits=0, prefetch=1, waves_per_cu=0, queue=1, visited=0, wide=0, pool=0) -> Schedule:
+    return Schedule(hash_bits, prefetch, waves_per_cu, queue, visited, wide, pool)
 
 
 def lib():

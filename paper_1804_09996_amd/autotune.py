@@ -21,9 +21,12 @@ DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "lc_autotune.jso
 
 def candidates(ef_max: int, S: int) -> list:
     """Grid of schedules: where the visited set lives (LDS table, or workspace
-    bitset behind an LDS cache), the LDS table size and id width, prefetch;
-    always the queue."""
+    bitset behind an LDS cache), the LDS table size and id width, prefetch,
+    the pool in registers or in LDS (pools up to 128 entries); always the
+    queue."""
     out = [schedule(hash_bits=0, prefetch=1, waves_per_cu=0, queue=1, visited=0)]  # the library's own choice
+    if max(ef_max, S) <= 128:
+        out.append(schedule(hash_bits=0, prefetch=1, waves_per_cu=0, queue=1, visited=0, pool=1))
     for hb in (9, 10, 11, 12):
         out.append(schedule(hash_bits=hb, prefetch=1, waves_per_cu=0, queue=1, visited=0))
     out.append(schedule(hash_bits=11, prefetch=0, waves_per_cu=0, queue=1, visited=0))

@@ -33,6 +33,8 @@
 // still the next two unexpanded entries.
 #include <hip/hip_fp16.h>
 
+#include <type_traits>
+
 #include "lc_internal.h"
 
 namespace {
@@ -427,6 +429,194 @@ __device__ __forceinline__ int merge_keys(uint64_t *W, uint64_t *Ks, int &nw, in
   return pos_min;
 }
 
+// ---------------------------------------------------------------------------
+// The pool held in registers (pools of up to 64 R entries): lane l of chunk c
+// holds entry 64 c + l, and entries at or past nw hold kKeyMax (whose expanded
+// flag keeps them out of every scan and whose key sorts last).  Entries
+// compare by key without the flag.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ bool key_lt(uint64_t a, uint64_t b) { return pure_key(a) < pure_key(b); }
+__device__ __forceinline__ uint64_t key_min(uint64_t a, uint64_t b) { return key_lt(b, a) ? b : a; }
+__device__ __forceinline__ uint64_t key_max(uint64_t a, uint64_t b) { return key_lt(b, a) ? a : b; }
+
+// The value of lane (lane ^ J), without the LDS crossbar: quad permutes for
+// J = 1, 2, row shifts for J = 4, 8, and the half-row / half-wave swaps of
+// gfx950 for J = 16, 32.
+template <int J>
+__device__ __forceinline__ uint32_t xor_lane(uint32_t v, int lane) {
+  if constexpr (J == 1) {
+    return uint32_t(__builtin_amdgcn_update_dpp(0, int(v), 0xB1, 0xf, 0xf, false));  // quad_perm [1,0,3,2]
+  } else if constexpr (J == 2) {
+    return uint32_t(__builtin_amdgcn_update_dpp(0, int(v), 0x4E, 0xf, 0xf, false));  // quad_perm [2,3,0,1]
+  } else if constexpr (J == 4 || J == 8) {
+    const uint32_t up = uint32_t(__builtin_amdgcn_update_dpp(0, int(v), 0x100 | J, 0xf, 0xf, false));  // row_shl:J
+    const uint32_t dn = uint32_t(__builtin_amdgcn_update_dpp(0, int(v), 0x110 | J, 0xf, 0xf, false));  // row_shr:J
+    return (lane & J) ? dn : up;
+  } else if constexpr (J == 16) {
+    const auto r = __builtin_amdgcn_permlane16_swap(v, v, false, false);
+    return (lane & 16) ? r[0] : r[1];
+  } else {
+    static_assert(J == 32, "xor distance");
+    const auto r = __builtin_amdgcn_permlane32_swap(v, v, false, false);
+    return (lane & 32) ? r[0] : r[1];
+  }
+}
+template <int J>
+__device__ __forceinline__ uint64_t xor_lane64(uint64_t v, int lane) {
+  const uint32_t lo = xor_lane<J>(uint32_t(v), lane), hi = xor_lane<J>(uint32_t(v >> 32), lane);
+  return (uint64_t(hi) << 32) | lo;
+}
+
+// Lane 63 - lane's value: each row of 16 mirrored, then rows r and 3 - r exchanged.
+__device__ __forceinline__ uint64_t reverse64(uint64_t v, int lane) {
+  const uint32_t lo = uint32_t(__builtin_amdgcn_update_dpp(0, int(uint32_t(v)), 0x140, 0xf, 0xf, false));
+  const uint32_t hi = uint32_t(__builtin_amdgcn_update_dpp(0, int(uint32_t(v >> 32)), 0x140, 0xf, 0xf, false));
+  return xor_lane64<16>(xor_lane64<32>((uint64_t(hi) << 32) | lo, lane), lane);
+}
+
+// Compare-exchange with the lane at xor-distance J: keep the smaller entry
+// when keep_min, else the larger.
+template <int J>
+__device__ __forceinline__ uint64_t cx(uint64_t v, bool keep_min, int lane) {
+  const uint64_t o = xor_lane64<J>(v, lane);
+  return keep_min == key_lt(o, v) ? o : v;
+}
+
+// A bitonic sequence over the 64 lanes, sorted ascending (distances J .. 1).
+template <int J = 32>
+__device__ __forceinline__ uint64_t bitonic_clean(uint64_t v, int lane) {
+  v = cx<J>(v, (lane & J) == 0, lane);
+  if constexpr (J > 1) return bitonic_clean<J / 2>(v, lane);
+  else return v;
+}
+
+// Two bitonic sequences sorted together, stage by stage (independent work).
+template <int J = 32>
+__device__ __forceinline__ void bitonic_clean2(uint64_t &a, uint64_t &b, int lane) {
+  const bool lo = (lane & J) == 0;
+  a = cx<J>(a, lo, lane);
+  b = cx<J>(b, lo, lane);
+  if constexpr (J > 1) bitonic_clean2<J / 2>(a, b, lane);
+}
+
+// Any 64 entries sorted ascending across the lanes: merges of sorted runs of
+// K / 2 into runs of K, K = 2 .. 64.
+template <int K = 2, int J = 1>
+__device__ __forceinline__ uint64_t bitonic_sort(uint64_t v, int lane) {
+  v = cx<J>(v, ((lane & J) == 0) == ((lane & K) == 0), lane);
+  if constexpr (J > 1) return bitonic_sort<K, J / 2>(v, lane);
+  else if constexpr (K < 64) return bitonic_sort<K * 2, K>(v, lane);
+  else return v;
+}
+
+// The pool's chunks as named registers (never an array, so that no access
+// can become an indexed one into private memory); R <= 2 are used.
+struct Pool {
+  uint64_t w0, w1;
+};
+template <int C>
+__device__ __forceinline__ uint64_t &chunk(Pool &p) {
+  static_assert(C >= 0 && C < 2, "chunk index");
+  if constexpr (C == 0) return p.w0;
+  else return p.w1;
+}
+
+// f(integral_constant<C>) for C = B, B+1, .., E-1 (ascending) or E-1 .. B (descending).
+template <int B, int E, typename F>
+__device__ __forceinline__ void for_chunks(F &&f) {
+  if constexpr (B < E) {
+    f(std::integral_constant<int, B>{});
+    for_chunks<B + 1, E>(f);
+  }
+}
+template <int B, int E, typename F>
+__device__ __forceinline__ void for_chunks_down(F &&f) {
+  if constexpr (B < E) {
+    f(std::integral_constant<int, E - 1>{});
+    for_chunks_down<B, E - 1>(f);
+  }
+}
+
+// Entry i of the pool (i uniform); the chunks come by value, so that the
+// choice between them is a choice between values, never between addresses.
+template <int R>
+__device__ __forceinline__ uint64_t entry_of(uint64_t w0, uint64_t w1, int i) {
+  return readlane64(R > 1 && (i >> 6) == 1 ? w1 : w0, i & 63);
+}
+template <int R>
+__device__ __forceinline__ uint64_t entry_at(const Pool &p, int i) {
+  return entry_of<R>(p.w0, p.w1, i);
+}
+
+// Sets the expanded flag of entry i (i uniform).
+template <int R>
+__device__ __forceinline__ void mark_expanded(Pool &p, int i, int lane) {
+  const bool here = lane == (i & 63);
+  for_chunks<0, R>([&](auto C) {
+    uint64_t &w = chunk<C>(p);
+    w = (here && (i >> 6) == C) ? (w | kExpanded) : w;
+  });
+}
+
+// Entries at or past efe are dropped.
+template <int R>
+__device__ __forceinline__ void truncate_pool(Pool &p, int efe, int lane) {
+  for_chunks<0, R>([&](auto C) {
+    uint64_t &w = chunk<C>(p);
+    w = (C << 6) + lane >= efe ? kKeyMax : w;
+  });
+}
+
+// One kept key kk (not in W, below the largest entry when W is full): the
+// entries above it move up one slot.
+template <int R>
+__device__ __forceinline__ void reg_insert_one(Pool &p, uint64_t kk, int efe, int lane) {
+  int pos = 0;
+  for_chunks<0, R>([&](auto C) { pos += __popcll(__ballot(key_lt(chunk<C>(p), kk))); });
+  for_chunks_down<0, R>([&](auto C) {
+    // entry 64 C + lane - 1, from the chunk below for lane 0 (read before that chunk changes)
+    uint64_t fill = kKeyMax;
+    if constexpr (C > 0) fill = readlane64(chunk<C - 1>(p), 63);
+    uint64_t &w = chunk<C>(p);
+    const uint32_t lo = uint32_t(__builtin_amdgcn_update_dpp(int(uint32_t(fill)), int(uint32_t(w)), 0x138, 0xf, 0xf,
+                                                             false));
+    const uint32_t hi = uint32_t(__builtin_amdgcn_update_dpp(int(uint32_t(fill >> 32)), int(uint32_t(w >> 32)),
+                                                             0x138, 0xf, 0xf, false));
+    const uint64_t up = (uint64_t(hi) << 32) | lo;
+    const int idx = (C << 6) + lane;
+    w = idx < pos ? w : (idx == pos ? kk : up);
+  });
+  truncate_pool<R>(p, efe, lane);
+}
+
+// Kept keys, sorted ascending (lane r holds the r-th, the rest kKeyMax),
+// merged into the pool: the best 64 R of pool and keys, sorted, of which the
+// first efe are kept.  The 64 largest of pool and keys lie in the top chunk
+// and the keys, so the keys first meet the top chunk; what is left below
+// meets the next chunk down, until a chunk lies wholly below what is left.
+template <int R>
+__device__ __forceinline__ void reg_merge_sorted(Pool &p, uint64_t kv, int efe, int lane) {
+  uint64_t x = bitonic_clean(key_min(chunk<R - 1>(p), reverse64(kv, lane)), lane);
+  bool done = false;
+  for_chunks_down<0, R - 1>([&](auto C) {
+    if (!done) {
+      uint64_t &w = chunk<C>(p);
+      if (key_lt(readlane64(w, 63), readlane64(x, 0))) {
+        chunk<C + 1>(p) = x;  // chunk C and those below stay as they are
+        done = true;
+      } else {
+        const uint64_t rx = reverse64(x, lane);
+        uint64_t hi = key_max(w, rx), lo = key_min(w, rx);
+        bitonic_clean2(hi, lo, lane);
+        chunk<C + 1>(p) = hi;
+        x = lo;
+      }
+    }
+  });
+  if (!done) p.w0 = x;
+  truncate_pool<R>(p, efe, lane);
+}
+
 // Links of the expanded entry c (lanes 0..31, nb) and of the next unexpanded
 // entry p (lanes 32..63 when `two`): test-and-set against the visited set,
 // codes and ADC keys, and whether p's expansion is the sequential walk's next
@@ -772,6 +962,238 @@ __global__ __launch_bounds__(64) void walk_kernel(WalkArgs a) {
   }
 }
 
+// The same walk with the pool in registers (pools of up to 64 R entries, R <= 2):
+// the scan for the next unexpanded entries is a ballot per chunk, one kept key
+// moves the entries above it up one lane, and several kept keys are sorted
+// and merged by bitonic networks; LDS holds only the table, the visited
+// table and 64 keys of sorting scratch.
+template <int M, typename T, int R>
+__global__ __launch_bounds__(64) void walk_reg_kernel(WalkArgs a) {
+  static_assert(R >= 1 && R <= 2, "pool chunks");
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int lane = threadIdx.x;
+  const int l32 = lane & 31;
+  const bool lo = lane < 32;
+  constexpr int kLutBytes = M * 256 * int(sizeof(T));
+  constexpr int kScaleBytes = sizeof(T) == 2 ? (M * 4 + 15) / 16 * 16 : 0;
+  T *lut = reinterpret_cast<T *>(smem);
+  float *sc = reinterpret_cast<float *>(smem + kLutBytes);
+  uint64_t *Ks = reinterpret_cast<uint64_t *>(smem + kLutBytes + kScaleBytes);  // 64 keys of sorting scratch
+  uint32_t *hash = reinterpret_cast<uint32_t *>(Ks + 64);
+  const int H = 1 << a.hash_bits;  // table words
+  VTable vt;
+  vt.t = hash;
+  vt.bshift = 32 - (a.hash_bits - 2);
+  vt.tbits = a.tag_bits;
+  vt.hmask = a.tag_bits ? uint32_t((1ull << (a.tag_bits + a.hash_bits - 2)) - 1ull) : 0u;
+  vt.narrow = a.tag_bits != 0;
+  uint32_t *bits = a.bits + int64_t(blockIdx.x) * a.words;
+  int32_t *vlist = a.vlists + int64_t(blockIdx.x) * a.list_cap;
+  // every row load reads a valid column, so that loads need no branch around them
+  const int lcol = l32 < a.deg0 ? l32 : a.deg0 - 1;
+  const bool col_ok = l32 < a.deg0;
+
+  int64_t pos = blockIdx.x;
+  if (a.queue) {
+    int64_t t = 0;
+    if (lane == 0) t = int64_t(atomicAdd(a.counters, 1u));
+    pos = __shfl(t, 0);
+  }
+  while (pos < a.nq) {
+    const int64_t q = a.order ? int64_t(a.order[pos]) : pos;
+    if (q < 0 || q >= a.nq) {
+      // not a query of this batch: nothing to do
+    } else {
+    const int32_t efq = a.ef ? a.ef[q] : a.ef_max;
+    if (efq < 1 || efq > a.ef_max) {
+      for (int i = lane; i < a.S; i += 64) {
+        a.cand_ids[q * a.S + i] = -1;
+        a.cand_adc[q * a.S + i] = __builtin_inff();
+      }
+      if (lane == 0) {
+        a.cand_n[q] = -1;
+        if (a.stats) {
+          a.stats[2 * q] = 0;
+          a.stats[2 * q + 1] = 0;
+        }
+      }
+    } else {
+      const int efe = efq > a.S ? efq : a.S;
+
+      // stage the table (and its row scales), clear the visited table
+      const float4 *src = reinterpret_cast<const float4 *>(static_cast<const T *>(a.lut) + q * (M * 256));
+      for (int i = lane; i < kLutBytes / 16; i += 64) reinterpret_cast<float4 *>(lut)[i] = src[i];
+      if (sizeof(T) == 2)
+        for (int i = lane; i < M; i += 64) sc[i] = a.scale[q * M + i];
+      for (int i = lane; i < H; i += 64) hash[i] = kEmpty;
+      wave_sync();
+
+      // greedy descent on levels max_level .. 1: the best link while it beats
+      // the current key (one lane per link)
+      int32_t cur = a.entry;
+      uint64_t curkey = make_key(adc_full<M, T>(lut, sc, a.codes, a.code_stride, cur), cur);
+      for (int l = a.max_level; l >= 1; --l) {
+        for (;;) {
+          const int64_t row = int64_t(a.up_base[cur]) + l - 1;
+          int32_t nb = -1;
+          if (lane < a.deg_up && row >= 0 && row < a.n_up_rows) nb = a.adj_up[row * a.deg_up + lane];
+          if (nb >= a.n) nb = -1;  // a malformed link is ignored rather than followed
+          const uint64_t k = nb >= 0 ? make_key(adc_full<M, T>(lut, sc, a.codes, a.code_stride, nb), nb) : kKeyMax;
+          const uint64_t mn = wave_min64(k);
+          if (mn < curkey) {
+            curkey = mn;
+            cur = key_id(mn);
+          } else {
+            break;
+          }
+        }
+      }
+
+      // best-first walk on level 0
+      if (lane == 0) {
+        uint32_t b0, t0;
+        vt_locate(vt, cur, b0, t0);
+        hash[4 * b0] = vt.narrow ? (t0 | 0xFFFF0000u) : t0;
+      }
+      Pool wr = {kKeyMax, kKeyMax};
+      if (lane == 0) wr.w0 = curkey;
+      int nw = 1, fu = 0, pidx = -1, E = 0, D = 0, vcount = 0;
+      uint64_t ck = curkey;                         // key of entry fu, the next expansion
+      uint64_t pk = kKeyMax;                        // key of entry pidx, the unexpanded entry after it
+      uint64_t wmax = efe == 1 ? curkey : kKeyMax;  // largest key of W once W is full
+      int32_t pre0 = -1, pre1 = -1;                 // ids whose rows `nxt` holds (lanes 0..31, 32..63)
+      int32_t row = a.adj0[int64_t(cur) * a.deg0 + lcol];
+      if (row >= a.n) row = -1;  // a malformed link is ignored rather than followed
+      wave_sync();
+      while (fu < nw) {
+        const int32_t cid = key_id(ck);
+        // rows of the entries likely to come next; every lane loads, from the
+        // expanded node's own row when there is no guess
+        int32_t nxt = 0;
+        if (a.prefetch) {
+          const int32_t g = lo ? pre0 : pre1;
+          nxt = a.adj0[int64_t(g >= 0 ? g : cid) * a.deg0 + lcol];
+        }
+        const bool two = pidx >= 0;
+        mark_expanded<R>(wr, fu, lane);
+        const int32_t nb = col_ok && (lo || two) ? row : -1;
+        // the codes of every link, fetched while the visited set is probed (a
+        // link that is not fresh reads its code for nothing)
+        CodeRegs<M> cr;
+        cr.load(a.codes, a.code_stride, nb >= 0 ? nb : cid);
+
+        const StepOut o = expand_links<M, T>(a, vt, bits, vlist, lut, sc, nb, cr, lo, two, pk, lane, D, E, vcount);
+        const bool dual = o.dual;
+        const uint64_t k = o.k;
+        if (dual) mark_expanded<R>(wr, pidx, lane);
+
+        const bool keep = o.fresh && k < wmax;
+        const uint64_t km = __ballot(keep);
+        if (km) {
+          const int nn = __popcll(km);
+          if (nn == 1) {
+            reg_insert_one<R>(wr, readlane64(k, __ffsll((unsigned long long)km) - 1), efe, lane);
+          } else {
+            uint64_t kv;
+            if (nn <= 12) {
+              // rank by broadcast; every lane takes one slot of a permutation
+              int rank = 0;
+              for (uint64_t mm = km; mm; mm &= mm - 1) {
+                const uint64_t kj = readlane64(k, __ffsll((unsigned long long)mm) - 1);
+                rank += kj < k ? 1 : 0;
+              }
+              const int below = __popcll(km & ((1ull << lane) - 1ull));
+              Ks[keep ? rank : nn + lane - below] = keep ? k : kKeyMax;
+              wave_sync();
+              kv = Ks[lane];
+              wave_sync();
+            } else {
+              kv = bitonic_sort(keep ? k : kKeyMax, lane);
+            }
+            reg_merge_sorted<R>(wr, kv, efe, lane);
+          }
+          nw = nw + nn < efe ? nw + nn : efe;
+          wmax = nw == efe ? pure_key(entry_at<R>(wr, efe - 1)) : kKeyMax;
+        }
+
+        // the first four unexpanded entries
+        Pick2 pm;
+        pm.lo = __ballot((wr.w0 & kExpanded) == 0);
+        pm.hi = R > 1 ? __ballot((wr.w1 & kExpanded) == 0) : 0ull;
+        const int f0 = pm.next(), f1 = pm.next(), f2 = pm.next(), f3 = pm.next();
+        fu = f0 >= 0 ? f0 : nw;
+        pidx = f1;
+        if (fu < nw) {
+          ck = entry_at<R>(wr, f0);
+          pk = f1 >= 0 ? entry_at<R>(wr, f1) : kKeyMax;
+          const int32_t g2 = f2 >= 0 ? key_id(entry_at<R>(wr, f2)) : -1;
+          const int32_t g3 = f3 >= 0 ? key_id(entry_at<R>(wr, f3)) : -1;
+          const int32_t nc = key_id(ck);
+          const int32_t np = f1 >= 0 ? key_id(pk) : -1;
+          // only a dual step can meet the guess: when p was not expanded, a
+          // kept key of c lies below key(p) and comes next
+          if (a.prefetch && dual && nc == pre0 && (np < 0 || np == pre1)) {
+            row = nxt;  // the guessed pair came next
+          } else {
+            row = a.adj0[int64_t(lo || np < 0 ? nc : np) * a.deg0 + lcol];
+          }
+          if (row >= a.n) row = -1;
+          pre0 = g2;
+          pre1 = g3;
+        }
+        // nothing is in flight across steps: the next step's loads are the only ones to wait for
+        __builtin_amdgcn_s_waitcnt(0);
+      }
+
+      // short-list = the first min(S, |W|) entries of W
+      const int ns = a.S < nw ? a.S : nw;
+      for_chunks<0, R>([&](auto C) {
+        const int i = (C << 6) + lane;
+        const uint64_t w = chunk<C>(wr);
+        if (i < a.S) {
+          a.cand_ids[q * a.S + i] = i < ns ? key_id(w) : -1;
+          a.cand_adc[q * a.S + i] = i < ns ? key_dist(w) : __builtin_inff();
+        }
+      });
+      if (lane == 0) {
+        a.cand_n[q] = ns;
+        if (a.stats) {
+          a.stats[2 * q] = E;
+          a.stats[2 * q + 1] = D;
+        }
+      }
+      if (vcount > 0) {
+        __threadfence();  // the recorded ids are visible to every lane
+        const int nl = vcount < a.list_cap ? vcount : a.list_cap;
+        if (vcount > a.list_cap) {
+          for (int64_t i = lane; i < a.words; i += 64) bits[i] = 0u;
+        } else {
+          for (int i = lane; i < nl; i += 64) bits[uint32_t(vlist[i]) >> 5] = 0u;
+        }
+        __threadfence();
+        for (int i = lane; i < nl; i += 64) vlist[i] = 0;  // the workspace is left zero-filled
+        __threadfence();
+      }
+      wave_sync();
+    }
+    }
+    if (a.queue) {
+      int64_t t = 0;
+      if (lane == 0) t = int64_t(atomicAdd(a.counters, 1u));
+      pos = __shfl(t, 0);
+    } else {
+      pos += gridDim.x;
+    }
+  }
+  if (a.queue && lane == 0) {
+    // the last slot to finish leaves both counters at zero for the next launch
+    if (atomicAdd(a.counters + 1, 1u) == gridDim.x - 1) {
+      atomicExch(a.counters, 0u);
+      atomicExch(a.counters + 1, 0u);
+    }
+  }
+}
+
 // Level-0 walk with the visited set in the slot's bitset behind a
 // direct-mapped LDS cache; one expansion per step.
 template <int M, typename T>
@@ -963,14 +1385,20 @@ __global__ __launch_bounds__(64) void walk_cache_kernel(WalkArgs a) {
 
 struct WalkPlan {
   int w_cap, hash_bits, lds_bytes, grid;
+  int reg_chunks;  // > 0: the pool lives in registers, this many chunks of 64 (walk_reg_kernel)
 };
+
+// Largest pool held in registers: two chunks (four chunks were measured
+// slower than the LDS pool: their merge networks cost more than they save).
+constexpr int kRegPoolMax = 128;
 
 constexpr size_t kHeaderBytes = 256;  // two queue counters, padded
 
 template <int M>
-int lds_bytes_for(int w_cap, int hash_bits, int lut_bytes) {
+int lds_bytes_for(int w_cap, int hash_bits, int lut_bytes, bool reg) {
   const int scale_bytes = lut_bytes == 2 ? (M * 4 + 15) / 16 * 16 : 0;
-  return M * 256 * lut_bytes + scale_bytes + w_cap * 8 + kMergeScratch * 8 + (1 << hash_bits) * 4;
+  const int pool_bytes = reg ? 64 * 8 : w_cap * 8 + kMergeScratch * 8;
+  return M * 256 * lut_bytes + scale_bytes + pool_bytes + (1 << hash_bits) * 4;
 }
 
 // Tag width of a narrow visited table with 2^(hash_bits-2) buckets for ids
@@ -988,9 +1416,9 @@ int table_tag_bits(int32_t n, int hash_bits) {
 // global bitset, which the longest walks pay for at every step, so capacity
 // beats residency down to about 8 slots); else 2^10 words.
 template <int M>
-int auto_hash_bits(int w_cap, int32_t n, int lut_bytes, int lds_per_cu) {
+int auto_hash_bits(int w_cap, int32_t n, int lut_bytes, int lds_per_cu, bool reg) {
   for (int hb = 12; hb >= 10; --hb)
-    if (table_tag_bits(n, hb) && lds_per_cu / lds_bytes_for<M>(w_cap, hb, lut_bytes) >= 8) return hb;
+    if (table_tag_bits(n, hb) && lds_per_cu / lds_bytes_for<M>(w_cap, hb, lut_bytes, reg) >= 8) return hb;
   return table_tag_bits(n, 10) || !table_tag_bits(n, 11) ? 10 : 11;
 }
 
@@ -1000,12 +1428,14 @@ WalkPlan plan_for(const lc_index *ix, int64_t nq, int32_t ef_max, int32_t S, con
   WalkPlan p;
   int ef_eff = ef_max > S ? ef_max : S;
   p.w_cap = (ef_eff + 63) / 64 * 64;
+  const bool reg = sc->visited == 0 && sc->pool == 0 && p.w_cap <= kRegPoolMax;
+  p.reg_chunks = reg ? 2 : 0;
   // visited mode 1 keeps only a small LDS cache; mode 0 sizes its table from the pool
-  p.hash_bits = (sc && sc->hash_bits) ? sc->hash_bits
-              : (sc && sc->visited == 1 ? 9
-                                        : auto_hash_bits<M>(p.w_cap, sc && sc->wide ? INT32_MAX : ix->v.n, lut_bytes,
-                                                            ix->lds_per_cu));
-  p.lds_bytes = lds_bytes_for<M>(p.w_cap, p.hash_bits, lut_bytes);
+  p.hash_bits = sc->hash_bits ? sc->hash_bits
+              : (sc->visited == 1 ? 9
+                                  : auto_hash_bits<M>(p.w_cap, sc->wide ? INT32_MAX : ix->v.n, lut_bytes,
+                                                      ix->lds_per_cu, reg));
+  p.lds_bytes = lds_bytes_for<M>(p.w_cap, p.hash_bits, lut_bytes, reg);
   int per_cu = ix->lds_per_cu / p.lds_bytes;
   if (sc && sc->waves_per_cu > 0 && sc->waves_per_cu < per_cu) per_cu = sc->waves_per_cu;
   if (per_cu < 1) per_cu = 1;
@@ -1021,11 +1451,12 @@ bool valid_schedule(const lc_schedule *sc) {
   if (!sc) return true;
   if (sc->hash_bits != 0 && (sc->hash_bits < 9 || sc->hash_bits > 14)) return false;
   if (sc->prefetch < 0 || sc->prefetch > 1 || sc->queue < 0 || sc->queue > 1 || sc->waves_per_cu < 0) return false;
-  if (sc->visited < 0 || sc->visited > 1 || sc->wide < 0 || sc->wide > 1) return false;
+  if (sc->visited < 0 || sc->visited > 1 || sc->wide < 0 || sc->wide > 1 || sc->pool < 0 || sc->pool > 1)
+    return false;
   return true;
 }
 
-const lc_schedule kDefaultSchedule = {0, 1, 0, 1, 0, 0};
+const lc_schedule kDefaultSchedule = {0, 1, 0, 1, 0, 0, 0};
 
 int list_cap_for(int w_cap) { return 16 * w_cap > 4096 ? 16 * w_cap : 4096; }
 
@@ -1087,11 +1518,14 @@ int launch_m(const lc_index *ix, const void *lut, const float *scale, int64_t nq
   a.cand_n = cand_n;
   a.stats = stats;
   const void *fn = sc->visited == 1 ? reinterpret_cast<const void *>(&walk_cache_kernel<M, T>)
-                                    : reinterpret_cast<const void *>(&walk_kernel<M, T>);
+                   : p.reg_chunks  ? reinterpret_cast<const void *>(&walk_reg_kernel<M, T, 2>)
+                                   : reinterpret_cast<const void *>(&walk_kernel<M, T>);
   if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, p.lds_bytes) != hipSuccess)
     return LC_EHIP;
   if (sc->visited == 1)
     hipLaunchKernelGGL((walk_cache_kernel<M, T>), dim3(p.grid), dim3(64), p.lds_bytes, st, a);
+  else if (p.reg_chunks)
+    hipLaunchKernelGGL((walk_reg_kernel<M, T, 2>), dim3(p.grid), dim3(64), p.lds_bytes, st, a);
   else
     hipLaunchKernelGGL((walk_kernel<M, T>), dim3(p.grid), dim3(64), p.lds_bytes, st, a);
   return hipGetLastError() == hipSuccess ? LC_OK : LC_EHIP;

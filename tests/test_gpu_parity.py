@@ -188,6 +188,8 @@ SCHEDULES = [dict(hash_bits=9, prefetch=0, waves_per_cu=0, queue=0, visited=0), 
              dict(hash_bits=14, prefetch=1, waves_per_cu=0, queue=1, visited=0),
              dict(hash_bits=0, prefetch=0, waves_per_cu=2, queue=1, visited=0),
              dict(hash_bits=11, prefetch=1, waves_per_cu=0, queue=0, visited=0, wide=1),
+             dict(hash_bits=0, prefetch=1, waves_per_cu=0, queue=1, visited=0, pool=1),   # pool in LDS
+             dict(hash_bits=9, prefetch=0, waves_per_cu=0, queue=0, visited=0, pool=1),
              dict(hash_bits=9, prefetch=0, waves_per_cu=0, queue=1, visited=1),   # bitset + LDS cache
              dict(hash_bits=10, prefetch=1, waves_per_cu=0, queue=0, visited=1)]
 
@@ -230,6 +232,31 @@ def test_overflow_path_with_large_pool(torch):
         assert np.array_equal(r.stats.cpu().numpy(), o["stats"])
         assert np.all(r.stats.cpu().numpy()[:, 1] == 2399)
         assert int(gix.workspace(12, 2400, 64, sc).count_nonzero().item()) == 0
+
+
+def test_register_pool_sizes(torch):
+    # pools of 1..256 entries across the chunk boundaries (in registers up to
+    # 128 entries, in LDS beyond), against the oracle and the LDS pool
+    import paper_1804_09996_amd as lc
+    w = datagen.small(name="regpool", n=2400, nq=12, d=32, m=8, n_train=1024, n_beta=16, n_beta_train=2400, k_reg=8)
+    ix, db, q = oracle.build_workload(w, nthreads=4)
+    gix = lc.Index.from_index(ix)
+    lut, _ = gix.build_lut(torch.from_numpy(q))
+    for ef, S in ((1, 1), (2, 1), (63, 8), (64, 64), (65, 10), (127, 16), (128, 128), (129, 32), (200, 100),
+                  (255, 255), (256, 64), (40, 256)):
+        o = ix.search(q, ef, S, 1)
+        got = []
+        for sd in (dict(), dict(pool=1), dict(hash_bits=9, prefetch=0)):
+            sc = lc.schedule(**sd)
+            r = gix.search(lut, ef=ef, ef_max=ef, S=S, sched=sc)
+            got.append((r.cand_ids.cpu().numpy(), r.cand_adc.cpu().numpy().view(np.uint32), r.cand_n.cpu().numpy(),
+                        r.stats.cpu().numpy()))
+            assert int(gix.workspace(12, ef, S, sc).count_nonzero().item()) == 0
+        assert np.array_equal(got[0][0], o["cand_ids"]), (ef, S)
+        assert np.array_equal(got[0][3], o["stats"]), (ef, S)
+        for g in got[1:]:
+            for a_, b_ in zip(got[0], g):
+                assert np.array_equal(a_, b_), (ef, S)
 
 
 # ---------------------------------------------------------------------------
