@@ -7,11 +7,14 @@
 //   d~   = || P y - x~_i ||^2
 //
 // and the K smallest (d~, id) are kept.  A block stages the centroids of all
-// sub-spaces in LDS once; each wavefront then owns one query at a time.  Four
-// lanes share a candidate, lane part p accumulating the sub-spaces s = p mod 4
-// in registers; the candidate's distance is the sum of the four partial sums
-// in a fixed order.  The short-list keys are sorted in LDS by a bitonic
-// network and the first K written out.
+// sub-spaces in LDS once; each wavefront then owns one query at a time.  L
+// lanes share a candidate (L = 2 for m <= 16, else 4), lane part p
+// accumulating the sub-spaces s = p mod L in registers; the candidate's
+// distance is the sum of the L partial sums in a fixed order.  A candidate's
+// rows are dependent gathers (its links, then their codes), so more
+// candidates per wavefront (fewer lanes each) means fewer rounds of them.
+// The short-list keys are sorted in LDS by a bitonic network and the first K
+// written out.
 //
 // Precision form: the centroids are staged in LDS as bfloat16 and the beta
 // weights rounded to bfloat16, products accumulated in float32; the best
@@ -63,6 +66,23 @@ struct CodeRow {
   __device__ __forceinline__ uint32_t byte(int s) const { return (w[s >> 2] >> (8 * (s & 3))) & 0xFFu; }
 };
 
+// NB consecutive code bytes (NB = 4 or 8, aligned to NB) of one code row.
+template <int NB>
+struct CodePiece {
+  uint32_t w[NB / 4];
+  __device__ __forceinline__ void load(const uint8_t *p) {
+    if constexpr (NB == 8) {
+      const uint2 v = *reinterpret_cast<const uint2 *>(p);
+      w[0] = v.x;
+      w[NB == 8 ? 1 : 0] = v.y;
+    } else {
+      static_assert(NB == 4, "code piece");
+      w[0] = *reinterpret_cast<const uint32_t *>(p);
+    }
+  }
+  __device__ __forceinline__ uint32_t byte(int u) const { return (w[u >> 2] >> (8 * (u & 3))) & 0xFFu; }
+};
+
 // Centroid element as float32: float32 storage, or bfloat16 (top 16 bits).
 __device__ __forceinline__ float cval(const float *C, int i) { return C[i]; }
 __device__ __forceinline__ float cval(const uint16_t *C, int i) { return __uint_as_float(uint32_t(C[i]) << 16); }
@@ -74,11 +94,21 @@ __device__ __forceinline__ float round_bf16(float x) {
   return __uint_as_float(u & 0xFFFF0000u);
 }
 
-// This lane part's share of || y' - x~_id ||^2 (sub-spaces s = part mod 4).
+// Lanes per candidate: two while the accumulators fit, else four.
+template <int M>
+constexpr int lanes_per_cand() {
+  return M <= 16 ? 2 : 4;
+}
+
+// This lane part's share of || y' - x~_id ||^2: with two lanes the sub-spaces
+// [part U, part U + U) (one aligned piece of each code row), with four the
+// sub-spaces s = part mod 4 (whole code rows).
 template <int M, int DSUB, int CS, typename CT, bool BF16W>
 __device__ __forceinline__ float part_dist(const RefineArgs &a, const CT *C, const float *yv, int32_t id,
                                            int part) {
-  constexpr int U = M / 4;
+  constexpr int L = lanes_per_cand<M>();
+  constexpr int U = M / L;
+  static_assert(L == 4 || U == 4 || U == 8, "two lanes take 4 or 8 sub-spaces each");
   constexpr int B = CS >= 64 ? 3 : CS >= 32 ? 4 : 6;  // rows in flight: their ids, then their code rows, then the sums
   float acc[U * DSUB];
 #pragma unroll
@@ -96,25 +126,41 @@ __device__ __forceinline__ float part_dist(const RefineArgs &a, const CT *C, con
       g[t] = ok ? gj : id;
       wj[t] = ok ? (BF16W ? round_bf16(bw[j]) : bw[j]) : 0.f;
     }
-    CodeRow<CS> row[B];
-#pragma unroll
-    for (int t = 0; t < B; ++t) row[t].load(a.codes + size_t(g[t]) * CS);
     // a row past k or a missing link has weight 0: it adds exact zeros
+    if constexpr (L == 2) {
+      CodePiece<U> row[B];
 #pragma unroll
-    for (int t = 0; t < B; ++t) {
+      for (int t = 0; t < B; ++t) row[t].load(a.codes + size_t(g[t]) * CS + part * U);
 #pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const int s = part + 4 * u;
-        const int base = (s * 256 + int(row[t].byte(s))) * DSUB;
+      for (int t = 0; t < B; ++t) {
 #pragma unroll
-        for (int q = 0; q < DSUB; ++q) acc[u * DSUB + q] += wj[t] * cval(C, base + q);
+        for (int u = 0; u < U; ++u) {
+          const int s = part * U + u;
+          const int base = (s * 256 + int(row[t].byte(u))) * DSUB;
+#pragma unroll
+          for (int q = 0; q < DSUB; ++q) acc[u * DSUB + q] += wj[t] * cval(C, base + q);
+        }
+      }
+    } else {
+      CodeRow<CS> row[B];
+#pragma unroll
+      for (int t = 0; t < B; ++t) row[t].load(a.codes + size_t(g[t]) * CS);
+#pragma unroll
+      for (int t = 0; t < B; ++t) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int s = part + L * u;
+          const int base = (s * 256 + int(row[t].byte(s))) * DSUB;
+#pragma unroll
+          for (int q = 0; q < DSUB; ++q) acc[u * DSUB + q] += wj[t] * cval(C, base + q);
+        }
       }
     }
   }
   float e = 0.f;
 #pragma unroll
   for (int u = 0; u < U; ++u) {
-    const int s = part + 4 * u;
+    const int s = L == 2 ? part * U + u : part + L * u;
 #pragma unroll
     for (int t = 0; t < DSUB; ++t) {
       const float df = yv[s * DSUB + t] - acc[u * DSUB + t];
@@ -124,10 +170,11 @@ __device__ __forceinline__ float part_dist(const RefineArgs &a, const CT *C, con
   return e;
 }
 
-// (p0 + p1) + (p2 + p3) over the four lanes of a candidate group.
+// p0 + p1, or (p0 + p1) + (p2 + p3), over the L lanes of a candidate group.
+template <int L>
 __device__ __forceinline__ float group_sum(float e) {
   e += __shfl_xor(e, 1);
-  e += __shfl_xor(e, 2);
+  if constexpr (L == 4) e += __shfl_xor(e, 2);
   return e;
 }
 
@@ -204,32 +251,34 @@ __global__ __launch_bounds__(1024) void refine_kernel(RefineArgs a) {
   }
   __syncthreads();
 
-  const int part = lane & 3, grp = lane >> 2;
+  constexpr int L = lanes_per_cand<M>();
+  constexpr int G = 64 / L;  // candidates per round
+  const int part = lane & (L - 1), grp = lane / L;
   for (int64_t q = int64_t(blockIdx.x) * a.wpb + wave; q < a.nq; q += int64_t(gridDim.x) * a.wpb) {
     project_query(a, q, yv, lane);
     wave_sync();
     const int cn = a.cand_n[q];
-    for (int c0 = 0; c0 < a.S_pad; c0 += 16) {
+    for (int c0 = 0; c0 < a.S_pad; c0 += G) {
       const int c = c0 + grp;
-      const int32_t id = candidate(a, q, c, cn);
+      const int32_t id = c < a.S_pad ? candidate(a, q, c, cn) : -1;
       float e = 0.f;
       if (id >= 0) e = part_dist<M, DSUB, CS, CT, kBF16>(a, C, yv, id, part);
-      e = group_sum(e);
-      if (part == 0) keys[c] = id >= 0 ? make_key(e, id) : kKeyMax;
+      e = group_sum<L>(e);
+      if (part == 0 && c < a.S_pad) keys[c] = id >= 0 ? make_key(e, id) : kKeyMax;
     }
     wave_sync();
     wave_sort(keys, a.S_pad, lane);
     if constexpr (kBF16) {
       // exact float32 re-score of the best K2, then re-sort those
-      for (int c0 = 0; c0 < a.K2_pad; c0 += 16) {
+      for (int c0 = 0; c0 < a.K2_pad; c0 += G) {
         const int c = c0 + grp;
         const uint64_t v = c < a.K2 ? keys[c] : kKeyMax;
         const int32_t id = v == kKeyMax ? -1 : key_id(v);
         float e = 0.f;
         if (id >= 0) e = part_dist<M, DSUB, CS, float, false>(a, a.cent, yv, id, part);
-        e = group_sum(e);
+        e = group_sum<L>(e);
         wave_sync();
-        if (part == 0) keys[c] = id >= 0 ? make_key(e, id) : kKeyMax;
+        if (part == 0 && c < a.K2_pad) keys[c] = id >= 0 ? make_key(e, id) : kKeyMax;
         wave_sync();
       }
       wave_sort(keys, a.K2_pad, lane);
@@ -280,7 +329,7 @@ __global__ __launch_bounds__(1024) void refine_f32_generic(RefineArgs a, int m, 
           }
         }
       }
-      e = group_sum(e);
+      e = group_sum<4>(e);
       if (part == 0) keys[c] = id >= 0 ? make_key(e, id) : kKeyMax;
     }
     wave_sync();
