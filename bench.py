@@ -265,7 +265,7 @@ def bench_serve(args):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--steps", type=int, default=30)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="C2-1M")
     ap.add_argument("--form", choices=("both", "plain", "batched", "serve"), default="both")
@@ -319,6 +319,8 @@ def main():
     FORMS = {"f32": (lc.LC_LUT_F32, lc.LC_REFINE_F32), "f16": (lc.LC_LUT_F16, lc.LC_REFINE_F32),
              "f16+bf16": (lc.LC_LUT_F16, lc.LC_REFINE_BF16_RESCORE)}
 
+    side_streams, ws_cache = [], {}
+
     def run(form, ef, S, steps, warmup, streams=None):
         """Time `steps` steps.  With several streams, step k runs on stream
         k mod streams with its own workspace and outputs, so consecutive
@@ -330,9 +332,14 @@ def main():
         if streams == 1:
             lanes = [(torch.cuda.current_stream(dev), gix.workspace(nq, max(ef, S), S))]
         else:
+            # the same streams for every configuration of the run, each with its own workspace
+            while len(side_streams) < streams:
+                side_streams.append(torch.cuda.Stream(device=dev))
             nb = gix.workspace_bytes(nq, max(ef, S), S)
-            lanes = [(torch.cuda.Stream(device=dev), torch.zeros(nb, dtype=torch.uint8, device=dev))
-                     for _ in range(streams)]
+            if ws_cache.get("bytes", 0) < nb or len(ws_cache.get("ws", [])) < streams:
+                ws_cache["ws"] = [torch.zeros(nb, dtype=torch.uint8, device=dev) for _ in range(streams)]
+                ws_cache["bytes"] = nb
+            lanes = list(zip(side_streams[:streams], ws_cache["ws"][:streams]))
         torch.cuda.synchronize()
 
         def step(k, ev=None):

@@ -229,18 +229,34 @@ __device__ __forceinline__ uint32_t dword_of(const uint4 &s, int i) {
   return i == 0 ? s.x : i == 1 ? s.y : i == 2 ? s.z : s.w;
 }
 
-// hit: the tag is in the bucket; e: its first free slot (-1: full)
+typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ u16x2 as_u16x2(uint32_t w) { return __builtin_bit_cast(u16x2, w); }
+
+// hit: the tag is in the bucket; e: its first free slot (-1: full).  Every
+// store takes the first free slot of the bucket as read, so the filled slots
+// are always a prefix and the first free slot is their count.  Narrow
+// buckets are inspected two tags at a time with packed 16-bit arithmetic:
+// min(x ^ tag, 1) is 0 exactly where x holds the tag, min(x + 1, 1) is 0
+// exactly where x is empty (0xFFFF).
 __device__ __forceinline__ void vt_inspect(const VTable &v, const uint4 &s, uint32_t tag, bool &hit, int &e) {
   uint32_t hm, em;
   if (v.narrow) {
-    const uint32_t w[4] = {s.x, s.y, s.z, s.w};
-    hm = em = 0u;
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const uint32_t l16 = w[i] & 0xFFFFu, h16 = w[i] >> 16;
-      hm |= (uint32_t(l16 == tag) | (uint32_t(h16 == tag) << 1)) << (2 * i);
-      em |= (uint32_t(l16 == kTagEmpty) | (uint32_t(h16 == kTagEmpty) << 1)) << (2 * i);
-    }
+    const u16x2 one = {1, 1};
+    const uint32_t t2 = tag | (tag << 16);
+    const u16x2 m0 = __builtin_elementwise_min(as_u16x2(s.x ^ t2), one);
+    const u16x2 m1 = __builtin_elementwise_min(as_u16x2(s.y ^ t2), one);
+    const u16x2 m2 = __builtin_elementwise_min(as_u16x2(s.z ^ t2), one);
+    const u16x2 m3 = __builtin_elementwise_min(as_u16x2(s.w ^ t2), one);
+    hit = __builtin_bit_cast(uint32_t, (m0 & m1) & (m2 & m3)) != 0x00010001u;
+    const u16x2 f0 = __builtin_elementwise_min(as_u16x2(s.x) + one, one);
+    const u16x2 f1 = __builtin_elementwise_min(as_u16x2(s.y) + one, one);
+    const u16x2 f2 = __builtin_elementwise_min(as_u16x2(s.z) + one, one);
+    const u16x2 f3 = __builtin_elementwise_min(as_u16x2(s.w) + one, one);
+    const uint32_t cnt = __builtin_bit_cast(uint32_t, (f0 + f1) + (f2 + f3));
+    const int filled = int(cnt & 0xFFFFu) + int(cnt >> 16);
+    e = filled < 8 ? filled : -1;
+    return;
   } else {
     hm = uint32_t(s.x == tag) | (uint32_t(s.y == tag) << 1) | (uint32_t(s.z == tag) << 2) |
          (uint32_t(s.w == tag) << 3);
