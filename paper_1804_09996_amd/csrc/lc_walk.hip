@@ -211,7 +211,6 @@ struct VTable {
   bool narrow;
 };
 
-constexpr uint32_t kTagEmpty = 0xFFFFu;
 
 __device__ __forceinline__ void vt_locate(const VTable &v, int32_t id, uint32_t &b, uint32_t &tag) {
   const uint32_t p = uint32_t(id) * 0x9E3779B1u;
@@ -229,9 +228,18 @@ __device__ __forceinline__ uint32_t dword_of(const uint4 &s, int i) {
   return i == 0 ? s.x : i == 1 ? s.y : i == 2 ? s.z : s.w;
 }
 
-typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
-
-__device__ __forceinline__ u16x2 as_u16x2(uint32_t w) { return __builtin_bit_cast(u16x2, w); }
+// Packed unsigned 16-bit minimum and sum of two words, as single instructions
+// (the compiler otherwise splits the halves into compares).
+__device__ __forceinline__ uint32_t pk_min_u16(uint32_t a, uint32_t b) {
+  uint32_t r;
+  asm("v_pk_min_u16 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
+  return r;
+}
+__device__ __forceinline__ uint32_t pk_add_u16(uint32_t a, uint32_t b) {
+  uint32_t r;
+  asm("v_pk_add_u16 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
+  return r;
+}
 
 // hit: the tag is in the bucket; e: its first free slot (-1: full).  Every
 // store takes the first free slot of the bucket as read, so the filled slots
@@ -242,18 +250,14 @@ __device__ __forceinline__ u16x2 as_u16x2(uint32_t w) { return __builtin_bit_cas
 __device__ __forceinline__ void vt_inspect(const VTable &v, const uint4 &s, uint32_t tag, bool &hit, int &e) {
   uint32_t hm, em;
   if (v.narrow) {
-    const u16x2 one = {1, 1};
+    const uint32_t one = 0x00010001u;
     const uint32_t t2 = tag | (tag << 16);
-    const u16x2 m0 = __builtin_elementwise_min(as_u16x2(s.x ^ t2), one);
-    const u16x2 m1 = __builtin_elementwise_min(as_u16x2(s.y ^ t2), one);
-    const u16x2 m2 = __builtin_elementwise_min(as_u16x2(s.z ^ t2), one);
-    const u16x2 m3 = __builtin_elementwise_min(as_u16x2(s.w ^ t2), one);
-    hit = __builtin_bit_cast(uint32_t, (m0 & m1) & (m2 & m3)) != 0x00010001u;
-    const u16x2 f0 = __builtin_elementwise_min(as_u16x2(s.x) + one, one);
-    const u16x2 f1 = __builtin_elementwise_min(as_u16x2(s.y) + one, one);
-    const u16x2 f2 = __builtin_elementwise_min(as_u16x2(s.z) + one, one);
-    const u16x2 f3 = __builtin_elementwise_min(as_u16x2(s.w) + one, one);
-    const uint32_t cnt = __builtin_bit_cast(uint32_t, (f0 + f1) + (f2 + f3));
+    const uint32_t m0 = pk_min_u16(s.x ^ t2, one), m1 = pk_min_u16(s.y ^ t2, one);
+    const uint32_t m2 = pk_min_u16(s.z ^ t2, one), m3 = pk_min_u16(s.w ^ t2, one);
+    hit = ((m0 & m1) & (m2 & m3)) != one;
+    const uint32_t f0 = pk_min_u16(pk_add_u16(s.x, one), one), f1 = pk_min_u16(pk_add_u16(s.y, one), one);
+    const uint32_t f2 = pk_min_u16(pk_add_u16(s.z, one), one), f3 = pk_min_u16(pk_add_u16(s.w, one), one);
+    const uint32_t cnt = pk_add_u16(pk_add_u16(f0, f1), pk_add_u16(f2, f3));
     const int filled = int(cnt & 0xFFFFu) + int(cnt >> 16);
     e = filled < 8 ? filled : -1;
     return;
