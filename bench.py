@@ -171,19 +171,20 @@ def bench_batched(args):
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     step_ms = np.array([a.elapsed_time(b) for a, b in evs])
-    # per-kernel times of one eager step on the same buffers
+    # per-kernel times of one eager step on the same buffers (the walk phase:
+    # the concurrent launches of every ef class)
     lut_dt = lc.LC_LUT_F32
     e = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
     e[0].record()
     lut, scale = gix.build_lut(bs.q, lut_dt)
     e[1].record()
-    r = gix.search(lut, scale, ef=bs.ef, ef_max=ef_max, S=S, sched=sched, order=bs.order)
+    bs._walks(lut, scale)
     e[2].record()
-    gix.refine(bs.q, r.cand_ids, r.cand_n, K)
+    gix.refine(bs.q, bs.res.cand_ids, bs.res.cand_n, K)
     e[3].record()
     torch.cuda.synchronize()
     kms = [e[j].elapsed_time(e[j + 1]) for j in range(3)]
-    st = r.stats.cpu().numpy()
+    st = bs.res.stats.cpu().numpy()
     E, D = st[:, 0].astype(np.int64), st[:, 1].astype(np.int64)
     wb = walk_bytes(w, E, D, S)
     idx, gt = ground_truth_sample(torch, db, q, dev, 10_000, w.seed)
@@ -196,10 +197,14 @@ def bench_batched(args):
            "config": {"workload": f"{w.name}: N={w.n} d={w.d} Gaussian mixture ({w.n_comp} components), PQ {w.m}x256, "
                                   f"k={w.k_reg}, {nq} queries in one step, efSearch per query round(exp(U(ln16, "
                                   f"ln512))), pool max(ef, {S}), short-list {S}, top-{K}, longest ef first, "
-                                  f"autotuned schedule {sched.as_dict()}, step replayed from a HIP graph"},
+                                  f"autotuned schedule {sched.as_dict()} and ef classes (pool limits "
+                                  f"{bs.limits}: one concurrent walk launch per class), step replayed from a HIP "
+                                  f"graph",
+                      "ef_classes": [{"rows": r1 - r0, "ef_max": efm} for r0, r1, efm in bs.ranges]},
            "roofline": {"bound": "hbm", "achieved": wb / (kms[1] * 1e-3) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                         "frac": wb / (kms[1] * 1e-3) / 1e9 / HBM_PEAK_GBS, "traffic": None,
-                        "kernel": f"walk_kernel<{w.m},float>", "algorithmic_bytes_per_launch": wb},
+                        "kernel": "walk phase: " + ", ".join(walk_kernel_name(w.m, "f32", efm, S) for _, _, efm in bs.ranges),
+                        "algorithmic_bytes_per_launch": wb},
            "kernels_ms": dict(zip(("build_lut", "walk", "refine"), kms)),
            "step_ms_p50": float(np.percentile(step_ms, 50)), "step_ms_p99": float(np.percentile(step_ms, 99)),
            "recall_10k_sample": rec, "walk_mean_E": float(E.mean()), "walk_mean_D": float(D.mean()),

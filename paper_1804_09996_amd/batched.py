@@ -3,19 +3,39 @@
 The whole path for the batch (tables, walk, refinement) runs on static device
 buffers and is captured once in a HIP graph; each step copies the queries and
 their ef into the static inputs and replays the graph.  The walk is the
-persistent kernel: resident slots take queries from an atomic counter, in an
-order fixed on the host as longest ef first, so the long walks start early
-and the short ones fill the tail.  The walk's schedule (visited-table size,
-prefetch, queue) comes from the autotuner; every schedule gives the same
-results.
+persistent kernel: resident slots take queries from an atomic counter, longest
+ef first, so the long walks start early and the short ones fill the tail.
+
+Queries are split into *ef classes* by the pool they need (max(ef, S),
+rounded up to 64): each class is walked by its own launch whose slots are
+sized for that class only (a pool of at most 128 entries lives in registers,
+and smaller pools leave LDS for more resident slots), the launches of all
+classes run concurrently inside the one graph (largest pools first), and the
+refinement runs once over the whole batch.  On the host the batch is permuted into (class, longest
+ef first) order so that every class is a contiguous range of rows; the
+results are permuted back on the device.  The class boundaries and the walk
+schedule come from the autotuner; neither changes any result.
 """
 from __future__ import annotations
 
-from typing import Optional
+from typing import List, Optional, Sequence
 
 import numpy as np
 
 from . import LC_LUT_F16, LC_LUT_F32, LC_REFINE_BF16_RESCORE, LC_REFINE_F32, SearchResult, autotune
+
+
+def class_limits_options(ef_max: int, S: int) -> List[List[int]]:
+    """Candidate splits: pool limits (ascending, last = the batch's largest
+    pool) at which the batch is cut into classes."""
+    top = max(ef_max, S)
+    top = (top + 63) // 64 * 64
+    opts = [[top]]
+    for cuts in ([128], [128, 256]):
+        lim = [c for c in cuts if max(S, 1) <= c < top] + [top]
+        if lim not in opts:
+            opts.append(lim)
+    return opts
 
 
 class BatchedSearcher:
@@ -26,44 +46,141 @@ class BatchedSearcher:
         self.lut_dtype = LC_LUT_F16 if precision == "f16" else LC_LUT_F32
         self.refine_p = LC_REFINE_BF16_RESCORE if precision == "f16" else LC_REFINE_F32
         dev = gix.device
+        # the batch in (class, longest ef first) order, and the map back to query order
         self.q = torch.empty((nq, gix.d), dtype=torch.float32, device=dev)
         self.ef = torch.empty(nq, dtype=torch.int32, device=dev)
-        self.order = torch.empty(nq, dtype=torch.int32, device=dev)
+        self.inv = torch.empty(nq, dtype=torch.int64, device=dev)
         self.res = SearchResult(torch.empty((nq, S), dtype=torch.int32, device=dev),
                                 torch.empty((nq, S), dtype=torch.float32, device=dev),
                                 torch.empty(nq, dtype=torch.int32, device=dev),
                                 torch.empty((nq, 2), dtype=torch.int32, device=dev))
         self.sched = None
+        self.limits = [max(ef_max, S)]
+        self.ranges = [(0, nq, max(ef_max, S))]
+        self.streams, self.ws = [], []
         self.graph = None
         self.table = None
+        self._host_q = None
+        self._host_ef = None
 
+    # -- inputs -------------------------------------------------------------
     def set_inputs(self, q, ef):
-        """Copy a batch in; the processing order is longest ef first (stable)."""
+        """Copy a batch in (query order); it is stored permuted by class and
+        longest ef first."""
+        self._host_q = np.ascontiguousarray(np.asarray(q, dtype=np.float32))
+        self._host_ef = np.asarray(ef, dtype=np.int32).reshape(-1)
+        self._apply()
+
+    def _apply(self):
         torch = self.torch
-        ef = np.asarray(ef, dtype=np.int32).reshape(-1)
-        order = np.argsort(-ef.astype(np.int64), kind="stable").astype(np.int32)
-        self.q.copy_(torch.as_tensor(q, dtype=torch.float32))
-        self.ef.copy_(torch.from_numpy(ef))
-        self.order.copy_(torch.from_numpy(order))
+        ef = self._host_ef
+        pool = np.maximum(ef.astype(np.int64), self.S)
+        cls = np.searchsorted(np.asarray(self.limits), pool, side="left")
+        cls = np.minimum(cls, len(self.limits) - 1)
+        perm = np.lexsort((-ef.astype(np.int64), cls)).astype(np.int64)  # class, then longest ef first (stable)
+        self.ranges = []
+        start = 0
+        for c, lim in enumerate(self.limits):
+            n = int((cls == c).sum())
+            if n:
+                # the class's own largest pool sizes its launch
+                top = int(pool[perm[start:start + n]].max())
+                self.ranges.append((start, start + n, min(top, lim)))
+            start += n
+        inv = np.empty_like(perm)
+        inv[perm] = np.arange(perm.size)
+        self.q.copy_(torch.from_numpy(self._host_q[perm]))
+        self.ef.copy_(torch.from_numpy(ef[perm]))
+        self.inv.copy_(torch.from_numpy(inv))
+        self._size_lanes()
+
+    def _size_lanes(self):
+        torch, gix = self.torch, self.gix
+        while len(self.streams) < len(self.ranges):
+            self.streams.append(torch.cuda.Stream(device=gix.device))
+        ws = []
+        for i, (r0, r1, efm) in enumerate(self.ranges):
+            nb = gix.workspace_bytes(r1 - r0, efm, self.S, self.sched)
+            old = self.ws[i] if i < len(self.ws) else None
+            ws.append(old if old is not None and old.numel() >= nb else
+                      torch.zeros(max(nb, 1), dtype=torch.uint8, device=gix.device))
+        self.ws = ws
+
+    def set_classes(self, limits: Sequence[int]):
+        """Pool limits of the ef classes (ascending); re-permutes the batch."""
+        self.limits = sorted(int(x) for x in limits)
+        if self._host_ef is not None:
+            self._apply()
+
+    # -- the step -----------------------------------------------------------
+    def _walks(self, lut, scale, sched=None):
+        """One walk launch per class, each on its own stream, joined back; the
+        class of the largest pools first, so that the longest walks start
+        first (a launch's resident slots take the device until its queue
+        drains, and the next class fills the slots it frees)."""
+        torch, gix = self.torch, self.gix
+        main = torch.cuda.current_stream(gix.device)
+        sched = sched if sched is not None else self.sched
+        for i in reversed(range(len(self.ranges))):
+            r0, r1, efm = self.ranges[i]
+            st = self.streams[i]
+            st.wait_stream(main)
+            with torch.cuda.stream(st):
+                out = SearchResult(self.res.cand_ids[r0:r1], self.res.cand_adc[r0:r1], self.res.cand_n[r0:r1],
+                                   self.res.stats[r0:r1])
+                gix.search(lut[r0:r1], None if scale is None else scale[r0:r1], ef=self.ef[r0:r1], ef_max=efm,
+                           S=self.S, sched=sched, out=out, ws=self.ws[i])
+        for i in range(len(self.ranges)):
+            main.wait_stream(self.streams[i])
 
     def _step(self):
         gix = self.gix
         lut, scale = gix.build_lut(self.q, self.lut_dtype)
-        gix.search(lut, scale, ef=self.ef, ef_max=self.ef_max, S=self.S, sched=self.sched, order=self.order,
-                   out=self.res)
-        return gix.refine(self.q, self.res.cand_ids, self.res.cand_n, self.K, self.refine_p)
+        self._walks(lut, scale)
+        ids, d = gix.refine(self.q, self.res.cand_ids, self.res.cand_n, self.K, self.refine_p)
+        return ids.index_select(0, self.inv), d.index_select(0, self.inv)
+
+    # -- tuning -------------------------------------------------------------
+    def _time_walks(self, lut, scale, sched, reps: int) -> float:
+        torch = self.torch
+        self._walks(lut, scale, sched)  # warm up
+        times = []
+        for _ in range(reps):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            self._walks(lut, scale, sched)
+            b.record()
+            b.synchronize()
+            times.append(a.elapsed_time(b))
+        times.sort()
+        return times[len(times) // 2]
 
     def tune(self, cands=None, reps: int = 3, cache_path: Optional[str] = autotune.DEFAULT_CACHE, log=None):
+        """Pick the walk schedule for the whole batch (one class), then the
+        class split, by timing the walk phase of this batch."""
+        self.set_classes([max(self.ef_max, self.S)])
         lut, scale = self.gix.build_lut(self.q, self.lut_dtype)
         self.sched, self.table = autotune.tune(self.gix, lut, ef=self.ef, ef_max=self.ef_max, S=self.S,
                                                cands=cands, reps=reps, cache_path=cache_path, log=log)
+        best = None
+        for lim in class_limits_options(self.ef_max, self.S):
+            self.set_classes(lim)
+            lut, scale = self.gix.build_lut(self.q, self.lut_dtype)
+            ms = self._time_walks(lut, scale, self.sched, reps)
+            self.table.append({"classes": lim, "schedule": self.sched.as_dict(), "ms": ms})
+            if log:
+                log(f"autotune ef classes {lim}: {ms:.3f} ms")
+            if best is None or ms < best[1]:
+                best = (lim, ms)
+        self.set_classes(best[0])
         return self.sched
 
+    # -- graph ----------------------------------------------------------------
     def capture(self):
-        """Record the step in a HIP graph (the workspace is sized beforehand so
-        that nothing is allocated or cleared by a memset inside the graph)."""
+        """Record the step in a HIP graph (the workspaces are sized beforehand
+        so that nothing is allocated or cleared by a memset inside the graph)."""
         torch = self.torch
-        self.gix.workspace(self.nq, self.ef_max, self.S, self.sched)
+        self._size_lanes()
         s = torch.cuda.Stream(device=self.gix.device)
         s.wait_stream(torch.cuda.current_stream(self.gix.device))
         with torch.cuda.stream(s):

@@ -348,8 +348,8 @@ def test_graph_replays_match_eager(c1, torch, precision):
         torch.cuda.synchronize()
         assert torch.equal(ids, eager_ids), rep
         assert torch.equal(d.view(torch.int32), eager_d.view(torch.int32)), rep
-        ws = gix.workspace(w.nq, 64, 32, bs.sched)
-        assert int(ws.count_nonzero().item()) == 0
+        for ws in bs.ws:
+            assert int(ws.count_nonzero().item()) == 0
     # a new batch through the same graph
     q2 = np.ascontiguousarray(q[::-1])
     bs.set_inputs(q2, ef[::-1].copy())
@@ -357,3 +357,32 @@ def test_graph_replays_match_eager(c1, torch, precision):
     ref_ids, ref_d, _ = gix.query(torch.from_numpy(q2), ef=torch.from_numpy(ef[::-1].copy()), ef_max=64, S=32, K=10,
                                   precision=precision)
     assert torch.equal(ids2, ref_ids)
+
+
+@pytest.mark.parametrize("precision", ["f32", "f16"])
+def test_ef_classes_give_the_same_results(c1, torch, precision):
+    # the batch split into ef classes (one concurrent walk launch each, rows
+    # permuted by class and back): every query as alone, eager and replayed
+    from paper_1804_09996_amd.batched import BatchedSearcher, class_limits_options
+    w, ix, gix, db, q = c1
+    ef = np.random.default_rng(24).integers(8, 301, w.nq).astype(np.int32)
+    assert class_limits_options(300, 32) == [[320], [128, 320], [128, 256, 320]]
+    bs = BatchedSearcher(gix, w.nq, ef_max=300, S=32, K=10, precision=precision)
+    bs.set_inputs(q, ef)
+    ref_ids, ref_d, _ = gix.query(torch.from_numpy(q), ef=torch.from_numpy(ef), ef_max=300, S=32, K=10,
+                                  precision=precision)
+    for limits in ([320], [128, 320], [128, 256, 320], [64, 128, 192, 256, 320]):
+        bs.set_classes(limits)
+        assert sum(r1 - r0 for r0, r1, _ in bs.ranges) == w.nq
+        ids, d = bs.run()
+        assert torch.equal(ids, ref_ids), limits
+        assert torch.equal(d.view(torch.int32), ref_d.view(torch.int32)), limits
+    bs.capture()
+    for rep in range(3):
+        gix.query(torch.from_numpy(q[:5]), ef=16, ef_max=16, S=16, K=5)
+        torch.cuda.synchronize()
+        ids, d = bs.run()
+        torch.cuda.synchronize()
+        assert torch.equal(ids, ref_ids), rep
+        for ws in bs.ws:
+            assert int(ws.count_nonzero().item()) == 0
