@@ -11,10 +11,11 @@ rounded up to 64): each class is walked by its own launch whose slots are
 sized for that class only (a pool of at most 128 entries lives in registers,
 and smaller pools leave LDS for more resident slots), the launches of all
 classes run concurrently inside the one graph (largest pools first), and the
-refinement runs once over the whole batch.  On the host the batch is permuted into (class, longest
-ef first) order so that every class is a contiguous range of rows; the
-results are permuted back on the device.  The class boundaries and the walk
-schedule come from the autotuner; neither changes any result.
+refinement runs once over the whole batch.  On the host the batch is
+permuted into (class, longest ef first) order so that every class is a
+contiguous range of rows; the results are permuted back on the device.  The
+class boundaries and the walk schedule come from the autotuner; neither
+changes any result.
 """
 from __future__ import annotations
 
