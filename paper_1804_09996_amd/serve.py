@@ -127,8 +127,11 @@ class GpuEngine:
         lut_t = torch.float16 if precision == "f16" else torch.float32
         self.slots = []
         for _ in range(n_slots):
-            ws_bytes = lc.lib().lc_search_workspace_bytes_sched(gix.handle, Q, ef_max, S,
-                                                               None if sched is None else lc.C.byref(sched))
+            # launches are sized by their batch's largest ef: smaller pools fit
+            # more slots (more bitsets), larger ones longer id lists
+            ws_bytes = max(lc.lib().lc_search_workspace_bytes_sched(gix.handle, Q, e, S,
+                                                                    None if sched is None else lc.C.byref(sched))
+                           for e in sorted(set(range(64, ef_max, 64)) | {1, ef_max}))
             self.slots.append({
                 "stream": torch.cuda.Stream(device=dev),
                 "q": torch.empty((Q, d), dtype=torch.float32, device=dev),
@@ -157,6 +160,9 @@ class GpuEngine:
             s["h_ef"][n:n + r.size].fill_(int(r.ef))
             n += r.size
         s["n"] = n
+        # the launch is sized for the batch's own largest ef (a pool of at most
+        # 128 entries is held in registers); the slot's workspace covers ef_max
+        ef_launch = max(int(r.ef) for r in batch)
         L, h = lc.lib(), self.gix.handle
         st = s["stream"]
         with torch.cuda.stream(st):
@@ -167,7 +173,7 @@ class GpuEngine:
             lc._check(L.lc_build_lut(h, s["q"].data_ptr(), n, self.lut_dtype, s["lut"].data_ptr(), scale, sp),
                       "lc_build_lut")
             lc._check(L.lc_search_sched(h, s["lut"].data_ptr(), self.lut_dtype, scale, n, s["ef"].data_ptr(),
-                                        self.ef_max, self.S, None, s["cand_ids"].data_ptr(), s["cand_adc"].data_ptr(),
+                                        ef_launch, self.S, None, s["cand_ids"].data_ptr(), s["cand_adc"].data_ptr(),
                                         s["cand_n"].data_ptr(), None, s["ws"].data_ptr(), s["ws"].numel(),
                                         None if self.sched is None else C.byref(self.sched), sp), "lc_search")
             lc._check(L.lc_refine(h, s["q"].data_ptr(), n, s["cand_ids"].data_ptr(), s["cand_n"].data_ptr(), self.S,

@@ -8,15 +8,18 @@ from paper_1804_09996_amd import serve
 pytestmark = pytest.mark.gpu
 
 
-@pytest.mark.parametrize("precision", ["f16", "f32"])
-def test_results_same_alone_and_in_the_mix(c1_build, precision):
+@pytest.mark.parametrize("precision,efs", [("f16", (16, 32, 64)), ("f32", (16, 32, 64)),
+                                           ("f16", (16, 64, 160, 256))])
+def test_results_same_alone_and_in_the_mix(c1_build, precision, efs):
+    # each launch is sized by its batch's largest ef (pools up to 128 in
+    # registers, larger in LDS); results never depend on it
     import torch
 
     import paper_1804_09996_amd as lc
     w, ix, db, q = c1_build
     gix = lc.Index.from_index(ix)
-    S, K, ef_max = 32, 10, 64
-    reqs = serve.poisson_requests(w.d, q, rate_rps=4000.0, n_requests=40, seed=5, efs=(16, 32, 64), max_batch=48)
+    S, K, ef_max = 32, 10, max(efs)
+    reqs = serve.poisson_requests(w.d, q, rate_rps=4000.0, n_requests=40, seed=5, efs=efs, max_batch=48)
     eng = serve.GpuEngine(gix, n_slots=3, slot_queries=128, ef_max=ef_max, S=S, K=K, precision=precision)
     sch = serve.Scheduler(3, 128, mem_budget=200 * serve.query_bytes(w.m, S, K, w.d), bytes_per_query=
                           serve.query_bytes(w.m, S, K, w.d))
