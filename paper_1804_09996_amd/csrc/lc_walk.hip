@@ -985,8 +985,8 @@ __global__ __launch_bounds__(64) void walk_kernel(WalkArgs a) {
 // The same walk with the pool in registers (pools of up to 64 R entries, R <= 2):
 // the scan for the next unexpanded entries is a ballot per chunk, one kept key
 // moves the entries above it up one lane, and several kept keys are sorted
-// and merged by bitonic networks; LDS holds only the table, the visited
-// table and 64 keys of sorting scratch.
+// and merged by bitonic networks; LDS holds only the table and the visited
+// table.
 template <int M, typename T, int R>
 __global__ __launch_bounds__(64) void walk_reg_kernel(WalkArgs a) {
   static_assert(R >= 1 && R <= 2, "pool chunks");
@@ -995,11 +995,11 @@ __global__ __launch_bounds__(64) void walk_reg_kernel(WalkArgs a) {
   const int l32 = lane & 31;
   const bool lo = lane < 32;
   constexpr int kLutBytes = M * 256 * int(sizeof(T));
-  constexpr int kScaleBytes = sizeof(T) == 2 ? (M * 4 + 15) / 16 * 16 : 0;
+  // LDS holds only the table and the visited table (the fp16 row scales live
+  // in registers, the sorting permutation goes through ds_permute), so that a
+  // slot of m = 16 fp16 with 2^11 table words takes exactly 16 KB
   T *lut = reinterpret_cast<T *>(smem);
-  float *sc = reinterpret_cast<float *>(smem + kLutBytes);
-  uint64_t *Ks = reinterpret_cast<uint64_t *>(smem + kLutBytes + kScaleBytes);  // 64 keys of sorting scratch
-  uint32_t *hash = reinterpret_cast<uint32_t *>(Ks + 64);
+  uint32_t *hash = reinterpret_cast<uint32_t *>(smem + kLutBytes);
   const int H = 1 << a.hash_bits;  // table words
   VTable vt;
   vt.t = hash;
@@ -1040,11 +1040,13 @@ __global__ __launch_bounds__(64) void walk_reg_kernel(WalkArgs a) {
     } else {
       const int efe = efq > a.S ? efq : a.S;
 
-      // stage the table (and its row scales), clear the visited table
+      // stage the table, take its row scales into registers, clear the visited table
       const float4 *src = reinterpret_cast<const float4 *>(static_cast<const T *>(a.lut) + q * (M * 256));
       for (int i = lane; i < kLutBytes / 16; i += 64) reinterpret_cast<float4 *>(lut)[i] = src[i];
-      if (sizeof(T) == 2)
-        for (int i = lane; i < M; i += 64) sc[i] = a.scale[q * M + i];
+      float scr[sizeof(T) == 2 ? M : 1];
+#pragma unroll
+      for (int i = 0; i < (sizeof(T) == 2 ? M : 1); ++i) scr[i] = sizeof(T) == 2 ? a.scale[q * M + i] : 1.f;
+      const float *sc = scr;
       for (int i = lane; i < H; i += 64) hash[i] = kEmpty;
       wave_sync();
 
@@ -1123,10 +1125,11 @@ __global__ __launch_bounds__(64) void walk_reg_kernel(WalkArgs a) {
                 rank += kj < k ? 1 : 0;
               }
               const int below = __popcll(km & ((1ull << lane) - 1ull));
-              Ks[keep ? rank : nn + lane - below] = keep ? k : kKeyMax;
-              wave_sync();
-              kv = Ks[lane];
-              wave_sync();
+              const int dst = (keep ? rank : nn + lane - below) * 4;
+              const uint64_t v = keep ? k : kKeyMax;
+              const uint32_t lo32 = uint32_t(__builtin_amdgcn_ds_permute(dst, int(uint32_t(v))));
+              const uint32_t hi32 = uint32_t(__builtin_amdgcn_ds_permute(dst, int(uint32_t(v >> 32))));
+              kv = (uint64_t(hi32) << 32) | lo32;
             } else {
               kv = bitonic_sort(keep ? k : kKeyMax, lane);
             }
@@ -1417,8 +1420,8 @@ constexpr size_t kHeaderBytes = 256;  // two queue counters, padded
 template <int M>
 int lds_bytes_for(int w_cap, int hash_bits, int lut_bytes, bool reg) {
   const int scale_bytes = lut_bytes == 2 ? (M * 4 + 15) / 16 * 16 : 0;
-  const int pool_bytes = reg ? 64 * 8 : w_cap * 8 + kMergeScratch * 8;
-  return M * 256 * lut_bytes + scale_bytes + pool_bytes + (1 << hash_bits) * 4;
+  if (reg) return M * 256 * lut_bytes + (1 << hash_bits) * 4;  // table and visited table only
+  return M * 256 * lut_bytes + scale_bytes + w_cap * 8 + kMergeScratch * 8 + (1 << hash_bits) * 4;
 }
 
 // Tag width of a narrow visited table with 2^(hash_bits-2) buckets for ids
