@@ -62,7 +62,9 @@ def traffic_from_profiles(kernel_src, precision, ef, S):
     t = json.load(open(path))
     sha = hashlib.sha1(open(kernel_src, "rb").read()).hexdigest()
     c = t.get("config", {})
-    if t.get("kernel_sha1") != sha or (c.get("precision"), c.get("ef"), c.get("S")) != (precision, ef, S):
+    # the walk depends on the table type only (the refinement precision does not enter it)
+    table = precision.split("+")[0]
+    if t.get("kernel_sha1") != sha or (c.get("precision"), c.get("ef"), c.get("S")) != (table, ef, S):
         return None
     return t.get("bytes_per_launch")
 
@@ -399,8 +401,10 @@ def main():
         head = run(args.precision, args.ef or w.ef, args.shortlist or w.shortlist, args.steps, args.warmup)
     curves = {}
     if args.form == "both":
+        # the workload's operating point, smaller short-lists, and larger pools in steps fine enough near
+        # it that a form just short of the recall target at one point meets it at the next
         grid = sorted({(w.ef, s_) for s_ in (K, (K + w.shortlist) // 2, w.shortlist) if s_ >= K} |
-                      {(e_, w.shortlist) for e_ in (w.ef_eff + 64, w.ef_eff + 128)})
+                      {(e_, w.shortlist) for e_ in (w.ef_eff + 16, w.ef_eff + 32, w.ef_eff + 64, w.ef_eff + 128)})
         for form in FORMS:
             curves[form] = []
             for ef_, s_ in grid:
