@@ -290,8 +290,9 @@ def main():
                     help="also run one device-to-device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this benchmark runs on exactly one GPU; multi-GPU runs are not part of this "
-                                   "build (see DESIGN.md for how the path would shard)", "n_gpus": args.gpus}))
+        print(json.dumps({"error": "this benchmark runs on exactly one GPU: the search shards over GPUs by query "
+                                   "slices or by database shards, each GPU running this path on its share",
+                          "n_gpus": args.gpus}))
         sys.exit(2)
 
     import torch
