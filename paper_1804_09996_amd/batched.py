@@ -39,6 +39,26 @@ def class_limits_options(ef_max: int, S: int) -> List[List[int]]:
     return opts
 
 
+def class_permutation(ef: np.ndarray, S: int, limits: Sequence[int]):
+    """Order of the batch by (class, longest ef first) and the classes' row
+    ranges (start, end, largest pool in the class).  A query's class is the
+    first limit at or above its pool max(ef, S); pools above the last limit go
+    to the last class."""
+    ef = np.asarray(ef, dtype=np.int64).reshape(-1)
+    limits = np.asarray(sorted(int(x) for x in limits))
+    pool = np.maximum(ef, S)
+    cls = np.minimum(np.searchsorted(limits, pool, side="left"), len(limits) - 1)
+    perm = np.lexsort((-ef, cls)).astype(np.int64)  # class, then longest ef first (stable)
+    ranges, start = [], 0
+    for c, lim in enumerate(limits):
+        n = int((cls == c).sum())
+        if n:
+            top = int(pool[perm[start:start + n]].max())  # the class's own largest pool sizes its launch
+            ranges.append((start, start + n, top))
+        start += n
+    return perm, ranges
+
+
 class BatchedSearcher:
     def __init__(self, gix, nq: int, ef_max: int, S: int, K: int, precision: str = "f32"):
         torch = gix.torch
@@ -75,19 +95,7 @@ class BatchedSearcher:
     def _apply(self):
         torch = self.torch
         ef = self._host_ef
-        pool = np.maximum(ef.astype(np.int64), self.S)
-        cls = np.searchsorted(np.asarray(self.limits), pool, side="left")
-        cls = np.minimum(cls, len(self.limits) - 1)
-        perm = np.lexsort((-ef.astype(np.int64), cls)).astype(np.int64)  # class, then longest ef first (stable)
-        self.ranges = []
-        start = 0
-        for c, lim in enumerate(self.limits):
-            n = int((cls == c).sum())
-            if n:
-                # the class's own largest pool sizes its launch
-                top = int(pool[perm[start:start + n]].max())
-                self.ranges.append((start, start + n, min(top, lim)))
-            start += n
+        perm, self.ranges = class_permutation(ef, self.S, self.limits)
         inv = np.empty_like(perm)
         inv[perm] = np.arange(perm.size)
         self.q.copy_(torch.from_numpy(self._host_q[perm]))
