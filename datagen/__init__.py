@@ -80,6 +80,7 @@ class Workload:
     beta_kmeans_iters: int = 20
     em_iters: int = 10            # Sec. 5.2
     seed: int = DEFAULT_SEED
+    m_beta: int = 1               # regression-codebook blocks (product codebook, Sec. 4.3 Eq. 9)
 
     @property
     def dsub(self) -> int:

@@ -47,7 +47,7 @@ _i64 = C.c_int64
 
 class OrcIndex(C.Structure):
     _fields_ = [(n, C.c_int32) for n in ("n", "d", "d_pad", "m", "ksub", "code_stride", "deg0", "deg_up",
-                                          "k_reg", "n_beta", "entry", "max_level")] + \
+                                          "k_reg", "n_beta", "entry", "max_level", "m_beta")] + \
                [(n, _p) for n in ("proj", "centroids", "codes", "adj0", "up_base", "adj_up", "beta", "beta_idx")]
 
 
@@ -59,10 +59,10 @@ def _declare(L):
     L.orc_levels.restype = _i64
     L.orc_hnsw_build.argtypes = [_p, _i64, _i, _p, _i, _i, _i, _p, _p, _i, _p, _i, _i, _i, _i, _p, _p, _p, _p, _p]
     L.orc_lsq_solve.argtypes = [_p, _p, _i, _p]
-    L.orc_beta_train.argtypes = [_p, _p, _i64, _i, _p, _i, _i, _i, _p, _p, _i, _p, _i, _i, _i, _p, _i, _i, _i,
-                                 _p, _p]
+    L.orc_beta_train.argtypes = [_p, _p, _i64, _i, _p, _i, _i, _i, _p, _p, _i, _p, _i, _i, _i, _i, _p, _i, _i,
+                                 _i, _p, _p]
     L.orc_beta_shared.argtypes = [_p, _p, _i64, _i, _p, _i, _i, _i, _p, _p, _i, _p, _i, _i, _p]
-    L.orc_beta_assign.argtypes = [_p, _i64, _i, _p, _i, _i, _i, _p, _p, _i, _p, _i, _i, _i, _p, _i, _p]
+    L.orc_beta_assign.argtypes = [_p, _i64, _i, _p, _i, _i, _i, _p, _p, _i, _p, _i, _i, _i, _i, _p, _i, _p]
     L.orc_lut.argtypes = [C.POINTER(OrcIndex), _p, _p]
     L.orc_lut.restype = None
     L.orc_search.argtypes = [C.POINTER(OrcIndex), _p, _i64, _p, C.c_int32, C.c_int32, _i, _p, _p, _p, _p, _p, _p]
@@ -183,19 +183,24 @@ def lsq_solve(a: np.ndarray, c: np.ndarray):
     return beta, int(rc)
 
 
-def beta_train(x, ids, proj, d_pad, cent, codes, adj0, k_reg, n_beta, init, km_iters, em_iters, nthreads=1):
+def beta_train(x, ids, proj, d_pad, cent, codes, adj0, k_reg, n_beta, init, km_iters, em_iters, nthreads=1,
+               m_beta=1):
+    """Regression codebook(s): [n_beta, k+1] for one block, [m_beta, n_beta, k+1]
+    for the product codebook (Eq. 9); the loss history likewise per block."""
     x = _c(x, np.float32)
     ids = _c(ids, np.int64)
     proj = None if proj is None else _c(proj, np.float32)
     init = _c(init, np.int64)
-    beta = np.empty((n_beta, k_reg + 1), np.float32)
-    hist = np.empty(em_iters + 1, np.float64)
+    beta = np.empty((m_beta, n_beta, k_reg + 1), np.float32)
+    hist = np.empty((m_beta, em_iters + 1), np.float64)
     rc = _load().orc_beta_train(_ptr(x), _ptr(ids), ids.shape[0], x.shape[1], _ptr(proj), d_pad, cent.shape[0],
                                 cent.shape[1], _ptr(_c(cent, np.float32)), _ptr(_c(codes, np.uint8)), codes.shape[1],
-                                _ptr(_c(adj0, np.int32)), adj0.shape[1], k_reg, n_beta, _ptr(init), km_iters, em_iters,
-                                nthreads, _ptr(beta), _ptr(hist))
+                                _ptr(_c(adj0, np.int32)), adj0.shape[1], k_reg, n_beta, m_beta, _ptr(init), km_iters,
+                                em_iters, nthreads, _ptr(beta), _ptr(hist))
     if rc != 0:
         raise ValueError(f"orc_beta_train failed ({rc})")
+    if m_beta == 1:
+        return beta[0], hist[0]
     return beta, hist
 
 
@@ -213,17 +218,20 @@ def beta_shared(x, ids, proj, d_pad, cent, codes, adj0, k_reg):
 
 
 def beta_assign(x, proj, d_pad, cent, codes, adj0, k_reg, beta, nthreads=1):
+    """Entry per vector: [n] for a [n_beta, k+1] codebook, [n, m_beta] for a
+    [m_beta, n_beta, k+1] product codebook."""
     x = _c(x, np.float32)
     proj = None if proj is None else _c(proj, np.float32)
     beta = _c(beta, np.float32)
-    out = np.empty(x.shape[0], np.uint8)
+    mb = 1 if beta.ndim == 2 else beta.shape[0]
+    out = np.empty((x.shape[0], mb), np.uint8)
     rc = _load().orc_beta_assign(_ptr(x), x.shape[0], x.shape[1], _ptr(proj), d_pad, cent.shape[0], cent.shape[1],
                                  _ptr(_c(cent, np.float32)), _ptr(_c(codes, np.uint8)), codes.shape[1],
-                                 _ptr(_c(adj0, np.int32)), adj0.shape[1], k_reg, beta.shape[0], _ptr(beta), nthreads,
-                                 _ptr(out))
+                                 _ptr(_c(adj0, np.int32)), adj0.shape[1], k_reg, beta.shape[-2], mb, _ptr(beta),
+                                 nthreads, _ptr(out))
     if rc != 0:
         raise ValueError(f"orc_beta_assign failed ({rc})")
-    return out
+    return out[:, 0].copy() if beta.ndim == 2 else out
 
 
 # ---------------------------------------------------------------------------
@@ -252,6 +260,7 @@ class Index:
     beta: np.ndarray
     beta_idx: np.ndarray
     ksub: int = 256
+    m_beta: int = 1       # product codebook blocks (Eq. 9): beta [m_beta, n_beta, k+1], beta_idx [n, m_beta]
 
     def arrays(self) -> dict:
         return {k: getattr(self, k) for k in ("proj", "centroids", "codes", "adj0", "level", "up_base", "adj_up",
@@ -262,7 +271,9 @@ class Index:
         s.n, s.d, s.d_pad, s.m, s.ksub = self.n, self.d, self.d_pad, self.m, self.ksub
         s.code_stride = self.codes.shape[1]
         s.deg0, s.deg_up, s.k_reg, s.n_beta = self.deg0, self.deg_up, self.k_reg, self.n_beta
-        s.entry, s.max_level = self.entry, self.max_level
+        s.entry, s.max_level, s.m_beta = self.entry, self.max_level, self.m_beta
+        if self.beta.size != self.m_beta * self.n_beta * (self.k_reg + 1) or self.beta_idx.size != self.n * self.m_beta:
+            raise ValueError("beta / beta_idx do not match (m_beta, n_beta, k_reg, n)")
         for name in ("proj", "centroids", "codes", "adj0", "up_base", "adj_up", "beta", "beta_idx"):
             a = getattr(self, name)
             setattr(s, name, None if a is None or a.size == 0 else a.ctypes.data)
@@ -313,11 +324,11 @@ def build_index(w, db: np.ndarray, train: np.ndarray, proj: Optional[np.ndarray]
     adj0, up_base, adj_up, entry, maxl = hnsw_build(db, proj, w.d_pad, cent, codes, lv, w.deg0, w.deg_up,
                                                     w.ef_construction, nt)
     beta, _ = beta_train(db, beta_ids, proj, w.d_pad, cent, codes, adj0, w.k_reg, w.n_beta, beta_init,
-                         w.beta_kmeans_iters, w.em_iters, nt)
+                         w.beta_kmeans_iters, w.em_iters, nt, m_beta=w.m_beta)
     bidx = beta_assign(db, proj, w.d_pad, cent, codes, adj0, w.k_reg, beta, nt)
     return Index(n=db.shape[0], d=db.shape[1], d_pad=w.d_pad, m=w.m, deg0=w.deg0, deg_up=w.deg_up, k_reg=w.k_reg,
                  n_beta=w.n_beta, entry=entry, max_level=maxl, proj=proj, centroids=cent, codes=codes, adj0=adj0,
-                 level=lv, up_base=up_base, adj_up=adj_up, beta=beta, beta_idx=bidx)
+                 level=lv, up_base=up_base, adj_up=adj_up, beta=beta, beta_idx=bidx, m_beta=w.m_beta)
 
 
 def build_workload(w, nthreads: Optional[int] = None) -> tuple:

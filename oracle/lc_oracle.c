@@ -782,12 +782,15 @@ typedef struct {
   const int32_t *adj0;
   const int64_t *ids;
   int d, d_pad, m, ksub, dsub, code_stride, deg0, p;
+  int t0, t1; /* coordinates of the block the Gram covers (Sec. 4.3, product codebook) */
   double *A;  /* [n][p][p] G^T G      */
   double *C;  /* [n][p]    G^T x      */
   double *XX; /* [n]       ||x||^2    */
 } gram_ctx;
 
-/* G(x) = [q(x), q(g_1(x)), ..., q(g_k(x))] (Sec. 4.2), a -1 link being a zero column */
+/* G(x) = [q(x), q(g_1(x)), ..., q(g_k(x))] (Sec. 4.2), a -1 link being a zero column;
+ * the products are taken over the coordinates [t0, t1) only, which is G^j(x) and
+ * x^j of the product codebook (Sec. 4.3, Eq. 9); [0, d_pad) is the whole vector */
 static void gram_one(int64_t r, int tid, void *vctx) {
   (void)tid;
   gram_ctx *g = (gram_ctx *)vctx;
@@ -807,15 +810,15 @@ static void gram_one(int64_t r, int tid, void *vctx) {
   for (int a = 0; a < p; a++) {
     for (int b = 0; b < p; b++) {
       double s = 0;
-      for (int t = 0; t < dp; t++) s += G[a * dp + t] * G[b * dp + t];
+      for (int t = g->t0; t < g->t1; t++) s += G[a * dp + t] * G[b * dp + t];
       A[a * p + b] = s;
     }
     double s = 0;
-    for (int t = 0; t < dp; t++) s += G[a * dp + t] * xp[t];
+    for (int t = g->t0; t < g->t1; t++) s += G[a * dp + t] * xp[t];
     C[a] = s;
   }
   double s = 0;
-  for (int t = 0; t < dp; t++) s += xp[t] * xp[t];
+  for (int t = g->t0; t < g->t1; t++) s += xp[t] * xp[t];
   g->XX[r] = s;
   free(G);
   free(xp);
@@ -870,26 +873,23 @@ static void gram_free(gram_ctx *g) {
   free(g->XX);
 }
 
-int orc_beta_train(const float *x, const int64_t *ids, int64_t n_sub, int d, const float *proj,
-                   int d_pad, int m, int ksub, const float *cent, const uint8_t *codes,
-                   int code_stride, const int32_t *adj0, int deg0, int k_reg, int n_beta,
-                   const int64_t *init, int km_iters, int em_iters, int nthreads, float *beta,
-                   double *loss_hist) {
-  if (k_reg > deg0 || n_beta > n_sub || n_sub < 1) return -1;
-  int p = k_reg + 1;
-  gram_ctx g = {x, proj, cent, codes, adj0, ids, d, d_pad, m, ksub, d_pad / m, code_stride, deg0, p, 0, 0, 0};
-  if (gram_alloc(&g, n_sub)) return -2;
-  orc_parallel_for(n_sub, nthreads, gram_one, &g);
+/* One codebook (Sec. 4.3): per-vector optimum, k-means on it, then EM over
+ * assignment (Eq. 7) and per-cluster least squares (Eq. 8), on the Grams of
+ * one block of coordinates. */
+static void beta_train_block(gram_ctx *g, int64_t n_sub, int n_beta, const int64_t *init, int km_iters,
+                             int em_iters, int nthreads, float *beta, double *loss_hist) {
+  int p = g->p;
+  orc_parallel_for(n_sub, nthreads, gram_one, g);
   /* per-vector optimum beta(x) (Eq. 2 with G(x) for N(x)) seeds a k-means */
   double *bx = (double *)malloc(sizeof(double) * (size_t)n_sub * p);
-  for (int64_t r = 0; r < n_sub; r++) orc_lsq_solve(g.A + r * p * p, g.C + r * p, p, bx + r * p);
+  for (int64_t r = 0; r < n_sub; r++) orc_lsq_solve(g->A + r * p * p, g->C + r * p, p, bx + r * p);
   double *B = (double *)malloc(sizeof(double) * (size_t)n_beta * p);
   int32_t *as = (int32_t *)malloc(sizeof(int32_t) * (size_t)n_sub);
   double *ls = (double *)malloc(sizeof(double) * (size_t)n_sub);
   orc_kmeans(bx, n_sub, p, n_beta, init, km_iters, nthreads, B, as, NULL);
   double *SA = (double *)malloc(sizeof(double) * (size_t)p * p);
   double *SC = (double *)malloc(sizeof(double) * (size_t)p);
-  asg_ctx ac = {&g, B, n_beta, as, ls};
+  asg_ctx ac = {g, B, n_beta, as, ls};
   for (int it = 0;; it++) {
     /* assignment step (Eq. 7) */
     orc_parallel_for(n_sub, nthreads, assign_one, &ac);
@@ -907,8 +907,8 @@ int orc_beta_train(const float *x, const int64_t *ids, int64_t n_sub, int d, con
       for (int64_t r = 0; r < n_sub; r++) {
         if (as[r] != b) continue;
         cnt++;
-        for (int t = 0; t < p * p; t++) SA[t] += g.A[r * p * p + t];
-        for (int t = 0; t < p; t++) SC[t] += g.C[r * p + t];
+        for (int t = 0; t < p * p; t++) SA[t] += g->A[r * p * p + t];
+        for (int t = 0; t < p; t++) SC[t] += g->C[r * p + t];
       }
       if (cnt > 0) orc_lsq_solve(SA, SC, p, B + (int64_t)b * p);
     }
@@ -920,6 +920,26 @@ int orc_beta_train(const float *x, const int64_t *ids, int64_t n_sub, int d, con
   free(ls);
   free(SA);
   free(SC);
+}
+
+int orc_beta_train(const float *x, const int64_t *ids, int64_t n_sub, int d, const float *proj,
+                   int d_pad, int m, int ksub, const float *cent, const uint8_t *codes,
+                   int code_stride, const int32_t *adj0, int deg0, int k_reg, int n_beta, int m_beta,
+                   const int64_t *init, int km_iters, int em_iters, int nthreads, float *beta,
+                   double *loss_hist) {
+  if (k_reg > deg0 || n_beta > n_sub || n_sub < 1 || m_beta < 1 || m % m_beta) return -1;
+  int p = k_reg + 1;
+  gram_ctx g = {x, proj, cent, codes, adj0, ids, d, d_pad, m, ksub, d_pad / m, code_stride, deg0, p, 0, d_pad, 0, 0, 0};
+  if (gram_alloc(&g, n_sub)) return -2;
+  /* product codebook (Sec. 4.3, Eq. 9): block j is the coordinates
+   * [j d_pad / m_beta, (j+1) d_pad / m_beta), m / m_beta whole sub-quantizers;
+   * each block trains its own codebook from the same seeds */
+  for (int jb = 0; jb < m_beta; jb++) {
+    g.t0 = jb * (d_pad / m_beta);
+    g.t1 = g.t0 + d_pad / m_beta;
+    beta_train_block(&g, n_sub, n_beta, init, km_iters, em_iters, nthreads, beta + (int64_t)jb * n_beta * p,
+                     loss_hist ? loss_hist + (int64_t)jb * (em_iters + 1) : NULL);
+  }
   gram_free(&g);
   return 0;
 }
@@ -929,7 +949,7 @@ int orc_beta_shared(const float *x, const int64_t *ids, int64_t n_sub, int d, co
                     int code_stride, const int32_t *adj0, int deg0, int k_reg, double *beta) {
   if (k_reg > deg0 || n_sub < 1) return -1;
   int p = k_reg + 1;
-  gram_ctx g = {x, proj, cent, codes, adj0, ids, d, d_pad, m, ksub, d_pad / m, code_stride, deg0, p, 0, 0, 0};
+  gram_ctx g = {x, proj, cent, codes, adj0, ids, d, d_pad, m, ksub, d_pad / m, code_stride, deg0, p, 0, d_pad, 0, 0, 0};
   if (gram_alloc(&g, n_sub)) return -2;
   orc_parallel_for(n_sub, 1, gram_one, &g);
   double *SA = (double *)calloc((size_t)p * p, sizeof(double));
@@ -947,12 +967,12 @@ int orc_beta_shared(const float *x, const int64_t *ids, int64_t n_sub, int d, co
 
 int orc_beta_assign(const float *x, int64_t n, int d, const float *proj, int d_pad, int m,
                     int ksub, const float *cent, const uint8_t *codes, int code_stride,
-                    const int32_t *adj0, int deg0, int k_reg, int n_beta, const float *beta,
+                    const int32_t *adj0, int deg0, int k_reg, int n_beta, int m_beta, const float *beta,
                     int nthreads, uint8_t *beta_idx) {
-  if (k_reg > deg0 || n_beta > 256) return -1;
+  if (k_reg > deg0 || n_beta > 256 || m_beta < 1 || m % m_beta) return -1;
   int p = k_reg + 1;
-  double *B = (double *)malloc(sizeof(double) * (size_t)n_beta * p);
-  for (int64_t t = 0; t < (int64_t)n_beta * p; t++) B[t] = (double)beta[t];
+  double *B = (double *)malloc(sizeof(double) * (size_t)m_beta * n_beta * p);
+  for (int64_t t = 0; t < (int64_t)m_beta * n_beta * p; t++) B[t] = (double)beta[t];
   int64_t chunk = 65536;
   int32_t *as = (int32_t *)malloc(sizeof(int32_t) * (size_t)chunk);
   double *ls = (double *)malloc(sizeof(double) * (size_t)chunk);
@@ -960,12 +980,17 @@ int orc_beta_assign(const float *x, int64_t n, int d, const float *proj, int d_p
   for (int64_t c0 = 0; c0 < n; c0 += chunk) {
     int64_t c1 = c0 + chunk < n ? c0 + chunk : n;
     for (int64_t i = c0; i < c1; i++) ids[i - c0] = i;
-    gram_ctx g = {x, proj, cent, codes, adj0, ids, d, d_pad, m, ksub, d_pad / m, code_stride, deg0, p, 0, 0, 0};
+    gram_ctx g = {x, proj, cent, codes, adj0, ids, d, d_pad, m, ksub, d_pad / m, code_stride, deg0, p, 0, d_pad, 0, 0, 0};
     if (gram_alloc(&g, c1 - c0)) return -2;
-    orc_parallel_for(c1 - c0, nthreads, gram_one, &g);
-    asg_ctx ac = {&g, B, n_beta, as, ls};
-    orc_parallel_for(c1 - c0, nthreads, assign_one, &ac);
-    for (int64_t i = c0; i < c1; i++) beta_idx[i] = (uint8_t)as[i - c0];
+    /* each block of the product codebook picks its own entry (Eq. 7 on x^j, G^j) */
+    for (int jb = 0; jb < m_beta; jb++) {
+      g.t0 = jb * (d_pad / m_beta);
+      g.t1 = g.t0 + d_pad / m_beta;
+      orc_parallel_for(c1 - c0, nthreads, gram_one, &g);
+      asg_ctx ac = {&g, B + (int64_t)jb * n_beta * p, n_beta, as, ls};
+      orc_parallel_for(c1 - c0, nthreads, assign_one, &ac);
+      for (int64_t i = c0; i < c1; i++) beta_idx[i * m_beta + jb] = (uint8_t)as[i - c0];
+    }
     gram_free(&g);
   }
   free(B);
@@ -1007,12 +1032,17 @@ double orc_refined_distance(const orc_index *ix, const float *y, int32_t i) {
   double *xr = (double *)calloc((size_t)dp, sizeof(double));
   double *q = (double *)malloc(sizeof(double) * dp);
   orc_project(ix->proj, dp, ix->d, y, yp);
-  const float *b = ix->beta + (int64_t)ix->beta_idx[i] * p;
+  /* block jb of x~ uses its own codebook entry (Sec. 4.3, Eq. 9); one block is Eq. 5 */
+  int mb = ix->m_beta, bw = dp / mb;
   for (int j = 0; j < p; j++) {
     int32_t g = j == 0 ? i : ix->adj0[(int64_t)i * ix->deg0 + (j - 1)];
     if (g < 0) continue; /* a missing link is a zero vector */
     decode(ix->centroids, ix->codes, ix->code_stride, ix->m, ix->ksub, dsub, g, q);
-    for (int t = 0; t < dp; t++) xr[t] += (double)b[j] * q[t];
+    for (int t = 0; t < dp; t++) {
+      int jb = t / bw;
+      const float *b = ix->beta + ((int64_t)jb * ix->n_beta + ix->beta_idx[(int64_t)i * mb + jb]) * p;
+      xr[t] += (double)b[j] * q[t];
+    }
   }
   double e = sqdist(yp, xr, dp);
   free(yp);

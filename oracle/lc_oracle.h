@@ -18,8 +18,11 @@
  *   up_base [n] i32                  first upper row of node i, -1 if level 0;
  *                                    the row of level l >= 1 is up_base[i]+l-1
  *   adj_up  [rows][deg_up] i32       upper-level links, -1 padded
- *   beta    [n_beta][k+1] f32        regression codebook (Sec. 4.3)
- *   beta_idx[n] u8                   selected codebook entry per vector
+ *   beta    [m_beta][n_beta][k+1] f32  regression codebook (Sec. 4.3), one per
+ *                                    block of d_pad / m_beta coordinates (the
+ *                                    product codebook of Eq. 9; m_beta = 1 is
+ *                                    the single codebook of Eq. 5-8)
+ *   beta_idx[n][m_beta] u8           selected entry per vector and block
  *
  * Parity: unpinned functions are marked "parity unpinned" below; every other
  * function is pinned by a CPU test against a closed form, brute force or a
@@ -37,6 +40,7 @@ typedef struct {
   int32_t n, d, d_pad, m, ksub, code_stride;
   int32_t deg0, deg_up, k_reg, n_beta;
   int32_t entry, max_level;
+  int32_t m_beta; /* regression-codebook blocks, divides m */
   const float *proj;       /* [d_pad][d] or NULL when d_pad == d */
   const float *centroids;  /* [m][ksub][dsub] */
   const uint8_t *codes;
@@ -82,11 +86,13 @@ int orc_hnsw_build(const float *x, int64_t n, int d, const float *proj, int d_pa
  * A = G^T G and c = G^T x; Cholesky, else eigen pseudo-inverse. */
 int orc_lsq_solve(const double *a, const double *c, int p, double *beta);
 
-/* Regression-codebook training (Sec. 4.3, Eq. 6-8).  loss_hist receives
- * em_iters+1 values of L'(B) after each assignment step. */
+/* Regression-codebook training (Sec. 4.3, Eq. 6-8), one codebook per block of
+ * d_pad / m_beta coordinates (Eq. 9; m_beta divides m).  beta receives
+ * [m_beta][n_beta][k+1]; loss_hist [m_beta][em_iters+1] values of L'(B) after
+ * each assignment step. */
 int orc_beta_train(const float *x, const int64_t *ids, int64_t n_sub, int d, const float *proj,
                    int d_pad, int m, int ksub, const float *cent, const uint8_t *codes,
-                   int code_stride, const int32_t *adj0, int deg0, int k_reg, int n_beta,
+                   int code_stride, const int32_t *adj0, int deg0, int k_reg, int n_beta, int m_beta,
                    const int64_t *init, int km_iters, int em_iters, int nthreads, float *beta,
                    double *loss_hist);
 
@@ -95,10 +101,11 @@ int orc_beta_shared(const float *x, const int64_t *ids, int64_t n_sub, int d, co
                     int d_pad, int m, int ksub, const float *cent, const uint8_t *codes,
                     int code_stride, const int32_t *adj0, int deg0, int k_reg, double *beta);
 
-/* Assignment (Sec. 4.3, Eq. 7) with the stored f32 codebook, lowest index on ties. */
+/* Assignment (Sec. 4.3, Eq. 7) with the stored f32 codebook, lowest index on
+ * ties, block by block; beta_idx receives [n][m_beta]. */
 int orc_beta_assign(const float *x, int64_t n, int d, const float *proj, int d_pad, int m,
                     int ksub, const float *cent, const uint8_t *codes, int code_stride,
-                    const int32_t *adj0, int deg0, int k_reg, int n_beta, const float *beta,
+                    const int32_t *adj0, int deg0, int k_reg, int n_beta, int m_beta, const float *beta,
                     int nthreads, uint8_t *beta_idx);
 
 /* Per-query ADC table LUT[s][c] = ||y'^s - C[s][c]||^2 in float64. */
@@ -112,7 +119,8 @@ int orc_search(const orc_index *ix, const float *q, int64_t nq, const int32_t *e
                int32_t K, int nthreads, int32_t *out_ids, double *out_d, int32_t *cand_ids,
                double *cand_adc, int32_t *cand_n, int32_t *stats);
 
-/* Refined squared distance ||y' - sum_j beta_j q(g_j(i))||^2 for any id. */
+/* Refined squared distance ||y' - x~_i||^2 for any id, x~_i = sum_j beta_j q(g_j(i))
+ * block by block (Eq. 5, Eq. 9). */
 double orc_refined_distance(const orc_index *ix, const float *y, int32_t i);
 
 /* Sequence of expanded ids of one query's level-0 walk (for trace diffs).

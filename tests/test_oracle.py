@@ -456,3 +456,115 @@ def test_beta_first_weight_soft_check(tiny_build, capsys):
     beta = oracle.beta_shared(db, np.arange(ix.n), ix.proj, w.d_pad, ix.centroids, ix.codes, ix.adj0, w.k_reg)
     assert np.all(np.isfinite(beta))
     print(f"shared beta_0 = {beta[0]:.3f}")
+
+
+# ---------------------------------------------------------------------------
+# product regression codebook (Sec. 4.3, Eq. 9): one codebook per block of
+# d_pad / m_beta coordinates, one byte per block and vector
+# ---------------------------------------------------------------------------
+def _block(ix, m_beta, jb):
+    bw = ix.d_pad // m_beta
+    return slice(jb * bw, (jb + 1) * bw)
+
+
+def _G(ix, rec, i, k_reg):
+    return np.stack([rec[i]] + [rec[g] if g >= 0 else np.zeros(ix.d_pad) for g in ix.adj0[i, :k_reg]], 1)
+
+
+def test_product_refine_bruteforce(tiny_build):
+    # x~ = [beta^1 G^1(x), ..., beta^M G^M(x)] with each block's own entry
+    import dataclasses
+    w, ix, db, q = tiny_build
+    rs = np.random.default_rng(11)
+    for mb in (2, 4):
+        B = rs.standard_normal((mb, 5, w.k_reg + 1)).astype(np.float32)
+        bi = rs.integers(0, 5, (ix.n, mb)).astype(np.uint8)
+        ixp = dataclasses.replace(ix, beta=B, beta_idx=bi, n_beta=5, m_beta=mb)
+        rec = decode_all(ix)
+        for y in q[:3]:
+            yp = proj_np(ix, y)
+            for i in range(0, ix.n, 113):
+                G = _G(ix, rec, i, w.k_reg)
+                xt = np.concatenate([G[_block(ix, mb, jb)] @ B[jb, bi[i, jb]].astype(np.float64) for jb in range(mb)])
+                assert ixp.refined_distance(y, i) == pytest.approx(((yp - xt) ** 2).sum(), rel=1e-12)
+
+
+def test_product_codebook_of_one_entry_is_blockwise_least_squares(tiny_build):
+    # With one entry per block, EM ends on Eq. 4 restricted to each block's
+    # coordinates: beta^j = argmin sum_x ||x^j - G^j(x) beta||^2 (numpy lstsq)
+    w, ix, db, q = tiny_build
+    ids = np.arange(0, ix.n, 5)
+    rec = decode_all(ix)
+    for mb in (2, 4):
+        beta, hist = oracle.beta_train(db, ids, ix.proj, w.d_pad, ix.centroids, ix.codes, ix.adj0, w.k_reg, 1,
+                                       np.zeros(1, np.int64), 2, 2, nthreads=2, m_beta=mb)
+        assert beta.shape == (mb, 1, w.k_reg + 1) and hist.shape == (mb, 3)
+        for jb in range(mb):
+            bl = _block(ix, mb, jb)
+            Y = np.concatenate([_G(ix, rec, i, w.k_reg)[bl] for i in ids], 0)
+            X = np.concatenate([proj_np(ix, db[i])[bl] for i in ids], 0)
+            ref = np.linalg.lstsq(Y, X, rcond=None)[0]
+            np.testing.assert_allclose(beta[jb, 0], ref, rtol=2e-6, atol=1e-6)  # stored as float32
+            assert hist[jb, -1] == pytest.approx(((X - Y @ ref) ** 2).sum(), rel=1e-9)
+
+
+def test_product_loss_at_most_single_codebook_loss(tiny_build):
+    # A block-diagonal estimator contains the single one (same beta in every
+    # block), so with one entry the product's training loss cannot be larger
+    w, ix, db, q = tiny_build
+    ids = np.arange(0, ix.n, 3)
+    args = (db, ids, ix.proj, w.d_pad, ix.centroids, ix.codes, ix.adj0, w.k_reg, 1, np.zeros(1, np.int64), 2, 2)
+    _, h1 = oracle.beta_train(*args, nthreads=2)
+    _, h4 = oracle.beta_train(*args, nthreads=2, m_beta=4)
+    assert h4[:, -1].sum() <= h1[-1] * (1 + 1e-12)
+    assert h4[:, -1].sum() < h1[-1]  # and strictly better on this data
+
+
+def test_product_em_loss_never_increases(tiny_build):
+    w, ix, db, q = tiny_build
+    ids = datagen.beta_train_ids(w)
+    init = datagen.beta_init_ids(w, ids.size)
+    beta, hist = oracle.beta_train(db, ids, ix.proj, w.d_pad, ix.centroids, ix.codes, ix.adj0, w.k_reg,
+                                   w.n_beta, init, w.beta_kmeans_iters, 5, nthreads=4, m_beta=2)
+    assert beta.shape == (2, w.n_beta, w.k_reg + 1)
+    assert np.all(np.diff(hist, axis=1) <= 1e-9 * hist[:, :1])
+
+
+def test_product_assignment_is_blockwise_bruteforce_argmin(tiny_build):
+    w, ix, db, q = tiny_build
+    rs = np.random.default_rng(12)
+    mb = 2
+    B = rs.standard_normal((mb, 7, w.k_reg + 1)).astype(np.float32)
+    B[:, :, 0] += 1.0  # keep the entries near q(x) so that the argmins differ between blocks
+    bidx = oracle.beta_assign(db, ix.proj, w.d_pad, ix.centroids, ix.codes, ix.adj0, w.k_reg, B, nthreads=2)
+    assert bidx.shape == (ix.n, mb)
+    rec = decode_all(ix)
+    differ = 0
+    for i in range(0, ix.n, 29):
+        G = _G(ix, rec, i, w.k_reg)
+        x = proj_np(ix, db[i])
+        for jb in range(mb):
+            bl = _block(ix, mb, jb)
+            losses = ((x[bl][:, None] - G[bl] @ B[jb].astype(np.float64).T) ** 2).sum(0)
+            assert losses[bidx[i, jb]] <= losses.min() * (1 + 1e-10) + 1e-15
+        differ += int(bidx[i, 0] != bidx[i, 1])
+    assert differ > 0
+
+
+def test_product_search_uses_blockwise_refinement(tiny_build):
+    # the search's returned distances are the product refined distances
+    w, ix, db, q = tiny_build
+    ids = datagen.beta_train_ids(w)
+    init = datagen.beta_init_ids(w, ids.size)
+    beta, _ = oracle.beta_train(db, ids, ix.proj, w.d_pad, ix.centroids, ix.codes, ix.adj0, w.k_reg,
+                                w.n_beta, init, w.beta_kmeans_iters, 3, nthreads=4, m_beta=4)
+    bidx = oracle.beta_assign(db, ix.proj, w.d_pad, ix.centroids, ix.codes, ix.adj0, w.k_reg, beta, nthreads=4)
+    import dataclasses
+    ixp = dataclasses.replace(ix, beta=beta, beta_idx=bidx, m_beta=4)
+    r = ixp.search(q[:6], w.ef, w.shortlist, w.topk)
+    for qi in range(6):
+        cand = r["cand_ids"][qi, :r["cand_n"][qi]]
+        dd = np.array([ixp.refined_distance(q[qi], int(i)) for i in cand])
+        order = np.lexsort((cand, dd))[:w.topk]
+        assert r["ids"][qi].tolist() == cand[order].tolist()
+        np.testing.assert_array_equal(r["d"][qi], dd[order])
