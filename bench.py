@@ -97,7 +97,7 @@ def cpu_baseline(ix, db, q, w, seconds=10.0):
     oix = oracle.Index(n=ix.n, d=ix.d, d_pad=ix.d_pad, m=ix.m, deg0=ix.deg0, deg_up=ix.deg_up, k_reg=ix.k_reg,
                        n_beta=ix.n_beta, entry=ix.entry, max_level=ix.max_level, proj=ix.proj,
                        centroids=ix.centroids, codes=ix.codes, adj0=ix.adj0, level=ix.level, up_base=ix.up_base,
-                       adj_up=ix.adj_up, beta=ix.beta, beta_idx=ix.beta_idx)
+                       adj_up=ix.adj_up, beta=ix.beta, beta_idx=ix.beta_idx, m_beta=ix.m_beta)
     nt = oracle.default_threads()
     t0 = time.time()
     probe = oix.search(q[:nt], w.ef, w.shortlist, w.topk, nthreads=nt)

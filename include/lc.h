@@ -15,8 +15,9 @@
  *                 strategy").
  *   lc_refine     re-ranks the short-list with the regression refinement
  *                 x~ = sum_j beta_j q(g_j(x)) (Sec. 4.2 Eq. 5 with a beta taken
- *                 from the learned codebook of Sec. 4.3, Eq. 7) and keeps the
- *                 top K by (squared L2 distance, id).
+ *                 from the learned codebook of Sec. 4.3, Eq. 7, or one beta per
+ *                 block of coordinates from the product codebook, Eq. 9) and
+ *                 keeps the top K by (squared L2 distance, id).
  *
  * Conventions (all calls):
  *  - Distances are squared Euclidean (Sec. 2 works with d = l2).
@@ -66,13 +67,18 @@ enum { LC_REFINE_F32 = 0, LC_REFINE_BF16_RESCORE = 1 };
  *   up_base   i32 [n]            first upper row of node i, -1 on level 0;
  *                               the row of level l >= 1 is up_base[i] + l - 1
  *   adj_up    i32 [n_up_rows][deg_up]  upper-level links, -1 padded
- *   beta      f32 [n_beta][k_reg + 1]  regression codebook (Sec. 4.3)
- *   beta_idx  u8  [n]            codebook entry of every vector (1 byte,
- *                               Sec. 4.3)
+ *   beta      f32 [m_beta][n_beta][k_reg + 1]  regression codebooks (Sec. 4.3):
+ *                               m_beta = 1 is the codebook of Eq. 6-8; with
+ *                               m_beta > 1 the d_pad coordinates are cut into
+ *                               m_beta equal blocks of m / m_beta whole
+ *                               sub-spaces, each with its own codebook (the
+ *                               product codebook of Eq. 9)
+ *   beta_idx  u8  [n][m_beta]    codebook entry of every vector and block
+ *                               (1 byte per block, Sec. 4.3)
  * entry is the single node of the top level, max_level its level (Sec. 2). */
 typedef struct {
   int32_t n, d, d_pad, m, ksub, code_stride, deg0, deg_up, k_reg, n_beta;
-  int32_t entry, max_level;
+  int32_t entry, max_level, m_beta;
   int64_t n_up_rows;
   const float *proj;
   const float *centroids;
@@ -89,7 +95,8 @@ typedef struct lc_index lc_index;
 /* Validate the view and keep a host-side copy of it (host memory only; the
  * device arrays are borrowed).  Requires ksub == 256, m % 8 == 0, m <= 64,
  * d_pad % m == 0, dsub <= 16, deg0 <= 32, deg_up <= 32, 1 <= k_reg <= deg0,
- * 1 <= n_beta <= 256, 0 <= entry < n.  Returns LC_OK and *out, or an error
+ * 1 <= n_beta <= 256, m_beta >= 1 dividing m, 0 <= entry < n.  Returns LC_OK
+ * and *out, or an error
  * code and *out = NULL. */
 int lc_index_bind(const lc_index_view *view, lc_index **out);
 void lc_index_release(lc_index *ix);
@@ -190,10 +197,13 @@ int lc_search_sched(const lc_index *ix, const void *lut, int lut_dtype, const fl
                     size_t ws_bytes, const lc_schedule *sched, void *stream);
 
 /* Second stage (Sec. 4.1 "Refinement strategy"; Sec. 4.2 Eq. 5; Sec. 4.3
- * Eq. 7).  For each valid short-list id i:
- *   b = beta_idx[i], g_0 = i, g_j = adj0[i][j-1] (j = 1..k_reg, -1 -> zero),
- *   x~ = sum_j beta[b][j] * q(g_j),   d~ = || P y - x~ ||^2,
- * then the K smallest (d~, id) in ascending order.
+ * Eq. 7 and Eq. 9).  For each valid short-list id i:
+ *   g_0 = i, g_j = adj0[i][j-1] (j = 1..k_reg, -1 -> zero),
+ *   block jb of x~ (coordinates [jb w, jb w + w), w = d_pad / m_beta):
+ *     x~ = sum_j beta[jb][beta_idx[i][jb]][j] * q(g_j),
+ *   d~ = || P y - x~ ||^2,
+ * then the K smallest (d~, id) in ascending order.  A short-list id with a
+ * codebook byte >= n_beta is treated as no candidate.
  * cand_ids, cand_n: as produced by lc_search (cand_n[q] <= 0 -> no candidates).
  * precision: LC_REFINE_F32 (fp32 throughout) or LC_REFINE_BF16_RESCORE.
  * out_ids i32 [nq][K] (-1 padded), out_d f32 [nq][K] (+inf padded).

@@ -54,18 +54,22 @@ int lcb_graph_build(const float *x, int64_t n, int d, const float *proj, int d_p
 
 /* Regression codebook (Sec. 4.3, Eq. 6-8) in float64 on the training ids:
  * per-vector least squares initialises a k-means (km_iters), then em_iters
- * rounds of assignment (Eq. 7) and per-cluster least squares (Eq. 8).
- * beta: f32 [n_beta][k_reg+1]; loss_hist (optional) em_iters+1 values. */
+ * rounds of assignment (Eq. 7) and per-cluster least squares (Eq. 8).  With
+ * m_beta > 1 (m_beta divides m) one codebook per block of d_pad / m_beta
+ * coordinates, each trained on its block alone from the same seeds (the
+ * product codebook, Eq. 9).
+ * beta: f32 [m_beta][n_beta][k_reg+1]; loss_hist (optional)
+ * [m_beta][em_iters+1] values. */
 int lcb_beta_train(const float *x, const int64_t *ids, int64_t n_sub, int d, const float *proj,
                    int d_pad, int m, const float *centroids, const uint8_t *codes, int code_stride,
-                   const int32_t *adj0, int deg0, int k_reg, int n_beta, const int64_t *init,
+                   const int32_t *adj0, int deg0, int k_reg, int n_beta, int m_beta, const int64_t *init,
                    int km_iters, int em_iters, int nthreads, float *beta, double *loss_hist);
 
-/* Codebook entry of every vector (Sec. 4.3, Eq. 7) with the f32 codebook:
- * beta_idx u8 [n]. */
+/* Codebook entry of every vector and block (Sec. 4.3, Eq. 7 per block) with
+ * the f32 codebooks: beta_idx u8 [n][m_beta]. */
 int lcb_beta_assign(const float *x, int64_t n, int d, const float *proj, int d_pad, int m,
                     const float *centroids, const uint8_t *codes, int code_stride,
-                    const int32_t *adj0, int deg0, int k_reg, int n_beta, const float *beta,
+                    const int32_t *adj0, int deg0, int k_reg, int n_beta, int m_beta, const float *beta,
                     int nthreads, uint8_t *beta_idx);
 
 #ifdef __cplusplus

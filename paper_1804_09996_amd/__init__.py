@@ -38,7 +38,7 @@ class LCError(RuntimeError):
 
 class IndexView(C.Structure):
     _fields_ = [(n, C.c_int32) for n in ("n", "d", "d_pad", "m", "ksub", "code_stride", "deg0", "deg_up", "k_reg",
-                                          "n_beta", "entry", "max_level")] + \
+                                          "n_beta", "entry", "max_level", "m_beta")] + \
                [("n_up_rows", C.c_int64)] + \
                [(n, C.c_void_p) for n in ("proj", "centroids", "codes", "adj0", "up_base", "adj_up", "beta",
                                           "beta_idx")]
@@ -127,7 +127,8 @@ class Index:
     ``arrays`` holds numpy arrays in the layout of include/lc.h (keys
     ``centroids, codes, adj0, up_base, adj_up, beta, beta_idx`` and optional
     ``proj``); ``meta`` the scalars ``d, d_pad, m, deg0, deg_up, k_reg,
-    entry, max_level``.
+    entry, max_level``.  ``beta`` is [n_beta, k+1] (one codebook) or
+    [m_beta, n_beta, k+1] (product codebook), ``beta_idx`` [n] or [n, m_beta].
     """
 
     def __init__(self, arrays: dict, meta: dict, device: Union[str, int] = "cuda"):
@@ -152,11 +153,19 @@ class Index:
             "adj_up": up("adj_up", np.int32), "beta": up("beta", np.float32), "beta_idx": up("beta_idx", np.uint8),
         }
         codes = arrays["codes"]
+        beta, bidx = np.asarray(arrays["beta"]), np.asarray(arrays["beta_idx"])
+        m_beta = beta.shape[0] if beta.ndim == 3 else 1
+        n_beta = beta.shape[-2]
+        # the kernels index beta and beta_idx by these sizes: check them before anything is bound
+        if beta.ndim not in (2, 3) or beta.shape[-1] != meta["k_reg"] + 1:
+            raise ValueError(f"beta has shape {beta.shape}, expected [(m_beta,) n_beta, {meta['k_reg'] + 1}]")
+        if bidx.size != codes.shape[0] * m_beta:
+            raise ValueError(f"beta_idx has {bidx.size} entries, expected n * m_beta = {codes.shape[0] * m_beta}")
         v = IndexView()
         v.n, v.d, v.d_pad, v.m = codes.shape[0], meta["d"], meta["d_pad"], meta["m"]
         v.ksub, v.code_stride = 256, codes.shape[1]
         v.deg0, v.deg_up, v.k_reg = meta["deg0"], meta["deg_up"], meta["k_reg"]
-        v.n_beta = arrays["beta"].shape[0]
+        v.n_beta, v.m_beta = n_beta, m_beta
         v.entry, v.max_level = meta["entry"], meta["max_level"]
         au = arrays.get("adj_up")
         v.n_up_rows = 0 if au is None else au.shape[0]

@@ -10,7 +10,7 @@ from __future__ import annotations
 import ctypes as C
 import os
 import time
-from dataclasses import dataclass, fields
+from dataclasses import MISSING, dataclass, fields
 from typing import Optional
 
 import numpy as np
@@ -33,8 +33,8 @@ def lib():
         L.lcb_levels.argtypes = [p, i64, i, i, p]
         L.lcb_levels.restype = i64
         L.lcb_graph_build.argtypes = [p, i64, i, p, i, i, p, p, i, p, i, i, i, i, p, p, p, p, p]
-        L.lcb_beta_train.argtypes = [p, p, i64, i, p, i, i, p, p, i, p, i, i, i, p, i, i, i, p, p]
-        L.lcb_beta_assign.argtypes = [p, i64, i, p, i, i, p, p, i, p, i, i, i, p, i, p]
+        L.lcb_beta_train.argtypes = [p, p, i64, i, p, i, i, p, p, i, p, i, i, i, i, p, i, i, i, p, p]
+        L.lcb_beta_assign.argtypes = [p, i64, i, p, i, i, p, p, i, p, i, i, i, i, p, i, p]
         _lib = L
     return _lib
 
@@ -84,6 +84,7 @@ class BuiltIndex:
     adj_up: np.ndarray
     beta: np.ndarray
     beta_idx: np.ndarray
+    m_beta: int = 1  # product codebook blocks: beta [m_beta, n_beta, k+1], beta_idx [n, m_beta]
 
     def save(self, path: str):
         arrays = {f.name: getattr(self, f.name) for f in fields(self) if isinstance(getattr(self, f.name), np.ndarray)}
@@ -99,6 +100,8 @@ class BuiltIndex:
                 kw[f.name] = z[f.name]
             elif "_" + f.name in z.files:
                 kw[f.name] = int(z["_" + f.name])
+            elif f.default is not MISSING:
+                kw[f.name] = f.default
             else:
                 kw[f.name] = None
         return cls(**kw)
@@ -135,20 +138,21 @@ def build_index(w, db, train, proj, level_u, pq_init, beta_ids, beta_init, nthre
     t2 = time.time()
     if log:
         log(f"index build: graph done ({t2 - t1:.1f}s)")
-    beta = np.empty((w.n_beta, w.k_reg + 1), np.float32)
+    mb = w.m_beta
+    beta = np.empty((w.n_beta, w.k_reg + 1) if mb == 1 else (mb, w.n_beta, w.k_reg + 1), np.float32)
     bids = _c(beta_ids, np.int64)
     _ok(L.lcb_beta_train(_p(db), _p(bids), bids.shape[0], d, _p(proj), w.d_pad, w.m, _p(cent), _p(codes), cs,
-                         _p(adj0), w.deg0, w.k_reg, w.n_beta, _p(_c(beta_init, np.int64)), w.beta_kmeans_iters,
+                         _p(adj0), w.deg0, w.k_reg, w.n_beta, mb, _p(_c(beta_init, np.int64)), w.beta_kmeans_iters,
                          w.em_iters, nt, _p(beta), None), "lcb_beta_train")
-    bidx = np.empty(n, np.uint8)
+    bidx = np.empty(n if mb == 1 else (n, mb), np.uint8)
     _ok(L.lcb_beta_assign(_p(db), n, d, _p(proj), w.d_pad, w.m, _p(cent), _p(codes), cs, _p(adj0), w.deg0, w.k_reg,
-                          w.n_beta, _p(beta), nt, _p(bidx)), "lcb_beta_assign")
+                          w.n_beta, mb, _p(beta), nt, _p(bidx)), "lcb_beta_assign")
     t3 = time.time()
     if log:
         log(f"index build: pq {t1 - t0:.1f}s graph {t2 - t1:.1f}s beta {t3 - t2:.1f}s ({nt} threads)")
     return BuiltIndex(n=n, d=d, d_pad=w.d_pad, m=w.m, deg0=w.deg0, deg_up=w.deg_up, k_reg=w.k_reg, n_beta=w.n_beta,
                       entry=int(entry.value), max_level=int(maxl.value), proj=proj, centroids=cent, codes=codes,
-                      adj0=adj0, level=level, up_base=up_base, adj_up=adj_up, beta=beta, beta_idx=bidx)
+                      adj0=adj0, level=level, up_base=up_base, adj_up=adj_up, beta=beta, beta_idx=bidx, m_beta=mb)
 
 
 def build_workload(w, nthreads: Optional[int] = None, cache_dir: Optional[str] = None, log=None):

@@ -599,8 +599,10 @@ struct Gram {
   std::vector<double> A, C, XX;  // [n][p][p], [n][p], [n]
 };
 
+// Grams of G(x) and x restricted to the coordinates [t0, t1) (a block of the
+// product codebook, Sec. 4.3 Eq. 9; the whole vector is [0, d_pad)).
 void build_grams(const float *x, const int64_t *ids, int64_t n_sub, const Space &sp, const uint8_t *codes,
-                 int cs, const int32_t *adj0, int deg0, int k_reg, int nthreads, Gram &g) {
+                 int cs, const int32_t *adj0, int deg0, int k_reg, int nthreads, int t0, int t1, Gram &g) {
   const int p = k_reg + 1, dp = sp.d_pad;
   g.p = p;
   g.dp = dp;
@@ -618,7 +620,7 @@ void build_grams(const float *x, const int64_t *ids, int64_t n_sub, const Space 
           const int64_t src = j == 0 ? i : adj0[i * deg0 + (j - 1)];
           if (src < 0) continue;
           const uint8_t *c = codes + src * cs;
-          for (int s = 0; s < sp.m; ++s) {
+          for (int s = t0 / sp.dsub; s < t1 / sp.dsub; ++s) {
             const float *cr = sp.cent + (int64_t(s) * 256 + c[s]) * sp.dsub;
             for (int t = 0; t < sp.dsub; ++t) G[size_t(j) * dp + s * sp.dsub + t] = cr[t];
           }
@@ -628,15 +630,15 @@ void build_grams(const float *x, const int64_t *ids, int64_t n_sub, const Space 
         for (int a = 0; a < p; ++a) {
           for (int b = a; b < p; ++b) {
             double s = 0;
-            for (int t = 0; t < dp; ++t) s += G[size_t(a) * dp + t] * G[size_t(b) * dp + t];
+            for (int t = t0; t < t1; ++t) s += G[size_t(a) * dp + t] * G[size_t(b) * dp + t];
             A[a * p + b] = A[b * p + a] = s;
           }
           double s = 0;
-          for (int t = 0; t < dp; ++t) s += G[size_t(a) * dp + t] * double(v[t]);
+          for (int t = t0; t < t1; ++t) s += G[size_t(a) * dp + t] * double(v[t]);
           C[a] = s;
         }
         double s = 0;
-        for (int t = 0; t < dp; ++t) s += double(v[t]) * v[t];
+        for (int t = t0; t < t1; ++t) s += double(v[t]) * v[t];
         g.XX[r] = s;
       },
       256);
@@ -668,14 +670,14 @@ int best_beta(const Gram &g, int64_t r, const double *B, int nb, double *loss) {
 
 }  // namespace
 
-int lcb_beta_train(const float *x, const int64_t *ids, int64_t n_sub, int d, const float *proj, int d_pad, int m,
-                   const float *centroids, const uint8_t *codes, int code_stride, const int32_t *adj0, int deg0,
-                   int k_reg, int n_beta, const int64_t *init, int km_iters, int em_iters, int nthreads, float *beta,
-                   double *loss_hist) {
-  if (k_reg < 1 || k_reg > deg0 || n_beta < 1 || n_beta > n_sub || d_pad % m) return -1;
-  Space sp{d, d_pad, m, d_pad / m, proj, centroids};
-  Gram g;
-  build_grams(x, ids, n_sub, sp, codes, code_stride, adj0, deg0, k_reg, nthreads, g);
+}  // extern "C"
+
+namespace {
+
+// One codebook on the Grams of one block: per-vector optimum, k-means on it,
+// then EM (assignment Eq. 7, per-cluster least squares Eq. 8).
+void train_block(const Gram &g, int64_t n_sub, int k_reg, int n_beta, const int64_t *init, int km_iters,
+                 int em_iters, int nthreads, float *beta, double *loss_hist) {
   const int p = k_reg + 1;
   // per-vector optimum, then k-means on it (float64)
   std::vector<double> bx(size_t(n_sub) * p);
@@ -750,16 +752,37 @@ int lcb_beta_train(const float *x, const int64_t *ids, int64_t n_sub, int d, con
     });
   }
   for (size_t t = 0; t < B.size(); ++t) beta[t] = float(B[t]);
+}
+
+}  // namespace
+
+extern "C" {
+
+int lcb_beta_train(const float *x, const int64_t *ids, int64_t n_sub, int d, const float *proj, int d_pad, int m,
+                   const float *centroids, const uint8_t *codes, int code_stride, const int32_t *adj0, int deg0,
+                   int k_reg, int n_beta, int m_beta, const int64_t *init, int km_iters, int em_iters, int nthreads,
+                   float *beta, double *loss_hist) {
+  if (k_reg < 1 || k_reg > deg0 || n_beta < 1 || n_beta > n_sub || d_pad % m || m_beta < 1 || m % m_beta)
+    return -1;
+  Space sp{d, d_pad, m, d_pad / m, proj, centroids};
+  const int p = k_reg + 1, bw = d_pad / m_beta;
+  // product codebook (Eq. 9): block jb covers coordinates [jb bw, jb bw + bw), m / m_beta whole sub-spaces
+  for (int jb = 0; jb < m_beta; ++jb) {
+    Gram g;
+    build_grams(x, ids, n_sub, sp, codes, code_stride, adj0, deg0, k_reg, nthreads, jb * bw, jb * bw + bw, g);
+    train_block(g, n_sub, k_reg, n_beta, init, km_iters, em_iters, nthreads, beta + size_t(jb) * n_beta * p,
+                loss_hist ? loss_hist + size_t(jb) * (em_iters + 1) : nullptr);
+  }
   return 0;
 }
 
 int lcb_beta_assign(const float *x, int64_t n, int d, const float *proj, int d_pad, int m, const float *centroids,
                     const uint8_t *codes, int code_stride, const int32_t *adj0, int deg0, int k_reg, int n_beta,
-                    const float *beta, int nthreads, uint8_t *beta_idx) {
-  if (k_reg < 1 || k_reg > deg0 || n_beta < 1 || n_beta > 256 || d_pad % m) return -1;
+                    int m_beta, const float *beta, int nthreads, uint8_t *beta_idx) {
+  if (k_reg < 1 || k_reg > deg0 || n_beta < 1 || n_beta > 256 || d_pad % m || m_beta < 1 || m % m_beta) return -1;
   Space sp{d, d_pad, m, d_pad / m, proj, centroids};
-  const int p = k_reg + 1;
-  std::vector<double> B(size_t(n_beta) * p);
+  const int p = k_reg + 1, bw = d_pad / m_beta;
+  std::vector<double> B(size_t(m_beta) * n_beta * p);
   for (size_t t = 0; t < B.size(); ++t) B[t] = beta[t];
   const int64_t chunk = 1 << 17;
   std::vector<int64_t> ids(chunk);
@@ -768,11 +791,17 @@ int lcb_beta_assign(const float *x, int64_t n, int d, const float *proj, int d_p
     prog.tick(c0, n);
     const int64_t c1 = std::min(n, c0 + chunk);
     for (int64_t i = c0; i < c1; ++i) ids[i - c0] = i;
-    Gram g;
-    build_grams(x, ids.data(), c1 - c0, sp, codes, code_stride, adj0, deg0, k_reg, nthreads, g);
-    parallel_for(c1 - c0, nthreads,
-                 [&](int64_t r, int) { beta_idx[c0 + r] = uint8_t(best_beta(g, r, B.data(), n_beta, nullptr)); },
-                 256);
+    for (int jb = 0; jb < m_beta; ++jb) {
+      Gram g;
+      build_grams(x, ids.data(), c1 - c0, sp, codes, code_stride, adj0, deg0, k_reg, nthreads, jb * bw,
+                  jb * bw + bw, g);
+      const double *Bj = B.data() + size_t(jb) * n_beta * p;
+      parallel_for(c1 - c0, nthreads,
+                   [&](int64_t r, int) {
+                     beta_idx[(c0 + r) * m_beta + jb] = uint8_t(best_beta(g, r, Bj, n_beta, nullptr));
+                   },
+                   256);
+    }
   }
   return 0;
 }

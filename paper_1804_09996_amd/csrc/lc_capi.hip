@@ -41,6 +41,7 @@ int lc_index_bind(const lc_index_view *v, lc_index **out) {
   if (!pow2(v->code_stride) || v->code_stride < v->m || (v->code_stride >> 1) >= v->m) return LC_EINVAL;
   if (v->deg0 < 1 || v->deg_up < 1 || v->k_reg < 1 || v->k_reg > v->deg0) return LC_EINVAL;
   if (v->n_beta < 1 || v->n_beta > 256) return LC_EINVAL;
+  if (v->m_beta < 1 || v->m % v->m_beta != 0) return LC_EINVAL;
   if (v->entry < 0 || v->entry >= v->n || v->max_level < 0 || v->n_up_rows < 0) return LC_EINVAL;
   if (v->max_level > 0 && v->n_up_rows < v->max_level) return LC_EINVAL;
   if (!v->centroids || !v->codes || !v->adj0 || !v->up_base || !v->beta || !v->beta_idx) return LC_EINVAL;

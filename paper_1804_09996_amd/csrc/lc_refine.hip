@@ -6,7 +6,10 @@
 //   x~_i = sum_{j=0..k} beta[b_i][j] * q(g_j(i)),  g_0 = i, g_j = adj0[i][j-1]
 //   d~   = || P y - x~_i ||^2
 //
-// and the K smallest (d~, id) are kept.  A block stages the centroids of all
+// and the K smallest (d~, id) are kept.  With a product regression codebook
+// (Sec. 4.3, Eq. 9) the coordinates are cut into m_beta equal blocks of m /
+// m_beta whole sub-spaces, and block jb of x~ takes its weights from codebook
+// jb at the vector's byte b_i[jb].  A block stages the centroids of all
 // sub-spaces in LDS once; each wavefront then owns one query at a time.  L
 // lanes share a candidate (L = 2 for m <= 16, else 4), lane part p
 // accumulating the sub-spaces s = p mod L in registers; the candidate's
@@ -35,7 +38,7 @@ struct RefineArgs {
   const uint8_t *codes;
   int code_stride;
   const int32_t *adj0;
-  int n, n_beta, deg0, k_reg;
+  int n, n_beta, m_beta, deg0, k_reg;
   const float *beta;
   const uint8_t *beta_idx;
   const int32_t *cand_ids, *cand_n;
@@ -103,28 +106,77 @@ constexpr int lanes_per_cand() {
 // This lane part's share of || y' - x~_id ||^2: with two lanes the sub-spaces
 // [part U, part U + U) (one aligned piece of each code row), with four the
 // sub-spaces s = part mod 4 (whole code rows).
-template <int M, int DSUB, int CS, typename CT, bool BF16W>
+// Blocks of the product codebook seen by one lane part.  MB blocks of SPB =
+// M / MB sub-spaces; a lane part's U sub-spaces fall into NJ distinct blocks,
+// sub-space u of the part into slot slot(u), and slot sl is block jb(sl).
+template <int M, int MB>
+struct BlockMap {
+  static constexpr int L = lanes_per_cand<M>();
+  static constexpr int U = M / L;
+  static constexpr int SPB = M / MB;
+  static_assert(M % MB == 0, "blocks hold whole sub-spaces");
+  // two lanes: contiguous sub-spaces [part U, part U + U); four: s = part + 4u
+  static constexpr bool kOne = L == 2 ? SPB >= U : MB == 1;
+  static constexpr bool kStrideAligned = L == 4 && SPB % 4 == 0;
+  static constexpr int NJ = kOne ? 1 : L == 2 ? U / SPB : kStrideAligned ? MB : U;
+  static_assert(L == 4 || kOne || U % SPB == 0, "a two-lane part holds whole blocks");
+  __device__ static constexpr int slot(int u) {
+    return kOne ? 0 : L == 2 ? u / SPB : kStrideAligned ? (4 * u) / SPB : u;
+  }
+  __device__ static int block(int sl, int part) {
+    if constexpr (kOne) return L == 2 ? (part * U) / SPB : 0;
+    else if constexpr (L == 2) return part * NJ + sl;
+    else if constexpr (kStrideAligned) return sl;
+    else return (part + 4 * sl) / SPB;
+  }
+};
+
+// A candidate whose code-book bytes are out of range is malformed input.
+template <int MB>
+__device__ __forceinline__ bool beta_ok(const RefineArgs &a, int32_t id) {
+  bool ok = true;
+#pragma unroll
+  for (int jb = 0; jb < MB; ++jb) ok = ok && a.beta_idx[int64_t(id) * MB + jb] < a.n_beta;
+  return ok;
+}
+
+template <int M, int DSUB, int CS, typename CT, bool BF16W, int MB>
 __device__ __forceinline__ float part_dist(const RefineArgs &a, const CT *C, const float *yv, int32_t id,
                                            int part) {
   constexpr int L = lanes_per_cand<M>();
   constexpr int U = M / L;
+  using BM = BlockMap<M, MB>;
+  constexpr int NJ = BM::NJ;
   static_assert(L == 4 || U == 4 || U == 8, "two lanes take 4 or 8 sub-spaces each");
-  constexpr int B = CS >= 64 ? 3 : CS >= 32 ? 4 : 6;  // rows in flight: their ids, then their code rows, then the sums
+  // rows in flight (their ids, then their code rows, then the sums); each row
+  // holds one weight per block, so fewer rows when a part spans many blocks
+  constexpr int B0 = CS >= 64 ? 3 : CS >= 32 ? 4 : 6;
+  constexpr int B = NJ == 1 ? B0 : (16 / NJ < 1 ? 1 : 16 / NJ < B0 ? 16 / NJ : B0);
   float acc[U * DSUB];
 #pragma unroll
   for (int t = 0; t < U * DSUB; ++t) acc[t] = 0.f;
-  const float *bw = a.beta + size_t(a.beta_idx[id]) * (a.k_reg + 1);
+  // the codebook row of every block this part touches (offsets into beta)
+  int bw[NJ];
+#pragma unroll
+  for (int sl = 0; sl < NJ; ++sl) {
+    const int jb = BM::block(sl, part);
+    bw[sl] = (jb * a.n_beta + int(a.beta_idx[int64_t(id) * MB + jb])) * (a.k_reg + 1);
+  }
   const int32_t *links = a.adj0 + int64_t(id) * a.deg0;
   for (int j0 = 0; j0 <= a.k_reg; j0 += B) {
     int32_t g[B];
-    float wj[B];
+    float wj[B][NJ];
 #pragma unroll
     for (int t = 0; t < B; ++t) {
       const int j = j0 + t;
       const int32_t gj = j == 0 ? id : (j <= a.k_reg ? links[j - 1] : -1);
       const bool ok = j <= a.k_reg && gj >= 0 && gj < a.n;  // a missing link is a zero vector
       g[t] = ok ? gj : id;
-      wj[t] = ok ? (BF16W ? round_bf16(bw[j]) : bw[j]) : 0.f;
+#pragma unroll
+      for (int sl = 0; sl < NJ; ++sl) {
+        const float v = ok ? a.beta[bw[sl] + j] : 0.f;
+        wj[t][sl] = BF16W ? round_bf16(v) : v;
+      }
     }
     // a row past k or a missing link has weight 0: it adds exact zeros
     if constexpr (L == 2) {
@@ -138,7 +190,7 @@ __device__ __forceinline__ float part_dist(const RefineArgs &a, const CT *C, con
           const int s = part * U + u;
           const int base = (s * 256 + int(row[t].byte(u))) * DSUB;
 #pragma unroll
-          for (int q = 0; q < DSUB; ++q) acc[u * DSUB + q] += wj[t] * cval(C, base + q);
+          for (int q = 0; q < DSUB; ++q) acc[u * DSUB + q] += wj[t][BM::slot(u)] * cval(C, base + q);
         }
       }
     } else {
@@ -152,7 +204,7 @@ __device__ __forceinline__ float part_dist(const RefineArgs &a, const CT *C, con
           const int s = part + L * u;
           const int base = (s * 256 + int(row[t].byte(s))) * DSUB;
 #pragma unroll
-          for (int q = 0; q < DSUB; ++q) acc[u * DSUB + q] += wj[t] * cval(C, base + q);
+          for (int q = 0; q < DSUB; ++q) acc[u * DSUB + q] += wj[t][BM::slot(u)] * cval(C, base + q);
         }
       }
     }
@@ -213,11 +265,16 @@ __device__ __forceinline__ void project_query(const RefineArgs &a, int64_t q, fl
   }
 }
 
-__device__ __forceinline__ int32_t candidate(const RefineArgs &a, int64_t q, int c, int cn) {
+__device__ __forceinline__ int32_t candidate_id(const RefineArgs &a, int64_t q, int c, int cn) {
   int32_t id = -1;
   if (c < a.S && c < cn) id = a.cand_ids[q * a.S + c];
-  if (id >= a.n || (id >= 0 && a.beta_idx[id] >= a.n_beta)) id = -1;  // malformed input: no candidate
-  return id;
+  return id >= a.n ? -1 : id;
+}
+
+template <int MB>
+__device__ __forceinline__ int32_t candidate(const RefineArgs &a, int64_t q, int c, int cn) {
+  const int32_t id = candidate_id(a, q, c, cn);
+  return id >= 0 && !beta_ok<MB>(a, id) ? -1 : id;  // malformed input: no candidate
 }
 
 __device__ __forceinline__ void write_topk(const RefineArgs &a, int64_t q, const uint64_t *keys, int lane) {
@@ -230,7 +287,7 @@ __device__ __forceinline__ void write_topk(const RefineArgs &a, int64_t q, const
 
 // CT = float: plain float32 refinement.  CT = uint16_t: bfloat16 first pass
 // plus exact float32 re-score of the best K2 candidates.
-template <int M, int DSUB, int CS, typename CT>
+template <int M, int DSUB, int CS, typename CT, int MB>
 __global__ __launch_bounds__(1024) void refine_kernel(RefineArgs a) {
   constexpr int DP = M * DSUB;
   constexpr bool kBF16 = sizeof(CT) == 2;
@@ -260,9 +317,9 @@ __global__ __launch_bounds__(1024) void refine_kernel(RefineArgs a) {
     const int cn = a.cand_n[q];
     for (int c0 = 0; c0 < a.S_pad; c0 += G) {
       const int c = c0 + grp;
-      const int32_t id = c < a.S_pad ? candidate(a, q, c, cn) : -1;
+      const int32_t id = c < a.S_pad ? candidate<MB>(a, q, c, cn) : -1;
       float e = 0.f;
-      if (id >= 0) e = part_dist<M, DSUB, CS, CT, kBF16>(a, C, yv, id, part);
+      if (id >= 0) e = part_dist<M, DSUB, CS, CT, kBF16, MB>(a, C, yv, id, part);
       e = group_sum<L>(e);
       if (part == 0 && c < a.S_pad) keys[c] = id >= 0 ? make_key(e, id) : kKeyMax;
     }
@@ -275,7 +332,7 @@ __global__ __launch_bounds__(1024) void refine_kernel(RefineArgs a) {
         const uint64_t v = c < a.K2 ? keys[c] : kKeyMax;
         const int32_t id = v == kKeyMax ? -1 : key_id(v);
         float e = 0.f;
-        if (id >= 0) e = part_dist<M, DSUB, CS, float, false>(a, a.cent, yv, id, part);
+        if (id >= 0) e = part_dist<M, DSUB, CS, float, false, MB>(a, a.cent, yv, id, part);
         e = group_sum<L>(e);
         wave_sync();
         if (part == 0 && c < a.K2_pad) keys[c] = id >= 0 ? make_key(e, id) : kKeyMax;
@@ -308,12 +365,16 @@ __global__ __launch_bounds__(1024) void refine_f32_generic(RefineArgs a, int m, 
     const int cn = a.cand_n[q];
     for (int c0 = 0; c0 < a.S_pad; c0 += 16) {
       const int c = c0 + grp;
-      const int32_t id = candidate(a, q, c, cn);
+      int32_t id = candidate_id(a, q, c, cn);
+      for (int jb = 0; id >= 0 && jb < a.m_beta; ++jb)
+        if (a.beta_idx[int64_t(id) * a.m_beta + jb] >= a.n_beta) id = -1;  // malformed input: no candidate
       float e = 0.f;
       if (id >= 0) {
-        const float *bw = a.beta + size_t(a.beta_idx[id]) * (a.k_reg + 1);
         const int32_t *links = a.adj0 + int64_t(id) * a.deg0;
         for (int s = part; s < m; s += 4) {
+          const int jb = s / (m / a.m_beta);  // block of the product codebook holding sub-space s
+          const float *bw =
+              a.beta + (size_t(jb) * a.n_beta + a.beta_idx[int64_t(id) * a.m_beta + jb]) * (a.k_reg + 1);
           float acc[16];
           for (int t = 0; t < 16; ++t) acc[t] = 0.f;
           for (int j = 0; j <= a.k_reg; ++j) {
@@ -359,6 +420,7 @@ RefineArgs make_args(const lc_index *ix, const float *q, int64_t nq, const int32
   a.adj0 = ix->v.adj0;
   a.n = ix->v.n;
   a.n_beta = ix->v.n_beta;
+  a.m_beta = ix->v.m_beta;
   a.deg0 = ix->v.deg0;
   a.k_reg = ix->v.k_reg;
   a.beta = ix->v.beta;
@@ -391,16 +453,28 @@ bool plan_blocks(const lc_index *ix, RefineArgs &a, int cent_elem_bytes, int *ld
   return true;
 }
 
-template <int M, int DSUB, int CS, typename CT>
+template <int M, int DSUB, int CS, typename CT, int MB>
 int launch_spec(const lc_index *ix, RefineArgs a, hipStream_t st) {
   int lds;
   int64_t blocks;
   if (!plan_blocks(ix, a, int(sizeof(CT)), &lds, &blocks)) return LC_ENOTSUP;
-  if (hipFuncSetAttribute(reinterpret_cast<const void *>(&refine_kernel<M, DSUB, CS, CT>),
+  if (hipFuncSetAttribute(reinterpret_cast<const void *>(&refine_kernel<M, DSUB, CS, CT, MB>),
                           hipFuncAttributeMaxDynamicSharedMemorySize, lds) != hipSuccess)
     return LC_EHIP;
-  hipLaunchKernelGGL((refine_kernel<M, DSUB, CS, CT>), dim3(int(blocks)), dim3(64 * a.wpb), lds, st, a);
+  hipLaunchKernelGGL((refine_kernel<M, DSUB, CS, CT, MB>), dim3(int(blocks)), dim3(64 * a.wpb), lds, st, a);
   return hipGetLastError() == hipSuccess ? LC_OK : LC_EHIP;
+}
+
+// The product codebook's block count as a kernel parameter (1, 2, 4 or 8 blocks).
+template <int M, int DSUB, int CS, typename CT>
+int launch_blocks(const lc_index *ix, const RefineArgs &a, hipStream_t st) {
+  switch (a.m_beta) {
+    case 1: return launch_spec<M, DSUB, CS, CT, 1>(ix, a, st);
+    case 2: return launch_spec<M, DSUB, CS, CT, 2>(ix, a, st);
+    case 4: return launch_spec<M, DSUB, CS, CT, 4>(ix, a, st);
+    case 8: return launch_spec<M, DSUB, CS, CT, 8>(ix, a, st);
+    default: return LC_ENOTSUP;
+  }
 }
 
 int launch_generic(const lc_index *ix, RefineArgs a, hipStream_t st) {
@@ -416,8 +490,9 @@ int launch_generic(const lc_index *ix, RefineArgs a, hipStream_t st) {
 
 }  // namespace
 
-// Specialised shapes (m, dsub, code stride); other shapes take the generic
-// float32 kernel, and the precision form needs a specialised shape.
+// Specialised shapes (m, dsub, code stride) with 1, 2, 4 or 8 codebook
+// blocks; other shapes and block counts take the generic float32 kernel, and
+// the precision form needs a specialised one.
 int lc_launch_refine(const lc_index *ix, const float *q, int64_t nq, const int32_t *cand_ids,
                      const int32_t *cand_n, int32_t S, int32_t K, int precision, int32_t *out_ids,
                      float *out_d, hipStream_t st) {
@@ -427,9 +502,10 @@ int lc_launch_refine(const lc_index *ix, const float *q, int64_t nq, const int32
   // when the re-score covers the whole short-list (2K >= S) the first pass decides nothing: every
   // candidate's distance is the float32 one and all are sorted by it, which is the plain kernel
   const bool bf_pass = bf && a.K2 < S;
+  const bool spec_mb = a.m_beta == 1 || a.m_beta == 2 || a.m_beta == 4 || a.m_beta == 8;
 #define SHAPE(MM, DS, CSS)                                                                              \
-  if (m == MM && ds == DS)                                                                              \
-    return bf_pass ? launch_spec<MM, DS, CSS, uint16_t>(ix, a, st) : launch_spec<MM, DS, CSS, float>(ix, a, st);
+  if (m == MM && ds == DS && spec_mb)                                                                   \
+    return bf_pass ? launch_blocks<MM, DS, CSS, uint16_t>(ix, a, st) : launch_blocks<MM, DS, CSS, float>(ix, a, st);
   SHAPE(8, 2, 8)
   SHAPE(8, 4, 8)
   SHAPE(8, 12, 8)

@@ -43,6 +43,19 @@ def test_builder_with_projection(nthreads):
     _compare(w, nthreads)
 
 
+def test_builder_product_codebook_matches_oracle(nthreads):
+    # product regression codebook (Sec. 4.3, Eq. 9): 4 blocks of 2 sub-spaces
+    w = datagen.small(name="prod-b", n=1500, d=32, m=8, n_beta=8, n_beta_train=1500, m_beta=4)
+    bix, _, _ = builder.build_workload(w, nthreads=nthreads)
+    oix, _, _ = oracle.build_workload(w, nthreads=nthreads)
+    assert bix.beta.shape == oix.beta.shape == (4, 8, w.k_reg + 1)
+    assert bix.beta_idx.shape == oix.beta_idx.shape == (w.n, 4)
+    assert bix.m_beta == oix.m_beta == 4
+    assert np.all(bix.adj0 == oix.adj0, axis=1).mean() >= 0.999
+    np.testing.assert_allclose(bix.beta, oix.beta, rtol=1e-4, atol=1e-5)
+    assert (bix.beta_idx == oix.beta_idx).mean() >= 0.999
+
+
 def test_builder_is_thread_count_independent():
     w = datagen.small(name="threads", n=1200)
     a, _, _ = builder.build_workload(w, nthreads=1)

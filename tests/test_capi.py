@@ -59,6 +59,7 @@ def test_bind_rejects_bad_views(L):
         g = lc.IndexView()
         g.n, g.d, g.d_pad, g.m, g.ksub, g.code_stride = 100, 96, 96, 16, 256, 16
         g.deg0, g.deg_up, g.k_reg, g.n_beta, g.entry, g.max_level, g.n_up_rows = 32, 32, 16, 256, 0, 0, 0
+        g.m_beta = 1
         for name in ("centroids", "codes", "adj0", "up_base", "beta", "beta_idx"):
             setattr(g, name, 0x1000)
         return g
@@ -69,6 +70,7 @@ def test_bind_rejects_bad_views(L):
         "nbeta": ("n_beta", 257, lc.LC_EINVAL), "entry": ("entry", 100, lc.LC_EINVAL),
         "dpad": ("d_pad", 100, lc.LC_EINVAL), "codes": ("codes", None, lc.LC_EINVAL),
         "deg0": ("deg0", 48, lc.LC_ENOTSUP), "level_rows": ("max_level", 2, lc.LC_EINVAL),
+        "mbeta0": ("m_beta", 0, lc.LC_EINVAL), "mbeta3": ("m_beta", 3, lc.LC_EINVAL),  # blocks must divide m
     }
     for key, (field, value, want) in cases.items():
         g = good()
