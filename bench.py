@@ -6,6 +6,7 @@ one batch of queries already resident in HBM.  Prints one JSON line.
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload C2-1M]
 """
 import argparse
+import dataclasses
 import hashlib
 import json
 import os
@@ -43,10 +44,10 @@ def walk_kernel_name(m, precision, ef, S):
 
 
 def refine_bytes(w, cand_n, K):
-    """Per candidate: its beta index (1), k links (4k), k+1 codes (m(k+1));
-    per query the output (8K)."""
+    """Per candidate: its beta index (1 byte per codebook block), k links
+    (4k), k+1 codes (m(k+1)); per query the output (8K)."""
     c = float(np.clip(cand_n, 0, None).sum())
-    return c * (1 + 4 * w.k_reg + w.m * (w.k_reg + 1)) + cand_n.shape[0] * 8 * K
+    return c * (w.m_beta + 4 * w.k_reg + w.m * (w.k_reg + 1)) + cand_n.shape[0] * 8 * K
 
 
 def lut_bytes(w, nq):
@@ -286,6 +287,9 @@ def main():
                     help="form timed by --form plain (default: the plain fp32 path)")
     ap.add_argument("--ef", type=int, default=0, help="efSearch for --form plain (default: the workload's)")
     ap.add_argument("--shortlist", type=int, default=0, help="short-list size for --form plain (default: the workload's)")
+    ap.add_argument("--m-beta", type=int, default=1,
+                    help="regression codebook blocks: 1 = one codebook, >1 = product codebook of that many blocks "
+                         "(plain and both forms)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="also run one device-to-device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -314,6 +318,8 @@ def main():
     if args.form == "serve":
         return bench_serve(args)
     w = datagen.WORKLOADS[args.workload]
+    if args.m_beta != 1:
+        w = dataclasses.replace(w, m_beta=args.m_beta)
     dev = torch.device("cuda:0")
     t0 = time.time()
     ix, db, q = builder.build_workload(w, cache_dir=args.cache, log=log)
@@ -450,8 +456,10 @@ def main():
         "warmup": args.warmup, "ms_per_step": head["ms_per_step"], "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f16" if f16 else "f32", "data": "synthetic",
         "config": {"workload": f"{w.name}: N={w.n} d={w.d} Gaussian mixture ({w.n_comp} components, "
-                               f"L2-normalised), PQ {w.m}x256, level-0 degree {w.deg0}, k={w.k_reg}, "
-                               f"beta codebook {w.n_beta}, top-{K}, {nq} queries per step; {form}; "
+                               f"L2-normalised), PQ {w.m}x256, level-0 degree {w.deg0}, k={w.k_reg}, " +
+                               (f"product beta codebook {w.m_beta} blocks x {w.n_beta}" if w.m_beta > 1
+                                else f"beta codebook {w.n_beta}") +
+                               f", top-{K}, {nq} queries per step; {form}; "
                                f"efSearch {head['ef']}, shortlist {S_h}; " +
                                (f"consecutive steps alternate over {args.streams} streams (each with its own workspace "
                                 f"and outputs), so one batch's walk tail overlaps the next batch" if args.streams > 1

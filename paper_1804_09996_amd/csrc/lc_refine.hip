@@ -103,31 +103,36 @@ constexpr int lanes_per_cand() {
   return M <= 16 ? 2 : 4;
 }
 
-// This lane part's share of || y' - x~_id ||^2: with two lanes the sub-spaces
-// [part U, part U + U) (one aligned piece of each code row), with four the
-// sub-spaces s = part mod 4 (whole code rows).
-// Blocks of the product codebook seen by one lane part.  MB blocks of SPB =
-// M / MB sub-spaces; a lane part's U sub-spaces fall into NJ distinct blocks,
-// sub-space u of the part into slot slot(u), and slot sl is block jb(sl).
+// This lane part's share of || y' - x~_id ||^2 over the sub-spaces BlockMap
+// gives it: with two lanes [part U, part U + U) (one aligned piece of each
+// code row), with four lanes a whole code row is loaded and its bytes picked.
+// Which sub-spaces a lane part sums, and the blocks of the product codebook
+// they fall in.  MB blocks of SPB = M / MB sub-spaces; accumulator u of part
+// p is sub-space sub(u, p): with two lanes the contiguous [p U, p U + U) (one
+// aligned piece of each code row), with four lanes s = p + 4u (the whole code
+// row is loaded and the word holding byte s is u, known at compile time).
+// Sub-space u lies in slot slot(u) of the part's NJ distinct blocks, and slot
+// sl is block block(sl, p).
 template <int M, int MB>
 struct BlockMap {
   static constexpr int L = lanes_per_cand<M>();
   static constexpr int U = M / L;
   static constexpr int SPB = M / MB;
   static_assert(M % MB == 0, "blocks hold whole sub-spaces");
-  // two lanes: contiguous sub-spaces [part U, part U + U); four: s = part + 4u
   static constexpr bool kOne = L == 2 ? SPB >= U : MB == 1;
+  // four lanes, SPB a multiple of 4: block (p + 4u) / SPB = 4u / SPB for every p
   static constexpr bool kStrideAligned = L == 4 && SPB % 4 == 0;
   static constexpr int NJ = kOne ? 1 : L == 2 ? U / SPB : kStrideAligned ? MB : U;
   static_assert(L == 4 || kOne || U % SPB == 0, "a two-lane part holds whole blocks");
+  __device__ static constexpr int sub(int u, int p) { return L == 2 ? p * U + u : p + L * u; }
   __device__ static constexpr int slot(int u) {
     return kOne ? 0 : L == 2 ? u / SPB : kStrideAligned ? (4 * u) / SPB : u;
   }
-  __device__ static int block(int sl, int part) {
-    if constexpr (kOne) return L == 2 ? (part * U) / SPB : 0;
-    else if constexpr (L == 2) return part * NJ + sl;
+  __device__ static int block(int sl, int p) {
+    if constexpr (kOne) return L == 2 ? (p * U) / SPB : 0;
+    else if constexpr (L == 2) return p * NJ + sl;
     else if constexpr (kStrideAligned) return sl;
-    else return (part + 4 * sl) / SPB;
+    else return (p + 4 * sl) / SPB;
   }
 };
 
@@ -140,6 +145,14 @@ __device__ __forceinline__ bool beta_ok(const RefineArgs &a, int32_t id) {
   return ok;
 }
 
+// Four consecutive 32-bit words from a 4-byte aligned address: one 16-byte
+// load (a global_load_dwordx4), so that four regression rows cost one memory
+// request for their links and one per codebook row for their weights.
+struct __attribute__((aligned(4))) Words4 {
+  uint32_t x, y, z, w;
+};
+__device__ __forceinline__ Words4 load4(const void *p) { return *reinterpret_cast<const Words4 *>(p); }
+
 template <int M, int DSUB, int CS, typename CT, bool BF16W, int MB>
 __device__ __forceinline__ float part_dist(const RefineArgs &a, const CT *C, const float *yv, int32_t id,
                                            int part) {
@@ -148,10 +161,15 @@ __device__ __forceinline__ float part_dist(const RefineArgs &a, const CT *C, con
   using BM = BlockMap<M, MB>;
   constexpr int NJ = BM::NJ;
   static_assert(L == 4 || U == 4 || U == 8, "two lanes take 4 or 8 sub-spaces each");
-  // rows in flight (their ids, then their code rows, then the sums); each row
-  // holds one weight per block, so fewer rows when a part spans many blocks
-  constexpr int B0 = CS >= 64 ? 3 : CS >= 32 ? 4 : 6;
-  constexpr int B = NJ == 1 ? B0 : (16 / NJ < 1 ? 1 : 16 / NJ < B0 ? 16 / NJ : B0);
+  // The rows are r = 0..k: r = 0 is the vector's own code, r >= 1 its link
+  // r-1.  They go in batches of RB rows; with RB >= 4 a group of four rows
+  // shares one load of its links and one load per codebook row of weights (a
+  // product codebook's rows do not stay in the L1 cache, so this is what
+  // bounds its cost).  A part spanning many blocks keeps fewer rows in
+  // registers and loads them one by one.  Code rows are fetched SB at a time,
+  // then summed.
+  constexpr int RB = (CS <= 16 && NJ <= 2) ? 8 : NJ <= 4 ? 4 : NJ <= 8 ? 2 : 1;
+  constexpr int SB = RB < 4 ? RB : CS >= 64 ? 2 : 4;
   float acc[U * DSUB];
 #pragma unroll
   for (int t = 0; t < U * DSUB; ++t) acc[t] = 0.f;
@@ -162,49 +180,92 @@ __device__ __forceinline__ float part_dist(const RefineArgs &a, const CT *C, con
     const int jb = BM::block(sl, part);
     bw[sl] = (jb * a.n_beta + int(a.beta_idx[int64_t(id) * MB + jb])) * (a.k_reg + 1);
   }
+  const int k = a.k_reg;
   const int32_t *links = a.adj0 + int64_t(id) * a.deg0;
-  for (int j0 = 0; j0 <= a.k_reg; j0 += B) {
-    int32_t g[B];
-    float wj[B][NJ];
+  for (int r0 = 0; r0 <= k; r0 += RB) {
+    int32_t lk[RB];
+    float wv[RB][NJ];
+    if constexpr (RB >= 4) {
 #pragma unroll
-    for (int t = 0; t < B; ++t) {
-      const int j = j0 + t;
-      const int32_t gj = j == 0 ? id : (j <= a.k_reg ? links[j - 1] : -1);
-      const bool ok = j <= a.k_reg && gj >= 0 && gj < a.n;  // a missing link is a zero vector
-      g[t] = ok ? gj : id;
+      for (int h = 0; h < RB / 4; ++h) {
+        const int rb = r0 + 4 * h;
+        if (rb >= 1 && rb + 3 <= k) {  // links rb-1 .. rb+2 in one load
+          const Words4 v = load4(links + rb - 1);
+          lk[4 * h] = int32_t(v.x), lk[4 * h + 1] = int32_t(v.y), lk[4 * h + 2] = int32_t(v.z),
+                  lk[4 * h + 3] = int32_t(v.w);
+        } else {
+          // the first group and the tail: rows clamped into 1..k, so every read is in bounds
 #pragma unroll
-      for (int sl = 0; sl < NJ; ++sl) {
-        const float v = ok ? a.beta[bw[sl] + j] : 0.f;
-        wj[t][sl] = BF16W ? round_bf16(v) : v;
-      }
-    }
-    // a row past k or a missing link has weight 0: it adds exact zeros
-    if constexpr (L == 2) {
-      CodePiece<U> row[B];
+          for (int t = 0; t < 4; ++t) {
+            const int r = rb + t;
+            lk[4 * h + t] = links[(r < 1 ? 1 : r > k ? k : r) - 1];
+          }
+        }
 #pragma unroll
-      for (int t = 0; t < B; ++t) row[t].load(a.codes + size_t(g[t]) * CS + part * U);
+        for (int sl = 0; sl < NJ; ++sl) {
+          if (rb + 3 <= k) {  // weights rb .. rb+3 of the block's codebook row in one load
+            const Words4 v = load4(a.beta + bw[sl] + rb);
+            wv[4 * h][sl] = __uint_as_float(v.x), wv[4 * h + 1][sl] = __uint_as_float(v.y);
+            wv[4 * h + 2][sl] = __uint_as_float(v.z), wv[4 * h + 3][sl] = __uint_as_float(v.w);
+          } else {
 #pragma unroll
-      for (int t = 0; t < B; ++t) {
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-          const int s = part * U + u;
-          const int base = (s * 256 + int(row[t].byte(u))) * DSUB;
-#pragma unroll
-          for (int q = 0; q < DSUB; ++q) acc[u * DSUB + q] += wj[t][BM::slot(u)] * cval(C, base + q);
+            for (int t = 0; t < 4; ++t) wv[4 * h + t][sl] = a.beta[bw[sl] + (rb + t > k ? k : rb + t)];
+          }
         }
       }
     } else {
-      CodeRow<CS> row[B];
 #pragma unroll
-      for (int t = 0; t < B; ++t) row[t].load(a.codes + size_t(g[t]) * CS);
+      for (int t = 0; t < RB; ++t) {
+        const int r = r0 + t;
+        const int rc = r > k ? k : r;
+        lk[t] = links[(rc < 1 ? 1 : rc) - 1];
 #pragma unroll
-      for (int t = 0; t < B; ++t) {
+        for (int sl = 0; sl < NJ; ++sl) wv[t][sl] = a.beta[bw[sl] + rc];
+      }
+    }
+    int32_t g[RB];
+    float wj[RB][NJ];
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-          const int s = part + L * u;
-          const int base = (s * 256 + int(row[t].byte(s))) * DSUB;
+    for (int t = 0; t < RB; ++t) {
+      const int r = r0 + t;
+      const int32_t gj = r == 0 ? id : lk[t];
+      const bool ok = r <= k && gj >= 0 && gj < a.n;  // a missing link is a zero vector
+      g[t] = ok ? gj : id;
 #pragma unroll
-          for (int q = 0; q < DSUB; ++q) acc[u * DSUB + q] += wj[t][BM::slot(u)] * cval(C, base + q);
+      for (int sl = 0; sl < NJ; ++sl) wj[t][sl] = ok ? (BF16W ? round_bf16(wv[t][sl]) : wv[t][sl]) : 0.f;
+    }
+    // a row past k or a missing link has weight 0: it adds exact zeros, and the
+    // sums run over the rows in ascending order whatever the batching
+#pragma unroll
+    for (int t0 = 0; t0 < RB; t0 += SB) {
+      if (r0 + t0 > k) break;  // uniform: the rest of the batch lies past row k
+      if constexpr (L == 2) {
+        CodePiece<U> row[SB];
+#pragma unroll
+        for (int t = 0; t < SB; ++t) row[t].load(a.codes + size_t(g[t0 + t]) * CS + part * U);
+#pragma unroll
+        for (int t = 0; t < SB; ++t) {
+#pragma unroll
+          for (int u = 0; u < U; ++u) {
+            const int s = BM::sub(u, part);
+            const int base = (s * 256 + int(row[t].byte(u))) * DSUB;
+#pragma unroll
+            for (int q = 0; q < DSUB; ++q) acc[u * DSUB + q] += wj[t0 + t][BM::slot(u)] * cval(C, base + q);
+          }
+        }
+      } else {
+        CodeRow<CS> row[SB];
+#pragma unroll
+        for (int t = 0; t < SB; ++t) row[t].load(a.codes + size_t(g[t0 + t]) * CS);
+#pragma unroll
+        for (int t = 0; t < SB; ++t) {
+#pragma unroll
+          for (int u = 0; u < U; ++u) {
+            const int s = BM::sub(u, part);
+            const int base = (s * 256 + int(row[t].byte(s))) * DSUB;
+#pragma unroll
+            for (int q = 0; q < DSUB; ++q) acc[u * DSUB + q] += wj[t0 + t][BM::slot(u)] * cval(C, base + q);
+          }
         }
       }
     }
@@ -212,7 +273,7 @@ __device__ __forceinline__ float part_dist(const RefineArgs &a, const CT *C, con
   float e = 0.f;
 #pragma unroll
   for (int u = 0; u < U; ++u) {
-    const int s = L == 2 ? part * U + u : part + L * u;
+    const int s = BM::sub(u, part);
 #pragma unroll
     for (int t = 0; t < DSUB; ++t) {
       const float df = yv[s * DSUB + t] - acc[u * DSUB + t];
