@@ -66,6 +66,8 @@ def _declare(L):
     L.orc_lut.argtypes = [C.POINTER(OrcIndex), _p, _p]
     L.orc_lut.restype = None
     L.orc_search.argtypes = [C.POINTER(OrcIndex), _p, _i64, _p, C.c_int32, C.c_int32, _i, _p, _p, _p, _p, _p, _p]
+    L.orc_search_capped.argtypes = [C.POINTER(OrcIndex), _p, _i64, _p, C.c_int32, C.c_int32, C.c_int32, _i, _p, _p,
+                                    _p, _p, _p, _p]
     L.orc_refined_distance.argtypes = [C.POINTER(OrcIndex), _p, C.c_int32]
     L.orc_refined_distance.restype = C.c_double
     L.orc_walk_trace.argtypes = [C.POINTER(OrcIndex), _p, C.c_int32, _p, C.c_int32]
@@ -295,7 +297,9 @@ class Index:
         nt = _load().orc_walk_trace(C.byref(s), _ptr(_c(y, np.float32)), int(ef_eff), _ptr(out), cap)
         return out[:nt].copy()
 
-    def search(self, q: np.ndarray, ef, S: int, K: int, nthreads: Optional[int] = None) -> dict:
+    def search(self, q: np.ndarray, ef, S: int, K: int, nthreads: Optional[int] = None, max_evals: int = 0) -> dict:
+        """Full search; ``max_evals`` > 0 is the budget T on level-0 distance
+        evaluations per query (Sec. 3.1), 0 none."""
         q = _c(q, np.float32)
         nq = q.shape[0]
         ef_arr = _c(np.broadcast_to(np.asarray(ef, dtype=np.int32), (nq,)), np.int32)
@@ -305,9 +309,10 @@ class Index:
             "cand_n": np.empty(nq, np.int32), "stats": np.empty((nq, 2), np.int32),
         }
         s = self._struct()
-        rc = _load().orc_search(C.byref(s), _ptr(q), nq, _ptr(ef_arr), S, K, nthreads or default_threads(),
-                                _ptr(out["ids"]), _ptr(out["d"]), _ptr(out["cand_ids"]), _ptr(out["cand_adc"]),
-                                _ptr(out["cand_n"]), _ptr(out["stats"]))
+        rc = _load().orc_search_capped(C.byref(s), _ptr(q), nq, _ptr(ef_arr), S, K, int(max_evals),
+                                       nthreads or default_threads(), _ptr(out["ids"]), _ptr(out["d"]),
+                                       _ptr(out["cand_ids"]), _ptr(out["cand_adc"]), _ptr(out["cand_n"]),
+                                       _ptr(out["stats"]))
         if rc != 0:
             raise ValueError(f"orc_search failed ({rc})")
         return out

@@ -1073,10 +1073,13 @@ static okey greedy_upper(const orc_index *ix, const double *lut) {
 
 /* level-0 best-first walk, textbook form with two heaps: C (candidates,
  * min-heap) and W (results, max-heap bounded by ef).  Returns |W| and writes W
- * sorted ascending; E counts expansions and D newly visited nodes. */
+ * sorted ascending; E counts expansions and D newly visited nodes (distance
+ * evaluations).  max_d > 0 is the paper's budget T on the number of distance
+ * computations (Sec. 3.1): the walk stops right after evaluation number max_d,
+ * leaving the rest of that expansion's links unvisited. */
 static int walk0(const orc_index *ix, const double *lut, okey ep, int ef, int32_t *stamp,
                  int32_t sv, okey *out, int32_t *E, int32_t *D, int32_t *trace, int32_t tcap,
-                 int32_t *tn) {
+                 int32_t *tn, int32_t max_d) {
   oheap C = {(okey *)malloc(sizeof(okey) * ((size_t)ix->n + 1)), 0, ix->n + 1, 0};
   oheap W = {(okey *)malloc(sizeof(okey) * (size_t)(ef + 2)), 0, ef + 2, 1};
   int32_t e = 0, dd = 0, nt = 0;
@@ -1102,8 +1105,10 @@ static int walk0(const orc_index *ix, const double *lut, okey ep, int ef, int32_
         oh_push(&W, k);
         if (W.n > ef) oh_pop(&W);
       }
+      if (max_d > 0 && dd >= max_d) goto done;
     }
   }
+done:;
   int nw = W.n;
   for (int i = nw - 1; i >= 0; i--) out[i] = oh_pop(&W);
   free(C.a);
@@ -1118,7 +1123,7 @@ typedef struct {
   const orc_index *ix;
   const float *q;
   const int32_t *ef;
-  int32_t S, K;
+  int32_t S, K, max_d;
   int32_t *out_ids, *cand_ids, *cand_n, *stats;
   double *out_d, *cand_adc;
   int32_t **stamp;
@@ -1135,7 +1140,7 @@ static void search_one(int64_t qi, int tid, void *vctx) {
   int ef = c->ef[qi] > c->S ? c->ef[qi] : c->S;
   okey *W = (okey *)malloc(sizeof(okey) * (size_t)(ef + 2));
   int32_t E, D;
-  int nw = walk0(ix, lut, ep, ef, c->stamp[tid], ++c->sv[tid], W, &E, &D, NULL, 0, NULL);
+  int nw = walk0(ix, lut, ep, ef, c->stamp[tid], ++c->sv[tid], W, &E, &D, NULL, 0, NULL, c->max_d);
   int ns = nw < c->S ? nw : c->S;
   if (c->cand_ids)
     for (int i = 0; i < c->S; i++) c->cand_ids[qi * c->S + i] = i < ns ? W[i].id : -1;
@@ -1162,12 +1167,12 @@ static void search_one(int64_t qi, int tid, void *vctx) {
   free(lut);
 }
 
-int orc_search(const orc_index *ix, const float *q, int64_t nq, const int32_t *ef, int32_t S,
-               int32_t K, int nthreads, int32_t *out_ids, double *out_d, int32_t *cand_ids,
-               double *cand_adc, int32_t *cand_n, int32_t *stats) {
-  if (nq < 0 || S < 1 || K < 0 || ix->n < 1) return -1;
+int orc_search_capped(const orc_index *ix, const float *q, int64_t nq, const int32_t *ef, int32_t S,
+                      int32_t K, int32_t max_d, int nthreads, int32_t *out_ids, double *out_d,
+                      int32_t *cand_ids, double *cand_adc, int32_t *cand_n, int32_t *stats) {
+  if (nq < 0 || S < 1 || K < 0 || ix->n < 1 || max_d < 0) return -1;
   if (nthreads < 1) nthreads = 1;
-  srch_ctx c = {ix, q, ef, S, K, out_ids, cand_ids, cand_n, stats, out_d, cand_adc, NULL, NULL};
+  srch_ctx c = {ix, q, ef, S, K, max_d, out_ids, cand_ids, cand_n, stats, out_d, cand_adc, NULL, NULL};
   c.stamp = (int32_t **)malloc(sizeof(int32_t *) * nthreads);
   c.sv = (int32_t *)calloc((size_t)nthreads, sizeof(int32_t));
   for (int t = 0; t < nthreads; t++) c.stamp[t] = (int32_t *)calloc((size_t)ix->n, sizeof(int32_t));
@@ -1178,6 +1183,13 @@ int orc_search(const orc_index *ix, const float *q, int64_t nq, const int32_t *e
   return 0;
 }
 
+int orc_search(const orc_index *ix, const float *q, int64_t nq, const int32_t *ef, int32_t S,
+               int32_t K, int nthreads, int32_t *out_ids, double *out_d, int32_t *cand_ids,
+               double *cand_adc, int32_t *cand_n, int32_t *stats) {
+  return orc_search_capped(ix, q, nq, ef, S, K, 0, nthreads, out_ids, out_d, cand_ids, cand_adc, cand_n,
+                           stats);
+}
+
 int32_t orc_walk_trace(const orc_index *ix, const float *y, int32_t ef_eff, int32_t *trace,
                        int32_t cap) {
   double *lut = (double *)malloc(sizeof(double) * (size_t)ix->m * ix->ksub);
@@ -1186,7 +1198,7 @@ int32_t orc_walk_trace(const orc_index *ix, const float *y, int32_t ef_eff, int3
   int32_t *stamp = (int32_t *)calloc((size_t)ix->n, sizeof(int32_t));
   okey *W = (okey *)malloc(sizeof(okey) * (size_t)(ef_eff + 2));
   int32_t E, D, nt;
-  walk0(ix, lut, ep, ef_eff, stamp, 1, W, &E, &D, trace, cap, &nt);
+  walk0(ix, lut, ep, ef_eff, stamp, 1, W, &E, &D, trace, cap, &nt, 0);
   free(stamp);
   free(W);
   free(lut);

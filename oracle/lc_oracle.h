@@ -119,6 +119,13 @@ int orc_search(const orc_index *ix, const float *q, int64_t nq, const int32_t *e
                int32_t K, int nthreads, int32_t *out_ids, double *out_d, int32_t *cand_ids,
                double *cand_adc, int32_t *cand_n, int32_t *stats);
 
+/* The same with the paper's budget T on distance computations (Sec. 3.1):
+ * max_d > 0 stops a query's level-0 walk right after its max_d-th distance
+ * evaluation (D = min(max_d, D of the unbounded walk)); 0 = no budget. */
+int orc_search_capped(const orc_index *ix, const float *q, int64_t nq, const int32_t *ef, int32_t S,
+                      int32_t K, int32_t max_d, int nthreads, int32_t *out_ids, double *out_d,
+                      int32_t *cand_ids, double *cand_adc, int32_t *cand_n, int32_t *stats);
+
 /* Refined squared distance ||y' - x~_i||^2 for any id, x~_i = sum_j beta_j q(g_j(i))
  * block by block (Eq. 5, Eq. 9). */
 double orc_refined_distance(const orc_index *ix, const float *y, int32_t i);

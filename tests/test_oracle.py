@@ -212,9 +212,10 @@ def test_small_graph_is_complete_and_walk_exact():
 # ---------------------------------------------------------------------------
 # walk (Sec. 2: greedy descent, then best-first on the base layer)
 # ---------------------------------------------------------------------------
-def walk_sorted_pool(ix, lut, ef):
+def walk_sorted_pool(ix, lut, ef, T=0):
     """The same walk written as one sorted pool with 'expanded' flags: pick the
-    first unexpanded entry, evaluate its unvisited links, keep the best ef."""
+    first unexpanded entry, evaluate its unvisited links, keep the best ef;
+    with T > 0 stop right after the T-th evaluation (Sec. 3.1)."""
     def key(i):
         return (adc_seq(lut, ix.codes[i], ix.m), int(i))
 
@@ -231,7 +232,8 @@ def walk_sorted_pool(ix, lut, ef):
     visited = {cur[1]}
     E = D = 0
     trace = []
-    while True:
+    stop = False
+    while not stop:
         idx = next((t for t, e in enumerate(pool) if not e[1]), None)
         if idx is None:
             break
@@ -245,6 +247,9 @@ def walk_sorted_pool(ix, lut, ef):
             visited.add(int(nb))
             D += 1
             pool.append([key(nb), False])
+            if T and D >= T:
+                stop = True
+                break
         pool.sort(key=lambda e: e[0])
         pool = pool[:ef]
     return [e[0][1] for e in pool], E, D, trace
@@ -261,6 +266,23 @@ def test_walk_matches_sorted_pool_form(tiny_build):
             assert r["cand_ids"][qi][: r["cand_n"][qi]].tolist() == ids[:S]
             if ef == w.ef:
                 assert ix.walk_trace(y, max(ef, S)).tolist() == trace
+
+
+def test_walk_budget_matches_sorted_pool_form(tiny_build):
+    # the budget T on distance evaluations (Sec. 3.1), from the sorted-pool form
+    w, ix, db, q = tiny_build
+    free = ix.search(q, 40, 16, 3)
+    for T in (1, 7, 32, 33, 100, 250):
+        r = ix.search(q, 40, 16, 3, max_evals=T)
+        for qi, y in enumerate(q):
+            ids, E, D, _ = walk_sorted_pool(ix, ix.lut(y), 40, T=T)
+            assert r["stats"][qi].tolist() == [E, D]
+            assert D == min(T, free["stats"][qi][1])
+            assert r["cand_ids"][qi][: r["cand_n"][qi]].tolist() == ids[:16]
+    # a budget at or above every query's unbounded D changes nothing
+    big = ix.search(q, 40, 16, 3, max_evals=int(free["stats"][:, 1].max()))
+    for k in ("ids", "d", "cand_ids", "stats"):
+        assert np.array_equal(big[k], free[k]), k
 
 
 def test_walk_with_ef_at_least_n_is_exhaustive(tiny_build):
