@@ -40,7 +40,7 @@ def walk_kernel_name(m, precision, ef, S):
     to 128 entries, in LDS beyond."""
     t = "half" if precision != "f32" else "float"
     w_cap = -(-max(ef, S) // 64) * 64
-    return f"walk_reg_kernel<{m},{t},2>" if w_cap <= 128 else f"walk_kernel<{m},{t}>"
+    return f"walk_reg_kernel<{m},{t},2,false>" if w_cap <= 128 else f"walk_kernel<{m},{t},false>"
 
 
 def refine_bytes(w, cand_n, K):

@@ -196,6 +196,20 @@ int lc_search_sched(const lc_index *ix, const void *lut, int lut_dtype, const fl
                     int32_t *cand_ids, float *cand_adc, int32_t *cand_n, int32_t *stats, void *ws,
                     size_t ws_bytes, const lc_schedule *sched, void *stream);
 
+/* lc_search_sched with the paper's budget T on distance computations (Sec.
+ * 3.1, "the number of comparisons after which the search is stopped"):
+ * max_evals > 0 ends a query's level-0 walk right after its max_evals-th
+ * distance evaluation, so D = min(max_evals, D of the unbounded walk); the
+ * links of that last expansion past the budget are not evaluated, and the
+ * short-list is the best S of the pool at that point.  Evaluations on the
+ * upper levels are not counted.  max_evals = 0: no budget (lc_search_sched);
+ * max_evals < 0: LC_EINVAL.  Other arguments, outputs and errors as
+ * lc_search_sched. */
+int lc_search_budget(const lc_index *ix, const void *lut, int lut_dtype, const float *lut_scale,
+                     int64_t nq, const int32_t *ef, int32_t ef_max, int32_t S, int32_t max_evals,
+                     const int32_t *order, int32_t *cand_ids, float *cand_adc, int32_t *cand_n,
+                     int32_t *stats, void *ws, size_t ws_bytes, const lc_schedule *sched, void *stream);
+
 /* Second stage (Sec. 4.1 "Refinement strategy"; Sec. 4.2 Eq. 5; Sec. 4.3
  * Eq. 7 and Eq. 9).  For each valid short-list id i:
  *   g_0 = i, g_j = adj0[i][j-1] (j = 1..k_reg, -1 -> zero),

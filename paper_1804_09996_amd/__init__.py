@@ -90,6 +90,8 @@ def lib():
         L.lc_search_workspace_bytes_sched.argtypes = [p, i64, i32, i32, C.POINTER(Schedule)]
         L.lc_search_workspace_bytes_sched.restype = sz
         L.lc_search_sched.argtypes = [p, p, C.c_int, p, i64, p, i32, i32, p, p, p, p, p, p, sz, C.POINTER(Schedule), p]
+        L.lc_search_budget.argtypes = [p, p, C.c_int, p, i64, p, i32, i32, i32, p, p, p, p, p, p, sz,
+                                       C.POINTER(Schedule), p]
         L.lc_refine.argtypes = [p, p, i64, p, p, i32, i32, C.c_int, p, p, p]
         _lib = L
     return _lib
@@ -97,7 +99,7 @@ def lib():
 
 def exported_symbols():
     return ["lc_build_id", "lc_strerror", "lc_index_bind", "lc_index_release", "lc_build_lut", "lc_search_workspace_bytes",
-            "lc_search", "lc_refine", "lc_search_workspace_bytes_sched", "lc_search_sched"]
+            "lc_search", "lc_refine", "lc_search_workspace_bytes_sched", "lc_search_sched", "lc_search_budget"]
 
 
 def _check(rc: int, where: str):
@@ -228,10 +230,11 @@ class Index:
 
     def search(self, lut, scale=None, ef=None, ef_max: int = 64, S: int = 64, stats: bool = True,
                lut_dtype: Optional[int] = None, sched: Optional[Schedule] = None, order=None,
-               out: Optional[SearchResult] = None, ws=None) -> SearchResult:
+               out: Optional[SearchResult] = None, ws=None, max_evals: int = 0) -> SearchResult:
         """``ws``: a zero-filled uint8 device tensor of at least
         ``workspace_bytes(...)`` bytes, or None for the index's own (searches
-        that may overlap on different streams need one each)."""
+        that may overlap on different streams need one each).  ``max_evals``
+        > 0: the budget T on level-0 distance evaluations per query."""
         torch = self.torch
         nq = lut.shape[0]
         if lut_dtype is None:
@@ -252,7 +255,12 @@ class Index:
             ws = self.workspace(nq, ef_max, S, sched)
         elif ws.numel() < self.workspace_bytes(nq, ef_max, S, sched):
             raise LCError(LC_ENOSPC, "lc_search")
-        if sched is None and order is None:
+        if max_evals:
+            rc = lib().lc_search_budget(self.handle, _ptr(lut), lut_dtype, _ptr(scale), nq, _ptr(ef_t), ef_max, S,
+                                        int(max_evals), _ptr(order), _ptr(cand_ids), _ptr(cand_adc), _ptr(cand_n),
+                                        _ptr(st), _ptr(ws), ws.numel(), None if sched is None else C.byref(sched),
+                                        _stream(torch, self.device))
+        elif sched is None and order is None:
             rc = lib().lc_search(self.handle, _ptr(lut), lut_dtype, _ptr(scale), nq, _ptr(ef_t), ef_max, S,
                                  _ptr(cand_ids), _ptr(cand_adc), _ptr(cand_n), _ptr(st), _ptr(ws), ws.numel(),
                                  _stream(torch, self.device))
@@ -275,12 +283,12 @@ class Index:
         return out_ids, out_d
 
     def query(self, q, ef=None, ef_max: int = 64, S: int = 64, K: int = 10, stats: bool = False,
-              sched: Optional[Schedule] = None, precision: str = "f32"):
+              sched: Optional[Schedule] = None, precision: str = "f32", max_evals: int = 0):
         """The whole path: tables, walk and short-list, refinement and top-K.
         ``precision="f16"`` selects the fp16 table and the bf16 refinement
         with exact fp32 re-scoring of the final candidates."""
         lp = precision == "f16"
         lut, scale = self.build_lut(q, LC_LUT_F16 if lp else LC_LUT_F32)
-        r = self.search(lut, scale, ef=ef, ef_max=ef_max, S=S, stats=stats, sched=sched)
+        r = self.search(lut, scale, ef=ef, ef_max=ef_max, S=S, stats=stats, sched=sched, max_evals=max_evals)
         ids, d = self.refine(q, r.cand_ids, r.cand_n, K, LC_REFINE_BF16_RESCORE if lp else LC_REFINE_F32)
         return ids, d, r

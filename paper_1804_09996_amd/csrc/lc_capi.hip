@@ -92,19 +92,27 @@ size_t lc_search_workspace_bytes(const lc_index *ix, int64_t nq, int32_t ef_max,
   return lc_search_workspace_bytes_sched(ix, nq, ef_max, S, nullptr);
 }
 
-int lc_search_sched(const lc_index *ix, const void *lut, int lut_dtype, const float *lut_scale, int64_t nq,
-                    const int32_t *ef, int32_t ef_max, int32_t S, const int32_t *order, int32_t *cand_ids,
-                    float *cand_adc, int32_t *cand_n, int32_t *stats, void *ws, size_t ws_bytes,
-                    const lc_schedule *sched, void *stream) {
-  if (!ix || nq < 0 || ef_max < 1 || S < 1) return LC_EINVAL;
+int lc_search_budget(const lc_index *ix, const void *lut, int lut_dtype, const float *lut_scale, int64_t nq,
+                     const int32_t *ef, int32_t ef_max, int32_t S, int32_t max_evals, const int32_t *order,
+                     int32_t *cand_ids, float *cand_adc, int32_t *cand_n, int32_t *stats, void *ws,
+                     size_t ws_bytes, const lc_schedule *sched, void *stream) {
+  if (!ix || nq < 0 || ef_max < 1 || S < 1 || max_evals < 0) return LC_EINVAL;
   if (ef_max > 4096 || S > 4096) return LC_ENOTSUP;
   if (lut_dtype != LC_LUT_F32 && lut_dtype != LC_LUT_F16) return LC_EINVAL;
   if (nq == 0) return LC_OK;
   if (nq > int64_t(0x7FFFFFFF)) return LC_EINVAL;
   if (!lut || !cand_ids || !cand_adc || !cand_n || !ws) return LC_EINVAL;
   if (lut_dtype == LC_LUT_F16 && !lut_scale) return LC_EINVAL;
-  return lc_launch_walk(ix, lut, lut_dtype, lut_scale, nq, ef, ef_max, S, order, cand_ids, cand_adc, cand_n, stats,
-                        ws, ws_bytes, sched, static_cast<hipStream_t>(stream));
+  return lc_launch_walk(ix, lut, lut_dtype, lut_scale, nq, ef, ef_max, S, max_evals, order, cand_ids, cand_adc,
+                        cand_n, stats, ws, ws_bytes, sched, static_cast<hipStream_t>(stream));
+}
+
+int lc_search_sched(const lc_index *ix, const void *lut, int lut_dtype, const float *lut_scale, int64_t nq,
+                    const int32_t *ef, int32_t ef_max, int32_t S, const int32_t *order, int32_t *cand_ids,
+                    float *cand_adc, int32_t *cand_n, int32_t *stats, void *ws, size_t ws_bytes,
+                    const lc_schedule *sched, void *stream) {
+  return lc_search_budget(ix, lut, lut_dtype, lut_scale, nq, ef, ef_max, S, 0, order, cand_ids, cand_adc, cand_n,
+                          stats, ws, ws_bytes, sched, stream);
 }
 
 int lc_search(const lc_index *ix, const void *lut, int lut_dtype, const float *lut_scale, int64_t nq,

@@ -83,7 +83,7 @@ int lc_launch_lut(const lc_index *ix, const float *q, int64_t nq, int dtype, voi
 size_t lc_walk_workspace_bytes(const lc_index *ix, int64_t nq, int32_t ef_max, int32_t S,
                                const lc_schedule *sched);
 int lc_launch_walk(const lc_index *ix, const void *lut, int dtype, const float *scale, int64_t nq,
-                   const int32_t *ef, int32_t ef_max, int32_t S, const int32_t *order, int32_t *cand_ids,
+                   const int32_t *ef, int32_t ef_max, int32_t S, int32_t max_d, const int32_t *order, int32_t *cand_ids,
                    float *cand_adc,
                    int32_t *cand_n, int32_t *stats, void *ws, size_t ws_bytes, const lc_schedule *sched,
                    hipStream_t st);

@@ -55,6 +55,7 @@ struct WalkArgs {
   int32_t n, code_stride, deg0, deg_up, entry, max_level;
   int32_t w_cap, hash_bits, prefetch, queue, vmode, list_cap;
   int32_t tag_bits;    // walk_kernel's table: 16-bit tags of this many bits, 0 = 32-bit ids
+  int32_t max_d;       // budget T on distance evaluations (Sec. 3.1), 0 = none
   uint32_t *counters;  // [0] next query, [1] finished slots (queue mode)
   uint32_t *bits;
   int32_t *vlists;     // [slots][list_cap] ids whose bit is set (visited mode 1)
@@ -675,13 +676,32 @@ __device__ __forceinline__ void greedy_descent(const WalkArgs &a, const T *lut, 
 // entry p (lanes 32..63 when `two`): test-and-set against the visited set,
 // codes and ADC keys, and whether p's expansion is the sequential walk's next
 // step (dual).  D, E and the bitset id list are updated; `fresh` marks the
-// keys that enter the merge (subject to the wmax filter).
+// keys that enter the merge (subject to the wmax filter).  With a budget T on
+// distance evaluations, the evaluation that reaches T is the walk's last: the
+// fresh links past it (in link order, c's before p's) are dropped and `stop`
+// ends the walk after this step's merge.
 struct StepOut {
   uint64_t k;
-  bool fresh, dual;
+  bool fresh, dual, stop;
 };
 
-template <int M, typename T>
+// Keep the first `room` lanes of mask m (in lane order) when m has more;
+// returns the kept mask and sets stop when the budget is reached.
+__device__ __forceinline__ uint64_t budget_cut(uint64_t m, int D, int max_d, bool &stop) {
+  if (max_d <= 0) return m;
+  const int room = max_d - D;  // >= 1: a walk that reached its budget has stopped
+  if (__popcll(m) < room) return m;
+  stop = true;
+  uint64_t kept = 0;
+  for (int i = 0; i < room; ++i) {
+    const uint64_t low = m & (~m + 1ull);
+    kept |= low;
+    m ^= low;
+  }
+  return kept;
+}
+
+template <int M, typename T, bool BUDGET>
 __device__ __forceinline__ StepOut expand_links(const WalkArgs &a, const VTable &vt, uint32_t *bits, int32_t *vlist,
                                                 const T *lut, const float *sc, int32_t nb, const CodeRegs<M> &cr,
                                                 bool lo, bool two, uint64_t pk, int lane, int &D, int &E,
@@ -709,15 +729,23 @@ __device__ __forceinline__ StepOut expand_links(const WalkArgs &a, const VTable 
       else cand = bit_clear(bits, nb);  // the bucket is full: the bitset decides
     }
   }
-  D += __popcll(__ballot(lo && cand));
+  StepOut o;
+  o.stop = false;
+  if constexpr (BUDGET) {
+    const uint64_t cm = __ballot(lo && cand);
+    const uint64_t kept = budget_cut(cm, D, a.max_d, o.stop);
+    if (lo) cand = cand && ((kept >> lane) & 1ull);  // a dropped link stays marked: the walk ends here
+    D += __popcll(kept);
+  } else {
+    D += __popcll(__ballot(lo && cand));
+  }
 
   // ADC keys of both halves' candidates, from the codes loaded at the start of the step
-  StepOut o;
   o.k = kKeyMax;
   if (cand) o.k = make_key(cr.adc(lut, sc), nb);
 
   // p is the next expansion of the sequential walk iff no fresh key of c is below it
-  o.dual = two && __ballot(lo && cand && o.k < pk) == 0ull;
+  o.dual = (!BUDGET || !o.stop) && two && __ballot(lo && cand && o.k < pk) == 0ull;
   o.fresh = lo && cand;
   if (o.dual) {
     // p's absent links, inserted for real: one CAS at the slot the look-up
@@ -730,7 +758,13 @@ __device__ __forceinline__ StepOut expand_links(const WalkArgs &a, const VTable 
     if (__ballot(rest2)) {
       if (rest2) o.fresh = vt_insert(vt, b, tag, nb, bits, set_bit);
     }
-    D += __popcll(__ballot(!lo && o.fresh));
+    if constexpr (BUDGET) {
+      const uint64_t pm = budget_cut(__ballot(!lo && o.fresh), D, a.max_d, o.stop);
+      if (!lo) o.fresh = o.fresh && ((pm >> lane) & 1ull);
+      D += __popcll(pm);
+    } else {
+      D += __popcll(__ballot(!lo && o.fresh));
+    }
     E += 2;
   } else {
     E += 1;
@@ -748,7 +782,7 @@ __device__ __forceinline__ StepOut expand_links(const WalkArgs &a, const VTable 
 // Level-0 walk with the visited set in an LDS table (and the bitset for ids
 // whose home bucket is full), two expansions per step when the sequential
 // order allows it.
-template <int M, typename T>
+template <int M, typename T, bool BUDGET>
 __global__ __launch_bounds__(64) void walk_kernel(WalkArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int lane = threadIdx.x;
@@ -846,7 +880,7 @@ __global__ __launch_bounds__(64) void walk_kernel(WalkArgs a) {
         CodeRegs<M> cr;
         cr.load(a.codes, a.code_stride, nb >= 0 ? nb : cid);
 
-        const StepOut o = expand_links<M, T>(a, vt, bits, vlist, lut, sc, nb, cr, lo, two, pk, lane, D, E, vcount);
+        const StepOut o = expand_links<M, T, BUDGET>(a, vt, bits, vlist, lut, sc, nb, cr, lo, two, pk, lane, D, E, vcount);
         const bool dual = o.dual;
         const bool fresh = o.fresh;
         const uint64_t k = o.k;
@@ -872,6 +906,7 @@ __global__ __launch_bounds__(64) void walk_kernel(WalkArgs a) {
           wave_sync();
           wmax = nw == efe ? pure_key(W[nw - 1]) : kKeyMax;
         }
+        if (BUDGET && o.stop) break;  // the budget of distance evaluations is spent
 
         // the first four unexpanded entries at or after p0 (all before are expanded),
         // from two chunks at a time
@@ -1005,7 +1040,7 @@ __global__ __launch_bounds__(64) void walk_kernel(WalkArgs a) {
 // moves the entries above it up one lane, and several kept keys are sorted
 // and merged by bitonic networks; LDS holds only the table and the visited
 // table.
-template <int M, typename T, int R>
+template <int M, typename T, int R, bool BUDGET>
 __global__ __launch_bounds__(64) void walk_reg_kernel(WalkArgs a) {
   static_assert(R >= 1 && R <= 2, "pool chunks");
   extern __shared__ __align__(16) unsigned char smem[];
@@ -1106,7 +1141,7 @@ __global__ __launch_bounds__(64) void walk_reg_kernel(WalkArgs a) {
         CodeRegs<M> cr;
         cr.load(a.codes, a.code_stride, nb >= 0 ? nb : cid);
 
-        const StepOut o = expand_links<M, T>(a, vt, bits, vlist, lut, sc, nb, cr, lo, two, pk, lane, D, E, vcount);
+        const StepOut o = expand_links<M, T, BUDGET>(a, vt, bits, vlist, lut, sc, nb, cr, lo, two, pk, lane, D, E, vcount);
         const bool dual = o.dual;
         const uint64_t k = o.k;
         if (dual) mark_expanded<R>(wr, pidx, lane);
@@ -1140,6 +1175,7 @@ __global__ __launch_bounds__(64) void walk_reg_kernel(WalkArgs a) {
           nw = nw + nn < efe ? nw + nn : efe;
           wmax = nw == efe ? pure_key(entry_at<R>(wr, efe - 1)) : kKeyMax;
         }
+        if (BUDGET && o.stop) break;  // the budget of distance evaluations is spent
 
         // the first four unexpanded entries
         Pick2 pm;
@@ -1221,7 +1257,7 @@ __global__ __launch_bounds__(64) void walk_reg_kernel(WalkArgs a) {
 
 // Level-0 walk with the visited set in the slot's bitset behind a
 // direct-mapped LDS cache; one expansion per step.
-template <int M, typename T>
+template <int M, typename T, bool BUDGET>
 __global__ __launch_bounds__(64) void walk_cache_kernel(WalkArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int lane = threadIdx.x;
@@ -1309,13 +1345,17 @@ __global__ __launch_bounds__(64) void walk_cache_kernel(WalkArgs a) {
         }
         const uint64_t fm = __ballot(fresh);
         const int nf = __popcll(fm);
+        bool stop = false;
+        const uint64_t kept = BUDGET ? budget_cut(fm, D, a.max_d, stop) : fm;  // the evaluations within the budget
         if (fresh) {
-          k = make_key(cr.adc(lut, sc), nb);
+          if ((kept >> lane) & 1ull) k = make_key(cr.adc(lut, sc), nb);
+          // every bit set is listed for clearing, a dropped link's too
           const int at = vcount + __popcll(fm & ((1ull << lane) - 1ull));
           if (at < a.list_cap) vlist[at] = nb;  // after the scoring, so that nothing waits on this store
+          fresh = (kept >> lane) & 1ull;
         }
         vcount += nf;
-        D += nf;
+        D += __popcll(kept);
         const bool keep = fresh && k < wmax;
         const uint64_t km = __ballot(keep);
         int p0 = fu;
@@ -1327,6 +1367,7 @@ __global__ __launch_bounds__(64) void walk_cache_kernel(WalkArgs a) {
           wmax = nw == efe ? pure_key(W[nw - 1]) : kKeyMax;
         }
         wave_sync();
+        if (BUDGET && stop) break;  // the budget of distance evaluations is spent
         int nfu = nw;
         uint64_t nck = 0;
         for (int base = p0; base < nw; base += 64) {
@@ -1485,10 +1526,28 @@ size_t ws_bytes_m(const lc_index *ix, int64_t nq, int32_t ef_max, int32_t S, con
   return a > b ? a : b;
 }
 
+// The kernel the plan picks; with a budget on distance evaluations, its
+// variant that counts them (the kernels without one carry no such test).
+template <int M, typename T, bool BUDGET>
+int launch_kernel(const WalkPlan &p, const lc_schedule *sc, const WalkArgs &a, hipStream_t st) {
+  const void *fn = sc->visited == 1 ? reinterpret_cast<const void *>(&walk_cache_kernel<M, T, BUDGET>)
+                   : p.reg_chunks  ? reinterpret_cast<const void *>(&walk_reg_kernel<M, T, 2, BUDGET>)
+                                   : reinterpret_cast<const void *>(&walk_kernel<M, T, BUDGET>);
+  if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, p.lds_bytes) != hipSuccess)
+    return LC_EHIP;
+  if (sc->visited == 1)
+    hipLaunchKernelGGL((walk_cache_kernel<M, T, BUDGET>), dim3(p.grid), dim3(64), p.lds_bytes, st, a);
+  else if (p.reg_chunks)
+    hipLaunchKernelGGL((walk_reg_kernel<M, T, 2, BUDGET>), dim3(p.grid), dim3(64), p.lds_bytes, st, a);
+  else
+    hipLaunchKernelGGL((walk_kernel<M, T, BUDGET>), dim3(p.grid), dim3(64), p.lds_bytes, st, a);
+  return hipGetLastError() == hipSuccess ? LC_OK : LC_EHIP;
+}
+
 template <int M, typename T>
 int launch_m(const lc_index *ix, const void *lut, const float *scale, int64_t nq, const int32_t *ef,
-             int32_t ef_max, int32_t S, const int32_t *order, int32_t *cand_ids, float *cand_adc, int32_t *cand_n,
-             int32_t *stats, void *ws, size_t ws_bytes, const lc_schedule *sc, hipStream_t st) {
+             int32_t ef_max, int32_t S, int32_t max_d, const int32_t *order, int32_t *cand_ids, float *cand_adc,
+             int32_t *cand_n, int32_t *stats, void *ws, size_t ws_bytes, const lc_schedule *sc, hipStream_t st) {
   WalkPlan p = plan_for<M>(ix, nq, ef_max, S, sc, int(sizeof(T)));
   const int64_t words = (int64_t(ix->v.n) + 31) / 32;
   if (ws_bytes < ws_need(p, words)) return LC_ENOSPC;
@@ -1504,6 +1563,7 @@ int launch_m(const lc_index *ix, const void *lut, const float *scale, int64_t nq
   a.order = order;
   a.ef_max = ef_max;
   a.S = S;
+  a.max_d = max_d;
   a.nq = nq;
   a.n = ix->v.n;
   a.n_up_rows = ix->v.n_up_rows;
@@ -1528,19 +1588,9 @@ int launch_m(const lc_index *ix, const void *lut, const float *scale, int64_t nq
   a.cand_adc = cand_adc;
   a.cand_n = cand_n;
   a.stats = stats;
-  const void *fn = sc->visited == 1 ? reinterpret_cast<const void *>(&walk_cache_kernel<M, T>)
-                   : p.reg_chunks  ? reinterpret_cast<const void *>(&walk_reg_kernel<M, T, 2>)
-                                   : reinterpret_cast<const void *>(&walk_kernel<M, T>);
-  if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, p.lds_bytes) != hipSuccess)
-    return LC_EHIP;
-  if (sc->visited == 1)
-    hipLaunchKernelGGL((walk_cache_kernel<M, T>), dim3(p.grid), dim3(64), p.lds_bytes, st, a);
-  else if (p.reg_chunks)
-    hipLaunchKernelGGL((walk_reg_kernel<M, T, 2>), dim3(p.grid), dim3(64), p.lds_bytes, st, a);
-  else
-    hipLaunchKernelGGL((walk_kernel<M, T>), dim3(p.grid), dim3(64), p.lds_bytes, st, a);
-  return hipGetLastError() == hipSuccess ? LC_OK : LC_EHIP;
+  return max_d > 0 ? launch_kernel<M, T, true>(p, sc, a, st) : launch_kernel<M, T, false>(p, sc, a, st);
 }
+
 
 }  // namespace
 
@@ -1560,8 +1610,8 @@ size_t lc_walk_workspace_bytes(const lc_index *ix, int64_t nq, int32_t ef_max, i
 }
 
 int lc_launch_walk(const lc_index *ix, const void *lut, int dtype, const float *scale, int64_t nq,
-                   const int32_t *ef, int32_t ef_max, int32_t S, const int32_t *order, int32_t *cand_ids,
-                   float *cand_adc,
+                   const int32_t *ef, int32_t ef_max, int32_t S, int32_t max_d, const int32_t *order,
+                   int32_t *cand_ids, float *cand_adc,
                    int32_t *cand_n, int32_t *stats, void *ws, size_t ws_bytes, const lc_schedule *sched,
                    hipStream_t st) {
   if (dtype != LC_LUT_F32 && dtype != LC_LUT_F16) return LC_ENOTSUP;
@@ -1570,10 +1620,10 @@ int lc_launch_walk(const lc_index *ix, const void *lut, int dtype, const float *
   switch (ix->v.m) {
 #define CASE(MM)                                                                                              \
   case MM:                                                                                                    \
-    return dtype == LC_LUT_F32 ? launch_m<MM, float>(ix, lut, scale, nq, ef, ef_max, S, order, cand_ids,     \
-                                                     cand_adc, cand_n, stats, ws, ws_bytes, sc, st)           \
-                               : launch_m<MM, __half>(ix, lut, scale, nq, ef, ef_max, S, order, cand_ids,    \
-                                                      cand_adc, cand_n, stats, ws, ws_bytes, sc, st);
+    return dtype == LC_LUT_F32 ? launch_m<MM, float>(ix, lut, scale, nq, ef, ef_max, S, max_d, order,        \
+                                                     cand_ids, cand_adc, cand_n, stats, ws, ws_bytes, sc, st) \
+                               : launch_m<MM, __half>(ix, lut, scale, nq, ef, ef_max, S, max_d, order,       \
+                                                      cand_ids, cand_adc, cand_n, stats, ws, ws_bytes, sc, st);
     LC_FOR_EACH_M(CASE)
 #undef CASE
     default: return LC_ENOTSUP;
