@@ -290,6 +290,10 @@ def main():
     ap.add_argument("--m-beta", type=int, default=1,
                     help="regression codebook blocks: 1 = one codebook, >1 = product codebook of that many blocks "
                          "(plain and both forms)")
+    ap.add_argument("--n-beta", type=int, default=0,
+                    help="regression codebook size (default: the workload's; 1 = one shared beta, the 0-byte form)")
+    ap.add_argument("--max-evals", type=int, default=0,
+                    help="budget T on level-0 distance evaluations per query (0 = none; plain and both forms)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="also run one device-to-device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -320,6 +324,8 @@ def main():
     w = datagen.WORKLOADS[args.workload]
     if args.m_beta != 1:
         w = dataclasses.replace(w, m_beta=args.m_beta)
+    if args.n_beta:
+        w = dataclasses.replace(w, n_beta=args.n_beta)
     dev = torch.device("cuda:0")
     t0 = time.time()
     ix, db, q = builder.build_workload(w, cache_dir=args.cache, log=log)
@@ -364,7 +370,7 @@ def main():
                 lut, scale = gix.build_lut(qd, lut_dt)
                 if ev is not None:
                     ev[1].record()
-                r = gix.search(lut, scale, ef=None, ef_max=ef, S=S, stats=True, ws=ws)
+                r = gix.search(lut, scale, ef=None, ef_max=ef, S=S, stats=True, ws=ws, max_evals=args.max_evals)
                 if ev is not None:
                     ev[2].record()
                 ids, d = gix.refine(qd, r.cand_ids, r.cand_n, K, ref_p)
@@ -459,6 +465,8 @@ def main():
                                f"L2-normalised), PQ {w.m}x256, level-0 degree {w.deg0}, k={w.k_reg}, " +
                                (f"product beta codebook {w.m_beta} blocks x {w.n_beta}" if w.m_beta > 1
                                 else f"beta codebook {w.n_beta}") +
+                               (f", at most {args.max_evals} level-0 distance evaluations per query"
+                                if args.max_evals else "") +
                                f", top-{K}, {nq} queries per step; {form}; "
                                f"efSearch {head['ef']}, shortlist {S_h}; " +
                                (f"consecutive steps alternate over {args.streams} streams (each with its own workspace "
