@@ -640,31 +640,25 @@ __device__ __forceinline__ void reg_merge_sorted(Pool &p, uint64_t kv, int efe, 
 
 // Greedy descent on levels max_level .. 1 (Sec. 2): from the entry node,
 // move to the best link while it beats the current key, one lane per link.
-// Each lane also fetches its link's first upper row index together with the
-// link's code, so that the winner's row is known without another round trip.
+// (Fetching every link's upper row index with its code saves one dependent
+// load per move but reads a cache line per link for it: more HBM traffic and
+// no measurable time, so the winner's row index is read after the move.)
 template <int M, typename T>
 __device__ __forceinline__ void greedy_descent(const WalkArgs &a, const T *lut, const float *sc, int lane,
                                                int32_t &cur, uint64_t &curkey) {
   cur = a.entry;
   curkey = make_key(adc_full<M, T>(lut, sc, a.codes, a.code_stride, cur), cur);
-  int64_t base = a.max_level >= 1 ? int64_t(a.up_base[cur]) : -1;
   for (int l = a.max_level; l >= 1; --l) {
     for (;;) {
-      const int64_t row = base + l - 1;
+      const int64_t row = int64_t(a.up_base[cur]) + l - 1;
       int32_t nb = -1;
-      if (lane < a.deg_up && base >= 0 && row < a.n_up_rows) nb = a.adj_up[row * a.deg_up + lane];
+      if (lane < a.deg_up && row >= 0 && row < a.n_up_rows) nb = a.adj_up[row * a.deg_up + lane];
       if (nb >= a.n) nb = -1;  // a malformed link is ignored rather than followed
-      int32_t nb_base = -1;
-      uint64_t k = kKeyMax;
-      if (nb >= 0) {
-        nb_base = a.up_base[nb];
-        k = make_key(adc_full<M, T>(lut, sc, a.codes, a.code_stride, nb), nb);
-      }
+      const uint64_t k = nb >= 0 ? make_key(adc_full<M, T>(lut, sc, a.codes, a.code_stride, nb), nb) : kKeyMax;
       const uint64_t mn = wave_min64(k);
       if (mn < curkey) {
         curkey = mn;
         cur = key_id(mn);
-        base = __builtin_amdgcn_readlane(nb_base, __ffsll((unsigned long long)__ballot(k == mn)) - 1);
       } else {
         break;
       }
