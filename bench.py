@@ -215,6 +215,56 @@ def bench_batched(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_assign(args):
+    """Index-build step on the GPU: the regression-codebook entry (Sec. 4.3
+    Eq. 7; per block, Eq. 9) of every database vector, float64 arg-min, against
+    the host builder's threaded assignment of a sample of the same vectors."""
+    import ctypes as C
+
+    import torch
+
+    import datagen
+    import paper_1804_09996_amd as lc
+    from paper_1804_09996_amd import builder
+
+    w = datagen.WORKLOADS[args.workload]
+    if args.m_beta != 1:
+        w = dataclasses.replace(w, m_beta=args.m_beta)
+    dev = torch.device("cuda:0")
+    ix, db, q = builder.build_workload(w, cache_dir=args.cache, log=log)
+    gix = lc.Index.from_index(ix, device=dev)
+    x = torch.from_numpy(db).to(dev)
+    out = gix.assign_beta(x)  # warm-up
+    torch.cuda.synchronize()
+    times = []
+    for _ in range(max(3, args.steps // 10)):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        out = gix.assign_beta(x)
+        b.record()
+        b.synchronize()
+        times.append(a.elapsed_time(b))
+    ms = float(np.median(times))
+    got = out.cpu().numpy().reshape(ix.n, -1)
+    agree = float((got == np.asarray(ix.beta_idx).reshape(ix.n, -1)).mean())
+    # the host builder's assignment of a sample, its own threads
+    L = builder.lib()
+    ns = min(ix.n, 100_000)
+    bidx = np.empty((ns, w.m_beta), np.uint8)
+    p_ = lambda a_: None if a_ is None else a_.ctypes.data
+    nt = min(16, os.cpu_count() or 1)
+    t0 = time.perf_counter()
+    rc = L.lcb_beta_assign(p_(np.ascontiguousarray(db[:ns])), ns, w.d, p_(ix.proj), w.d_pad, w.m, p_(ix.centroids),
+                           p_(ix.codes), ix.codes.shape[1], p_(ix.adj0), w.deg0, w.k_reg, w.n_beta, w.m_beta,
+                           p_(np.ascontiguousarray(ix.beta, np.float32)), nt, p_(bidx))
+    cpu_s = time.perf_counter() - t0
+    assert rc == 0
+    print(json.dumps({"form": "beta assignment (index build)", "workload": w.name, "n": ix.n, "m_beta": w.m_beta,
+                      "n_beta": w.n_beta, "k": w.k_reg, "gpu_ms": ms, "gpu_vectors_per_s": ix.n / (ms * 1e-3),
+                      "agreement_with_host_builder": agree,
+                      "host_builder": {"vectors": ns, "seconds": cpu_s, "vectors_per_s": ns / cpu_s, "threads": nt}}))
+
+
 def bench_serve(args):
     """Serving form: Poisson arrivals of requests (batch size log-uniform
     1..1024, ef in {32, 64, 128, 256}) at fractions of the measured
@@ -276,7 +326,7 @@ def main():
     ap.add_argument("--steps", type=int, default=30)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="C2-1M")
-    ap.add_argument("--form", choices=("both", "plain", "batched", "serve"), default="both")
+    ap.add_argument("--form", choices=("both", "plain", "batched", "serve", "assign"), default="both")
     ap.add_argument("--n", type=int, default=0, help="override the database size (serving form)")
     ap.add_argument("--loads", default="0.5,0.8", help="offered loads as fractions of saturation (serving form)")
     ap.add_argument("--cache", default=os.environ.get("LC_INDEX_CACHE", os.path.join("/tmp", "lc_index_cache")))
@@ -321,6 +371,8 @@ def main():
         return bench_batched(args)
     if args.form == "serve":
         return bench_serve(args)
+    if args.form == "assign":
+        return bench_assign(args)
     w = datagen.WORKLOADS[args.workload]
     if args.m_beta != 1:
         w = dataclasses.replace(w, m_beta=args.m_beta)

@@ -226,6 +226,24 @@ int lc_refine(const lc_index *ix, const float *q, int64_t nq, const int32_t *can
               const int32_t *cand_n, int32_t S, int32_t K, int precision, int32_t *out_ids,
               float *out_d, void *stream);
 
+/* Regression-codebook assignment of database vectors (Sec. 4.3, Eq. 7; one
+ * entry per block for the product codebook, Eq. 9) — the step of the index
+ * build that touches every vector.  For vectors i = n0 .. n0+count-1 of this
+ * index, with G(x_i) = [q(x_i), q(g_1), ..., q(g_k_reg)] (its code and the
+ * codes of its first k_reg level-0 links, a -1 link a zero column) and x' =
+ * P x_i, block jb's entry is the b minimising
+ *   ||x'||^2 - 2 beta^T (G^T x') + beta^T (G^T G) beta,  beta = beta[jb][b],
+ * over the block's coordinates [jb w, jb w + w), w = d_pad / m_beta, lowest b
+ * on ties.  The arg-min is taken in float64 with every sum in ascending order
+ * and no fused multiply-add, so it is the entry a plain sequential float64
+ * evaluation picks.
+ * x:   f32 [count][d] device, row r is vector n0 + r (raw, before P).
+ * out: u8 [count][m_beta] device.
+ * Uses the bound index's centroids, codes, adj0, proj and beta (not its
+ * beta_idx).  Requires 0 <= n0, 0 <= count, n0 + count <= n (LC_EINVAL). */
+int lc_assign_beta(const lc_index *ix, const float *x, int64_t n0, int64_t count, uint8_t *out,
+                   void *stream);
+
 const char *lc_strerror(int code);
 
 /* Identity of the build: a hex sha1 over this header and the library's

@@ -93,13 +93,15 @@ def lib():
         L.lc_search_budget.argtypes = [p, p, C.c_int, p, i64, p, i32, i32, i32, p, p, p, p, p, p, sz,
                                        C.POINTER(Schedule), p]
         L.lc_refine.argtypes = [p, p, i64, p, p, i32, i32, C.c_int, p, p, p]
+        L.lc_assign_beta.argtypes = [p, p, i64, i64, p, p]
         _lib = L
     return _lib
 
 
 def exported_symbols():
     return ["lc_build_id", "lc_strerror", "lc_index_bind", "lc_index_release", "lc_build_lut", "lc_search_workspace_bytes",
-            "lc_search", "lc_refine", "lc_search_workspace_bytes_sched", "lc_search_sched", "lc_search_budget"]
+            "lc_search", "lc_refine", "lc_search_workspace_bytes_sched", "lc_search_sched", "lc_search_budget",
+            "lc_assign_beta"]
 
 
 def _check(rc: int, where: str):
@@ -281,6 +283,19 @@ class Index:
         _check(lib().lc_refine(self.handle, _ptr(q), nq, _ptr(cand_ids), _ptr(cand_n), S, K, precision,
                                _ptr(out_ids), _ptr(out_d), _stream(torch, self.device)), "lc_refine")
         return out_ids, out_d
+
+    def assign_beta(self, x, n0: int = 0):
+        """Codebook entries (Sec. 4.3 Eq. 7, per block Eq. 9) of the vectors
+        n0 .. n0 + len(x) - 1 from their raw rows ``x`` [count, d]: a uint8
+        device tensor [count, m_beta]."""
+        torch = self.torch
+        x = torch.as_tensor(x).to(self.device, torch.float32).contiguous()
+        if x.dim() != 2 or x.shape[1] != self.d:
+            raise ValueError(f"x must be [count, {self.d}]")
+        out = torch.empty((x.shape[0], int(self.view.m_beta)), dtype=torch.uint8, device=self.device)
+        _check(lib().lc_assign_beta(self.handle, _ptr(x), int(n0), x.shape[0], _ptr(out),
+                                    _stream(torch, self.device)), "lc_assign_beta")
+        return out
 
     def query(self, q, ef=None, ef_max: int = 64, S: int = 64, K: int = 10, stats: bool = False,
               sched: Optional[Schedule] = None, precision: str = "f32", max_evals: int = 0):

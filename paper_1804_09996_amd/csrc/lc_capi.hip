@@ -122,6 +122,13 @@ int lc_search(const lc_index *ix, const void *lut, int lut_dtype, const float *l
                          stats, ws, ws_bytes, nullptr, stream);
 }
 
+int lc_assign_beta(const lc_index *ix, const float *x, int64_t n0, int64_t count, uint8_t *out, void *stream) {
+  if (!ix || n0 < 0 || count < 0 || n0 > ix->v.n || count > int64_t(ix->v.n) - n0) return LC_EINVAL;
+  if (count == 0) return LC_OK;
+  if (!x || !out) return LC_EINVAL;
+  return lc_launch_assign(ix, x, n0, count, out, static_cast<hipStream_t>(stream));
+}
+
 int lc_refine(const lc_index *ix, const float *q, int64_t nq, const int32_t *cand_ids,
               const int32_t *cand_n, int32_t S, int32_t K, int precision, int32_t *out_ids, float *out_d,
               void *stream) {
