@@ -68,8 +68,8 @@ def lib():
     global _lib
     if _lib is None:
         if not os.path.exists(LIB_PATH):
-            raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_1804_09996_amd.build_ext` "
-                              "(or __graft_entry__.build()); there is no CPU fallback")
+            raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_1804_09996_amd.build_ext`; "
+                              "there is no CPU fallback")
         L = C.CDLL(LIB_PATH)
         L.lc_build_id.restype = C.c_char_p
         from .build_ext import source_id
