@@ -386,3 +386,22 @@ def test_ef_classes_give_the_same_results(c1, torch, precision):
         assert torch.equal(ids, ref_ids), rep
         for ws in bs.ws:
             assert int(ws.count_nonzero().item()) == 0
+
+
+def test_golden_fixture_on_gpu(torch):
+    # the frozen oracle outputs of tests/golden/tiny_search.json, from the GPU path
+    import json
+    import os
+    import paper_1804_09996_amd as lc
+    from tests.golden import make_golden
+    g = json.load(open(os.path.join(os.path.dirname(make_golden.__file__), "tiny_search.json")))
+    ix, db, q = make_golden.build()
+    w = make_golden.W
+    gix = lc.Index.from_index(ix)
+    ids, d, r = gix.query(torch.from_numpy(q), ef=w.ef, ef_max=w.ef, S=w.shortlist, K=w.topk, stats=True)
+    assert r.cand_ids.cpu().numpy().tolist() == g["cand_ids"]
+    assert r.stats.cpu().numpy().tolist() == g["stats"]
+    gold = {"ids": np.array(g["ids"]), "d": np.array([[float.fromhex(x) for x in row] for row in g["d"]])}
+    s = parity.summarize(ix, q, ids.cpu().numpy(), d.cpu().numpy(), gold)
+    assert s["exact_frac"] == 1.0 and s["max_rel_err"] <= 1e-5
+    gix.close()

@@ -590,3 +590,21 @@ def test_product_search_uses_blockwise_refinement(tiny_build):
         order = np.lexsort((cand, dd))[:w.topk]
         assert r["ids"][qi].tolist() == cand[order].tolist()
         np.testing.assert_array_equal(r["d"][qi], dd[order])
+
+
+# ---------------------------------------------------------------------------
+# frozen outputs (tests/golden/tiny_search.json, written by make_golden.py)
+# ---------------------------------------------------------------------------
+def test_golden_fixture_reproduced():
+    import json
+    import os
+    from tests.golden import make_golden
+    g = json.load(open(os.path.join(os.path.dirname(make_golden.__file__), "tiny_search.json")))
+    ix, db, q = make_golden.build()
+    w = make_golden.W
+    r = ix.search(q, w.ef, w.shortlist, w.topk, nthreads=3)
+    assert (ix.entry, ix.max_level) == (g["entry"], g["max_level"])
+    assert ix.codes[:4].tolist() == g["codes_head"] and ix.beta_idx[:32].tolist() == g["beta_idx_head"]
+    for k in ("ids", "cand_ids", "cand_n", "stats"):
+        assert r[k].tolist() == g[k], k
+    assert [[float(x).hex() for x in row] for row in r["d"]] == g["d"]
