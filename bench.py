@@ -342,6 +342,8 @@ def main():
                          "(plain and both forms)")
     ap.add_argument("--n-beta", type=int, default=0,
                     help="regression codebook size (default: the workload's; 1 = one shared beta, the 0-byte form)")
+    ap.add_argument("--opq-iters", type=int, default=0,
+                    help="learn the rotation ahead of PQ (OPQ) with this many rotation steps (0 = the workload's)")
     ap.add_argument("--max-evals", type=int, default=0,
                     help="budget T on level-0 distance evaluations per query (0 = none; plain and both forms)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
@@ -378,6 +380,8 @@ def main():
         w = dataclasses.replace(w, m_beta=args.m_beta)
     if args.n_beta:
         w = dataclasses.replace(w, n_beta=args.n_beta)
+    if args.opq_iters:
+        w = dataclasses.replace(w, opq_iters=args.opq_iters)
     dev = torch.device("cuda:0")
     t0 = time.time()
     ix, db, q = builder.build_workload(w, cache_dir=args.cache, log=log)
@@ -419,13 +423,15 @@ def main():
             with torch.cuda.stream(st_):
                 if ev is not None:
                     ev[0].record()
-                lut, scale = gix.build_lut(qd, lut_dt)
+                # an index with a projection projects the batch once (timed with the tables)
+                qx = gix.project(qd) if gix.has_projection else qd
+                lut, scale = gix.build_lut(qx, lut_dt, projected=gix.has_projection)
                 if ev is not None:
                     ev[1].record()
                 r = gix.search(lut, scale, ef=None, ef_max=ef, S=S, stats=True, ws=ws, max_evals=args.max_evals)
                 if ev is not None:
                     ev[2].record()
-                ids, d = gix.refine(qd, r.cand_ids, r.cand_n, K, ref_p)
+                ids, d = gix.refine(qx, r.cand_ids, r.cand_n, K, ref_p, projected=gix.has_projection)
                 if ev is not None:
                     ev[3].record()
             return ids, d, r
@@ -514,7 +520,8 @@ def main():
         "warmup": args.warmup, "ms_per_step": head["ms_per_step"], "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f16" if f16 else "f32", "data": "synthetic",
         "config": {"workload": f"{w.name}: N={w.n} d={w.d} Gaussian mixture ({w.n_comp} components, "
-                               f"L2-normalised), PQ {w.m}x256, level-0 degree {w.deg0}, k={w.k_reg}, " +
+                               f"L2-normalised), " + (f"learned rotation ({w.opq_iters} steps) + " if w.opq_iters else "") +
+                               f"PQ {w.m}x256, level-0 degree {w.deg0}, k={w.k_reg}, " +
                                (f"product beta codebook {w.m_beta} blocks x {w.n_beta}" if w.m_beta > 1
                                 else f"beta codebook {w.n_beta}") +
                                (f", at most {args.max_evals} level-0 distance evaluations per query"

@@ -81,6 +81,7 @@ class Workload:
     em_iters: int = 10            # Sec. 5.2
     seed: int = DEFAULT_SEED
     m_beta: int = 1               # regression-codebook blocks (product codebook, Sec. 4.3 Eq. 9)
+    opq_iters: int = 0            # learned rotation ahead of PQ (OPQ): rotation steps, 0 = none
 
     @property
     def dsub(self) -> int:

@@ -56,9 +56,11 @@ enum { LC_REFINE_F32 = 0, LC_REFINE_BF16_RESCORE = 1 };
 
 /* Borrowed device views of an index (the caller keeps the memory alive).
  * Layout (row-major, all device memory):
- *   proj      f32 [d_pad][d]    orthonormal rotation applied before PQ, or
- *                               NULL when d_pad == d (a rotation ahead of the
- *                               product quantizer, as OPQ does, Sec. 5.1)
+ *   proj      f32 [d_pad][d]    projection with orthonormal columns applied
+ *                               before PQ: required when d_pad > d (a
+ *                               rotation ahead of the product quantizer, as
+ *                               OPQ does, Sec. 5.1), optional when d_pad == d
+ *                               (e.g. a learned rotation), NULL for none
  *   centroids f32 [m][256][dsub], dsub = d_pad / m (8-bit PQ, Sec. 3.3)
  *   codes     u8  [n][code_stride], code_stride = next power of two >= m
  *   adj0      i32 [n][deg0]      level-0 links, -1 padded at the end, each
@@ -225,6 +227,23 @@ int lc_search_budget(const lc_index *ix, const void *lut, int lut_dtype, const f
 int lc_refine(const lc_index *ix, const float *q, int64_t nq, const int32_t *cand_ids,
               const int32_t *cand_n, int32_t S, int32_t K, int precision, int32_t *out_ids,
               float *out_d, void *stream);
+
+/* Projected queries for an index with a projection P (required when d_pad > d,
+ * e.g. a rotation learned ahead of PQ): qp[i] = P q[i], f32 [nq][d_pad]
+ * device, each coordinate summed over the inputs in order (float32).  Without
+ * P the rows are copied (d == d_pad).  lc_build_lut_projected and
+ * lc_refine_projected then take qp in place of q and skip the projection,
+ * which the plain entry points apply per table block and per refined query:
+ * projecting a batch once reads P once per block of queries instead of once
+ * per query.  Results equal the plain entry points' up to float32 rounding of
+ * the projection.  Errors: LC_EINVAL (null pointers, nq < 0), LC_ENOTSUP (P
+ * and a block of queries do not fit the LDS of one compute unit). */
+int lc_project_queries(const lc_index *ix, const float *q, int64_t nq, float *qp, void *stream);
+int lc_build_lut_projected(const lc_index *ix, const float *qp, int64_t nq, int lut_dtype, void *lut,
+                           float *lut_scale, void *stream);
+int lc_refine_projected(const lc_index *ix, const float *qp, int64_t nq, const int32_t *cand_ids,
+                        const int32_t *cand_n, int32_t S, int32_t K, int precision, int32_t *out_ids,
+                        float *out_d, void *stream);
 
 /* Regression-codebook assignment of database vectors (Sec. 4.3, Eq. 7; one
  * entry per block for the product codebook, Eq. 9) — the step of the index

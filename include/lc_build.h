@@ -72,6 +72,25 @@ int lcb_beta_assign(const float *x, int64_t n, int d, const float *proj, int d_p
                     const int32_t *adj0, int deg0, int k_reg, int n_beta, int m_beta, const float *beta,
                     int nthreads, uint8_t *beta_idx);
 
+/* Learned rotation ahead of the product quantizer (OPQ: the codec of Sec. 4.1
+ * and Sec. 5.1 rotates the vectors before PQ).  Starting from init_proj
+ * [d_pad][d] (orthonormal columns; NULL = identity, d_pad == d only), repeat
+ * opq_iters times: project the training vectors, train the PQ (km_iters Lloyd
+ * iterations, seeded by init [m][256] the first time, warm after), and replace
+ * the rotation by the P with orthonormal columns minimising
+ * sum_i ||P x_i - q(P x_i)||^2 for those reconstructions (orthogonal
+ * Procrustes: P = S^T (S S^T)^(-1/2), S = X^T Yhat).  proj_out [d_pad][d];
+ * mse_hist (optional) opq_iters+1 values of the mean distortion, the last for
+ * the returned rotation's PQ.  Independent of nthreads.  Returns 0, -1 on bad
+ * arguments, 2 if a rotation step meets a rank-deficient S. */
+int lcb_opq_train(const float *train, int64_t n, int d, int d_pad, int m, const float *init_proj,
+                  const int64_t *init, int opq_iters, int km_iters, int nthreads, float *proj_out,
+                  double *mse_hist);
+
+/* The Procrustes step alone: P [D][d] from S [d][D] (0, or 1 if S is rank
+ * deficient). */
+int lcb_procrustes(const double *S, int d, int D, double *P);
+
 #ifdef __cplusplus
 }
 #endif

@@ -94,6 +94,9 @@ def lib():
                                        C.POINTER(Schedule), p]
         L.lc_refine.argtypes = [p, p, i64, p, p, i32, i32, C.c_int, p, p, p]
         L.lc_assign_beta.argtypes = [p, p, i64, i64, p, p]
+        L.lc_project_queries.argtypes = [p, p, i64, p, p]
+        L.lc_build_lut_projected.argtypes = [p, p, i64, C.c_int, p, p, p]
+        L.lc_refine_projected.argtypes = [p, p, i64, p, p, i32, i32, C.c_int, p, p, p]
         _lib = L
     return _lib
 
@@ -101,7 +104,7 @@ def lib():
 def exported_symbols():
     return ["lc_build_id", "lc_strerror", "lc_index_bind", "lc_index_release", "lc_build_lut", "lc_search_workspace_bytes",
             "lc_search", "lc_refine", "lc_search_workspace_bytes_sched", "lc_search_sched", "lc_search_budget",
-            "lc_assign_beta"]
+            "lc_assign_beta", "lc_project_queries", "lc_build_lut_projected", "lc_refine_projected"]
 
 
 def _check(rc: int, where: str):
@@ -205,7 +208,21 @@ class Index:
             pass
 
     # -- the three calls of the path ---------------------------------------
-    def build_lut(self, q, lut_dtype: int = LC_LUT_F32):
+    @property
+    def has_projection(self) -> bool:
+        return bool(self.view.proj)
+
+    def project(self, q):
+        """Projected queries P q [nq, d_pad] (a copy without a projection)."""
+        torch = self.torch
+        q = q.to(self.device, torch.float32).contiguous()
+        out = torch.empty((q.shape[0], self.d_pad), dtype=torch.float32, device=self.device)
+        _check(lib().lc_project_queries(self.handle, _ptr(q), q.shape[0], _ptr(out), _stream(torch, self.device)),
+               "lc_project_queries")
+        return out
+
+    def build_lut(self, q, lut_dtype: int = LC_LUT_F32, projected: bool = False):
+        """``projected``: q holds projected queries [nq, d_pad] (from project())."""
         torch = self.torch
         q = q.to(self.device, torch.float32).contiguous()
         nq = q.shape[0]
@@ -215,8 +232,9 @@ class Index:
         else:
             lut = torch.empty((nq, self.m, 256), dtype=torch.float16, device=self.device)
             scale = torch.empty((nq, self.m), dtype=torch.float32, device=self.device)
-        _check(lib().lc_build_lut(self.handle, _ptr(q), nq, lut_dtype, _ptr(lut), _ptr(scale),
-                                  _stream(torch, self.device)), "lc_build_lut")
+        fn = lib().lc_build_lut_projected if projected else lib().lc_build_lut
+        _check(fn(self.handle, _ptr(q), nq, lut_dtype, _ptr(lut), _ptr(scale), _stream(torch, self.device)),
+               "lc_build_lut")
         return lut, scale
 
     def workspace_bytes(self, nq: int, ef_max: int, S: int, sched: Optional[Schedule] = None) -> int:
@@ -274,14 +292,15 @@ class Index:
         _check(rc, "lc_search")
         return SearchResult(cand_ids, cand_adc, cand_n, st)
 
-    def refine(self, q, cand_ids, cand_n, K: int, precision: int = LC_REFINE_F32):
+    def refine(self, q, cand_ids, cand_n, K: int, precision: int = LC_REFINE_F32, projected: bool = False):
         torch = self.torch
         q = q.to(self.device, torch.float32).contiguous()
         nq, S = cand_ids.shape
         out_ids = torch.empty((nq, K), dtype=torch.int32, device=self.device)
         out_d = torch.empty((nq, K), dtype=torch.float32, device=self.device)
-        _check(lib().lc_refine(self.handle, _ptr(q), nq, _ptr(cand_ids), _ptr(cand_n), S, K, precision,
-                               _ptr(out_ids), _ptr(out_d), _stream(torch, self.device)), "lc_refine")
+        fn = lib().lc_refine_projected if projected else lib().lc_refine
+        _check(fn(self.handle, _ptr(q), nq, _ptr(cand_ids), _ptr(cand_n), S, K, precision, _ptr(out_ids),
+                  _ptr(out_d), _stream(torch, self.device)), "lc_refine")
         return out_ids, out_d
 
     def assign_beta(self, x, n0: int = 0):
@@ -303,7 +322,11 @@ class Index:
         ``precision="f16"`` selects the fp16 table and the bf16 refinement
         with exact fp32 re-scoring of the final candidates."""
         lp = precision == "f16"
-        lut, scale = self.build_lut(q, LC_LUT_F16 if lp else LC_LUT_F32)
+        pj = self.has_projection  # project the batch once for the tables and the refinement
+        if pj:
+            q = self.project(q)
+        lut, scale = self.build_lut(q, LC_LUT_F16 if lp else LC_LUT_F32, projected=pj)
         r = self.search(lut, scale, ef=ef, ef_max=ef_max, S=S, stats=stats, sched=sched, max_evals=max_evals)
-        ids, d = self.refine(q, r.cand_ids, r.cand_n, K, LC_REFINE_BF16_RESCORE if lp else LC_REFINE_F32)
+        ids, d = self.refine(q, r.cand_ids, r.cand_n, K, LC_REFINE_BF16_RESCORE if lp else LC_REFINE_F32,
+                             projected=pj)
         return ids, d, r

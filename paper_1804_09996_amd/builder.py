@@ -35,6 +35,8 @@ def lib():
         L.lcb_graph_build.argtypes = [p, i64, i, p, i, i, p, p, i, p, i, i, i, i, p, p, p, p, p]
         L.lcb_beta_train.argtypes = [p, p, i64, i, p, i, i, p, p, i, p, i, i, i, i, p, i, i, i, p, p]
         L.lcb_beta_assign.argtypes = [p, i64, i, p, i, i, p, p, i, p, i, i, i, i, p, i, p]
+        L.lcb_opq_train.argtypes = [p, i64, i, i, i, p, p, i, i, i, p, p]
+        L.lcb_procrustes.argtypes = [p, i, i, p]
         _lib = L
     return _lib
 
@@ -116,6 +118,11 @@ def build_index(w, db, train, proj, level_u, pq_init, beta_ids, beta_init, nthre
     t0 = time.time()
     if log:
         log(f"index build: {n} vectors, m={w.m}, {nt} threads")
+    if getattr(w, "opq_iters", 0) > 0:
+        # learned rotation ahead of PQ (OPQ), started from the given projection (or the identity)
+        proj, hist = opq_train(train, w.d_pad, w.m, proj, pq_init, w.opq_iters, max(2, w.pq_iters // 5), nt)
+        if log:
+            log(f"index build: rotation learned, PQ distortion {hist[0]:.5f} -> {hist[-1]:.5f}")
     cent = np.empty((w.m, 256, w.d_pad // w.m), np.float32)
     _ok(L.lcb_pq_train(_p(train), train.shape[0], d, _p(proj), w.d_pad, w.m, _p(_c(pq_init, np.int64)), w.pq_iters,
                        nt, _p(cent)), "lcb_pq_train")
@@ -175,3 +182,24 @@ def build_workload(w, nthreads: Optional[int] = None, cache_dir: Optional[str] =
         ix.save(path + ".tmp.npz")
         os.replace(path + ".tmp.npz", path)
     return ix, db, q
+
+
+def opq_train(train, d_pad, m, init_proj, init, opq_iters, km_iters, nthreads=None):
+    """Learned rotation ahead of PQ (OPQ): (proj [d_pad, d], distortion history)."""
+    L = lib()
+    train = _c(train, np.float32)
+    n, d = train.shape
+    proj = np.empty((d_pad, d), np.float32)
+    hist = np.empty(opq_iters + 1, np.float64)
+    _ok(L.lcb_opq_train(_p(train), n, d, d_pad, m, _p(_c(init_proj, np.float32)), _p(_c(init, np.int64)), opq_iters,
+                        km_iters, nthreads or threads(), _p(proj), _p(hist)), "lcb_opq_train")
+    return proj, hist
+
+
+def procrustes(S):
+    """P [D, d] with orthonormal columns maximising tr(P S) for S [d, D]."""
+    S = _c(S, np.float64)
+    d, D = S.shape
+    P = np.empty((D, d), np.float64)
+    _ok(lib().lcb_procrustes(_p(S), d, D, _p(P)), "lcb_procrustes")
+    return P

@@ -103,9 +103,11 @@ struct Space {
 // ---------------------------------------------------------------------------
 // k-means (float32 distances, float64 sums)
 // ---------------------------------------------------------------------------
+// init: seed rows of x, or NULL to start from the centroids already in cent
 void kmeans_f32(const float *x, int64_t n, int dim, int k, const int64_t *init, int iters, int nthreads,
                 float *cent) {
-  for (int j = 0; j < k; ++j) std::memcpy(cent + int64_t(j) * dim, x + init[j] * dim, sizeof(float) * dim);
+  if (init)
+    for (int j = 0; j < k; ++j) std::memcpy(cent + int64_t(j) * dim, x + init[j] * dim, sizeof(float) * dim);
   std::vector<int32_t> as(n);
   std::vector<float> err(n);
   std::vector<double> sum(size_t(k) * dim);
@@ -803,6 +805,142 @@ int lcb_beta_assign(const float *x, int64_t n, int d, const float *proj, int d_p
                    256);
     }
   }
+  return 0;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// learned rotation ahead of the product quantizer (OPQ, the codec of Sec. 4.1
+// and Sec. 5.1): alternate PQ training on the rotated vectors with the
+// rotation that best maps the vectors onto their reconstructions
+// ---------------------------------------------------------------------------
+namespace {
+
+// P = S^T (S S^T)^(-1/2) for S [d][D] of full row rank: the D x d matrix with
+// orthonormal columns maximising tr(P S) (orthogonal Procrustes; with
+// S = U Sigma V^T it is V U^T).
+bool procrustes(const std::vector<double> &S, int d, int D, std::vector<double> &P) {
+  std::vector<double> SS(size_t(d) * d, 0.0);
+  for (int i = 0; i < d; ++i)
+    for (int j = 0; j < d; ++j) {
+      double s = 0;
+      for (int t = 0; t < D; ++t) s += S[size_t(i) * D + t] * S[size_t(j) * D + t];
+      SS[size_t(i) * d + j] = s;
+    }
+  std::vector<double> w, v;
+  eig_sym(SS, d, w, v);
+  double wmax = 0;
+  for (double x : w) wmax = std::max(wmax, x);
+  // (S S^T)^(-1/2) = V diag(w^-1/2) V^T
+  std::vector<double> inv(size_t(d) * d, 0.0);
+  for (int e = 0; e < d; ++e) {
+    if (!(w[e] > 1e-24 * wmax)) return false;  // S is rank deficient
+    const double f = 1.0 / std::sqrt(w[e]);
+    for (int i = 0; i < d; ++i)
+      for (int j = 0; j < d; ++j) inv[size_t(i) * d + j] += v[size_t(i) * d + e] * f * v[size_t(j) * d + e];
+  }
+  P.assign(size_t(D) * d, 0.0);
+  for (int r = 0; r < D; ++r)
+    for (int j = 0; j < d; ++j) {
+      double s = 0;
+      for (int i = 0; i < d; ++i) s += S[size_t(i) * D + r] * inv[size_t(i) * d + j];
+      P[size_t(r) * d + j] = s;
+    }
+  return true;
+}
+
+}  // namespace
+
+extern "C" {
+
+int lcb_procrustes(const double *S, int d, int D, double *P) {
+  if (d < 1 || D < d) return -1;
+  std::vector<double> s(S, S + size_t(d) * D), p;
+  if (!procrustes(s, d, D, p)) return 1;
+  std::memcpy(P, p.data(), sizeof(double) * p.size());
+  return 0;
+}
+
+int lcb_opq_train(const float *train, int64_t n, int d, int d_pad, int m, const float *init_proj,
+                  const int64_t *init, int opq_iters, int km_iters, int nthreads, float *proj_out,
+                  double *mse_hist) {
+  if (n < 256 || m < 1 || d_pad % m || d_pad < d || opq_iters < 0 || km_iters < 1) return -1;
+  if (!init_proj && d_pad != d) return -1;
+  const int dsub = d_pad / m;
+  std::vector<float> P(size_t(d_pad) * d, 0.f);
+  if (init_proj) std::memcpy(P.data(), init_proj, sizeof(float) * P.size());
+  else
+    for (int i = 0; i < d; ++i) P[size_t(i) * d + i] = 1.f;
+  std::vector<float> cent(size_t(m) * 256 * dsub), y(size_t(n) * d_pad), sub(size_t(n) * dsub),
+      rec(size_t(n) * d_pad);
+  const int64_t chunk = 4096;  // fixed reduction chunks: the result does not depend on the thread count
+  const int64_t nch = (n + chunk - 1) / chunk;
+  for (int it = 0;; ++it) {
+    Space sp{d, d_pad, m, dsub, P.data(), nullptr};
+    parallel_for(n, nthreads, [&](int64_t i, int) { sp.project(train + i * d, y.data() + i * d_pad); }, 4096);
+    // PQ on the rotated vectors: from the seeds the first time, from the last centroids after
+    for (int s = 0; s < m; ++s) {
+      for (int64_t i = 0; i < n; ++i)
+        for (int t = 0; t < dsub; ++t) sub[size_t(i) * dsub + t] = y[size_t(i) * d_pad + s * dsub + t];
+      kmeans_f32(sub.data(), n, dsub, 256, it == 0 ? init + int64_t(s) * 256 : nullptr, km_iters, nthreads,
+                 cent.data() + int64_t(s) * 256 * dsub);
+    }
+    // reconstructions and the distortion ||y - q(y)||^2 (mean over the training vectors)
+    std::vector<double> part(nch, 0.0);
+    parallel_for(nch, nthreads, [&](int64_t c, int) {
+      double acc = 0;
+      for (int64_t i = c * chunk; i < std::min(n, (c + 1) * chunk); ++i) {
+        const float *yi = y.data() + i * d_pad;
+        float *ri = rec.data() + i * d_pad;
+        for (int s = 0; s < m; ++s) {
+          const float *cs = cent.data() + int64_t(s) * 256 * dsub;
+          float best = FLT_MAX;
+          int bj = 0;
+          for (int j = 0; j < 256; ++j) {
+            float e = 0;
+            for (int t = 0; t < dsub; ++t) {
+              float df = yi[s * dsub + t] - cs[j * dsub + t];
+              e += df * df;
+            }
+            if (e < best) {
+              best = e;
+              bj = j;
+            }
+          }
+          for (int t = 0; t < dsub; ++t) ri[s * dsub + t] = cs[bj * dsub + t];
+          acc += best;
+        }
+      }
+      part[c] = acc;
+    });
+    double mse = 0;
+    for (double x : part) mse += x;
+    if (mse_hist) mse_hist[it] = mse / double(n);
+    if (it == opq_iters) break;
+    // S = X^T Yhat [d][d_pad], summed chunk by chunk in order
+    std::vector<std::vector<double>> ps(nch);
+    parallel_for(nch, nthreads, [&](int64_t c, int) {
+      std::vector<double> acc(size_t(d) * d_pad, 0.0);
+      for (int64_t i = c * chunk; i < std::min(n, (c + 1) * chunk); ++i) {
+        const float *xi = train + i * d;
+        const float *ri = rec.data() + i * d_pad;
+        for (int a = 0; a < d; ++a) {
+          const double xa = xi[a];
+          double *row = acc.data() + size_t(a) * d_pad;
+          for (int t = 0; t < d_pad; ++t) row[t] += xa * ri[t];
+        }
+      }
+      ps[c] = std::move(acc);
+    });
+    std::vector<double> S(size_t(d) * d_pad, 0.0);
+    for (int64_t c = 0; c < nch; ++c)
+      for (size_t t = 0; t < S.size(); ++t) S[t] += ps[c][t];
+    std::vector<double> Pd;
+    if (!procrustes(S, d, d_pad, Pd)) return 2;
+    for (size_t t = 0; t < P.size(); ++t) P[t] = float(Pd[t]);
+  }
+  std::memcpy(proj_out, P.data(), sizeof(float) * P.size());
   return 0;
 }
 

@@ -46,7 +46,7 @@ int lc_index_bind(const lc_index_view *v, lc_index **out) {
   if (v->max_level > 0 && v->n_up_rows < v->max_level) return LC_EINVAL;
   if (!v->centroids || !v->codes || !v->adj0 || !v->up_base || !v->beta || !v->beta_idx) return LC_EINVAL;
   if (v->max_level > 0 && !v->adj_up) return LC_EINVAL;
-  if ((v->d_pad != v->d) != (v->proj != nullptr)) return LC_EINVAL;
+  if (v->d_pad != v->d && !v->proj) return LC_EINVAL;  // padding needs the projection; a rotation is optional
   if (v->m % 8 != 0 || v->m > 64 || v->deg0 > 32 || v->deg_up > 32) return LC_ENOTSUP;
   if (!supported_dsub(v->d_pad / v->m)) return LC_ENOTSUP;
   lc_index *ix = new (std::nothrow) lc_index;
@@ -72,14 +72,44 @@ int lc_index_bind(const lc_index_view *v, lc_index **out) {
 
 void lc_index_release(lc_index *ix) { delete ix; }
 
-int lc_build_lut(const lc_index *ix, const float *q, int64_t nq, int lut_dtype, void *lut,
-                 float *lut_scale, void *stream) {
+namespace {
+int build_lut(const lc_index *ix, const float *q, int64_t nq, int lut_dtype, void *lut, float *lut_scale,
+              bool projected, void *stream) {
   if (!ix || nq < 0) return LC_EINVAL;
   if (lut_dtype != LC_LUT_F32 && lut_dtype != LC_LUT_F16) return LC_EINVAL;
   if (nq == 0) return LC_OK;
   if (!q || !lut) return LC_EINVAL;
   if (lut_dtype == LC_LUT_F16 && !lut_scale) return LC_EINVAL;
-  return lc_launch_lut(ix, q, nq, lut_dtype, lut, lut_scale, static_cast<hipStream_t>(stream));
+  return lc_launch_lut(ix, q, nq, lut_dtype, lut, lut_scale, projected, static_cast<hipStream_t>(stream));
+}
+
+int refine(const lc_index *ix, const float *q, int64_t nq, const int32_t *cand_ids, const int32_t *cand_n,
+           int32_t S, int32_t K, int precision, int32_t *out_ids, float *out_d, bool projected, void *stream) {
+  if (!ix || nq < 0 || S < 1 || K < 1 || K > S) return LC_EINVAL;
+  if (S > 4096) return LC_ENOTSUP;
+  if (precision != LC_REFINE_F32 && precision != LC_REFINE_BF16_RESCORE) return LC_EINVAL;
+  if (nq == 0) return LC_OK;
+  if (!q || !cand_ids || !cand_n || !out_ids || !out_d) return LC_EINVAL;
+  return lc_launch_refine(ix, q, nq, cand_ids, cand_n, S, K, precision, out_ids, out_d, projected,
+                          static_cast<hipStream_t>(stream));
+}
+}  // namespace
+
+int lc_build_lut(const lc_index *ix, const float *q, int64_t nq, int lut_dtype, void *lut,
+                 float *lut_scale, void *stream) {
+  return build_lut(ix, q, nq, lut_dtype, lut, lut_scale, false, stream);
+}
+
+int lc_build_lut_projected(const lc_index *ix, const float *qp, int64_t nq, int lut_dtype, void *lut,
+                           float *lut_scale, void *stream) {
+  return build_lut(ix, qp, nq, lut_dtype, lut, lut_scale, true, stream);
+}
+
+int lc_project_queries(const lc_index *ix, const float *q, int64_t nq, float *qp, void *stream) {
+  if (!ix || nq < 0) return LC_EINVAL;
+  if (nq == 0) return LC_OK;
+  if (!q || !qp) return LC_EINVAL;
+  return lc_launch_project(ix, q, nq, qp, static_cast<hipStream_t>(stream));
 }
 
 size_t lc_search_workspace_bytes_sched(const lc_index *ix, int64_t nq, int32_t ef_max, int32_t S,
@@ -132,13 +162,13 @@ int lc_assign_beta(const lc_index *ix, const float *x, int64_t n0, int64_t count
 int lc_refine(const lc_index *ix, const float *q, int64_t nq, const int32_t *cand_ids,
               const int32_t *cand_n, int32_t S, int32_t K, int precision, int32_t *out_ids, float *out_d,
               void *stream) {
-  if (!ix || nq < 0 || S < 1 || K < 1 || K > S) return LC_EINVAL;
-  if (S > 4096) return LC_ENOTSUP;
-  if (precision != LC_REFINE_F32 && precision != LC_REFINE_BF16_RESCORE) return LC_EINVAL;
-  if (nq == 0) return LC_OK;
-  if (!q || !cand_ids || !cand_n || !out_ids || !out_d) return LC_EINVAL;
-  return lc_launch_refine(ix, q, nq, cand_ids, cand_n, S, K, precision, out_ids, out_d,
-                          static_cast<hipStream_t>(stream));
+  return refine(ix, q, nq, cand_ids, cand_n, S, K, precision, out_ids, out_d, false, stream);
+}
+
+int lc_refine_projected(const lc_index *ix, const float *qp, int64_t nq, const int32_t *cand_ids,
+                        const int32_t *cand_n, int32_t S, int32_t K, int precision, int32_t *out_ids,
+                        float *out_d, void *stream) {
+  return refine(ix, qp, nq, cand_ids, cand_n, S, K, precision, out_ids, out_d, true, stream);
 }
 
 }  // extern "C"

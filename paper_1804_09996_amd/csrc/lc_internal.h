@@ -78,7 +78,9 @@ inline int ceil_div(int64_t a, int64_t b) { return int((a + b - 1) / b); }
 }  // namespace lc
 
 // Launchers (return LC_* codes).
+int lc_launch_project(const lc_index *ix, const float *q, int64_t nq, float *out, hipStream_t st);
 int lc_launch_lut(const lc_index *ix, const float *q, int64_t nq, int dtype, void *lut, float *scale,
+                  bool projected,
                   hipStream_t st);
 size_t lc_walk_workspace_bytes(const lc_index *ix, int64_t nq, int32_t ef_max, int32_t S,
                                const lc_schedule *sched);
@@ -90,4 +92,4 @@ int lc_launch_walk(const lc_index *ix, const void *lut, int dtype, const float *
                    hipStream_t st);
 int lc_launch_refine(const lc_index *ix, const float *q, int64_t nq, const int32_t *cand_ids,
                      const int32_t *cand_n, int32_t S, int32_t K, int precision, int32_t *out_ids,
-                     float *out_d, hipStream_t st);
+                     float *out_d, bool projected, hipStream_t st);

@@ -57,24 +57,41 @@ __global__ __launch_bounds__(64) void lut_kernel(const float *__restrict__ q, in
     }
     nc[c] = nrm;
   }
-  for (int e = lane; e < 16 * DP; e += 64) {
-    const int i = e / DP, t = e % DP;
+  if (proj) {
+    // the sub-space's DSUB rows of P y for the 16 queries: four lanes per query,
+    // each over a quarter of the inputs (contiguous runs of the query and of
+    // every row of P, the rows shared by all queries), summed over the four
+    const int i = lane >> 2, part = lane & 3;
     const int64_t qi = q0 + i;
-    float v = 0.f;
-    if (qi < nq && t < DSUB) {
-      const int r = s * DSUB + t;
+    const int span = (d + 3) / 4, u0 = part * span, u1 = u0 + span < d ? u0 + span : d;
+    float acc[DSUB];
+#pragma unroll
+    for (int t = 0; t < DSUB; ++t) acc[t] = 0.f;
+    if (qi < nq) {
       const float *y = q + qi * d;
-      float yp;
-      if (proj) {
-        const float *pr = proj + size_t(r) * d;
-        yp = 0.f;
-        for (int u = 0; u < d; ++u) yp += pr[u] * y[u];
-      } else {
-        yp = y[r];
+      for (int u = u0; u < u1; ++u) {
+        const float yu = y[u];
+#pragma unroll
+        for (int t = 0; t < DSUB; ++t) acc[t] += proj[size_t(s * DSUB + t) * d + u] * yu;
       }
-      v = yp - mu[t];
     }
-    ya[e] = v;
+#pragma unroll
+    for (int t = 0; t < DSUB; ++t) {
+      acc[t] += __shfl_xor(acc[t], 1);
+      acc[t] += __shfl_xor(acc[t], 2);
+    }
+    if (part == 0) {
+#pragma unroll
+      for (int t = 0; t < DP; ++t) ya[i * DP + t] = qi < nq && t < DSUB ? acc[t < DSUB ? t : 0] - mu[t] : 0.f;
+    }
+  } else {
+    for (int e = lane; e < 16 * DP; e += 64) {
+      const int i = e / DP, t = e % DP;
+      const int64_t qi = q0 + i;
+      float v = 0.f;
+      if (qi < nq && t < DSUB) v = q[qi * d + s * DSUB + t] - mu[t];
+      ya[e] = v;
+    }
   }
   __syncthreads();
   if (lane < 16) {
@@ -147,27 +164,74 @@ __global__ __launch_bounds__(64) void lut_kernel(const float *__restrict__ q, in
 
 template <int DSUB>
 hipError_t launch_dsub(const lc_index *ix, const float *q, int64_t nq, int dtype, void *lut, float *scale,
-                       hipStream_t st) {
+                       bool projected, hipStream_t st) {
   dim3 grid(lc::ceil_div(nq, 16), ix->v.m);
+  // projected queries [nq][d_pad] need no projection
+  const float *proj = projected ? nullptr : ix->v.proj;
+  const int d = projected ? ix->v.d_pad : ix->v.d;
   if (dtype == LC_LUT_F32)
-    hipLaunchKernelGGL((lut_kernel<DSUB, float>), grid, dim3(64), 0, st, q, nq, ix->v.d, ix->v.proj, ix->v.m,
+    hipLaunchKernelGGL((lut_kernel<DSUB, float>), grid, dim3(64), 0, st, q, nq, d, proj, ix->v.m,
                        ix->v.centroids, static_cast<float *>(lut), scale);
   else
-    hipLaunchKernelGGL((lut_kernel<DSUB, __half>), grid, dim3(64), 0, st, q, nq, ix->v.d, ix->v.proj, ix->v.m,
+    hipLaunchKernelGGL((lut_kernel<DSUB, __half>), grid, dim3(64), 0, st, q, nq, d, proj, ix->v.m,
                        ix->v.centroids, static_cast<__half *>(lut), scale);
   return hipGetLastError();
 }
 
+// y' = P y for a batch: a block stages P (rows padded by one word, so that
+// the lanes reading different rows at one column hit different banks) and
+// kQB queries in LDS, then every thread forms some of the kQB x d_pad outputs,
+// each summed over the inputs in order.  Without a projection the rows are
+// copied.
+constexpr int kQB = 32;
+
+__global__ __launch_bounds__(256) void project_kernel(const float *__restrict__ q, int64_t nq, int d, int d_pad,
+                                                      const float *__restrict__ proj, float *__restrict__ out) {
+  extern __shared__ float sm[];
+  float *P = sm;                       // [d_pad][d + 1]
+  float *Y = sm + size_t(d_pad) * (d + 1);  // [kQB][d]
+  const int64_t q0 = int64_t(blockIdx.x) * kQB;
+  const int nqb = nq - q0 < kQB ? int(nq - q0) : kQB;
+  for (int e = threadIdx.x; e < d_pad * d; e += blockDim.x) P[(e / d) * (d + 1) + e % d] = proj[e];
+  for (int e = threadIdx.x; e < nqb * d; e += blockDim.x) Y[e] = q[q0 * d + e];
+  __syncthreads();
+  for (int e = threadIdx.x; e < nqb * d_pad; e += blockDim.x) {
+    const int i = e / d_pad, r = e % d_pad;
+    const float *pr = P + size_t(r) * (d + 1), *y = Y + size_t(i) * d;
+    float v = 0.f;
+    for (int u = 0; u < d; ++u) v += pr[u] * y[u];
+    out[(q0 + i) * d_pad + r] = v;
+  }
+}
+
 }  // namespace
 
+int lc_launch_project(const lc_index *ix, const float *q, int64_t nq, float *out, hipStream_t st) {
+  const int d = ix->v.d, dp = ix->v.d_pad;
+  if (!ix->v.proj) {
+    // no projection: the rows themselves (d == d_pad)
+    return hipMemcpyAsync(out, q, size_t(nq) * d * sizeof(float), hipMemcpyDeviceToDevice, st) == hipSuccess
+               ? LC_OK
+               : LC_EHIP;
+  }
+  const size_t lds = (size_t(dp) * (d + 1) + size_t(kQB) * d) * sizeof(float);
+  if (lds > size_t(ix->lds_per_cu)) return LC_ENOTSUP;
+  if (hipFuncSetAttribute(reinterpret_cast<const void *>(&project_kernel),
+                          hipFuncAttributeMaxDynamicSharedMemorySize, int(lds)) != hipSuccess)
+    return LC_EHIP;
+  hipLaunchKernelGGL(project_kernel, dim3(int(lc::ceil_div(nq, kQB))), dim3(256), lds, st, q, nq, d, dp,
+                     ix->v.proj, out);
+  return hipGetLastError() == hipSuccess ? LC_OK : LC_EHIP;
+}
+
 int lc_launch_lut(const lc_index *ix, const float *q, int64_t nq, int dtype, void *lut, float *scale,
-                  hipStream_t st) {
+                  bool projected, hipStream_t st) {
   if (dtype != LC_LUT_F32 && dtype != LC_LUT_F16) return LC_ENOTSUP;
   if (nq > int64_t(0x7FFFFFFF) * 16) return LC_EINVAL;
   hipError_t e;
   switch (ix->dsub) {
 #define CASE(DS) \
-  case DS: e = launch_dsub<DS>(ix, q, nq, dtype, lut, scale, st); break;
+  case DS: e = launch_dsub<DS>(ix, q, nq, dtype, lut, scale, projected, st); break;
     CASE(1) CASE(2) CASE(3) CASE(4) CASE(6) CASE(8) CASE(12) CASE(16)
 #undef CASE
     default: return LC_ENOTSUP;

@@ -311,18 +311,21 @@ __device__ __forceinline__ void wave_sort(uint64_t *keys, int n, int lane) {
   }
 }
 
+// y' = P y for one query into yv: each row of P is read by the wave as one
+// contiguous run (lanes over its columns), then summed across the lanes.
 __device__ __forceinline__ void project_query(const RefineArgs &a, int64_t q, float *yv, int lane) {
   const float *y = a.q + q * a.d;
-  for (int r = lane; r < a.d_pad; r += 64) {
-    float v;
-    if (a.proj) {
-      const float *pr = a.proj + size_t(r) * a.d;
-      v = 0.f;
-      for (int u = 0; u < a.d; ++u) v += pr[u] * y[u];
-    } else {
-      v = y[r];
-    }
-    yv[r] = v;
+  if (!a.proj) {
+    for (int r = lane; r < a.d_pad; r += 64) yv[r] = y[r];
+    return;
+  }
+  for (int r = 0; r < a.d_pad; ++r) {
+    const float *pr = a.proj + size_t(r) * a.d;
+    float v = 0.f;
+    for (int u = lane; u < a.d; u += 64) v += pr[u] * y[u];
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off);
+    if (lane == 0) yv[r] = v;
   }
 }
 
@@ -556,8 +559,12 @@ int launch_generic(const lc_index *ix, RefineArgs a, hipStream_t st) {
 // the precision form needs a specialised one.
 int lc_launch_refine(const lc_index *ix, const float *q, int64_t nq, const int32_t *cand_ids,
                      const int32_t *cand_n, int32_t S, int32_t K, int precision, int32_t *out_ids,
-                     float *out_d, hipStream_t st) {
-  const RefineArgs a = make_args(ix, q, nq, cand_ids, cand_n, S, K, out_ids, out_d);
+                     float *out_d, bool projected, hipStream_t st) {
+  RefineArgs a = make_args(ix, q, nq, cand_ids, cand_n, S, K, out_ids, out_d);
+  if (projected) {  // queries already projected: rows of d_pad
+    a.proj = nullptr;
+    a.d = ix->v.d_pad;
+  }
   const int m = ix->v.m, ds = ix->dsub;
   const bool bf = precision == LC_REFINE_BF16_RESCORE;
   // when the re-score covers the whole short-list (2K >= S) the first pass decides nothing: every

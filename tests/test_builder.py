@@ -71,3 +71,53 @@ def test_index_cache_roundtrip(tmp_path):
     for name in ("codes", "adj0", "up_base", "adj_up", "beta", "beta_idx", "centroids"):
         assert np.array_equal(getattr(a, name), getattr(b, name)), name
     assert (a.entry, a.max_level) == (b.entry, b.max_level)
+
+
+# ---------------------------------------------------------------------------
+# learned rotation ahead of PQ (OPQ; the codec of Sec. 4.1 / Sec. 5.1)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("d,D", [(12, 12), (12, 16), (40, 48)])
+def test_procrustes_is_the_svd_closed_form(d, D):
+    # argmax over P with orthonormal columns of tr(P S) = V U^T for S = U Sigma V^T
+    rs = np.random.default_rng(d * 100 + D)
+    S = rs.standard_normal((d, D))
+    P = builder.procrustes(S)
+    U, s, Vt = np.linalg.svd(S, full_matrices=False)
+    np.testing.assert_allclose(P, Vt.T @ U.T, atol=1e-10)
+    np.testing.assert_allclose(P.T @ P, np.eye(d), atol=1e-10)
+    # and no rotation nearby does better
+    for _ in range(5):
+        Q, _ = np.linalg.qr(P + 1e-3 * rs.standard_normal(P.shape))
+        assert np.trace(Q @ S) <= np.trace(P @ S) + 1e-9
+
+
+def test_opq_lowers_distortion_and_is_thread_independent():
+    w = datagen.small(name="opq-b", n=2000, d=32, m=8, n_train=4096)
+    train = datagen.vectors(w, "train")
+    init = datagen.pq_init_ids(w, train.shape[0])
+    p1, h1 = builder.opq_train(train, w.d_pad, w.m, None, init, 5, 4, nthreads=1)
+    p7, h7 = builder.opq_train(train, w.d_pad, w.m, None, init, 5, 4, nthreads=7)
+    assert np.array_equal(p1, p7) and np.array_equal(h1, h7)
+    assert np.all(np.diff(h1) <= 1e-6 * h1[0]), h1  # PQ steps and rotation steps never raise the distortion
+    assert h1[-1] < 0.95 * h1[0]
+    np.testing.assert_allclose(p1.T.astype(np.float64) @ p1, np.eye(32), atol=1e-5)
+    # from a padded start (d 44 -> d_pad 48 through the seeded projection)
+    wp = datagen.small(name="opq-p", n=2000, d=44, m=8, n_train=4096)
+    tp = datagen.vectors(wp, "train")
+    pp, hp = builder.opq_train(tp, wp.d_pad, wp.m, datagen.projection(wp), datagen.pq_init_ids(wp, tp.shape[0]), 4, 4)
+    assert pp.shape == (48, 44) and np.all(np.diff(hp) <= 1e-6 * hp[0])
+    np.testing.assert_allclose(pp.T.astype(np.float64) @ pp, np.eye(44), atol=1e-5)
+
+
+def test_builder_with_learned_rotation_matches_oracle(nthreads):
+    # the rotation is learned by the builder; given it, the rest of the build is the oracle's
+    w = datagen.small(name="opq-build", n=1500, d=32, m=8, n_train=2048, n_beta=8, n_beta_train=1500, opq_iters=3)
+    bix, db, q = builder.build_workload(w, nthreads=nthreads)
+    assert bix.proj is not None and bix.proj.shape == (32, 32)
+    oix = oracle.build_index(w, db, datagen.vectors(w, "train"), bix.proj, datagen.level_uniforms(w),
+                             datagen.pq_init_ids(w, w.n_train), datagen.beta_train_ids(w),
+                             datagen.beta_init_ids(w, min(w.n, w.n_beta_train)), nthreads)
+    assert np.array_equal(bix.codes, oix.codes)
+    assert np.all(bix.adj0 == oix.adj0, axis=1).mean() >= 0.999
+    np.testing.assert_allclose(bix.centroids, oix.centroids, rtol=1e-6, atol=1e-7)
+    assert (bix.beta_idx == oix.beta_idx).mean() >= 0.999

@@ -405,3 +405,69 @@ def test_golden_fixture_on_gpu(torch):
     s = parity.summarize(ix, q, ids.cpu().numpy(), d.cpu().numpy(), gold)
     assert s["exact_frac"] == 1.0 and s["max_rel_err"] <= 1e-5
     gix.close()
+
+
+def test_learned_rotation_index(torch):
+    # a rotation with d_pad == d (learned ahead of PQ by the builder) is applied by the tables and the
+    # refinement exactly as the oracle applies it
+    import paper_1804_09996_amd as lc
+    from paper_1804_09996_amd import builder
+    w = datagen.small(name="gpu-opq", n=1500, nq=24, d=32, m=8, n_train=2048, n_beta=8, n_beta_train=1500,
+                      opq_iters=3, ef=32, shortlist=32, topk=10)
+    bix, db, q = builder.build_workload(w, nthreads=4)
+    ix = oracle.build_index(w, db, datagen.vectors(w, "train"), bix.proj, datagen.level_uniforms(w),
+                            datagen.pq_init_ids(w, w.n_train), datagen.beta_train_ids(w),
+                            datagen.beta_init_ids(w, min(w.n, w.n_beta_train)), 4)
+    assert ix.proj is not None and ix.d_pad == ix.d
+    gix = lc.Index.from_index(ix)
+    o = ix.search(q, w.ef, w.shortlist, w.topk)
+    lut, _ = gix.build_lut(torch.from_numpy(q))
+    got = lut.cpu().numpy().astype(np.float64)
+    ref = np.stack([ix.lut(y) for y in q])
+    assert np.all(np.abs(got - ref) <= _lut_bound(ix, q))
+    ids, d, r = gix.query(torch.from_numpy(q), ef=w.ef, ef_max=w.ef, S=w.shortlist, K=w.topk, stats=True)
+    assert np.array_equal(r.cand_ids.cpu().numpy(), o["cand_ids"]) and np.array_equal(r.stats.cpu().numpy(), o["stats"])
+    s = parity.summarize(ix, q, ids.cpu().numpy(), d.cpu().numpy(), o)
+    assert s["exact_frac"] == 1.0 and s["max_rel_err"] <= 1e-5
+    _projected_entry_points(ix, gix, q, w, o, torch)
+    gix.close()
+
+
+def _projected_entry_points(ix, gix, q, w, o, torch):
+    # the batch projected once (lc_project_queries) and the *_projected entry points, against the oracle and
+    # against the entry points that project by themselves
+    import paper_1804_09996_amd as lc
+    qt = torch.from_numpy(q)
+    qp = gix.project(qt)
+    ref = np.stack([oracle.project(ix.proj, y, ix.d_pad) for y in q])
+    np.testing.assert_allclose(qp.cpu().numpy(), ref, rtol=0, atol=1e-5 * np.abs(ref).max())
+    lut_p, _ = gix.build_lut(qp, projected=True)
+    assert np.all(np.abs(lut_p.cpu().numpy() - np.stack([ix.lut(y) for y in q])) <= _lut_bound(ix, q))
+    r = gix.search(lut_p, ef=w.ef, ef_max=w.ef, S=w.shortlist)
+    for prec in (lc.LC_REFINE_F32, lc.LC_REFINE_BF16_RESCORE):
+        i_p, d_p = gix.refine(qp, r.cand_ids, r.cand_n, w.topk, prec, projected=True)
+        i_q, d_q = gix.refine(qt, r.cand_ids, r.cand_n, w.topk, prec)
+        err = parity.distance_errors(ix, q, i_p.cpu().numpy(), d_p.cpu().numpy())
+        assert np.nanmax(err) <= 1e-5
+        np.testing.assert_allclose(d_p.cpu().numpy(), d_q.cpu().numpy(), rtol=1e-5)
+    i_f, d_f = gix.refine(qp, r.cand_ids, r.cand_n, w.topk, projected=True)
+    s = parity.summarize(ix, q, i_f.cpu().numpy(), d_f.cpu().numpy(), o)
+    assert s["exact_frac"] >= 0.95
+
+
+def test_padded_projection_index(torch):
+    # d 28 -> d_pad 32 through the seeded projection (required), the batch projected once by query()
+    import paper_1804_09996_amd as lc
+    w = datagen.small(name="gpu-pad", n=1500, nq=24, d=28, m=8, n_train=2048, n_beta=8, n_beta_train=1500,
+                      ef=32, shortlist=32, topk=10)
+    ix, db, q = oracle.build_workload(w, nthreads=4)
+    assert ix.proj is not None and ix.proj.shape == (32, 28)
+    gix = lc.Index.from_index(ix)
+    o = ix.search(q, w.ef, w.shortlist, w.topk)
+    ids, d, r = gix.query(torch.from_numpy(q), ef=w.ef, ef_max=w.ef, S=w.shortlist, K=w.topk, stats=True)
+    same = np.mean([np.array_equal(r.cand_ids.cpu().numpy()[i], o["cand_ids"][i]) for i in range(w.nq)])
+    assert same >= 0.95
+    s = parity.summarize(ix, q, ids.cpu().numpy(), d.cpu().numpy(), o)
+    assert s["exact_frac"] >= 0.95 and s["max_rel_err"] <= 1e-5
+    _projected_entry_points(ix, gix, q, w, o, torch)
+    gix.close()
