@@ -289,7 +289,7 @@ def bench_serve(args):
     gix = lc.Index.from_index(ix, device=dev)
     S, K, ef_max = 32, w.topk, 256
     slot_q, n_slots = 2048, 4
-    bpq = serve.query_bytes(w.m, S, K, w.d)
+    bpq = serve.query_bytes(w.m, S, K, w.d, d_proj=w.d_pad if ix.proj is not None else 0)
     budget = n_slots * slot_q * bpq
     eng = serve.GpuEngine(gix, n_slots=n_slots, slot_queries=slot_q, ef_max=ef_max, S=S, K=K, precision="f16")
     # saturation: a backlog of requests all present at t = 0

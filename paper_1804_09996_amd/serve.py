@@ -52,10 +52,11 @@ class Request:
         return self.done - self.arrival
 
 
-def query_bytes(m: int, S: int, K: int, d: int, lut_bytes: int = 2) -> int:
+def query_bytes(m: int, S: int, K: int, d: int, lut_bytes: int = 2, d_proj: int = 0) -> int:
     """Device bytes one query holds while in flight: its table (+ scales),
-    pool output (ids + distances), results, the query itself and its ef."""
-    return m * 256 * lut_bytes + 4 * m + 8 * S + 4 + 8 * K + 4 * d + 4
+    pool output (ids + distances), results, the query itself (and its
+    projection, d_proj values, when the index has one) and its ef."""
+    return m * 256 * lut_bytes + 4 * m + 8 * S + 4 + 8 * K + 4 * d + 4 * d_proj + 4
 
 
 class Scheduler:
@@ -124,6 +125,11 @@ class GpuEngine:
         self.refine_p = lc.LC_REFINE_BF16_RESCORE if precision == "f16" else lc.LC_REFINE_F32
         dev = gix.device
         Q, d, m = slot_queries, gix.d, gix.m
+        # an index with a projection projects a large batch once, for the tables and the refinement (the
+        # kernels that project by themselves read the projection once per query: L2 traffic that a large
+        # batch feels, while a small one feels the extra launch more)
+        self.projected = gix.has_projection
+        self.project_min = 256
         lut_t = torch.float16 if precision == "f16" else torch.float32
         self.slots = []
         for _ in range(n_slots):
@@ -135,6 +141,7 @@ class GpuEngine:
             self.slots.append({
                 "stream": torch.cuda.Stream(device=dev),
                 "q": torch.empty((Q, d), dtype=torch.float32, device=dev),
+                "qp": torch.empty((Q, gix.d_pad) if self.projected else (1,), dtype=torch.float32, device=dev),
                 "ef": torch.empty(Q, dtype=torch.int32, device=dev),
                 "lut": torch.empty((Q, m, 256), dtype=lut_t, device=dev),
                 "scale": torch.empty((Q, m), dtype=torch.float32, device=dev),
@@ -170,14 +177,22 @@ class GpuEngine:
             s["ef"][:n].copy_(s["h_ef"][:n], non_blocking=True)
             sp = C.c_void_p(st.cuda_stream)
             scale = s["scale"].data_ptr() if self.lut_dtype == lc.LC_LUT_F16 else None
-            lc._check(L.lc_build_lut(h, s["q"].data_ptr(), n, self.lut_dtype, s["lut"].data_ptr(), scale, sp),
-                      "lc_build_lut")
+            proj = self.projected and n >= self.project_min
+            if proj:
+                lc._check(L.lc_project_queries(h, s["q"].data_ptr(), n, s["qp"].data_ptr(), sp), "lc_project_queries")
+                lc._check(L.lc_build_lut_projected(h, s["qp"].data_ptr(), n, self.lut_dtype, s["lut"].data_ptr(), scale,
+                                                   sp), "lc_build_lut")
+            else:
+                lc._check(L.lc_build_lut(h, s["q"].data_ptr(), n, self.lut_dtype, s["lut"].data_ptr(), scale, sp),
+                          "lc_build_lut")
             lc._check(L.lc_search_sched(h, s["lut"].data_ptr(), self.lut_dtype, scale, n, s["ef"].data_ptr(),
                                         ef_launch, self.S, None, s["cand_ids"].data_ptr(), s["cand_adc"].data_ptr(),
                                         s["cand_n"].data_ptr(), None, s["ws"].data_ptr(), s["ws"].numel(),
                                         None if self.sched is None else C.byref(self.sched), sp), "lc_search")
-            lc._check(L.lc_refine(h, s["q"].data_ptr(), n, s["cand_ids"].data_ptr(), s["cand_n"].data_ptr(), self.S,
-                                  self.K, self.refine_p, s["ids"].data_ptr(), s["d"].data_ptr(), sp), "lc_refine")
+            refine = L.lc_refine_projected if proj else L.lc_refine
+            qin = s["qp"] if proj else s["q"]
+            lc._check(refine(h, qin.data_ptr(), n, s["cand_ids"].data_ptr(), s["cand_n"].data_ptr(), self.S, self.K,
+                             self.refine_p, s["ids"].data_ptr(), s["d"].data_ptr(), sp), "lc_refine")
             s["h_ids"][:n].copy_(s["ids"][:n], non_blocking=True)
             s["h_d"][:n].copy_(s["d"][:n], non_blocking=True)
             ev = torch.cuda.Event()
