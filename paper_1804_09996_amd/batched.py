@@ -69,6 +69,8 @@ class BatchedSearcher:
         dev = gix.device
         # the batch in (class, longest ef first) order, and the map back to query order
         self.q = torch.empty((nq, gix.d), dtype=torch.float32, device=dev)
+        # an index with a projection: the batch projected once (static, so that a captured step reuses it)
+        self.qp = torch.empty((nq, gix.d_pad), dtype=torch.float32, device=dev) if gix.has_projection else None
         self.ef = torch.empty(nq, dtype=torch.int32, device=dev)
         self.inv = torch.empty(nq, dtype=torch.int64, device=dev)
         self.res = SearchResult(torch.empty((nq, S), dtype=torch.int32, device=dev),
@@ -142,11 +144,22 @@ class BatchedSearcher:
         for i in range(len(self.ranges)):
             main.wait_stream(self.streams[i])
 
+    def _queries(self):
+        """The batch as the tables and the refinement take it (projected once
+        when the index has a projection) and whether it is projected."""
+        if self.qp is None:
+            return self.q, False
+        lc = __import__("paper_1804_09996_amd")
+        lc._check(lc.lib().lc_project_queries(self.gix.handle, self.q.data_ptr(), self.nq, self.qp.data_ptr(),
+                                              lc._stream(self.torch, self.gix.device)), "lc_project_queries")
+        return self.qp, True
+
     def _step(self):
         gix = self.gix
-        lut, scale = gix.build_lut(self.q, self.lut_dtype)
+        qx, pj = self._queries()
+        lut, scale = gix.build_lut(qx, self.lut_dtype, projected=pj)
         self._walks(lut, scale)
-        ids, d = gix.refine(self.q, self.res.cand_ids, self.res.cand_n, self.K, self.refine_p)
+        ids, d = gix.refine(qx, self.res.cand_ids, self.res.cand_n, self.K, self.refine_p, projected=pj)
         return ids.index_select(0, self.inv), d.index_select(0, self.inv)
 
     # -- tuning -------------------------------------------------------------
@@ -168,13 +181,15 @@ class BatchedSearcher:
         """Pick the walk schedule for the whole batch (one class), then the
         class split, by timing the walk phase of this batch."""
         self.set_classes([max(self.ef_max, self.S)])
-        lut, scale = self.gix.build_lut(self.q, self.lut_dtype)
+        qx, pj = self._queries()
+        lut, scale = self.gix.build_lut(qx, self.lut_dtype, projected=pj)
         self.sched, self.table = autotune.tune(self.gix, lut, ef=self.ef, ef_max=self.ef_max, S=self.S,
                                                cands=cands, reps=reps, cache_path=cache_path, log=log)
         best = None
         for lim in class_limits_options(self.ef_max, self.S):
             self.set_classes(lim)
-            lut, scale = self.gix.build_lut(self.q, self.lut_dtype)
+            qx, pj = self._queries()
+            lut, scale = self.gix.build_lut(qx, self.lut_dtype, projected=pj)
             ms = self._time_walks(lut, scale, self.sched, reps)
             self.table.append({"classes": lim, "schedule": self.sched.as_dict(), "ms": ms})
             if log:

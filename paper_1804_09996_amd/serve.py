@@ -125,11 +125,9 @@ class GpuEngine:
         self.refine_p = lc.LC_REFINE_BF16_RESCORE if precision == "f16" else lc.LC_REFINE_F32
         dev = gix.device
         Q, d, m = slot_queries, gix.d, gix.m
-        # an index with a projection projects a large batch once, for the tables and the refinement (the
-        # kernels that project by themselves read the projection once per query: L2 traffic that a large
-        # batch feels, while a small one feels the extra launch more)
+        # an index with a projection projects each batch once, for the tables and the refinement, as
+        # Index.query does: the same rounding whatever the batch, so results never depend on it
         self.projected = gix.has_projection
-        self.project_min = 256
         lut_t = torch.float16 if precision == "f16" else torch.float32
         self.slots = []
         for _ in range(n_slots):
@@ -177,7 +175,7 @@ class GpuEngine:
             s["ef"][:n].copy_(s["h_ef"][:n], non_blocking=True)
             sp = C.c_void_p(st.cuda_stream)
             scale = s["scale"].data_ptr() if self.lut_dtype == lc.LC_LUT_F16 else None
-            proj = self.projected and n >= self.project_min
+            proj = self.projected
             if proj:
                 lc._check(L.lc_project_queries(h, s["q"].data_ptr(), n, s["qp"].data_ptr(), sp), "lc_project_queries")
                 lc._check(L.lc_build_lut_projected(h, s["qp"].data_ptr(), n, self.lut_dtype, s["lut"].data_ptr(), scale,

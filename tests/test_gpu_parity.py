@@ -471,3 +471,23 @@ def test_padded_projection_index(torch):
     assert s["exact_frac"] >= 0.95 and s["max_rel_err"] <= 1e-5
     _projected_entry_points(ix, gix, q, w, o, torch)
     gix.close()
+
+
+def test_batched_form_on_projected_index(torch):
+    # the batched form projects its batch once too: per query the same bits as Index.query
+    import paper_1804_09996_amd as lc
+    from paper_1804_09996_amd.batched import BatchedSearcher
+    w = datagen.small(name="batch-pad", n=1500, nq=64, d=28, m=8, n_train=2048, n_beta=8, n_beta_train=1500)
+    ix, db, q = oracle.build_workload(w, nthreads=4)
+    gix = lc.Index.from_index(ix)
+    ef = np.where(np.arange(w.nq) % 3 == 0, 48, 16).astype(np.int32)
+    bs = BatchedSearcher(gix, w.nq, 48, 16, 5, precision="f32")
+    bs.set_inputs(q, ef)
+    ids, d = bs.run()
+    ids, d = ids.cpu().numpy(), d.cpu().numpy()
+    for e in (16, 48):
+        sel = np.flatnonzero(ef == e)
+        ri, rd, _ = gix.query(torch.from_numpy(q[sel]), ef=e, ef_max=48, S=16, K=5)
+        assert np.array_equal(ids[sel], ri.cpu().numpy())
+        assert np.array_equal(d[sel].view(np.uint32), rd.cpu().numpy().view(np.uint32))
+    gix.close()
