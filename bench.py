@@ -293,11 +293,16 @@ def bench_serve(args):
     budget = n_slots * slot_q * bpq
     eng = serve.GpuEngine(gix, n_slots=n_slots, slot_queries=slot_q, ef_max=ef_max, S=S, K=K, precision="f16")
     # saturation: a backlog of requests all present at t = 0
-    sat_reqs = serve.poisson_requests(w.d, q, 1e9, 200, w.seed + 1)
-    for r in sat_reqs:
-        r.arrival = 0.0
-    sat = serve.serve(eng, serve.Scheduler(n_slots, slot_q, budget, bpq), sat_reqs)
-    log(f"saturation {sat['qps']:.0f} queries/s")
+    # saturation: a backlog of 1000 requests (~150k queries) all present at t = 0, run three times (the
+    # first also warms the slots); the median of the three
+    sat_runs = []
+    for k in range(3):
+        sat_reqs = serve.poisson_requests(w.d, q, 1e9, 1000, w.seed + 1)
+        for r in sat_reqs:
+            r.arrival = 0.0
+        sat_runs.append(serve.serve(eng, serve.Scheduler(n_slots, slot_q, budget, bpq), sat_reqs))
+        log(f"saturation run {k}: {sat_runs[-1]['qps']:.0f} queries/s")
+    sat = sorted(sat_runs, key=lambda r_: r_["qps"])[1]
     mean_batch = float(np.mean([r.size for r in sat_reqs]))
     runs = []
     for frac in [float(x) for x in args.loads.split(",")]:
@@ -316,7 +321,7 @@ def bench_serve(args):
                                   f"{{32,64,128,256}}, short-list {S}, top-{K}; fp16 tables, bf16 refinement, fp32 "
                                   f"re-score; {n_slots} slots x {slot_q} queries, memory budget {budget} B"},
            "latency_ms": {"p50": head["latency_ms_p50"], "p99": head["latency_ms_p99"]},
-           "saturation_qps": sat["qps"], "loads": runs}
+           "saturation_qps": sat["qps"], "saturation_runs_qps": [r_["qps"] for r_ in sat_runs], "loads": runs}
     print(json.dumps(out), flush=True)
 
 
