@@ -93,6 +93,12 @@ def test_calls_reject_bad_arguments_before_launch(L):
     assert L.lc_search(None, p, 0, None, 1, None, 8, 8, p, p, p, None, p, 1, None) == lc.LC_EINVAL
     assert L.lc_refine(None, p, 1, p, p, 8, 8, 0, p, p, None) == lc.LC_EINVAL
     assert L.lc_search_workspace_bytes(None, 1, 8, 8) == 0
+    assert L.lc_search_budget(None, p, 0, None, 1, None, 8, 8, 10, None, p, p, p, None, p, 1, None, None) == \
+        lc.LC_EINVAL
+    assert L.lc_assign_beta(None, p, 0, 1, p, None) == lc.LC_EINVAL
+    assert L.lc_project_queries(None, p, 1, p, None) == lc.LC_EINVAL
+    assert L.lc_build_lut_projected(None, p, 1, 0, p, None, None) == lc.LC_EINVAL
+    assert L.lc_refine_projected(None, p, 1, p, p, 8, 8, 0, p, p, None) == lc.LC_EINVAL
 
 
 def test_library_is_built_from_these_sources(L):
