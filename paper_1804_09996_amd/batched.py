@@ -23,7 +23,8 @@ from typing import List, Optional, Sequence
 
 import numpy as np
 
-from . import LC_LUT_F16, LC_LUT_F32, LC_REFINE_BF16_RESCORE, LC_REFINE_F32, SearchResult, autotune
+from . import LC_LUT_F16, LC_LUT_F32, LC_REFINE_BF16_RESCORE, LC_REFINE_F32, SearchResult, _check, _stream, autotune, \
+    lib
 
 
 def class_limits_options(ef_max: int, S: int) -> List[List[int]]:
@@ -149,9 +150,8 @@ class BatchedSearcher:
         when the index has a projection) and whether it is projected."""
         if self.qp is None:
             return self.q, False
-        lc = __import__("paper_1804_09996_amd")
-        lc._check(lc.lib().lc_project_queries(self.gix.handle, self.q.data_ptr(), self.nq, self.qp.data_ptr(),
-                                              lc._stream(self.torch, self.gix.device)), "lc_project_queries")
+        _check(lib().lc_project_queries(self.gix.handle, self.q.data_ptr(), self.nq, self.qp.data_ptr(),
+                                        _stream(self.torch, self.gix.device)), "lc_project_queries")
         return self.qp, True
 
     def _step(self):
