@@ -468,6 +468,35 @@ def main():
             out["one_stream"] = {k_: one[k_] for k_ in ("qps", "ms_per_step", "step_ms_p50", "step_ms_p99")}
         return out
 
+    def end_to_end(form, ef, S, reps=7):
+        """One batch from pinned host memory to results in pinned host memory
+        (queries copied in, the whole path, ids and distances copied out), on
+        one stream; the median over reps."""
+        lut_dt, ref_p = FORMS[form]
+        hq = torch.from_numpy(q).pin_memory()
+        h_ids = torch.empty((nq, K), dtype=torch.int32).pin_memory()
+        h_d = torch.empty((nq, K), dtype=torch.float32).pin_memory()
+        qbuf = torch.empty_like(qd)
+        ws = gix.workspace(nq, max(ef, S), S)
+        times = []
+        for _ in range(reps + 1):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            torch.cuda.synchronize()
+            a.record()
+            qbuf.copy_(hq, non_blocking=True)
+            qx = gix.project(qbuf) if gix.has_projection else qbuf
+            lut, scale = gix.build_lut(qx, lut_dt, projected=gix.has_projection)
+            r = gix.search(lut, scale, ef=None, ef_max=ef, S=S, stats=False, ws=ws, max_evals=args.max_evals)
+            ids, d = gix.refine(qx, r.cand_ids, r.cand_n, K, ref_p, projected=gix.has_projection)
+            h_ids.copy_(ids, non_blocking=True)
+            h_d.copy_(d, non_blocking=True)
+            b.record()
+            b.synchronize()
+            times.append(a.elapsed_time(b))
+        ms = float(np.median(times[1:]))
+        return {"ms_per_batch": ms, "qps": nq / (ms * 1e-3),
+                "note": "one stream, queries from and results to pinned host memory (PCIe both ways)"}
+
     # the plain path at the workload's own operating point defines the target recall
     plain = run("f32", w.ef, w.shortlist, args.steps, args.warmup)
     r_target = plain["recall"]["R@1"]
@@ -548,6 +577,7 @@ def main():
                                      "refine": rb / (head["kernels_ms"]["refine"] * 1e-3) / 1e9},
         "recall": head["recall"], "batch_latency_ms": {"p50": head["step_ms_p50"], "p99": head["step_ms_p99"]},
         "one_stream": head.get("one_stream"),
+        "end_to_end": end_to_end(head["precision"], head["ef"], S_h),
         "walk_mean_E": float(E.mean()), "walk_mean_D": float(D.mean()),
         "plain_fp32": {"qps": plain["qps"], "recall": plain["recall"], "ef": plain["ef"], "S": plain["S"],
                        "kernels_ms": plain["kernels_ms"], "one_stream": plain.get("one_stream")},
