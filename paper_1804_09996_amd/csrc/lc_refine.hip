@@ -87,8 +87,33 @@ struct CodePiece {
 };
 
 // Centroid element as float32: float32 storage, or bfloat16 (top 16 bits).
-__device__ __forceinline__ float cval(const float *C, int i) { return C[i]; }
-__device__ __forceinline__ float cval(const uint16_t *C, int i) { return __uint_as_float(uint32_t(C[i]) << 16); }
+[[maybe_unused]] __device__ __forceinline__ float cval(const float *C, int i) { return C[i]; }
+[[maybe_unused]] __device__ __forceinline__ float cval(const uint16_t *C, int i) { return __uint_as_float(uint32_t(C[i]) << 16); }
+
+// One centroid row (DSUB elements from index base) as float32.  bfloat16 rows
+// of an even length are read as 32-bit words, two elements each (a row starts
+// at a multiple of DSUB elements, so the words are aligned): half the LDS
+// reads of element-wise 16-bit loads.
+template <int DSUB>
+__device__ __forceinline__ void crow(const float *C, int base, float *out) {
+#pragma unroll
+  for (int q = 0; q < DSUB; ++q) out[q] = C[base + q];
+}
+template <int DSUB>
+__device__ __forceinline__ void crow(const uint16_t *C, int base, float *out) {
+  if constexpr (DSUB % 2 == 0) {
+    const uint32_t *w = reinterpret_cast<const uint32_t *>(C + base);
+#pragma unroll
+    for (int h = 0; h < DSUB / 2; ++h) {
+      const uint32_t v = w[h];
+      out[2 * h] = __uint_as_float(v << 16);
+      out[2 * h + 1] = __uint_as_float(v & 0xFFFF0000u);
+    }
+  } else {
+#pragma unroll
+    for (int q = 0; q < DSUB; ++q) out[q] = cval(C, base + q);
+  }
+}
 
 // Round a float32 to the nearest bfloat16 (ties to even), returned as float32.
 __device__ __forceinline__ float round_bf16(float x) {
@@ -249,8 +274,10 @@ __device__ __forceinline__ float part_dist(const RefineArgs &a, const CT *C, con
           for (int u = 0; u < U; ++u) {
             const int s = BM::sub(u, part);
             const int base = (s * 256 + int(row[t].byte(u))) * DSUB;
+            float cr[DSUB];
+            crow<DSUB>(C, base, cr);
 #pragma unroll
-            for (int q = 0; q < DSUB; ++q) acc[u * DSUB + q] += wj[t0 + t][BM::slot(u)] * cval(C, base + q);
+            for (int q = 0; q < DSUB; ++q) acc[u * DSUB + q] += wj[t0 + t][BM::slot(u)] * cr[q];
           }
         }
       } else {
@@ -263,8 +290,10 @@ __device__ __forceinline__ float part_dist(const RefineArgs &a, const CT *C, con
           for (int u = 0; u < U; ++u) {
             const int s = BM::sub(u, part);
             const int base = (s * 256 + int(row[t].byte(s))) * DSUB;
+            float cr[DSUB];
+            crow<DSUB>(C, base, cr);
 #pragma unroll
-            for (int q = 0; q < DSUB; ++q) acc[u * DSUB + q] += wj[t0 + t][BM::slot(u)] * cval(C, base + q);
+            for (int q = 0; q < DSUB; ++q) acc[u * DSUB + q] += wj[t0 + t][BM::slot(u)] * cr[q];
           }
         }
       }
