@@ -490,4 +490,13 @@ def test_batched_form_on_projected_index(torch):
         ri, rd, _ = gix.query(torch.from_numpy(q[sel]), ef=e, ef_max=48, S=16, K=5)
         assert np.array_equal(ids[sel], ri.cpu().numpy())
         assert np.array_equal(d[sel].view(np.uint32), rd.cpu().numpy().view(np.uint32))
+    # the captured step (the projection included) replays to the same bits, with eager work between replays
+    bs.capture()
+    for _ in range(3):
+        gi, gd = bs.run()
+        torch.cuda.synchronize()
+        assert np.array_equal(gi.cpu().numpy(), ids)
+        assert np.array_equal(gd.cpu().numpy().view(np.uint32), d.view(np.uint32))
+        gix.query(torch.from_numpy(q[:7]), ef=16, ef_max=48, S=16, K=5)
+        torch.cuda.synchronize()
     gix.close()
