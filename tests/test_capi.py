@@ -6,6 +6,7 @@ import glob
 import os
 import re
 
+import numpy as np
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -106,3 +107,15 @@ def test_library_is_built_from_these_sources(L):
     # older kernel) must never be loaded
     from paper_1804_09996_amd import build_ext
     assert L.lc_build_id().decode() == build_ext.source_id()
+
+
+def test_missing_library_fails_loudly(tmp_path, monkeypatch):
+    # no CPU fallback: without liblc.so every entry point raises instead of computing elsewhere
+    import paper_1804_09996_amd as lc
+    monkeypatch.setattr(lc, "LIB_PATH", str(tmp_path / "absent" / "liblc.so"))
+    monkeypatch.setattr(lc, "_lib", None)
+    with pytest.raises(ImportError, match="no CPU fallback"):
+        lc.lib()
+    with pytest.raises(ImportError):
+        lc.Index({"codes": np.zeros((4, 8), np.uint8)}, {"d": 8, "d_pad": 8, "m": 8, "deg0": 32, "deg_up": 32,
+                                                         "k_reg": 1, "entry": 0, "max_level": 0}, device="cpu")
