@@ -158,7 +158,10 @@ def bench_batched(args):
     nq, K = q.shape[0], w.topk
     ef = datagen.per_query_ef(w)
     S, ef_max = K, 512
-    bs = BatchedSearcher(gix, nq, ef_max=ef_max, S=S, K=K, precision="f32")
+    # --precision f16: fp16 tables in the walk (the refinement stays fp32 at this short-list: K = S leaves
+    # nothing for a bf16 first pass to skip)
+    prec = "f16" if args.precision != "f32" else "f32"
+    bs = BatchedSearcher(gix, nq, ef_max=ef_max, S=S, K=K, precision=prec)
     bs.set_inputs(q, ef)
     sched = bs.tune(cache_path=None, log=log)
     bs.capture()
@@ -176,27 +179,30 @@ def bench_batched(args):
     step_ms = np.array([a.elapsed_time(b) for a, b in evs])
     # per-kernel times of one eager step on the same buffers (the walk phase:
     # the concurrent launches of every ef class)
-    lut_dt = lc.LC_LUT_F32
+    lut_dt = bs.lut_dtype
     e = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
     e[0].record()
-    lut, scale = gix.build_lut(bs.q, lut_dt)
+    qx, pj = bs._queries()
+    lut, scale = gix.build_lut(qx, lut_dt, projected=pj)
     e[1].record()
     bs._walks(lut, scale)
     e[2].record()
-    gix.refine(bs.q, bs.res.cand_ids, bs.res.cand_n, K)
+    gix.refine(qx, bs.res.cand_ids, bs.res.cand_n, K, bs.refine_p, projected=pj)
     e[3].record()
     torch.cuda.synchronize()
     kms = [e[j].elapsed_time(e[j + 1]) for j in range(3)]
     st = bs.res.stats.cpu().numpy()
     E, D = st[:, 0].astype(np.int64), st[:, 1].astype(np.int64)
     wb = walk_bytes(w, E, D, S)
+    if prec == "f16":
+        wb += -nq * 2 * w.m * 256 + nq * 4 * w.m  # fp16 table + scales
     idx, gt = ground_truth_sample(torch, db, q, dev, 10_000, w.seed)
     ids_np = ids.cpu().numpy()[idx]
     rec = {f"R@{r_}": recall(ids_np, gt, r_) for r_ in (1, 10, 100) if r_ <= K}
     out = {"metric": "QPS, batched persistent form (per-query efSearch), 1 GPU", "value": nq * args.steps / wall,
            "unit": "queries/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
            "ms_per_step": wall / args.steps * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-           "dtype": "f32", "data": "synthetic",
+           "dtype": prec, "data": "synthetic",
            "config": {"workload": f"{w.name}: N={w.n} d={w.d} Gaussian mixture ({w.n_comp} components), PQ {w.m}x256, "
                                   f"k={w.k_reg}, {nq} queries in one step, efSearch per query round(exp(U(ln16, "
                                   f"ln512))), pool max(ef, {S}), short-list {S}, top-{K}, longest ef first, "
@@ -206,7 +212,7 @@ def bench_batched(args):
                       "ef_classes": [{"rows": r1 - r0, "ef_max": efm} for r0, r1, efm in bs.ranges]},
            "roofline": {"bound": "hbm", "achieved": wb / (kms[1] * 1e-3) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                         "frac": wb / (kms[1] * 1e-3) / 1e9 / HBM_PEAK_GBS, "traffic": None,
-                        "kernel": "walk phase: " + ", ".join(walk_kernel_name(w.m, "f32", efm, S) for _, _, efm in bs.ranges),
+                        "kernel": "walk phase: " + ", ".join(walk_kernel_name(w.m, prec, efm, S) for _, _, efm in bs.ranges),
                         "algorithmic_bytes_per_launch": wb},
            "kernels_ms": dict(zip(("build_lut", "walk", "refine"), kms)),
            "step_ms_p50": float(np.percentile(step_ms, 50)), "step_ms_p99": float(np.percentile(step_ms, 99)),

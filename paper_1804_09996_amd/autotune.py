@@ -35,11 +35,11 @@ def candidates(ef_max: int, S: int) -> list:
     return out
 
 
-def _key(gix, nq: int, ef_max: int, S: int) -> str:
+def _key(gix, nq: int, ef_max: int, S: int, table: str = "f32") -> str:
     torch = gix.torch
     name = torch.cuda.get_device_properties(gix.device).name
     bucket = 1 << max(0, (int(nq) - 1).bit_length())
-    return f"{name}|n={gix.n}|m={gix.m}|ef={ef_max}|S={S}|nq~{bucket}"
+    return f"{name}|n={gix.n}|m={gix.m}|ef={ef_max}|S={S}|nq~{bucket}|table={table}"
 
 
 def load_cache(path: str) -> dict:
@@ -58,16 +58,17 @@ def save_cache(path: str, cache: dict):
     os.replace(tmp, path)
 
 
-def time_schedule(gix, lut, ef, ef_max: int, S: int, sc: Schedule, reps: int = 3) -> float:
-    """Median milliseconds of one walk launch with schedule ``sc``."""
+def time_schedule(gix, lut, ef, ef_max: int, S: int, sc: Schedule, reps: int = 3, scale=None) -> float:
+    """Median milliseconds of one walk launch with schedule ``sc`` (``scale``:
+    the row scales of an fp16 table)."""
     torch = gix.torch
-    gix.search(lut, ef=ef, ef_max=ef_max, S=S, stats=False, sched=sc)  # warm up, size the workspace
+    gix.search(lut, scale, ef=ef, ef_max=ef_max, S=S, stats=False, sched=sc)  # warm up, size the workspace
     times = []
     for _ in range(reps):
         a = torch.cuda.Event(enable_timing=True)
         b = torch.cuda.Event(enable_timing=True)
         a.record()
-        gix.search(lut, ef=ef, ef_max=ef_max, S=S, stats=False, sched=sc)
+        gix.search(lut, scale, ef=ef, ef_max=ef_max, S=S, stats=False, sched=sc)
         b.record()
         b.synchronize()
         times.append(a.elapsed_time(b))
@@ -76,15 +77,16 @@ def time_schedule(gix, lut, ef, ef_max: int, S: int, sc: Schedule, reps: int = 3
 
 
 def tune(gix, lut, ef=None, ef_max: int = 64, S: int = 64, cands: Optional[Iterable[Schedule]] = None,
-         reps: int = 3, cache_path: Optional[str] = DEFAULT_CACHE, log=None):
-    """Best schedule for this index and batch, and the timing table."""
-    key = _key(gix, lut.shape[0], ef_max, S)
+         reps: int = 3, cache_path: Optional[str] = DEFAULT_CACHE, log=None, scale=None):
+    """Best schedule for this index and batch, and the timing table (``scale``:
+    the row scales when ``lut`` is an fp16 table)."""
+    key = _key(gix, lut.shape[0], ef_max, S, "f16" if scale is not None else "f32")
     cache = load_cache(cache_path) if cache_path else {}
     if key in cache:
         return schedule(**cache[key]["schedule"]), cache[key]["table"]
     table = []
     for sc in (cands or candidates(ef_max, S)):
-        ms = time_schedule(gix, lut, ef, ef_max, S, sc, reps)
+        ms = time_schedule(gix, lut, ef, ef_max, S, sc, reps, scale=scale)
         table.append({"schedule": sc.as_dict(), "ms": ms})
         if log:
             log(f"autotune {sc}: {ms:.3f} ms")

@@ -184,7 +184,7 @@ class BatchedSearcher:
         qx, pj = self._queries()
         lut, scale = self.gix.build_lut(qx, self.lut_dtype, projected=pj)
         self.sched, self.table = autotune.tune(self.gix, lut, ef=self.ef, ef_max=self.ef_max, S=self.S,
-                                               cands=cands, reps=reps, cache_path=cache_path, log=log)
+                                               cands=cands, reps=reps, cache_path=cache_path, log=log, scale=scale)
         best = None
         for lim in class_limits_options(self.ef_max, self.S):
             self.set_classes(lim)

@@ -500,3 +500,25 @@ def test_batched_form_on_projected_index(torch):
         gix.query(torch.from_numpy(q[:7]), ef=16, ef_max=48, S=16, K=5)
         torch.cuda.synchronize()
     gix.close()
+
+
+@pytest.mark.parametrize("precision", ["f32", "f16"])
+def test_autotuned_batched_form(c1, torch, precision):
+    # the autotuner times schedules and ef-class splits on the batch (fp16 tables with their row scales);
+    # whatever it picks, the results are the untuned ones
+    import paper_1804_09996_amd as lc
+    from paper_1804_09996_amd.batched import BatchedSearcher
+    w, ix, gix, db, q = c1
+    ef = np.where(np.arange(w.nq) % 4 == 0, 200, 24).astype(np.int32)
+    bs = BatchedSearcher(gix, w.nq, 200, 32, 10, precision=precision)
+    bs.set_inputs(q, ef)
+    ref_ids, ref_d = (t.cpu().numpy() for t in bs.run())
+    cands = [lc.schedule(), lc.schedule(hash_bits=9, prefetch=0), lc.schedule(pool=1)]
+    bs.tune(cands=cands, reps=1, cache_path=None)
+    assert len(bs.table) >= len(cands)
+    bs.capture()
+    for _ in range(2):
+        ids, d = bs.run()
+        torch.cuda.synchronize()
+        assert np.array_equal(ids.cpu().numpy(), ref_ids)
+        assert np.array_equal(d.cpu().numpy().view(np.uint32), ref_d.view(np.uint32))
