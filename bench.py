@@ -115,9 +115,26 @@ def cpu_baseline(ix, db, q, w, seconds=10.0):
     del probe
     what = f"first {n} of the {q.shape[0]} benchmark queries" if passes == 1 else \
         f"the {n} benchmark queries, {passes} passes"
+    # and one thread on the first 1000 queries, in the paper's unit (ms per query)
+    n1 = min(1000, q.shape[0])
+    t1 = time.time()
+    oix.search(q[:n1], w.ef, w.shortlist, w.topk, nthreads=1)
+    ms1 = (time.time() - t1) / n1 * 1e3
     return {"value": n * passes / dt, "unit": "queries/s", "cores": nt, "kind": "oracle",
             "sample": f"{what}, float64 oracle search (LUT, walk, refine, top-{w.topk}), {nt} threads, "
-                      f"{dt:.1f} s"}, oix, res, n
+                      f"{dt:.1f} s",
+            "single_thread_ms_per_query": ms1, "single_thread_sample": f"first {n1} queries, 1 thread",
+            "cpu_model": cpu_model()}, oix, res, n
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def interp_at(points, r_target):
