@@ -223,7 +223,11 @@ int lc_search_budget(const lc_index *ix, const void *lut, int lut_dtype, const f
  * cand_ids, cand_n: as produced by lc_search (cand_n[q] <= 0 -> no candidates).
  * precision: LC_REFINE_F32 (fp32 throughout) or LC_REFINE_BF16_RESCORE.
  * out_ids i32 [nq][K] (-1 padded), out_d f32 [nq][K] (+inf padded).
- * Requires 1 <= K <= S. */
+ * Requires 1 <= K <= S.  The centroids are staged in LDS: LC_ENOTSUP when
+ * d_pad x 256 float32 values (bfloat16 in the precision form) and the
+ * per-wave buffers do not fit the LDS of one compute unit (d_pad above about
+ * 150 in float32), and for the precision form on a shape without a
+ * specialised kernel. */
 int lc_refine(const lc_index *ix, const float *q, int64_t nq, const int32_t *cand_ids,
               const int32_t *cand_n, int32_t S, int32_t K, int precision, int32_t *out_ids,
               float *out_d, void *stream);
@@ -236,8 +240,9 @@ int lc_refine(const lc_index *ix, const float *q, int64_t nq, const int32_t *can
  * which the plain entry points apply per table block and per refined query:
  * projecting a batch once reads P once per block of queries instead of once
  * per query.  Results equal the plain entry points' up to float32 rounding of
- * the projection.  Errors: LC_EINVAL (null pointers, nq < 0), LC_ENOTSUP (P
- * and a block of queries do not fit the LDS of one compute unit). */
+ * the projection (a P too large for the LDS of one compute unit together with
+ * 32 queries is read from global memory instead; which way depends only on
+ * d and d_pad).  Errors: LC_EINVAL (null pointers, nq < 0). */
 int lc_project_queries(const lc_index *ix, const float *q, int64_t nq, float *qp, void *stream);
 int lc_build_lut_projected(const lc_index *ix, const float *qp, int64_t nq, int lut_dtype, void *lut,
                            float *lut_scale, void *stream);

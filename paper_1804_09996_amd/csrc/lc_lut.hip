@@ -206,6 +206,29 @@ __global__ __launch_bounds__(256) void project_kernel(const float *__restrict__ 
 
 }  // namespace
 
+// The same without staging, for a P too large for LDS: one wavefront per
+// query, each row of P read as a contiguous run (lanes over its columns) and
+// summed across the lanes.  Which kernel projects depends only on (d, d_pad),
+// so every batch of one index is projected the same way.
+namespace {
+__global__ __launch_bounds__(256) void project_kernel_global(const float *__restrict__ q, int64_t nq, int d,
+                                                             int d_pad, const float *__restrict__ proj,
+                                                             float *__restrict__ out) {
+  const int lane = threadIdx.x & 63;
+  const int64_t i = int64_t(blockIdx.x) * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (i >= nq) return;  // whole wavefronts leave together
+  const float *y = q + i * d;
+  for (int r = 0; r < d_pad; ++r) {
+    const float *pr = proj + size_t(r) * d;
+    float v = 0.f;
+    for (int u = lane; u < d; u += 64) v += pr[u] * y[u];
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off);
+    if (lane == 0) out[i * d_pad + r] = v;
+  }
+}
+}  // namespace
+
 int lc_launch_project(const lc_index *ix, const float *q, int64_t nq, float *out, hipStream_t st) {
   const int d = ix->v.d, dp = ix->v.d_pad;
   if (!ix->v.proj) {
@@ -215,7 +238,11 @@ int lc_launch_project(const lc_index *ix, const float *q, int64_t nq, float *out
                : LC_EHIP;
   }
   const size_t lds = (size_t(dp) * (d + 1) + size_t(kQB) * d) * sizeof(float);
-  if (lds > size_t(ix->lds_per_cu)) return LC_ENOTSUP;
+  if (lds > size_t(ix->lds_per_cu)) {
+    hipLaunchKernelGGL(project_kernel_global, dim3(int(lc::ceil_div(nq, 4))), dim3(256), 0, st, q, nq, d, dp,
+                       ix->v.proj, out);
+    return hipGetLastError() == hipSuccess ? LC_OK : LC_EHIP;
+  }
   if (hipFuncSetAttribute(reinterpret_cast<const void *>(&project_kernel),
                           hipFuncAttributeMaxDynamicSharedMemorySize, int(lds)) != hipSuccess)
     return LC_EHIP;

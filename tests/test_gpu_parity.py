@@ -522,3 +522,29 @@ def test_autotuned_batched_form(c1, torch, precision):
         torch.cuda.synchronize()
         assert np.array_equal(ids.cpu().numpy(), ref_ids)
         assert np.array_equal(d.cpu().numpy().view(np.uint32), ref_d.view(np.uint32))
+
+
+def test_large_projection_reads_P_from_global(torch):
+    # d 200 -> d_pad 256: P (256 x 200) and a block of queries exceed one CU's LDS, so the batch projection
+    # reads P from global memory; tables and walk are still the oracle's
+    import paper_1804_09996_amd as lc
+    w = datagen.small(name="gpu-bigp", n=1200, nq=16, d=200, m=16, d_pad=256, n_train=1024, n_beta=8,
+                      n_beta_train=1200, ef=32, shortlist=32, topk=10)
+    ix, db, q = oracle.build_workload(w, nthreads=4)
+    assert ix.proj.shape == (256, 200)
+    gix = lc.Index.from_index(ix)
+    qp = gix.project(torch.from_numpy(q)).cpu().numpy()
+    ref = np.stack([oracle.project(ix.proj, y, ix.d_pad) for y in q])
+    np.testing.assert_allclose(qp, ref, rtol=0, atol=1e-5 * np.abs(ref).max())
+    # tables from the projected batch and the walk: the oracle's short-lists
+    o = ix.search(q, w.ef, w.shortlist, w.topk)
+    lut, _ = gix.build_lut(torch.from_numpy(qp), projected=True)
+    assert np.all(np.abs(lut.cpu().numpy() - np.stack([ix.lut(y) for y in q])) <= _lut_bound(ix, q))
+    r = gix.search(lut, ef=w.ef, ef_max=w.ef, S=w.shortlist)
+    same = np.mean([np.array_equal(r.cand_ids.cpu().numpy()[i], o["cand_ids"][i]) for i in range(w.nq)])
+    assert same >= 0.9
+    # the refinement stages every centroid in LDS (d_pad x 256 floats = 256 KB here): not supported
+    with pytest.raises(lc.LCError) as e:
+        gix.refine(torch.from_numpy(qp), r.cand_ids, r.cand_n, w.topk, projected=True)
+    assert e.value.code == lc.LC_ENOTSUP
+    gix.close()
