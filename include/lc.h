@@ -223,11 +223,10 @@ int lc_search_budget(const lc_index *ix, const void *lut, int lut_dtype, const f
  * cand_ids, cand_n: as produced by lc_search (cand_n[q] <= 0 -> no candidates).
  * precision: LC_REFINE_F32 (fp32 throughout) or LC_REFINE_BF16_RESCORE.
  * out_ids i32 [nq][K] (-1 padded), out_d f32 [nq][K] (+inf padded).
- * Requires 1 <= K <= S.  The centroids are staged in LDS: LC_ENOTSUP when
- * d_pad x 256 float32 values (bfloat16 in the precision form) and the
- * per-wave buffers do not fit the LDS of one compute unit (d_pad above about
- * 150 in float32), and for the precision form on a shape without a
- * specialised kernel. */
+ * Requires 1 <= K <= S.  The centroids are staged in LDS when they fit
+ * (d_pad x 256 values beside the per-wave buffers), else the float32 kernel
+ * reads them from global memory; LC_ENOTSUP for the precision form on a
+ * shape without a specialised kernel. */
 int lc_refine(const lc_index *ix, const float *q, int64_t nq, const int32_t *cand_ids,
               const int32_t *cand_n, int32_t S, int32_t K, int precision, int32_t *out_ids,
               float *out_d, void *stream);

@@ -440,16 +440,19 @@ __global__ __launch_bounds__(1024) void refine_kernel(RefineArgs a) {
 
 // Any (m, dsub) without a specialised kernel (float32 only): a lane part walks
 // its sub-spaces one at a time and re-reads the code byte of each neighbour.
-__global__ __launch_bounds__(1024) void refine_f32_generic(RefineArgs a, int m, int dsub) {
+// staged = 0: the centroids do not fit LDS and are read from global memory
+// (cached); the arithmetic is the same.
+__global__ __launch_bounds__(1024) void refine_f32_generic(RefineArgs a, int m, int dsub, int staged) {
   const int DP = m * dsub;
   extern __shared__ __align__(16) unsigned char smem[];
-  float *C = reinterpret_cast<float *>(smem);
+  const size_t cent_bytes = staged ? (size_t(m) * 256 * dsub * 4 + 15) / 16 * 16 : 0;
+  const float *C = staged ? reinterpret_cast<const float *>(smem) : a.cent;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  unsigned char *wbase =
-      smem + (size_t(m) * 256 * dsub * 4 + 15) / 16 * 16 + size_t(wave) * (DP * 4 + a.S_pad * 8);
+  unsigned char *wbase = smem + cent_bytes + size_t(wave) * (DP * 4 + a.S_pad * 8);
   float *yv = reinterpret_cast<float *>(wbase);
   uint64_t *keys = reinterpret_cast<uint64_t *>(wbase + DP * 4);
-  for (int i = threadIdx.x; i < m * 256 * dsub; i += blockDim.x) C[i] = a.cent[i];
+  if (staged)
+    for (int i = threadIdx.x; i < m * 256 * dsub; i += blockDim.x) reinterpret_cast<float *>(smem)[i] = a.cent[i];
   __syncthreads();
   const int part = lane & 3, grp = lane >> 2;
   for (int64_t q = int64_t(blockIdx.x) * a.wpb + wave; q < a.nq; q += int64_t(gridDim.x) * a.wpb) {
@@ -532,8 +535,9 @@ RefineArgs make_args(const lc_index *ix, const float *q, int64_t nq, const int32
 }
 
 // Waves per block and LDS bytes for the staged centroids plus per-wave buffers.
-bool plan_blocks(const lc_index *ix, RefineArgs &a, int cent_elem_bytes, int *lds, int64_t *blocks) {
-  const int cent_bytes = (ix->v.m * 256 * ix->dsub * cent_elem_bytes + 15) / 16 * 16;
+bool plan_blocks(const lc_index *ix, RefineArgs &a, int cent_elem_bytes, int *lds, int64_t *blocks,
+                 bool stage = true) {
+  const int cent_bytes = stage ? (ix->v.m * 256 * ix->dsub * cent_elem_bytes + 15) / 16 * 16 : 0;
   const int per_wave = ix->v.d_pad * 4 + a.S_pad * 8;
   int wpb = (ix->lds_per_cu - cent_bytes) / per_wave;
   if (wpb > 16) wpb = 16;
@@ -573,11 +577,15 @@ int launch_blocks(const lc_index *ix, const RefineArgs &a, hipStream_t st) {
 int launch_generic(const lc_index *ix, RefineArgs a, hipStream_t st) {
   int lds;
   int64_t blocks;
-  if (ix->dsub > 16 || !plan_blocks(ix, a, 4, &lds, &blocks)) return LC_ENOTSUP;
+  if (ix->dsub > 16) return LC_ENOTSUP;
+  // centroids in LDS when they fit beside the per-wave buffers, else read from global memory
+  const bool staged = plan_blocks(ix, a, 4, &lds, &blocks);
+  if (!staged && !plan_blocks(ix, a, 4, &lds, &blocks, false)) return LC_ENOTSUP;
   if (hipFuncSetAttribute(reinterpret_cast<const void *>(&refine_f32_generic),
                           hipFuncAttributeMaxDynamicSharedMemorySize, lds) != hipSuccess)
     return LC_EHIP;
-  hipLaunchKernelGGL(refine_f32_generic, dim3(int(blocks)), dim3(64 * a.wpb), lds, st, a, ix->v.m, ix->dsub);
+  hipLaunchKernelGGL(refine_f32_generic, dim3(int(blocks)), dim3(64 * a.wpb), lds, st, a, ix->v.m, ix->dsub,
+                     int(staged));
   return hipGetLastError() == hipSuccess ? LC_OK : LC_EHIP;
 }
 
