@@ -43,6 +43,7 @@ _STREAMS = {
     "PROJ": 11,
     "EF": 12,
     "MISC": 13,
+    "COARSE_INIT": 14,
 }
 
 
@@ -82,6 +83,7 @@ class Workload:
     seed: int = DEFAULT_SEED
     m_beta: int = 1               # regression-codebook blocks (product codebook, Sec. 4.3 Eq. 9)
     opq_iters: int = 0            # learned rotation ahead of PQ (OPQ): rotation steps, 0 = none
+    coarse_k: int = 0             # 2-level residual codec (Sec. 5.1): first-level centroids per half, 0 = none
 
     @property
     def dsub(self) -> int:
@@ -219,6 +221,12 @@ def sample_ids(seed: int, stream: str, n: int, k: int, sub: int = 0) -> np.ndarr
 def pq_init_ids(w: Workload, n_train: int) -> np.ndarray:
     """Per-subspace k-means seeds: ``[m, 256]`` distinct training row ids."""
     return np.stack([sample_ids(w.seed, "PQ_INIT", n_train, 256, s) for s in range(w.m)])
+
+
+def coarse_init_ids(w: Workload, n_train: int) -> np.ndarray:
+    """k-means seeds of the 2-level codec's first level: ``[2, coarse_k]``
+    distinct training row ids."""
+    return np.stack([sample_ids(w.seed, "COARSE_INIT", n_train, w.coarse_k, h) for h in range(2)])
 
 
 def beta_train_ids(w: Workload) -> np.ndarray:

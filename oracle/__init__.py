@@ -45,10 +45,15 @@ _i = C.c_int
 _i64 = C.c_int64
 
 
+class OrcCoarse(C.Structure):
+    _fields_ = [("k", C.c_int32), ("cent", _p), ("codes", _p)]
+
+
 class OrcIndex(C.Structure):
     _fields_ = [(n, C.c_int32) for n in ("n", "d", "d_pad", "m", "ksub", "code_stride", "deg0", "deg_up",
                                           "k_reg", "n_beta", "entry", "max_level", "m_beta")] + \
-               [(n, _p) for n in ("proj", "centroids", "codes", "adj0", "up_base", "adj_up", "beta", "beta_idx")]
+               [(n, _p) for n in ("proj", "centroids", "codes", "adj0", "up_base", "adj_up", "beta", "beta_idx")] + \
+               [("coarse", OrcCoarse)]
 
 
 def _declare(L):
@@ -57,12 +62,16 @@ def _declare(L):
     L.orc_pq_encode.argtypes = [_p, _i64, _i, _p, _i, _i, _i, _p, _i, _p, _i]
     L.orc_levels.argtypes = [_p, _i64, _i, _i, _p]
     L.orc_levels.restype = _i64
-    L.orc_hnsw_build.argtypes = [_p, _i64, _i, _p, _i, _i, _i, _p, _p, _i, _p, _i, _i, _i, _i, _p, _p, _p, _p, _p]
+    L.orc_hnsw_build.argtypes = [_p, _i64, _i, _p, _i, _i, _i, _p, _p, _i, _p, _i, _i, _i, _i, _p, _p, _p, _p, _p,
+                                 C.POINTER(OrcCoarse)]
     L.orc_lsq_solve.argtypes = [_p, _p, _i, _p]
     L.orc_beta_train.argtypes = [_p, _p, _i64, _i, _p, _i, _i, _i, _p, _p, _i, _p, _i, _i, _i, _i, _p, _i, _i,
-                                 _i, _p, _p]
-    L.orc_beta_shared.argtypes = [_p, _p, _i64, _i, _p, _i, _i, _i, _p, _p, _i, _p, _i, _i, _p]
-    L.orc_beta_assign.argtypes = [_p, _i64, _i, _p, _i, _i, _i, _p, _p, _i, _p, _i, _i, _i, _i, _p, _i, _p]
+                                 _i, _p, _p, C.POINTER(OrcCoarse)]
+    L.orc_beta_shared.argtypes = [_p, _p, _i64, _i, _p, _i, _i, _i, _p, _p, _i, _p, _i, _i, _p, C.POINTER(OrcCoarse)]
+    L.orc_beta_assign.argtypes = [_p, _i64, _i, _p, _i, _i, _i, _p, _p, _i, _p, _i, _i, _i, _i, _p, _i, _p,
+                                  C.POINTER(OrcCoarse)]
+    L.orc_coarse_encode.argtypes = [_p, _i64, _i, _p, _i, _i, _p, _i, _p, _p]
+    L.orc_coarse_norms.argtypes = [C.POINTER(OrcIndex), _p]
     L.orc_lut.argtypes = [C.POINTER(OrcIndex), _p, _p]
     L.orc_lut.restype = None
     L.orc_search.argtypes = [C.POINTER(OrcIndex), _p, _i64, _p, C.c_int32, C.c_int32, _i, _p, _p, _p, _p, _p, _p]
@@ -147,6 +156,40 @@ def pq_encode(x, proj, d_pad, cent, nthreads=1, code_stride=None):
     return codes
 
 
+def _coarse(coarse) -> Optional[OrcCoarse]:
+    """(first-level centroids [2, k, d_pad/2] f32, codes [n, 2] u16) of a
+    2-level codec as the C struct, or None for the one-level codec.  The
+    arrays must stay alive while the struct is used."""
+    if coarse is None:
+        return None
+    cent, codes = coarse
+    if cent.dtype != np.float32 or codes.dtype != np.uint16 or not (cent.flags.c_contiguous and
+                                                                       codes.flags.c_contiguous):
+        raise ValueError("coarse codec arrays must be contiguous float32 / uint16")
+    if cent.ndim != 3 or cent.shape[0] != 2 or codes.ndim != 2 or codes.shape[1] != 2:
+        raise ValueError("coarse codec: centroids [2, k, d_pad/2], codes [n, 2]")
+    return OrcCoarse(cent.shape[1], cent.ctypes.data, codes.ctypes.data)
+
+
+def _cref(cs):
+    return None if cs is None else C.byref(cs)
+
+
+def coarse_encode(x, proj, d_pad, cent, nthreads=1):
+    """First level of the 2-level codec: codes [n, 2] u16 and the residuals
+    P x - c [n, d_pad] f32 that the second-level PQ encodes."""
+    x = _c(x, np.float32)
+    proj = None if proj is None else _c(proj, np.float32)
+    cent = _c(cent, np.float32)
+    codes = np.empty((x.shape[0], 2), np.uint16)
+    resid = np.empty((x.shape[0], d_pad), np.float32)
+    rc = _load().orc_coarse_encode(_ptr(x), x.shape[0], x.shape[1], _ptr(proj), d_pad, cent.shape[1], _ptr(cent),
+                                   nthreads, _ptr(codes), _ptr(resid))
+    if rc != 0:
+        raise ValueError(f"orc_coarse_encode failed ({rc})")
+    return codes, resid
+
+
 def levels(u: np.ndarray, ratio: int = 30, cap: int = 16):
     u = _c(u, np.float64)
     lv = np.empty(u.shape[0], np.int8)
@@ -154,7 +197,7 @@ def levels(u: np.ndarray, ratio: int = 30, cap: int = 16):
     return lv, int(rows)
 
 
-def hnsw_build(x, proj, d_pad, cent, codes, level, deg0, deg_up, efc, nthreads=1):
+def hnsw_build(x, proj, d_pad, cent, codes, level, deg0, deg_up, efc, nthreads=1, coarse=None):
     x = _c(x, np.float32)
     proj = None if proj is None else _c(proj, np.float32)
     cent = _c(cent, np.float32)
@@ -169,7 +212,7 @@ def hnsw_build(x, proj, d_pad, cent, codes, level, deg0, deg_up, efc, nthreads=1
     maxl = C.c_int32()
     rc = _load().orc_hnsw_build(_ptr(x), n, x.shape[1], _ptr(proj), d_pad, cent.shape[0], cent.shape[1], _ptr(cent),
                                 _ptr(codes), codes.shape[1], _ptr(level), deg0, deg_up, efc, nthreads, _ptr(adj0),
-                                _ptr(up_base), _ptr(adj_up), C.byref(entry), C.byref(maxl))
+                                _ptr(up_base), _ptr(adj_up), C.byref(entry), C.byref(maxl), _cref(_coarse(coarse)))
     if rc != 0:
         raise ValueError(f"orc_hnsw_build failed ({rc})")
     if rows == 0:
@@ -186,7 +229,7 @@ def lsq_solve(a: np.ndarray, c: np.ndarray):
 
 
 def beta_train(x, ids, proj, d_pad, cent, codes, adj0, k_reg, n_beta, init, km_iters, em_iters, nthreads=1,
-               m_beta=1):
+               m_beta=1, coarse=None):
     """Regression codebook(s): [n_beta, k+1] for one block, [m_beta, n_beta, k+1]
     for the product codebook (Eq. 9); the loss history likewise per block."""
     x = _c(x, np.float32)
@@ -198,7 +241,7 @@ def beta_train(x, ids, proj, d_pad, cent, codes, adj0, k_reg, n_beta, init, km_i
     rc = _load().orc_beta_train(_ptr(x), _ptr(ids), ids.shape[0], x.shape[1], _ptr(proj), d_pad, cent.shape[0],
                                 cent.shape[1], _ptr(_c(cent, np.float32)), _ptr(_c(codes, np.uint8)), codes.shape[1],
                                 _ptr(_c(adj0, np.int32)), adj0.shape[1], k_reg, n_beta, m_beta, _ptr(init), km_iters,
-                                em_iters, nthreads, _ptr(beta), _ptr(hist))
+                                em_iters, nthreads, _ptr(beta), _ptr(hist), _cref(_coarse(coarse)))
     if rc != 0:
         raise ValueError(f"orc_beta_train failed ({rc})")
     if m_beta == 1:
@@ -206,20 +249,20 @@ def beta_train(x, ids, proj, d_pad, cent, codes, adj0, k_reg, n_beta, init, km_i
     return beta, hist
 
 
-def beta_shared(x, ids, proj, d_pad, cent, codes, adj0, k_reg):
+def beta_shared(x, ids, proj, d_pad, cent, codes, adj0, k_reg, coarse=None):
     x = _c(x, np.float32)
     ids = _c(ids, np.int64)
     proj = None if proj is None else _c(proj, np.float32)
     beta = np.empty(k_reg + 1, np.float64)
     rc = _load().orc_beta_shared(_ptr(x), _ptr(ids), ids.shape[0], x.shape[1], _ptr(proj), d_pad, cent.shape[0],
                                  cent.shape[1], _ptr(_c(cent, np.float32)), _ptr(_c(codes, np.uint8)), codes.shape[1],
-                                 _ptr(_c(adj0, np.int32)), adj0.shape[1], k_reg, _ptr(beta))
+                                 _ptr(_c(adj0, np.int32)), adj0.shape[1], k_reg, _ptr(beta), _cref(_coarse(coarse)))
     if rc != 0:
         raise ValueError(f"orc_beta_shared failed ({rc})")
     return beta
 
 
-def beta_assign(x, proj, d_pad, cent, codes, adj0, k_reg, beta, nthreads=1):
+def beta_assign(x, proj, d_pad, cent, codes, adj0, k_reg, beta, nthreads=1, coarse=None):
     """Entry per vector: [n] for a [n_beta, k+1] codebook, [n, m_beta] for a
     [m_beta, n_beta, k+1] product codebook."""
     x = _c(x, np.float32)
@@ -230,7 +273,7 @@ def beta_assign(x, proj, d_pad, cent, codes, adj0, k_reg, beta, nthreads=1):
     rc = _load().orc_beta_assign(_ptr(x), x.shape[0], x.shape[1], _ptr(proj), d_pad, cent.shape[0], cent.shape[1],
                                  _ptr(_c(cent, np.float32)), _ptr(_c(codes, np.uint8)), codes.shape[1],
                                  _ptr(_c(adj0, np.int32)), adj0.shape[1], k_reg, beta.shape[-2], mb, _ptr(beta),
-                                 nthreads, _ptr(out))
+                                 nthreads, _ptr(out), _cref(_coarse(coarse)))
     if rc != 0:
         raise ValueError(f"orc_beta_assign failed ({rc})")
     return out[:, 0].copy() if beta.ndim == 2 else out
@@ -263,10 +306,22 @@ class Index:
     beta_idx: np.ndarray
     ksub: int = 256
     m_beta: int = 1       # product codebook blocks (Eq. 9): beta [m_beta, n_beta, k+1], beta_idx [n, m_beta]
+    # 2-level residual codec (Sec. 5.1): first-level centroids [2, k, d_pad/2] f32,
+    # their codes [n, 2] u16 (the PQ codes then encode the residual), and the
+    # per-node term ||c + r||^2 - ||c||^2 [n] f32 of the decomposed distance
+    coarse_cent: Optional[np.ndarray] = None
+    coarse_codes: Optional[np.ndarray] = None
+    coarse_norm: Optional[np.ndarray] = None
+
+    @property
+    def coarse_k(self) -> int:
+        return 0 if self.coarse_cent is None else int(self.coarse_cent.shape[1])
 
     def arrays(self) -> dict:
-        return {k: getattr(self, k) for k in ("proj", "centroids", "codes", "adj0", "level", "up_base", "adj_up",
-                                              "beta", "beta_idx")}
+        names = ["proj", "centroids", "codes", "adj0", "level", "up_base", "adj_up", "beta", "beta_idx"]
+        if self.coarse_cent is not None:
+            names += ["coarse_cent", "coarse_codes", "coarse_norm"]
+        return {k: getattr(self, k) for k in names}
 
     def _struct(self) -> OrcIndex:
         s = OrcIndex()
@@ -279,7 +334,20 @@ class Index:
         for name in ("proj", "centroids", "codes", "adj0", "up_base", "adj_up", "beta", "beta_idx"):
             a = getattr(self, name)
             setattr(s, name, None if a is None or a.size == 0 else a.ctypes.data)
+        if self.coarse_cent is not None:
+            if (self.coarse_cent.shape != (2, self.coarse_k, self.d_pad // 2) or self.d_pad % 2
+                    or self.coarse_codes.shape != (self.n, 2) or self.d_pad > self.m * self.ksub):
+                raise ValueError("coarse codec arrays do not match (n, d_pad)")
+            s.coarse = _coarse((self.coarse_cent, self.coarse_codes))
         return s
+
+    def coarse_norms(self) -> np.ndarray:
+        """Per-node term ||c + r||^2 - ||c||^2 of the 2-level asymmetric distance."""
+        out = np.empty(self.n, np.float32)
+        s = self._struct()
+        if _load().orc_coarse_norms(C.byref(s), _ptr(out)) != 0:
+            raise ValueError("orc_coarse_norms failed")
+        return out
 
     def lut(self, y: np.ndarray) -> np.ndarray:
         out = np.empty((self.m, self.ksub), np.float64)
@@ -321,19 +389,35 @@ class Index:
 def build_index(w, db: np.ndarray, train: np.ndarray, proj: Optional[np.ndarray], level_u: np.ndarray,
                 pq_init: np.ndarray, beta_ids: np.ndarray, beta_init: np.ndarray,
                 nthreads: Optional[int] = None) -> Index:
-    """Whole build from the seeded inputs: PQ, levels, graph, regression codebook."""
+    """Whole build from the seeded inputs: PQ (2-level when ``w.coarse_k``),
+    levels, graph, regression codebook."""
     nt = nthreads or default_threads()
-    cent, _ = pq_train(train, proj, w.d_pad, w.m, pq_init, w.pq_iters, nt)
-    codes = pq_encode(db, proj, w.d_pad, cent, nt)
+    coarse = None
+    if getattr(w, "coarse_k", 0):
+        import datagen
+        ccent, _ = pq_train(train, proj, w.d_pad, 2, datagen.coarse_init_ids(w, train.shape[0]), w.pq_iters, nt,
+                            ksub=w.coarse_k)
+        _, rtrain = coarse_encode(train, proj, w.d_pad, ccent, nt)
+        ccodes, rdb = coarse_encode(db, proj, w.d_pad, ccent, nt)
+        cent, _ = pq_train(rtrain, None, w.d_pad, w.m, pq_init, w.pq_iters, nt)
+        codes = pq_encode(rdb, None, w.d_pad, cent, nt)
+        coarse = (ccent, ccodes)
+    else:
+        cent, _ = pq_train(train, proj, w.d_pad, w.m, pq_init, w.pq_iters, nt)
+        codes = pq_encode(db, proj, w.d_pad, cent, nt)
     lv, _ = levels(level_u, w.level_ratio, w.max_level_cap)
     adj0, up_base, adj_up, entry, maxl = hnsw_build(db, proj, w.d_pad, cent, codes, lv, w.deg0, w.deg_up,
-                                                    w.ef_construction, nt)
+                                                    w.ef_construction, nt, coarse=coarse)
     beta, _ = beta_train(db, beta_ids, proj, w.d_pad, cent, codes, adj0, w.k_reg, w.n_beta, beta_init,
-                         w.beta_kmeans_iters, w.em_iters, nt, m_beta=w.m_beta)
-    bidx = beta_assign(db, proj, w.d_pad, cent, codes, adj0, w.k_reg, beta, nt)
-    return Index(n=db.shape[0], d=db.shape[1], d_pad=w.d_pad, m=w.m, deg0=w.deg0, deg_up=w.deg_up, k_reg=w.k_reg,
-                 n_beta=w.n_beta, entry=entry, max_level=maxl, proj=proj, centroids=cent, codes=codes, adj0=adj0,
-                 level=lv, up_base=up_base, adj_up=adj_up, beta=beta, beta_idx=bidx, m_beta=w.m_beta)
+                         w.beta_kmeans_iters, w.em_iters, nt, m_beta=w.m_beta, coarse=coarse)
+    bidx = beta_assign(db, proj, w.d_pad, cent, codes, adj0, w.k_reg, beta, nt, coarse=coarse)
+    ix = Index(n=db.shape[0], d=db.shape[1], d_pad=w.d_pad, m=w.m, deg0=w.deg0, deg_up=w.deg_up, k_reg=w.k_reg,
+               n_beta=w.n_beta, entry=entry, max_level=maxl, proj=proj, centroids=cent, codes=codes, adj0=adj0,
+               level=lv, up_base=up_base, adj_up=adj_up, beta=beta, beta_idx=bidx, m_beta=w.m_beta)
+    if coarse is not None:
+        ix.coarse_cent, ix.coarse_codes = coarse
+        ix.coarse_norm = ix.coarse_norms()
+    return ix
 
 
 def build_workload(w, nthreads: Optional[int] = None) -> tuple:

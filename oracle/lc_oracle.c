@@ -277,6 +277,52 @@ int orc_pq_encode(const float *x, int64_t n, int d, const float *proj, int d_pad
   return 0;
 }
 
+/* 2-level residual codec (Sec. 3.3, Sec. 5.1): nearest first-level centroid
+ * of each half, and the residual that the second level encodes */
+typedef struct {
+  const float *x, *proj, *cent;
+  int d, d_pad, k;
+  uint16_t *codes;
+  float *resid;
+} cenc_ctx;
+
+static void cenc_one(int64_t i, int tid, void *vctx) {
+  (void)tid;
+  cenc_ctx *c = (cenc_ctx *)vctx;
+  double xp[4096];
+  int h = c->d_pad / 2;
+  orc_project(c->proj, c->d_pad, c->d, c->x + i * c->d, xp);
+  for (int half = 0; half < 2; half++) {
+    double best = DBL_MAX;
+    int bj = 0;
+    for (int j = 0; j < c->k; j++) {
+      const float *cj = c->cent + ((int64_t)half * c->k + j) * h;
+      double e = 0;
+      for (int t = 0; t < h; t++) {
+        double df = xp[half * h + t] - (double)cj[t];
+        e += df * df;
+      }
+      if (e < best) {
+        best = e;
+        bj = j;
+      }
+    }
+    c->codes[i * 2 + half] = (uint16_t)bj;
+    if (c->resid) {
+      const float *cj = c->cent + ((int64_t)half * c->k + bj) * h;
+      for (int t = 0; t < h; t++) c->resid[i * c->d_pad + half * h + t] = (float)(xp[half * h + t] - (double)cj[t]);
+    }
+  }
+}
+
+int orc_coarse_encode(const float *x, int64_t n, int d, const float *proj, int d_pad, int k,
+                      const float *cent, int nthreads, uint16_t *codes, float *resid) {
+  if (d_pad % 2 || d_pad > 4096 || k < 1 || k > 65536) return -1;
+  cenc_ctx c = {x, proj, cent, d, d_pad, k, codes, resid};
+  orc_parallel_for(n, nthreads, cenc_one, &c);
+  return 0;
+}
+
 /* Levels (Sec. 2: geometric layer sizes; Sec. 4.1: ratio 30 between levels). */
 int64_t orc_levels(const double *u, int64_t n, int ratio, int cap, int8_t *level) {
   int64_t rows = 0;
@@ -290,12 +336,20 @@ int64_t orc_levels(const double *u, int64_t n, int ratio, int cap, int8_t *level
   return rows;
 }
 
-/* decode q(i) (its PQ reconstruction) into out[d_pad] */
+/* decode q(i) (its reconstruction) into out[d_pad]: the PQ reconstruction,
+ * plus, for a 2-level codec, the first-level centroid of each half */
 static void decode(const float *cent, const uint8_t *codes, int code_stride, int m, int ksub,
-                   int dsub, int64_t i, double *out) {
+                   int dsub, const orc_coarse *cq, int64_t i, double *out) {
   for (int s = 0; s < m; s++) {
     const float *c = cent + ((int64_t)s * ksub + codes[i * code_stride + s]) * dsub;
     for (int t = 0; t < dsub; t++) out[s * dsub + t] = (double)c[t];
+  }
+  if (cq && cq->k > 0) {
+    int h = m * dsub / 2;
+    for (int half = 0; half < 2; half++) {
+      const float *c = cq->cent + ((int64_t)half * cq->k + cq->codes[i * 2 + half]) * h;
+      for (int t = 0; t < h; t++) out[half * h + t] += (double)c[t];
+    }
   }
 }
 
@@ -308,6 +362,23 @@ static double sqdist(const double *a, const double *b, int n) {
   return s;
 }
 
+int orc_coarse_norms(const orc_index *ix, float *norm) {
+  int dp = ix->d_pad, h = dp / 2;
+  if (ix->coarse.k < 1 || dp % 2 || dp > 4096) return -1;
+  double rec[4096];
+  for (int64_t i = 0; i < ix->n; i++) {
+    decode(ix->centroids, ix->codes, ix->code_stride, ix->m, ix->ksub, dp / ix->m, &ix->coarse, i, rec);
+    double cc = 0, qq = 0;
+    for (int half = 0; half < 2; half++) {
+      const float *c = ix->coarse.cent + ((int64_t)half * ix->coarse.k + ix->coarse.codes[i * 2 + half]) * h;
+      for (int t = 0; t < h; t++) cc += (double)c[t] * (double)c[t];
+    }
+    for (int t = 0; t < dp; t++) qq += rec[t] * rec[t];
+    norm[i] = (float)(qq - cc);
+  }
+  return 0;
+}
+
 /* ------------------------------------------------------------------------ */
 /* graph build (Sec. 2; Sec. 4.1 "Graph-based structure"; Sec. 5.1)           */
 /* ------------------------------------------------------------------------ */
@@ -317,6 +388,7 @@ typedef struct {
   const float *x, *proj, *cent;
   const uint8_t *codes;
   const int8_t *level;
+  const orc_coarse *cq;
   int deg0, deg_up, efc;
   double *xp;    /* [n][d_pad] projected raw vectors        */
   double *rec;   /* [n][d_pad] PQ reconstructions q(i)      */
@@ -523,15 +595,16 @@ static void prep_one(int64_t i, int tid, void *vctx) {
   (void)tid;
   gb *g = (gb *)vctx;
   orc_project(g->proj, g->d_pad, g->d, g->x + i * g->d, g->xp + i * g->d_pad);
-  decode(g->cent, g->codes, g->code_stride, g->m, g->ksub, g->dsub, i, g->rec + i * g->d_pad);
+  decode(g->cent, g->codes, g->code_stride, g->m, g->ksub, g->dsub, g->cq, i, g->rec + i * g->d_pad);
 }
 
 int orc_hnsw_build(const float *x, int64_t n, int d, const float *proj, int d_pad, int m,
                    int ksub, const float *cent, const uint8_t *codes, int code_stride,
                    const int8_t *level, int deg0, int deg_up, int ef_construction, int nthreads,
                    int32_t *adj0, int32_t *up_base, int32_t *adj_up, int32_t *entry,
-                   int32_t *max_level) {
+                   int32_t *max_level, const orc_coarse *cq) {
   if (n < 1 || d_pad % m || deg0 < 1 || deg_up < 1 || ef_construction < 1) return -1;
+  if (cq && cq->k > 0 && d_pad % 2) return -1;
   if (nthreads < 1) nthreads = 1;
   gb G;
   memset(&G, 0, sizeof(G));
@@ -548,6 +621,7 @@ int orc_hnsw_build(const float *x, int64_t n, int d, const float *proj, int d_pa
   g->cent = cent;
   g->codes = codes;
   g->level = level;
+  g->cq = cq;
   g->deg0 = deg0;
   g->deg_up = deg_up;
   g->efc = ef_construction;
@@ -786,6 +860,7 @@ typedef struct {
   double *A;  /* [n][p][p] G^T G      */
   double *C;  /* [n][p]    G^T x      */
   double *XX; /* [n]       ||x||^2    */
+  const orc_coarse *cq;
 } gram_ctx;
 
 /* G(x) = [q(x), q(g_1(x)), ..., q(g_k(x))] (Sec. 4.2), a -1 link being a zero column;
@@ -804,7 +879,7 @@ static void gram_one(int64_t r, int tid, void *vctx) {
     if (src < 0)
       for (int t = 0; t < dp; t++) G[j * dp + t] = 0;
     else
-      decode(g->cent, g->codes, g->code_stride, g->m, g->ksub, g->dsub, src, G + (int64_t)j * dp);
+      decode(g->cent, g->codes, g->code_stride, g->m, g->ksub, g->dsub, g->cq, src, G + (int64_t)j * dp);
   }
   double *A = g->A + r * p * p, *C = g->C + r * p;
   for (int a = 0; a < p; a++) {
@@ -926,10 +1001,10 @@ int orc_beta_train(const float *x, const int64_t *ids, int64_t n_sub, int d, con
                    int d_pad, int m, int ksub, const float *cent, const uint8_t *codes,
                    int code_stride, const int32_t *adj0, int deg0, int k_reg, int n_beta, int m_beta,
                    const int64_t *init, int km_iters, int em_iters, int nthreads, float *beta,
-                   double *loss_hist) {
+                   double *loss_hist, const orc_coarse *cq) {
   if (k_reg > deg0 || n_beta > n_sub || n_sub < 1 || m_beta < 1 || m % m_beta) return -1;
   int p = k_reg + 1;
-  gram_ctx g = {x, proj, cent, codes, adj0, ids, d, d_pad, m, ksub, d_pad / m, code_stride, deg0, p, 0, d_pad, 0, 0, 0};
+  gram_ctx g = {x, proj, cent, codes, adj0, ids, d, d_pad, m, ksub, d_pad / m, code_stride, deg0, p, 0, d_pad, 0, 0, 0, cq};
   if (gram_alloc(&g, n_sub)) return -2;
   /* product codebook (Sec. 4.3, Eq. 9): block j is the coordinates
    * [j d_pad / m_beta, (j+1) d_pad / m_beta), m / m_beta whole sub-quantizers;
@@ -946,10 +1021,11 @@ int orc_beta_train(const float *x, const int64_t *ids, int64_t n_sub, int d, con
 
 int orc_beta_shared(const float *x, const int64_t *ids, int64_t n_sub, int d, const float *proj,
                     int d_pad, int m, int ksub, const float *cent, const uint8_t *codes,
-                    int code_stride, const int32_t *adj0, int deg0, int k_reg, double *beta) {
+                    int code_stride, const int32_t *adj0, int deg0, int k_reg, double *beta,
+                    const orc_coarse *cq) {
   if (k_reg > deg0 || n_sub < 1) return -1;
   int p = k_reg + 1;
-  gram_ctx g = {x, proj, cent, codes, adj0, ids, d, d_pad, m, ksub, d_pad / m, code_stride, deg0, p, 0, d_pad, 0, 0, 0};
+  gram_ctx g = {x, proj, cent, codes, adj0, ids, d, d_pad, m, ksub, d_pad / m, code_stride, deg0, p, 0, d_pad, 0, 0, 0, cq};
   if (gram_alloc(&g, n_sub)) return -2;
   orc_parallel_for(n_sub, 1, gram_one, &g);
   double *SA = (double *)calloc((size_t)p * p, sizeof(double));
@@ -968,7 +1044,7 @@ int orc_beta_shared(const float *x, const int64_t *ids, int64_t n_sub, int d, co
 int orc_beta_assign(const float *x, int64_t n, int d, const float *proj, int d_pad, int m,
                     int ksub, const float *cent, const uint8_t *codes, int code_stride,
                     const int32_t *adj0, int deg0, int k_reg, int n_beta, int m_beta, const float *beta,
-                    int nthreads, uint8_t *beta_idx) {
+                    int nthreads, uint8_t *beta_idx, const orc_coarse *cq) {
   if (k_reg > deg0 || n_beta > 256 || m_beta < 1 || m % m_beta) return -1;
   int p = k_reg + 1;
   double *B = (double *)malloc(sizeof(double) * (size_t)m_beta * n_beta * p);
@@ -980,7 +1056,7 @@ int orc_beta_assign(const float *x, int64_t n, int d, const float *proj, int d_p
   for (int64_t c0 = 0; c0 < n; c0 += chunk) {
     int64_t c1 = c0 + chunk < n ? c0 + chunk : n;
     for (int64_t i = c0; i < c1; i++) ids[i - c0] = i;
-    gram_ctx g = {x, proj, cent, codes, adj0, ids, d, d_pad, m, ksub, d_pad / m, code_stride, deg0, p, 0, d_pad, 0, 0, 0};
+    gram_ctx g = {x, proj, cent, codes, adj0, ids, d, d_pad, m, ksub, d_pad / m, code_stride, deg0, p, 0, d_pad, 0, 0, 0, cq};
     if (gram_alloc(&g, c1 - c0)) return -2;
     /* each block of the product codebook picks its own entry (Eq. 7 on x^j, G^j) */
     for (int jb = 0; jb < m_beta; jb++) {
@@ -1007,6 +1083,11 @@ void orc_lut(const orc_index *ix, const float *y, double *lut) {
   int dsub = ix->d_pad / ix->m;
   double *yp = (double *)malloc(sizeof(double) * ix->d_pad);
   orc_project(ix->proj, ix->d_pad, ix->d, y, yp);
+  if (ix->coarse.k > 0) { /* 2-level codec: the distance is taken from y' directly */
+    for (int t = 0; t < ix->d_pad; t++) lut[t] = yp[t];
+    free(yp);
+    return;
+  }
   for (int s = 0; s < ix->m; s++)
     for (int c = 0; c < ix->ksub; c++) {
       const float *cc = ix->centroids + ((int64_t)s * ix->ksub + c) * dsub;
@@ -1021,6 +1102,11 @@ void orc_lut(const orc_index *ix, const float *y, double *lut) {
 }
 
 static double adc(const orc_index *ix, const double *lut, int32_t i) {
+  if (ix->coarse.k > 0) { /* ||y' - q(x_i)||^2, q = first level + residual PQ */
+    double rec[4096];
+    decode(ix->centroids, ix->codes, ix->code_stride, ix->m, ix->ksub, ix->d_pad / ix->m, &ix->coarse, i, rec);
+    return sqdist(lut, rec, ix->d_pad);
+  }
   double s = 0;
   for (int t = 0; t < ix->m; t++) s += lut[t * ix->ksub + ix->codes[(int64_t)i * ix->code_stride + t]];
   return s;
@@ -1037,7 +1123,7 @@ double orc_refined_distance(const orc_index *ix, const float *y, int32_t i) {
   for (int j = 0; j < p; j++) {
     int32_t g = j == 0 ? i : ix->adj0[(int64_t)i * ix->deg0 + (j - 1)];
     if (g < 0) continue; /* a missing link is a zero vector */
-    decode(ix->centroids, ix->codes, ix->code_stride, ix->m, ix->ksub, dsub, g, q);
+    decode(ix->centroids, ix->codes, ix->code_stride, ix->m, ix->ksub, dsub, &ix->coarse, g, q);
     for (int t = 0; t < dp; t++) {
       int jb = t / bw;
       const float *b = ix->beta + ((int64_t)jb * ix->n_beta + ix->beta_idx[(int64_t)i * mb + jb]) * p;

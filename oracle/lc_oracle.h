@@ -36,6 +36,16 @@
 extern "C" {
 #endif
 
+/* First level of the 2-level residual codec (Sec. 3.3 / Sec. 5.1): a product
+ * quantizer over the two halves of the (projected) vector, k centroids each;
+ * the PQ codes then encode the residual, so that
+ * q(x) = [C1[0][c0(x)], C1[1][c1(x)]] + PQ(residual).  k = 0: one-level codec. */
+typedef struct {
+  int32_t k;
+  const float *cent;     /* [2][k][d_pad/2] */
+  const uint16_t *codes; /* [n][2] */
+} orc_coarse;
+
 typedef struct {
   int32_t n, d, d_pad, m, ksub, code_stride;
   int32_t deg0, deg_up, k_reg, n_beta;
@@ -49,6 +59,7 @@ typedef struct {
   const int32_t *adj_up;
   const float *beta;
   const uint8_t *beta_idx;
+  orc_coarse coarse; /* k = 0: one-level codec */
 } orc_index;
 
 /* k-means (Lloyd) in float64, used for PQ (Sec. 3.3) and for initialising the
@@ -80,7 +91,7 @@ int orc_hnsw_build(const float *x, int64_t n, int d, const float *proj, int d_pa
                    int ksub, const float *cent, const uint8_t *codes, int code_stride,
                    const int8_t *level, int deg0, int deg_up, int ef_construction, int nthreads,
                    int32_t *adj0, int32_t *up_base, int32_t *adj_up, int32_t *entry,
-                   int32_t *max_level);
+                   int32_t *max_level, const orc_coarse *cq /* NULL: one-level codec */);
 
 /* Least squares (Sec. 4.2, Eq. 4): beta minimising ||x - G beta||^2 given
  * A = G^T G and c = G^T x; Cholesky, else eigen pseudo-inverse. */
@@ -94,21 +105,39 @@ int orc_beta_train(const float *x, const int64_t *ids, int64_t n_sub, int d, con
                    int d_pad, int m, int ksub, const float *cent, const uint8_t *codes,
                    int code_stride, const int32_t *adj0, int deg0, int k_reg, int n_beta, int m_beta,
                    const int64_t *init, int km_iters, int em_iters, int nthreads, float *beta,
-                   double *loss_hist);
+                   double *loss_hist, const orc_coarse *cq);
 
 /* Shared 0-byte regression weights (Sec. 4.2, Eq. 3-5) over the given ids. */
 int orc_beta_shared(const float *x, const int64_t *ids, int64_t n_sub, int d, const float *proj,
                     int d_pad, int m, int ksub, const float *cent, const uint8_t *codes,
-                    int code_stride, const int32_t *adj0, int deg0, int k_reg, double *beta);
+                    int code_stride, const int32_t *adj0, int deg0, int k_reg, double *beta,
+                    const orc_coarse *cq);
 
 /* Assignment (Sec. 4.3, Eq. 7) with the stored f32 codebook, lowest index on
  * ties, block by block; beta_idx receives [n][m_beta]. */
 int orc_beta_assign(const float *x, int64_t n, int d, const float *proj, int d_pad, int m,
                     int ksub, const float *cent, const uint8_t *codes, int code_stride,
                     const int32_t *adj0, int deg0, int k_reg, int n_beta, int m_beta, const float *beta,
-                    int nthreads, uint8_t *beta_idx);
+                    int nthreads, uint8_t *beta_idx, const orc_coarse *cq);
 
-/* Per-query ADC table LUT[s][c] = ||y'^s - C[s][c]||^2 in float64. */
+/* 2-level residual codec (Sec. 3.3 "residual" codecs; Sec. 5.1 "two-level
+ * encodings"): the first level is trained with orc_pq_train(m = 2, ksub = k).
+ * Encoding: per half, the nearest first-level centroid in float64 (lowest index
+ * on ties) into codes [n][2], and, when resid is not NULL, the residual
+ * P x - c rounded to f32 into resid [n][d_pad], which the second-level PQ
+ * (orc_pq_train / orc_pq_encode with proj NULL, d = d_pad) trains on and encodes. */
+int orc_coarse_encode(const float *x, int64_t n, int d, const float *proj, int d_pad, int k,
+                      const float *cent, int nthreads, uint16_t *codes, float *resid);
+
+/* Per-node term of the 2-level asymmetric distance: with c the first-level and
+ * r the second-level reconstruction, ||y - c - r||^2 = ||y - c||^2
+ * - 2 <y, r> + (||c + r||^2 - ||c||^2); norm[i] receives the last term, in
+ * float64 rounded to f32. */
+int orc_coarse_norms(const orc_index *ix, float *norm /*[n]*/);
+
+/* Per-query ADC table LUT[s][c] = ||y'^s - C[s][c]||^2 in float64.  For a
+ * 2-level codec the oracle takes the asymmetric distance by its definition,
+ * ||y' - q(x)||^2, and the "table" is y' itself (its first d_pad entries). */
 void orc_lut(const orc_index *ix, const float *y, double *lut /*[m][ksub]*/);
 
 /* Full search (Sec. 2 and Sec. 4.1): greedy descent on the upper levels,
