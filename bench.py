@@ -279,7 +279,7 @@ def bench_assign(args):
     t0 = time.perf_counter()
     rc = L.lcb_beta_assign(p_(np.ascontiguousarray(db[:ns])), ns, w.d, p_(ix.proj), w.d_pad, w.m, p_(ix.centroids),
                            p_(ix.codes), ix.codes.shape[1], p_(ix.adj0), w.deg0, w.k_reg, w.n_beta, w.m_beta,
-                           p_(np.ascontiguousarray(ix.beta, np.float32)), nt, p_(bidx))
+                           p_(np.ascontiguousarray(ix.beta, np.float32)), nt, p_(bidx), None)
     cpu_s = time.perf_counter() - t0
     assert rc == 0
     print(json.dumps({"form": "beta assignment (index build)", "workload": w.name, "n": ix.n, "m_beta": w.m_beta,

@@ -90,6 +90,16 @@ typedef struct {
   const int32_t *adj_up;
   const float *beta;
   const uint8_t *beta_idx;
+  /* 2-level residual codec (Sec. 3.3 residual codecs; Sec. 5.1 two-level
+   * encodings), or coarse_k = 0 for the one-level PQ codec.  A vector is
+   * q(x) = [C1[0][c0], C1[1][c1]] + PQ(codes): a first-level product
+   * quantizer over the two halves of the (projected) vector, coarse_k
+   * centroids each (coarse_k <= 65536, d_pad even), and the PQ codes encode
+   * the residual. */
+  int32_t coarse_k;
+  const float *coarse_cent;      /* [2][coarse_k][d_pad/2] */
+  const uint16_t *coarse_codes;  /* [n][2] (c0, c1), 4-byte aligned */
+  const float *coarse_norm;      /* [n] ||c + r||^2 - ||c||^2, the node's term of the distance */
 } lc_index_view;
 
 typedef struct lc_index lc_index;
@@ -103,6 +113,11 @@ typedef struct lc_index lc_index;
 int lc_index_bind(const lc_index_view *view, lc_index **out);
 void lc_index_release(lc_index *ix);
 
+/* Entries per query of a distance table: m * 256 for the one-level codec;
+ * for the 2-level codec m * 256 + 2 * coarse_k rounded up to a multiple of 64
+ * (table layout below).  0 for a NULL index. */
+int64_t lc_lut_stride(const lc_index *ix);
+
 /* Distance tables, Sec. 4.1 (asymmetric distances):
  *   LUT[q][s][c] = || (P y_q)^s - C[s][c] ||^2,  s < m, c < 256.
  * q:   f32 [nq][d] queries.
@@ -111,6 +126,13 @@ void lc_index_release(lc_index *ix);
  *      rounded to nearest, with lut_scale f32 [nq][m] a power of two per
  *      (query, sub-space) that maps the largest entry of the row to at most
  *      2^15 (precision form; lut_scale is NULL for F32).
+ * 2-level codec (coarse_k > 0; LC_LUT_F32 only, else LC_ENOTSUP): with
+ * z = P y_q, c the first-level and r the second-level reconstruction,
+ * ||z - c - r||^2 = ||z^0 - c^0||^2 + ||z^1 - c^1||^2 - 2 <z, r> + coarse_norm,
+ * so row q of lut (lc_lut_stride entries) holds [m][256] entries
+ * -2 <z^s, C[s][c]>, then [2][coarse_k] entries ||z^h - C1[h][c]||^2, then
+ * padding; lc_search adds a node's two first-level entries and its
+ * coarse_norm to the sum over its codes, and clamps the result at 0.
  * nq == 0 is a no-op. */
 int lc_build_lut(const lc_index *ix, const float *q, int64_t nq, int lut_dtype, void *lut,
                  float *lut_scale, void *stream);

@@ -32,6 +32,27 @@ int lcb_pq_train(const float *train, int64_t n, int d, const float *proj, int d_
 int lcb_pq_encode(const float *x, int64_t n, int d, const float *proj, int d_pad, int m,
                   const float *centroids, int nthreads, uint8_t *codes, int code_stride);
 
+/* 2-level residual codec (Sec. 3.3 residual codecs; Sec. 5.1 two-level
+ * encodings): a first-level product quantizer over the two halves of the
+ * (projected) vector, k centroids each (k <= 65536; PQ2 x log2 k), whose
+ * residual the PQ of lcb_pq_train / lcb_pq_encode then encodes (called with
+ * proj NULL and d = d_pad on the residuals).
+ * lcb_coarse_train: per-half k-means seeded by init [2][k] -> cent f32 [2][k][d_pad/2].
+ * lcb_coarse_encode: nearest centroid per half (lowest index on ties) ->
+ * codes u16 [n][2], and the residuals P x - c -> resid f32 [n][d_pad].
+ * lcb_coarse_decode: the reconstructions q(x) = c + r -> rec f32 [n][d_pad]
+ * (either output may be NULL), and the per-node term of the decomposed
+ * asymmetric distance, ||c + r||^2 - ||c||^2 -> norm f32 [n].
+ * The graph build and the regression codebook take rec (their last argument)
+ * in place of the PQ decoding; NULL there means the one-level codec. */
+int lcb_coarse_train(const float *train, int64_t n, int d, const float *proj, int d_pad, int k,
+                     const int64_t *init, int iters, int nthreads, float *cent);
+int lcb_coarse_encode(const float *x, int64_t n, int d, const float *proj, int d_pad, int k,
+                      const float *cent, int nthreads, uint16_t *codes, float *resid);
+int lcb_coarse_decode(int64_t n, int d_pad, int m, const float *centroids, const uint8_t *codes,
+                      int code_stride, int k, const float *cent, const uint16_t *ccodes, int nthreads,
+                      float *rec, float *norm);
+
 /* Node levels (Sec. 2 geometric layers, Sec. 4.1 ratio between levels):
  * level_i = min(cap, floor(-ln(u_i) / ln(ratio))).  Returns sum_i level_i,
  * the number of upper-level rows. */
@@ -50,7 +71,7 @@ int lcb_graph_build(const float *x, int64_t n, int d, const float *proj, int d_p
                     const float *centroids, const uint8_t *codes, int code_stride,
                     const int8_t *level, int deg0, int deg_up, int ef_construction, int nthreads,
                     int32_t *adj0, int32_t *up_base, int32_t *adj_up, int32_t *entry,
-                    int32_t *max_level);
+                    int32_t *max_level, const float *rec);
 
 /* Regression codebook (Sec. 4.3, Eq. 6-8) in float64 on the training ids:
  * per-vector least squares initialises a k-means (km_iters), then em_iters
@@ -63,14 +84,15 @@ int lcb_graph_build(const float *x, int64_t n, int d, const float *proj, int d_p
 int lcb_beta_train(const float *x, const int64_t *ids, int64_t n_sub, int d, const float *proj,
                    int d_pad, int m, const float *centroids, const uint8_t *codes, int code_stride,
                    const int32_t *adj0, int deg0, int k_reg, int n_beta, int m_beta, const int64_t *init,
-                   int km_iters, int em_iters, int nthreads, float *beta, double *loss_hist);
+                   int km_iters, int em_iters, int nthreads, float *beta, double *loss_hist,
+                   const float *rec);
 
 /* Codebook entry of every vector and block (Sec. 4.3, Eq. 7 per block) with
  * the f32 codebooks: beta_idx u8 [n][m_beta]. */
 int lcb_beta_assign(const float *x, int64_t n, int d, const float *proj, int d_pad, int m,
                     const float *centroids, const uint8_t *codes, int code_stride,
                     const int32_t *adj0, int deg0, int k_reg, int n_beta, int m_beta, const float *beta,
-                    int nthreads, uint8_t *beta_idx);
+                    int nthreads, uint8_t *beta_idx, const float *rec);
 
 /* Learned rotation ahead of the product quantizer (OPQ: the codec of Sec. 4.1
  * and Sec. 5.1 rotates the vectors before PQ).  Starting from init_proj

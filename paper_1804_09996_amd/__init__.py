@@ -41,7 +41,9 @@ class IndexView(C.Structure):
                                           "n_beta", "entry", "max_level", "m_beta")] + \
                [("n_up_rows", C.c_int64)] + \
                [(n, C.c_void_p) for n in ("proj", "centroids", "codes", "adj0", "up_base", "adj_up", "beta",
-                                          "beta_idx")]
+                                          "beta_idx")] + \
+               [("coarse_k", C.c_int32)] + \
+               [(n, C.c_void_p) for n in ("coarse_cent", "coarse_codes", "coarse_norm")]
 
 
 class Schedule(C.Structure):
@@ -97,6 +99,8 @@ def lib():
         L.lc_project_queries.argtypes = [p, p, i64, p, p]
         L.lc_build_lut_projected.argtypes = [p, p, i64, C.c_int, p, p, p]
         L.lc_refine_projected.argtypes = [p, p, i64, p, p, i32, i32, C.c_int, p, p, p]
+        L.lc_lut_stride.argtypes = [p]
+        L.lc_lut_stride.restype = i64
         _lib = L
     return _lib
 
@@ -104,7 +108,7 @@ def lib():
 def exported_symbols():
     return ["lc_build_id", "lc_strerror", "lc_index_bind", "lc_index_release", "lc_build_lut", "lc_search_workspace_bytes",
             "lc_search", "lc_refine", "lc_search_workspace_bytes_sched", "lc_search_sched", "lc_search_budget",
-            "lc_assign_beta", "lc_project_queries", "lc_build_lut_projected", "lc_refine_projected"]
+            "lc_assign_beta", "lc_project_queries", "lc_build_lut_projected", "lc_refine_projected", "lc_lut_stride"]
 
 
 def _check(rc: int, where: str):
@@ -136,6 +140,8 @@ class Index:
     ``proj``); ``meta`` the scalars ``d, d_pad, m, deg0, deg_up, k_reg,
     entry, max_level``.  ``beta`` is [n_beta, k+1] (one codebook) or
     [m_beta, n_beta, k+1] (product codebook), ``beta_idx`` [n] or [n, m_beta].
+    A 2-level codec adds ``coarse_cent`` [2, k, d_pad/2], ``coarse_codes``
+    [n, 2] (uint16) and ``coarse_norm`` [n].
     """
 
     def __init__(self, arrays: dict, meta: dict, device: Union[str, int] = "cuda"):
@@ -158,7 +164,22 @@ class Index:
             "proj": up("proj", np.float32), "centroids": up("centroids", np.float32),
             "codes": up("codes", np.uint8), "adj0": up("adj0", np.int32), "up_base": up("up_base", np.int32),
             "adj_up": up("adj_up", np.int32), "beta": up("beta", np.float32), "beta_idx": up("beta_idx", np.uint8),
+            "coarse_cent": up("coarse_cent", np.float32), "coarse_norm": up("coarse_norm", np.float32),
         }
+        cc = arrays.get("coarse_codes")
+        if cc is not None:
+            # (c0, c1) pairs of uint16 travel as one 32-bit word per vector
+            cc = np.ascontiguousarray(cc, np.uint16)
+            if cc.ndim != 2 or cc.shape != (arrays["codes"].shape[0], 2):
+                raise ValueError(f"coarse_codes has shape {cc.shape}, expected [n, 2]")
+            self.t["coarse_codes"] = torch.from_numpy(cc.view(np.int32).reshape(-1).copy()).to(self.device)
+        else:
+            self.t["coarse_codes"] = None
+        ccent = arrays.get("coarse_cent")
+        if ccent is not None and (ccent.ndim != 3 or ccent.shape[0] != 2 or ccent.shape[2] * 2 != meta["d_pad"]
+                                  or arrays.get("coarse_norm") is None or cc is None
+                                  or np.asarray(arrays["coarse_norm"]).size != arrays["codes"].shape[0]):
+            raise ValueError("coarse_cent [2, k, d_pad/2], coarse_codes [n, 2] and coarse_norm [n] go together")
         codes = arrays["codes"]
         beta, bidx = np.asarray(arrays["beta"]), np.asarray(arrays["beta_idx"])
         m_beta = beta.shape[0] if beta.ndim == 3 else 1
@@ -178,6 +199,9 @@ class Index:
         v.n_up_rows = 0 if au is None else au.shape[0]
         for name in ("proj", "centroids", "codes", "adj0", "up_base", "adj_up", "beta", "beta_idx"):
             setattr(v, name, _ptr(self.t[name]))
+        v.coarse_k = 0 if ccent is None else ccent.shape[1]
+        for name in ("coarse_cent", "coarse_codes", "coarse_norm"):
+            setattr(v, name, _ptr(self.t[name]))
         self.view = v
         h = C.c_void_p()
         with torch.cuda.device(self.device):
@@ -185,6 +209,8 @@ class Index:
         self.handle = h
         self.n, self.m, self.d, self.d_pad = v.n, v.m, v.d, v.d_pad
         self.k_reg = v.k_reg
+        self.coarse_k = v.coarse_k
+        self.lut_stride = int(L.lc_lut_stride(h))
         self._ws = None
 
     @classmethod
@@ -192,6 +218,9 @@ class Index:
         """From any object with the index attributes (e.g. a built index)."""
         arrays = {k: getattr(ix, k) for k in ("proj", "centroids", "codes", "adj0", "up_base", "adj_up", "beta",
                                               "beta_idx")}
+        for k in ("coarse_cent", "coarse_codes", "coarse_norm"):
+            if getattr(ix, k, None) is not None:
+                arrays[k] = getattr(ix, k)
         meta = {k: int(getattr(ix, k)) for k in ("d", "d_pad", "m", "deg0", "deg_up", "k_reg", "entry",
                                                  "max_level")}
         return cls(arrays, meta, device)
@@ -227,7 +256,8 @@ class Index:
         q = q.to(self.device, torch.float32).contiguous()
         nq = q.shape[0]
         if lut_dtype == LC_LUT_F32:
-            lut = torch.empty((nq, self.m, 256), dtype=torch.float32, device=self.device)
+            shape = (nq, self.lut_stride) if self.coarse_k else (nq, self.m, 256)
+            lut = torch.empty(shape, dtype=torch.float32, device=self.device)
             scale = None
         else:
             lut = torch.empty((nq, self.m, 256), dtype=torch.float16, device=self.device)

@@ -32,9 +32,12 @@ def lib():
         L.lcb_pq_encode.argtypes = [p, i64, i, p, i, i, p, i, p, i]
         L.lcb_levels.argtypes = [p, i64, i, i, p]
         L.lcb_levels.restype = i64
-        L.lcb_graph_build.argtypes = [p, i64, i, p, i, i, p, p, i, p, i, i, i, i, p, p, p, p, p]
-        L.lcb_beta_train.argtypes = [p, p, i64, i, p, i, i, p, p, i, p, i, i, i, i, p, i, i, i, p, p]
-        L.lcb_beta_assign.argtypes = [p, i64, i, p, i, i, p, p, i, p, i, i, i, i, p, i, p]
+        L.lcb_graph_build.argtypes = [p, i64, i, p, i, i, p, p, i, p, i, i, i, i, p, p, p, p, p, p]
+        L.lcb_beta_train.argtypes = [p, p, i64, i, p, i, i, p, p, i, p, i, i, i, i, p, i, i, i, p, p, p]
+        L.lcb_beta_assign.argtypes = [p, i64, i, p, i, i, p, p, i, p, i, i, i, i, p, i, p, p]
+        L.lcb_coarse_train.argtypes = [p, i64, i, p, i, i, p, i, i, p]
+        L.lcb_coarse_encode.argtypes = [p, i64, i, p, i, i, p, i, p, p]
+        L.lcb_coarse_decode.argtypes = [i64, i, i, p, p, i, i, p, p, i, p, p]
         L.lcb_opq_train.argtypes = [p, i64, i, i, i, p, p, i, i, i, p, p]
         L.lcb_procrustes.argtypes = [p, i, i, p]
         _lib = L
@@ -87,6 +90,10 @@ class BuiltIndex:
     beta: np.ndarray
     beta_idx: np.ndarray
     m_beta: int = 1  # product codebook blocks: beta [m_beta, n_beta, k+1], beta_idx [n, m_beta]
+    # 2-level residual codec: first-level centroids [2, k, d_pad/2], codes [n, 2] u16, per-node term [n]
+    coarse_cent: Optional[np.ndarray] = None
+    coarse_codes: Optional[np.ndarray] = None
+    coarse_norm: Optional[np.ndarray] = None
 
     def save(self, path: str):
         arrays = {f.name: getattr(self, f.name) for f in fields(self) if isinstance(getattr(self, f.name), np.ndarray)}
@@ -124,11 +131,37 @@ def build_index(w, db, train, proj, level_u, pq_init, beta_ids, beta_init, nthre
         if log:
             log(f"index build: rotation learned, PQ distortion {hist[0]:.5f} -> {hist[-1]:.5f}")
     cent = np.empty((w.m, 256, w.d_pad // w.m), np.float32)
-    _ok(L.lcb_pq_train(_p(train), train.shape[0], d, _p(proj), w.d_pad, w.m, _p(_c(pq_init, np.int64)), w.pq_iters,
-                       nt, _p(cent)), "lcb_pq_train")
     cs = code_stride_for(w.m)
     codes = np.empty((n, cs), np.uint8)
-    _ok(L.lcb_pq_encode(_p(db), n, d, _p(proj), w.d_pad, w.m, _p(cent), nt, _p(codes), cs), "lcb_pq_encode")
+    ck = getattr(w, "coarse_k", 0)
+    ccent = ccodes = cnorm = rec = None
+    if ck:
+        # 2-level residual codec: first level over the two halves, then the PQ of the residual
+        import datagen
+        ccent = np.empty((2, ck, w.d_pad // 2), np.float32)
+        _ok(L.lcb_coarse_train(_p(train), train.shape[0], d, _p(proj), w.d_pad, ck,
+                               _p(_c(datagen.coarse_init_ids(w, train.shape[0]), np.int64)), w.pq_iters, nt,
+                               _p(ccent)), "lcb_coarse_train")
+        tcodes = np.empty((train.shape[0], 2), np.uint16)
+        rtrain = np.empty((train.shape[0], w.d_pad), np.float32)
+        _ok(L.lcb_coarse_encode(_p(train), train.shape[0], d, _p(proj), w.d_pad, ck, _p(ccent), nt, _p(tcodes),
+                                _p(rtrain)), "lcb_coarse_encode")
+        ccodes = np.empty((n, 2), np.uint16)
+        rdb = np.empty((n, w.d_pad), np.float32)
+        _ok(L.lcb_coarse_encode(_p(db), n, d, _p(proj), w.d_pad, ck, _p(ccent), nt, _p(ccodes), _p(rdb)),
+            "lcb_coarse_encode")
+        _ok(L.lcb_pq_train(_p(rtrain), rtrain.shape[0], w.d_pad, None, w.d_pad, w.m, _p(_c(pq_init, np.int64)),
+                           w.pq_iters, nt, _p(cent)), "lcb_pq_train")
+        _ok(L.lcb_pq_encode(_p(rdb), n, w.d_pad, None, w.d_pad, w.m, _p(cent), nt, _p(codes), cs), "lcb_pq_encode")
+        del rdb, rtrain
+        rec = np.empty((n, w.d_pad), np.float32)
+        cnorm = np.empty(n, np.float32)
+        _ok(L.lcb_coarse_decode(n, w.d_pad, w.m, _p(cent), _p(codes), cs, ck, _p(ccent), _p(ccodes), nt, _p(rec),
+                                _p(cnorm)), "lcb_coarse_decode")
+    else:
+        _ok(L.lcb_pq_train(_p(train), train.shape[0], d, _p(proj), w.d_pad, w.m, _p(_c(pq_init, np.int64)),
+                           w.pq_iters, nt, _p(cent)), "lcb_pq_train")
+        _ok(L.lcb_pq_encode(_p(db), n, d, _p(proj), w.d_pad, w.m, _p(cent), nt, _p(codes), cs), "lcb_pq_encode")
     t1 = time.time()
     if log:
         log(f"index build: product quantizer done ({t1 - t0:.1f}s)")
@@ -140,7 +173,7 @@ def build_index(w, db, train, proj, level_u, pq_init, beta_ids, beta_init, nthre
     entry, maxl = C.c_int32(), C.c_int32()
     _ok(L.lcb_graph_build(_p(db), n, d, _p(proj), w.d_pad, w.m, _p(cent), _p(codes), cs, _p(level), w.deg0,
                           w.deg_up, w.ef_construction, nt, _p(adj0), _p(up_base), _p(adj_up), C.byref(entry),
-                          C.byref(maxl)), "lcb_graph_build")
+                          C.byref(maxl), _p(rec)), "lcb_graph_build")
     adj_up = adj_up[:rows]
     t2 = time.time()
     if log:
@@ -150,16 +183,17 @@ def build_index(w, db, train, proj, level_u, pq_init, beta_ids, beta_init, nthre
     bids = _c(beta_ids, np.int64)
     _ok(L.lcb_beta_train(_p(db), _p(bids), bids.shape[0], d, _p(proj), w.d_pad, w.m, _p(cent), _p(codes), cs,
                          _p(adj0), w.deg0, w.k_reg, w.n_beta, mb, _p(_c(beta_init, np.int64)), w.beta_kmeans_iters,
-                         w.em_iters, nt, _p(beta), None), "lcb_beta_train")
+                         w.em_iters, nt, _p(beta), None, _p(rec)), "lcb_beta_train")
     bidx = np.empty(n if mb == 1 else (n, mb), np.uint8)
     _ok(L.lcb_beta_assign(_p(db), n, d, _p(proj), w.d_pad, w.m, _p(cent), _p(codes), cs, _p(adj0), w.deg0, w.k_reg,
-                          w.n_beta, mb, _p(beta), nt, _p(bidx)), "lcb_beta_assign")
+                          w.n_beta, mb, _p(beta), nt, _p(bidx), _p(rec)), "lcb_beta_assign")
     t3 = time.time()
     if log:
         log(f"index build: pq {t1 - t0:.1f}s graph {t2 - t1:.1f}s beta {t3 - t2:.1f}s ({nt} threads)")
     return BuiltIndex(n=n, d=d, d_pad=w.d_pad, m=w.m, deg0=w.deg0, deg_up=w.deg_up, k_reg=w.k_reg, n_beta=w.n_beta,
                       entry=int(entry.value), max_level=int(maxl.value), proj=proj, centroids=cent, codes=codes,
-                      adj0=adj0, level=level, up_base=up_base, adj_up=adj_up, beta=beta, beta_idx=bidx, m_beta=mb)
+                      adj0=adj0, level=level, up_base=up_base, adj_up=adj_up, beta=beta, beta_idx=bidx, m_beta=mb,
+                      coarse_cent=ccent, coarse_codes=ccodes, coarse_norm=cnorm)
 
 
 def build_workload(w, nthreads: Optional[int] = None, cache_dir: Optional[str] = None, log=None):

@@ -31,11 +31,16 @@ struct AssignArgs {
   const uint8_t *codes;
   const int32_t *adj0;
   uint8_t *out;  // [count][m_beta]
+  const float *ccent;        // 2-level codec: first-level centroids [2][coarse_k][d_pad/2], or null
+  const uint32_t *ccodes;    // (c0 | c1 << 16)
+  int coarse_k;
 };
 
-// LDS per wave: G float32 [p][d_pad], x' float64 [d_pad], G^T G [p][p], G^T x [p], ||x'||^2
-__host__ __device__ inline size_t wave_lds_bytes(int p, int d_pad) {
-  return (size_t(p) * d_pad * 4 + 7) / 8 * 8 + size_t(d_pad) * 8 + (size_t(p) * p + p + 1) * 8;
+// LDS per wave: G [p][d_pad] (float32: the centroids' own values; float64 for
+// the 2-level codec, whose rows are sums of two centroids), x' float64
+// [d_pad], G^T G [p][p], G^T x [p], ||x'||^2
+__host__ __device__ inline size_t wave_lds_bytes(int p, int d_pad, int gbytes) {
+  return (size_t(p) * d_pad * gbytes + 7) / 8 * 8 + size_t(d_pad) * 8 + (size_t(p) * p + p + 1) * 8;
 }
 
 // ||x||^2 - 2 beta^T c + beta^T A beta for one codebook entry, in the order of
@@ -72,14 +77,14 @@ __device__ __forceinline__ double entry_loss(const float *be, int p, const doubl
   return l;
 }
 
-template <int P>
+template <int P, typename GT>
 __global__ __launch_bounds__(512) void beta_assign_kernel(AssignArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int p = P > 0 ? P : a.k_reg + 1, dp = a.d_pad;
-  unsigned char *base = smem + size_t(wave) * wave_lds_bytes(p, dp);
-  float *G = reinterpret_cast<float *>(base);
-  double *xv = reinterpret_cast<double *>(base + (size_t(p) * dp * 4 + 7) / 8 * 8);
+  unsigned char *base = smem + size_t(wave) * wave_lds_bytes(p, dp, int(sizeof(GT)));
+  GT *G = reinterpret_cast<GT *>(base);
+  double *xv = reinterpret_cast<double *>(base + (size_t(p) * dp * sizeof(GT) + 7) / 8 * 8);
   double *A = xv + dp;
   double *Cv = A + p * p;
   double *XX = Cv + p;
@@ -102,12 +107,19 @@ __global__ __launch_bounds__(512) void beta_assign_kernel(AssignArgs a) {
     for (int e = lane; e < p * a.m; e += 64) {
       const int j = e / a.m, s = e % a.m;
       const int32_t src = j == 0 ? int32_t(i) : a.adj0[i * a.deg0 + (j - 1)];
-      float *dst = G + j * dp + s * a.dsub;
+      GT *dst = G + j * dp + s * a.dsub;
       if (src < 0 || src >= a.n) {
-        for (int t = 0; t < a.dsub; ++t) dst[t] = 0.f;  // a missing link is a zero vector
+        for (int t = 0; t < a.dsub; ++t) dst[t] = GT(0);  // a missing link is a zero vector
       } else {
         const float *c = a.cent + (int64_t(s) * 256 + a.codes[int64_t(src) * a.code_stride + s]) * a.dsub;
-        for (int t = 0; t < a.dsub; ++t) dst[t] = c[t];
+        for (int t = 0; t < a.dsub; ++t) dst[t] = GT(c[t]);
+        if (a.ccent) {  // 2-level codec: plus the first-level centroid's part, summed in float64
+          const int half = s >= a.m / 2;
+          const uint32_t cc = a.ccodes[src];
+          const float *c1 = a.ccent + (int64_t(half) * a.coarse_k + (half ? cc >> 16 : cc & 0xFFFFu)) * (dp / 2) +
+                            (s - half * (a.m / 2)) * a.dsub;
+          for (int t = 0; t < a.dsub; ++t) dst[t] = GT(double(dst[t]) + double(c1[t]));
+        }
       }
     }
     wave_sync();
@@ -117,11 +129,11 @@ __global__ __launch_bounds__(512) void beta_assign_kernel(AssignArgs a) {
       for (int e = lane; e < p * p + p + 1; e += 64) {
         double s = 0.0;
         if (e < p * p) {
-          const float *ga = G + (e / p) * dp, *gb = G + (e % p) * dp;
+          const GT *ga = G + (e / p) * dp, *gb = G + (e % p) * dp;
           for (int t = t0; t < t1; ++t) s += double(ga[t]) * double(gb[t]);
           A[e] = s;
         } else if (e < p * p + p) {
-          const float *ga = G + (e - p * p) * dp;
+          const GT *ga = G + (e - p * p) * dp;
           for (int t = t0; t < t1; ++t) s += double(ga[t]) * xv[t];
           Cv[e - p * p] = s;
         } else {
@@ -157,12 +169,12 @@ __global__ __launch_bounds__(512) void beta_assign_kernel(AssignArgs a) {
   }
 }
 
-template <int P>
+template <int P, typename GT>
 int launch_p(const AssignArgs &a, int64_t blocks, size_t lds, hipStream_t st) {
-  if (hipFuncSetAttribute(reinterpret_cast<const void *>(&beta_assign_kernel<P>),
+  if (hipFuncSetAttribute(reinterpret_cast<const void *>(&beta_assign_kernel<P, GT>),
                           hipFuncAttributeMaxDynamicSharedMemorySize, int(lds)) != hipSuccess)
     return LC_EHIP;
-  hipLaunchKernelGGL((beta_assign_kernel<P>), dim3(int(blocks)), dim3(64 * a.wpb), lds, st, a);
+  hipLaunchKernelGGL((beta_assign_kernel<P, GT>), dim3(int(blocks)), dim3(64 * a.wpb), lds, st, a);
   return hipGetLastError() == hipSuccess ? LC_OK : LC_EHIP;
 }
 
@@ -190,7 +202,11 @@ int lc_launch_assign(const lc_index *ix, const float *x, int64_t n0, int64_t cou
   a.codes = v.codes;
   a.adj0 = v.adj0;
   a.out = out;
-  const size_t per_wave = wave_lds_bytes(v.k_reg + 1, v.d_pad);
+  a.ccent = v.coarse_k > 0 ? v.coarse_cent : nullptr;
+  a.ccodes = reinterpret_cast<const uint32_t *>(v.coarse_codes);
+  a.coarse_k = v.coarse_k;
+  const bool two = a.ccent != nullptr;
+  const size_t per_wave = wave_lds_bytes(v.k_reg + 1, v.d_pad, two ? 8 : 4);
   int wpb = int(size_t(ix->lds_per_cu) / per_wave);
   if (wpb > 8) wpb = 8;
   if (wpb < 1) return LC_ENOTSUP;
@@ -199,8 +215,9 @@ int lc_launch_assign(const lc_index *ix, const float *x, int64_t n0, int64_t cou
   int64_t blocks = (count + wpb - 1) / wpb;
   if (blocks > int64_t(ix->num_cus) * 4) blocks = int64_t(ix->num_cus) * 4;
   const int p = v.k_reg + 1;
-  return p == 9    ? launch_p<9>(a, blocks, lds, st)
-         : p == 17 ? launch_p<17>(a, blocks, lds, st)
-         : p == 33 ? launch_p<33>(a, blocks, lds, st)
-                   : launch_p<0>(a, blocks, lds, st);
+  if (two) return launch_p<0, double>(a, blocks, lds, st);
+  return p == 9    ? launch_p<9, float>(a, blocks, lds, st)
+         : p == 17 ? launch_p<17, float>(a, blocks, lds, st)
+         : p == 33 ? launch_p<33, float>(a, blocks, lds, st)
+                   : launch_p<0, float>(a, blocks, lds, st);
 }

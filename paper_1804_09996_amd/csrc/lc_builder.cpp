@@ -70,7 +70,8 @@ void parallel_for(int64_t n, int nthreads, const std::function<void(int64_t, int
 struct Space {
   int d, d_pad, m, dsub;
   const float *proj;
-  const float *cent;  // [m][256][dsub]
+  const float *cent;           // [m][256][dsub]
+  const float *rec = nullptr;  // [n][d_pad] reconstructions of a 2-level codec, else decoded from the codes
   void project(const float *x, float *out) const {
     if (!proj) {
       std::memcpy(out, x, sizeof(float) * d);
@@ -83,8 +84,12 @@ struct Space {
       out[r] = float(s);
     }
   }
-  // table[s][c] = ||v^s - C[s][c]||^2
+  // table[s][c] = ||v^s - C[s][c]||^2; with reconstructions given, v itself
   void table(const float *v, float *tab) const {
+    if (rec) {
+      std::memcpy(tab, v, sizeof(float) * d_pad);
+      return;
+    }
     for (int s = 0; s < m; ++s) {
       const float *vs = v + s * dsub;
       const float *cs = cent + int64_t(s) * 256 * dsub;
@@ -266,19 +271,30 @@ struct Builder {
   int32_t *row(int l, int32_t i) const {
     return l == 0 ? adj0 + int64_t(i) * deg0 : adj_up + (int64_t(up_base[i]) + l - 1) * deg_up;
   }
+  static float dist2(const float *a, const float *b, int n) {
+    float s = 0;
+    for (int u = 0; u < n; ++u) {
+      float df = a[u] - b[u];
+      s += df * df;
+    }
+    return s;
+  }
   float adc(const float *tab, int32_t i) const {
+    if (sp.rec) return dist2(tab, sp.rec + int64_t(i) * sp.d_pad, sp.d_pad);
     const uint8_t *c = codes + int64_t(i) * cs;
     float s = 0;
     for (int t = 0; t < sp.m; ++t) s += tab[t * 256 + c[t]];
     return s;
   }
   float rec_rec(int32_t a, int32_t b) const {
+    if (sp.rec) return dist2(sp.rec + int64_t(a) * sp.d_pad, sp.rec + int64_t(b) * sp.d_pad, sp.d_pad);
     const uint8_t *ca = codes + int64_t(a) * cs, *cb = codes + int64_t(b) * cs;
     float s = 0;
     for (int t = 0; t < sp.m; ++t) s += sdc[(size_t(t) * 256 + ca[t]) * 256 + cb[t]];
     return s;
   }
   float raw_rec(const float *v, int32_t j) const {
+    if (sp.rec) return dist2(v, sp.rec + int64_t(j) * sp.d_pad, sp.d_pad);
     const uint8_t *c = codes + int64_t(j) * cs;
     float s = 0;
     for (int t = 0; t < sp.m; ++t) {
@@ -423,6 +439,77 @@ int lcb_pq_encode(const float *x, int64_t n, int d, const float *proj, int d_pad
   return 0;
 }
 
+int lcb_coarse_train(const float *train, int64_t n, int d, const float *proj, int d_pad, int k, const int64_t *init,
+                     int iters, int nthreads, float *cent) {
+  if (k < 1 || k > 65536 || n < k || d_pad % 2 || d_pad < d || d_pad > 1024) return -1;
+  const int h = d_pad / 2;
+  Space sp{d, d_pad, 2, h, proj, nullptr};
+  std::vector<float> xp(size_t(n) * d_pad), sub(size_t(n) * h);
+  parallel_for(n, nthreads, [&](int64_t i, int) { sp.project(train + i * d, xp.data() + i * d_pad); }, 4096);
+  for (int half = 0; half < 2; ++half) {
+    for (int64_t i = 0; i < n; ++i)
+      for (int t = 0; t < h; ++t) sub[size_t(i) * h + t] = xp[size_t(i) * d_pad + half * h + t];
+    kmeans_f32(sub.data(), n, h, k, init + int64_t(half) * k, iters, nthreads, cent + int64_t(half) * k * h);
+  }
+  return 0;
+}
+
+int lcb_coarse_encode(const float *x, int64_t n, int d, const float *proj, int d_pad, int k, const float *cent,
+                      int nthreads, uint16_t *codes, float *resid) {
+  if (k < 1 || k > 65536 || d_pad % 2 || d_pad < d || d_pad > 1024) return -1;
+  const int h = d_pad / 2;
+  Space sp{d, d_pad, 2, h, proj, nullptr};
+  parallel_for(
+      n, nthreads,
+      [&](int64_t i, int) {
+        float v[1024];
+        sp.project(x + i * d, v);
+        for (int half = 0; half < 2; ++half) {
+          const float *ch = cent + int64_t(half) * k * h;
+          float best = FLT_MAX;
+          int bj = 0;
+          for (int j = 0; j < k; ++j) {
+            float e = 0;
+            for (int t = 0; t < h; ++t) {
+              float df = v[half * h + t] - ch[int64_t(j) * h + t];
+              e += df * df;
+            }
+            if (e < best) {
+              best = e;
+              bj = j;
+            }
+          }
+          codes[i * 2 + half] = uint16_t(bj);
+          for (int t = 0; t < h; ++t) resid[i * d_pad + half * h + t] = v[half * h + t] - ch[int64_t(bj) * h + t];
+        }
+      },
+      256);
+  return 0;
+}
+
+int lcb_coarse_decode(int64_t n, int d_pad, int m, const float *centroids, const uint8_t *codes, int code_stride,
+                      int k, const float *cent, const uint16_t *ccodes, int nthreads, float *rec, float *norm) {
+  if (m < 1 || d_pad % m || d_pad % 2 || k < 1 || code_stride < m) return -1;
+  const int h = d_pad / 2, dsub = d_pad / m;
+  parallel_for(
+      n, nthreads,
+      [&](int64_t i, int) {
+        double cc = 0, qq = 0;
+        for (int t = 0; t < d_pad; ++t) {
+          const int half = t / h, s = t / dsub;
+          const float c = cent[(int64_t(half) * k + ccodes[i * 2 + half]) * h + (t - half * h)];
+          const float r = centroids[(int64_t(s) * 256 + codes[i * code_stride + s]) * dsub + (t - s * dsub)];
+          const double q = double(c) + double(r);
+          if (rec) rec[i * d_pad + t] = float(q);
+          cc += double(c) * c;
+          qq += q * q;
+        }
+        if (norm) norm[i] = float(qq - cc);
+      },
+      4096);
+  return 0;
+}
+
 int64_t lcb_levels(const double *u, int64_t n, int ratio, int cap, int8_t *level) {
   int64_t rows = 0;
   const double lr = std::log(double(ratio));
@@ -439,13 +526,13 @@ int64_t lcb_levels(const double *u, int64_t n, int ratio, int cap, int8_t *level
 int lcb_graph_build(const float *x, int64_t n, int d, const float *proj, int d_pad, int m,
                     const float *centroids, const uint8_t *codes, int code_stride, const int8_t *level,
                     int deg0, int deg_up, int ef_construction, int nthreads, int32_t *adj0, int32_t *up_base,
-                    int32_t *adj_up, int32_t *entry, int32_t *max_level) {
+                    int32_t *adj_up, int32_t *entry, int32_t *max_level, const float *rec) {
   if (n < 1 || m < 1 || d_pad % m || deg0 < 1 || deg0 > 64 || deg_up < 1 || deg_up > 64 || ef_construction < 1)
     return -1;
   if (nthreads < 1) nthreads = 1;
   Builder B;
   B.n = n;
-  B.sp = Space{d, d_pad, m, d_pad / m, proj, centroids};
+  B.sp = Space{d, d_pad, m, d_pad / m, proj, centroids, rec};
   B.codes = codes;
   B.cs = code_stride;
   B.level = level;
@@ -464,8 +551,8 @@ int lcb_graph_build(const float *x, int64_t n, int d, const float *proj, int d_p
     B.xp = x;
   }
   const int dsub = B.sp.dsub;
-  B.sdc.resize(size_t(m) * 256 * 256);
-  parallel_for(m * 256, nthreads, [&](int64_t sa, int) {
+  if (!rec) B.sdc.resize(size_t(m) * 256 * 256);
+  if (!rec) parallel_for(m * 256, nthreads, [&](int64_t sa, int) {
     const int s = int(sa / 256), a = int(sa % 256);
     const float *ca = centroids + (int64_t(s) * 256 + a) * dsub;
     for (int b = 0; b < 256; ++b) {
@@ -621,6 +708,10 @@ void build_grams(const float *x, const int64_t *ids, int64_t n_sub, const Space 
         for (int j = 0; j < p; ++j) {
           const int64_t src = j == 0 ? i : adj0[i * deg0 + (j - 1)];
           if (src < 0) continue;
+          if (sp.rec) {
+            for (int t = t0; t < t1; ++t) G[size_t(j) * dp + t] = sp.rec[src * dp + t];
+            continue;
+          }
           const uint8_t *c = codes + src * cs;
           for (int s = t0 / sp.dsub; s < t1 / sp.dsub; ++s) {
             const float *cr = sp.cent + (int64_t(s) * 256 + c[s]) * sp.dsub;
@@ -763,10 +854,10 @@ extern "C" {
 int lcb_beta_train(const float *x, const int64_t *ids, int64_t n_sub, int d, const float *proj, int d_pad, int m,
                    const float *centroids, const uint8_t *codes, int code_stride, const int32_t *adj0, int deg0,
                    int k_reg, int n_beta, int m_beta, const int64_t *init, int km_iters, int em_iters, int nthreads,
-                   float *beta, double *loss_hist) {
+                   float *beta, double *loss_hist, const float *rec) {
   if (k_reg < 1 || k_reg > deg0 || n_beta < 1 || n_beta > n_sub || d_pad % m || m_beta < 1 || m % m_beta)
     return -1;
-  Space sp{d, d_pad, m, d_pad / m, proj, centroids};
+  Space sp{d, d_pad, m, d_pad / m, proj, centroids, rec};
   const int p = k_reg + 1, bw = d_pad / m_beta;
   // product codebook (Eq. 9): block jb covers coordinates [jb bw, jb bw + bw), m / m_beta whole sub-spaces
   for (int jb = 0; jb < m_beta; ++jb) {
@@ -780,9 +871,9 @@ int lcb_beta_train(const float *x, const int64_t *ids, int64_t n_sub, int d, con
 
 int lcb_beta_assign(const float *x, int64_t n, int d, const float *proj, int d_pad, int m, const float *centroids,
                     const uint8_t *codes, int code_stride, const int32_t *adj0, int deg0, int k_reg, int n_beta,
-                    int m_beta, const float *beta, int nthreads, uint8_t *beta_idx) {
+                    int m_beta, const float *beta, int nthreads, uint8_t *beta_idx, const float *rec) {
   if (k_reg < 1 || k_reg > deg0 || n_beta < 1 || n_beta > 256 || d_pad % m || m_beta < 1 || m % m_beta) return -1;
-  Space sp{d, d_pad, m, d_pad / m, proj, centroids};
+  Space sp{d, d_pad, m, d_pad / m, proj, centroids, rec};
   const int p = k_reg + 1, bw = d_pad / m_beta;
   std::vector<double> B(size_t(m_beta) * n_beta * p);
   for (size_t t = 0; t < B.size(); ++t) B[t] = beta[t];

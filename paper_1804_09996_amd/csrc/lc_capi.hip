@@ -47,6 +47,10 @@ int lc_index_bind(const lc_index_view *v, lc_index **out) {
   if (!v->centroids || !v->codes || !v->adj0 || !v->up_base || !v->beta || !v->beta_idx) return LC_EINVAL;
   if (v->max_level > 0 && !v->adj_up) return LC_EINVAL;
   if (v->d_pad != v->d && !v->proj) return LC_EINVAL;  // padding needs the projection; a rotation is optional
+  if (v->coarse_k < 0 || v->coarse_k > 65536) return LC_EINVAL;
+  if (v->coarse_k > 0 && (v->d_pad % 2 != 0 || !v->coarse_cent || !v->coarse_codes || !v->coarse_norm ||
+                          (reinterpret_cast<uintptr_t>(v->coarse_codes) & 3) != 0))
+    return LC_EINVAL;
   if (v->m % 8 != 0 || v->m > 64 || v->deg0 > 32 || v->deg_up > 32) return LC_ENOTSUP;
   if (!supported_dsub(v->d_pad / v->m)) return LC_ENOTSUP;
   lc_index *ix = new (std::nothrow) lc_index;
@@ -71,6 +75,8 @@ int lc_index_bind(const lc_index_view *v, lc_index **out) {
 }
 
 void lc_index_release(lc_index *ix) { delete ix; }
+
+int64_t lc_lut_stride(const lc_index *ix) { return ix ? lc_lut_entries(ix) : 0; }
 
 namespace {
 int build_lut(const lc_index *ix, const float *q, int64_t nq, int lut_dtype, void *lut, float *lut_scale,

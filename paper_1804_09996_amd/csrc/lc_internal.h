@@ -77,6 +77,14 @@ inline int ceil_div(int64_t a, int64_t b) { return int((a + b - 1) / b); }
 
 }  // namespace lc
 
+// Entries per query of a distance table: m * 256, or for the 2-level codec
+// m * 256 + 2 * coarse_k rounded up to a multiple of 64.
+inline int64_t lc_lut_entries(const lc_index *ix) {
+  const int64_t base = int64_t(ix->v.m) * 256;
+  if (ix->v.coarse_k <= 0) return base;
+  return (base + 2 * int64_t(ix->v.coarse_k) + 63) / 64 * 64;
+}
+
 // Launchers (return LC_* codes).
 int lc_launch_project(const lc_index *ix, const float *q, int64_t nq, float *out, hipStream_t st);
 int lc_launch_lut(const lc_index *ix, const float *q, int64_t nq, int dtype, void *lut, float *scale,

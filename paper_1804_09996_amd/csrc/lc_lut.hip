@@ -251,10 +251,98 @@ int lc_launch_project(const lc_index *ix, const float *q, int64_t nq, float *out
   return hipGetLastError() == hipSuccess ? LC_OK : LC_EHIP;
 }
 
+namespace {
+
+// Tables of the 2-level codec (Sec. 5.1) for kQR queries per block, with
+// z = P y: the [m][256] entries -2 <z^s, C[s][c]> and the [2][coarse_k]
+// entries ||z^h - C1[h][c]||^2, then zero padding up to the row stride.  One
+// thread per table entry, its centroid row read once for the block's queries.
+constexpr int kQR = 8;
+
+struct ResLutArgs {
+  const float *q, *proj, *cent, *ccent;
+  int64_t nq, stride;
+  int d, d_pad, m, dsub, k1;
+  float *lut;
+};
+
+__global__ __launch_bounds__(256) void lut_res_kernel(ResLutArgs a) {
+  extern __shared__ float zs[];  // [kQR][d_pad]
+  const int64_t q0 = int64_t(blockIdx.x) * kQR;
+  const int nqb = int(a.nq - q0 < kQR ? a.nq - q0 : kQR);
+  for (int e = threadIdx.x; e < kQR * a.d_pad; e += blockDim.x) {
+    const int qi = e / a.d_pad, t = e % a.d_pad;
+    float v = 0.f;
+    if (qi < nqb) {
+      const float *y = a.q + (q0 + qi) * a.d;
+      if (a.proj) {
+        for (int u = 0; u < a.d; ++u) v += a.proj[int64_t(t) * a.d + u] * y[u];
+      } else {
+        v = y[t];
+      }
+    }
+    zs[e] = v;
+  }
+  __syncthreads();
+  const int h = a.d_pad / 2, e1 = a.m * 256, e2 = e1 + 2 * a.k1;
+  for (int e = threadIdx.x; e < a.stride; e += blockDim.x) {
+    float acc[kQR];
+#pragma unroll
+    for (int i = 0; i < kQR; ++i) acc[i] = 0.f;
+    if (e < e1) {
+      const int s = e >> 8;
+      const float *c = a.cent + int64_t(e) * a.dsub;
+      for (int t = 0; t < a.dsub; ++t) {
+        const float cv = c[t];
+#pragma unroll
+        for (int i = 0; i < kQR; ++i) acc[i] += zs[i * a.d_pad + s * a.dsub + t] * cv;
+      }
+#pragma unroll
+      for (int i = 0; i < kQR; ++i) acc[i] *= -2.f;
+    } else if (e < e2) {
+      const int half = (e - e1) / a.k1;
+      const float *c = a.ccent + int64_t(e - e1) * h;
+      for (int t = 0; t < h; ++t) {
+        const float cv = c[t];
+#pragma unroll
+        for (int i = 0; i < kQR; ++i) {
+          const float df = zs[i * a.d_pad + half * h + t] - cv;
+          acc[i] += df * df;
+        }
+      }
+    }
+    for (int i = 0; i < nqb; ++i) a.lut[(q0 + i) * a.stride + e] = acc[i];
+  }
+}
+
+int launch_res(const lc_index *ix, const float *q, int64_t nq, int dtype, void *lut, bool projected, hipStream_t st) {
+  if (dtype != LC_LUT_F32) return LC_ENOTSUP;
+  ResLutArgs a;
+  a.q = q;
+  a.proj = projected ? nullptr : ix->v.proj;
+  a.cent = ix->v.centroids;
+  a.ccent = ix->v.coarse_cent;
+  a.nq = nq;
+  a.stride = lc_lut_entries(ix);
+  a.d = projected ? ix->v.d_pad : ix->v.d;
+  a.d_pad = ix->v.d_pad;
+  a.m = ix->v.m;
+  a.dsub = ix->dsub;
+  a.k1 = ix->v.coarse_k;
+  a.lut = static_cast<float *>(lut);
+  const size_t lds = size_t(kQR) * a.d_pad * 4;
+  if (lds > 65536) return LC_ENOTSUP;
+  hipLaunchKernelGGL(lut_res_kernel, dim3(lc::ceil_div(nq, kQR)), dim3(256), lds, st, a);
+  return hipGetLastError() == hipSuccess ? LC_OK : LC_EHIP;
+}
+
+}  // namespace
+
 int lc_launch_lut(const lc_index *ix, const float *q, int64_t nq, int dtype, void *lut, float *scale,
                   bool projected, hipStream_t st) {
   if (dtype != LC_LUT_F32 && dtype != LC_LUT_F16) return LC_ENOTSUP;
   if (nq > int64_t(0x7FFFFFFF) * 16) return LC_EINVAL;
+  if (ix->v.coarse_k > 0) return launch_res(ix, q, nq, dtype, lut, projected, st);
   hipError_t e;
   switch (ix->dsub) {
 #define CASE(DS) \

@@ -45,6 +45,10 @@ struct RefineArgs {
   int S, K, S_pad, K2, K2_pad, wpb;
   int32_t *out_ids;
   float *out_d;
+  // 2-level codec: first-level centroids [2][coarse_k][d_pad/2] and codes (c0 | c1 << 16), or null
+  const float *ccent;
+  const uint32_t *ccodes;
+  int coarse_k;
 };
 
 template <int CS>
@@ -479,6 +483,13 @@ __global__ __launch_bounds__(1024) void refine_f32_generic(RefineArgs a, int m, 
             const float w = bw[j];
             const float *cr = C + (s * 256 + int(a.codes[size_t(g) * a.code_stride + s])) * dsub;
             for (int t = 0; t < dsub; ++t) acc[t] += w * cr[t];
+            if (a.ccent) {  // 2-level codec: the first-level centroid's part over sub-space s
+              const int half = s >= m / 2;
+              const uint32_t cc = a.ccodes[g];
+              const float *c1 = a.ccent + (size_t(half) * a.coarse_k + (half ? cc >> 16 : cc & 0xFFFFu)) * (DP / 2) +
+                                (s - half * (m / 2)) * dsub;
+              for (int t = 0; t < dsub; ++t) acc[t] += w * c1[t];
+            }
           }
           for (int t = 0; t < dsub; ++t) {
             const float df = yv[s * dsub + t] - acc[t];
@@ -517,6 +528,9 @@ RefineArgs make_args(const lc_index *ix, const float *q, int64_t nq, const int32
   a.n = ix->v.n;
   a.n_beta = ix->v.n_beta;
   a.m_beta = ix->v.m_beta;
+  a.ccent = ix->v.coarse_k > 0 ? ix->v.coarse_cent : nullptr;
+  a.ccodes = reinterpret_cast<const uint32_t *>(ix->v.coarse_codes);
+  a.coarse_k = ix->v.coarse_k;
   a.deg0 = ix->v.deg0;
   a.k_reg = ix->v.k_reg;
   a.beta = ix->v.beta;
@@ -608,6 +622,7 @@ int lc_launch_refine(const lc_index *ix, const float *q, int64_t nq, const int32
   // candidate's distance is the float32 one and all are sorted by it, which is the plain kernel
   const bool bf_pass = bf && a.K2 < S;
   const bool spec_mb = a.m_beta == 1 || a.m_beta == 2 || a.m_beta == 4 || a.m_beta == 8;
+  if (a.ccent) return bf_pass ? LC_ENOTSUP : launch_generic(ix, a, st);  // 2-level codec: the float32 kernel
 #define SHAPE(MM, DS, CSS)                                                                              \
   if (m == MM && ds == DS && spec_mb)                                                                   \
     return bf_pass ? launch_blocks<MM, DS, CSS, uint16_t>(ix, a, st) : launch_blocks<MM, DS, CSS, float>(ix, a, st);

@@ -63,6 +63,11 @@ struct WalkArgs {
   int32_t *cand_ids;
   float *cand_adc;
   int32_t *cand_n, *stats;
+  // 2-level codec (rfloat tables): first-level codes (c0 | c1 << 16), per-node terms, centroids per half
+  const uint32_t *ccodes;
+  const float *cnorm;
+  int32_t coarse_k;
+  int64_t lut_stride;  // table entries per query
 };
 
 // One table entry as float32: the entry itself, or the fp16 entry times its
@@ -72,6 +77,24 @@ __device__ __forceinline__ float lut_at(const float *lut, const float *, int s, 
 }
 __device__ __forceinline__ float lut_at(const __half *lut, const float *sc, int s, uint32_t c) {
   return __half2float(lut[s * 256 + c]) * sc[s];
+}
+
+// Table of the 2-level codec (Sec. 5.1): its [m][256] part holds
+// -2 <z^s, C[s][c]>; a node's key adds its two first-level entries (read from
+// the query's table in global memory) and its stored term, clamped at 0.
+struct rfloat {
+  float v;
+};
+__device__ __forceinline__ float lut_at(const rfloat *lut, const float *, int s, uint32_t c) {
+  return lut[s * 256 + c].v;
+}
+template <typename T>
+constexpr bool kRes = std::is_same<T, rfloat>::value;
+
+// First-level entries of node id plus its stored term (2-level codec).
+__device__ __forceinline__ float coarse_term(const WalkArgs &a, const float *ctab, int32_t id) {
+  const uint32_t c = a.ccodes[id];
+  return (ctab[c & 0xFFFFu] + ctab[a.coarse_k + (c >> 16)]) + a.cnorm[id];
 }
 
 // Sum of LUT[s][code[s]] over all sub-spaces, s ascending (one lane per node).
@@ -105,6 +128,7 @@ __device__ __forceinline__ float adc_full(const T *lut, const float *sc, const u
 template <int M>
 struct CodeRegs {
   uint32_t w[M / 4];
+  float extra;  // 2-level codec: the node's first-level entries and term
   __device__ __forceinline__ void load(const uint8_t *codes, int cs, int32_t id) {
     const uint8_t *row = codes + size_t(id) * cs;
     if constexpr (M % 16 == 0) {
@@ -125,11 +149,15 @@ struct CodeRegs {
       }
     }
   }
+  __device__ __forceinline__ void load_coarse(const WalkArgs &a, const float *ctab, int32_t id) {
+    extra = coarse_term(a, ctab, id);
+  }
   template <typename T>
   __device__ __forceinline__ float adc(const T *lut, const float *sc) const {
     float acc = 0.f;
 #pragma unroll
     for (int s = 0; s < M; ++s) acc += lut_at(lut, sc, s, (w[s >> 2] >> (8 * (s & 3))) & 0xFFu);
+    if constexpr (kRes<T>) acc = clamp0(acc + extra);
     return acc;
   }
 };
@@ -645,16 +673,21 @@ __device__ __forceinline__ void reg_merge_sorted(Pool &p, uint64_t kv, int efe, 
 // no measurable time, so the winner's row index is read after the move.)
 template <int M, typename T>
 __device__ __forceinline__ void greedy_descent(const WalkArgs &a, const T *lut, const float *sc, int lane,
-                                               int32_t &cur, uint64_t &curkey) {
+                                               int32_t &cur, uint64_t &curkey, const float *ctab) {
+  auto dist = [&](int32_t id) {
+    float v = adc_full<M, T>(lut, sc, a.codes, a.code_stride, id);
+    if constexpr (kRes<T>) v = clamp0(v + coarse_term(a, ctab, id));
+    return v;
+  };
   cur = a.entry;
-  curkey = make_key(adc_full<M, T>(lut, sc, a.codes, a.code_stride, cur), cur);
+  curkey = make_key(dist(cur), cur);
   for (int l = a.max_level; l >= 1; --l) {
     for (;;) {
       const int64_t row = int64_t(a.up_base[cur]) + l - 1;
       int32_t nb = -1;
       if (lane < a.deg_up && row >= 0 && row < a.n_up_rows) nb = a.adj_up[row * a.deg_up + lane];
       if (nb >= a.n) nb = -1;  // a malformed link is ignored rather than followed
-      const uint64_t k = nb >= 0 ? make_key(adc_full<M, T>(lut, sc, a.codes, a.code_stride, nb), nb) : kKeyMax;
+      const uint64_t k = nb >= 0 ? make_key(dist(nb), nb) : kKeyMax;
       const uint64_t mn = wave_min64(k);
       if (mn < curkey) {
         curkey = mn;
@@ -830,7 +863,9 @@ __global__ __launch_bounds__(64) void walk_kernel(WalkArgs a) {
       const int efe = efq > a.S ? efq : a.S;
 
       // stage the table (and its row scales), clear the visited table
-      const float4 *src = reinterpret_cast<const float4 *>(static_cast<const T *>(a.lut) + q * (M * 256));
+      const float4 *src = reinterpret_cast<const float4 *>(static_cast<const T *>(a.lut) + q * a.lut_stride);
+      [[maybe_unused]] const float *ctab =
+          kRes<T> ? reinterpret_cast<const float *>(a.lut) + q * a.lut_stride + M * 256 : nullptr;
       for (int i = lane; i < kLutBytes / 16; i += 64) reinterpret_cast<float4 *>(lut)[i] = src[i];
       if (sizeof(T) == 2)
         for (int i = lane; i < M; i += 64) sc[i] = a.scale[q * M + i];
@@ -840,7 +875,7 @@ __global__ __launch_bounds__(64) void walk_kernel(WalkArgs a) {
       // greedy descent on levels max_level .. 1
       int32_t cur;
       uint64_t curkey;
-      greedy_descent<M, T>(a, lut, sc, lane, cur, curkey);
+      greedy_descent<M, T>(a, lut, sc, lane, cur, curkey, ctab);
 
       // best-first walk on level 0
       if (lane == 0) {
@@ -873,6 +908,7 @@ __global__ __launch_bounds__(64) void walk_kernel(WalkArgs a) {
         // link that is not fresh reads its code for nothing)
         CodeRegs<M> cr;
         cr.load(a.codes, a.code_stride, nb >= 0 ? nb : cid);
+        if constexpr (kRes<T>) cr.load_coarse(a, ctab, nb >= 0 ? nb : cid);
 
         const StepOut o = expand_links<M, T, BUDGET>(a, vt, bits, vlist, lut, sc, nb, cr, lo, two, pk, lane, D, E, vcount);
         const bool dual = o.dual;
@@ -1088,7 +1124,9 @@ __global__ __launch_bounds__(64) void walk_reg_kernel(WalkArgs a) {
       const int efe = efq > a.S ? efq : a.S;
 
       // stage the table, take its row scales into registers, clear the visited table
-      const float4 *src = reinterpret_cast<const float4 *>(static_cast<const T *>(a.lut) + q * (M * 256));
+      const float4 *src = reinterpret_cast<const float4 *>(static_cast<const T *>(a.lut) + q * a.lut_stride);
+      [[maybe_unused]] const float *ctab =
+          kRes<T> ? reinterpret_cast<const float *>(a.lut) + q * a.lut_stride + M * 256 : nullptr;
       for (int i = lane; i < kLutBytes / 16; i += 64) reinterpret_cast<float4 *>(lut)[i] = src[i];
       float scr[sizeof(T) == 2 ? M : 1];
 #pragma unroll
@@ -1100,7 +1138,7 @@ __global__ __launch_bounds__(64) void walk_reg_kernel(WalkArgs a) {
       // greedy descent on levels max_level .. 1
       int32_t cur;
       uint64_t curkey;
-      greedy_descent<M, T>(a, lut, sc, lane, cur, curkey);
+      greedy_descent<M, T>(a, lut, sc, lane, cur, curkey, ctab);
 
       // best-first walk on level 0
       if (lane == 0) {
@@ -1134,6 +1172,7 @@ __global__ __launch_bounds__(64) void walk_reg_kernel(WalkArgs a) {
         // link that is not fresh reads its code for nothing)
         CodeRegs<M> cr;
         cr.load(a.codes, a.code_stride, nb >= 0 ? nb : cid);
+        if constexpr (kRes<T>) cr.load_coarse(a, ctab, nb >= 0 ? nb : cid);
 
         const StepOut o = expand_links<M, T, BUDGET>(a, vt, bits, vlist, lut, sc, nb, cr, lo, two, pk, lane, D, E, vcount);
         const bool dual = o.dual;
@@ -1294,7 +1333,9 @@ __global__ __launch_bounds__(64) void walk_cache_kernel(WalkArgs a) {
     } else {
       const int efe = efq > a.S ? efq : a.S;
 
-      const float4 *src = reinterpret_cast<const float4 *>(static_cast<const T *>(a.lut) + q * (M * 256));
+      const float4 *src = reinterpret_cast<const float4 *>(static_cast<const T *>(a.lut) + q * a.lut_stride);
+      [[maybe_unused]] const float *ctab =
+          kRes<T> ? reinterpret_cast<const float *>(a.lut) + q * a.lut_stride + M * 256 : nullptr;
       for (int i = lane; i < kLutBytes / 16; i += 64) reinterpret_cast<float4 *>(lut)[i] = src[i];
       if (sizeof(T) == 2)
         for (int i = lane; i < M; i += 64) sc[i] = a.scale[q * M + i];
@@ -1304,7 +1345,7 @@ __global__ __launch_bounds__(64) void walk_cache_kernel(WalkArgs a) {
       // greedy descent on levels max_level .. 1
       int32_t cur;
       uint64_t curkey;
-      greedy_descent<M, T>(a, lut, sc, lane, cur, curkey);
+      greedy_descent<M, T>(a, lut, sc, lane, cur, curkey, ctab);
 
       if (lane == 0) {
         W[0] = curkey;
@@ -1333,6 +1374,7 @@ __global__ __launch_bounds__(64) void walk_cache_kernel(WalkArgs a) {
             const uint32_t bit = 1u << (uint32_t(nb) & 31u);
             const uint32_t old = atomicOr(&bits[uint32_t(nb) >> 5], bit);
             cr.load(a.codes, a.code_stride, nb);
+            if constexpr (kRes<T>) cr.load_coarse(a, ctab, nb);
             fresh = (old & bit) == 0;
             hash[h] = uint32_t(nb);
           }
@@ -1582,6 +1624,10 @@ int launch_m(const lc_index *ix, const void *lut, const float *scale, int64_t nq
   a.cand_adc = cand_adc;
   a.cand_n = cand_n;
   a.stats = stats;
+  a.ccodes = reinterpret_cast<const uint32_t *>(ix->v.coarse_codes);
+  a.cnorm = ix->v.coarse_norm;
+  a.coarse_k = ix->v.coarse_k;
+  a.lut_stride = lc_lut_entries(ix);
   return max_d > 0 ? launch_kernel<M, T, true>(p, sc, a, st) : launch_kernel<M, T, false>(p, sc, a, st);
 }
 
@@ -1611,6 +1657,18 @@ int lc_launch_walk(const lc_index *ix, const void *lut, int dtype, const float *
   if (dtype != LC_LUT_F32 && dtype != LC_LUT_F16) return LC_ENOTSUP;
   if (!valid_schedule(sched)) return LC_EINVAL;
   const lc_schedule *sc = sched ? sched : &kDefaultSchedule;
+  if (ix->v.coarse_k > 0) {  // 2-level codec: float32 tables only
+    if (dtype != LC_LUT_F32) return LC_ENOTSUP;
+    switch (ix->v.m) {
+#define CASE(MM)                                                                                       \
+  case MM:                                                                                             \
+    return launch_m<MM, rfloat>(ix, lut, scale, nq, ef, ef_max, S, max_d, order, cand_ids, cand_adc, cand_n, \
+                                stats, ws, ws_bytes, sc, st);
+      LC_FOR_EACH_M(CASE)
+#undef CASE
+      default: return LC_ENOTSUP;
+    }
+  }
   switch (ix->v.m) {
 #define CASE(MM)                                                                                              \
   case MM:                                                                                                    \

@@ -141,7 +141,7 @@ class GpuEngine:
                 "q": torch.empty((Q, d), dtype=torch.float32, device=dev),
                 "qp": torch.empty((Q, gix.d_pad) if self.projected else (1,), dtype=torch.float32, device=dev),
                 "ef": torch.empty(Q, dtype=torch.int32, device=dev),
-                "lut": torch.empty((Q, m, 256), dtype=lut_t, device=dev),
+                "lut": torch.empty((Q, gix.lut_stride) if gix.coarse_k else (Q, m, 256), dtype=lut_t, device=dev),
                 "scale": torch.empty((Q, m), dtype=torch.float32, device=dev),
                 "cand_ids": torch.empty((Q, S), dtype=torch.int32, device=dev),
                 "cand_adc": torch.empty((Q, S), dtype=torch.float32, device=dev),

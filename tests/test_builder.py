@@ -121,3 +121,19 @@ def test_builder_with_learned_rotation_matches_oracle(nthreads):
     assert np.all(bix.adj0 == oix.adj0, axis=1).mean() >= 0.999
     np.testing.assert_allclose(bix.centroids, oix.centroids, rtol=1e-6, atol=1e-7)
     assert (bix.beta_idx == oix.beta_idx).mean() >= 0.999
+
+
+def test_builder_two_level_codec_matches_oracle(nthreads):
+    # 2-level residual codec (Sec. 5.1): a first level of 2 x 32 centroids, PQ on the residual
+    w = datagen.small(name="coarse-b", n=1500, d=32, m=8, n_beta=8, n_beta_train=1500, coarse_k=32)
+    bix, _, _ = builder.build_workload(w, nthreads=nthreads)
+    oix, _, _ = oracle.build_workload(w, nthreads=nthreads)
+    assert bix.coarse_cent.shape == oix.coarse_cent.shape == (2, 32, 16)
+    np.testing.assert_allclose(bix.coarse_cent, oix.coarse_cent, rtol=1e-6, atol=1e-7)
+    assert np.array_equal(bix.coarse_codes, oix.coarse_codes)
+    np.testing.assert_allclose(bix.centroids, oix.centroids, rtol=1e-5, atol=1e-6)
+    assert (bix.codes == oix.codes).mean() >= 0.999
+    np.testing.assert_allclose(bix.coarse_norm, oix.coarse_norm, rtol=1e-5, atol=1e-5)
+    assert np.all(bix.adj0 == oix.adj0, axis=1).mean() >= 0.99
+    np.testing.assert_allclose(bix.beta, oix.beta, rtol=1e-3, atol=1e-4)
+    assert (bix.beta_idx == oix.beta_idx).mean() >= 0.99

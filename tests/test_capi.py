@@ -119,3 +119,30 @@ def test_missing_library_fails_loudly(tmp_path, monkeypatch):
     with pytest.raises(ImportError):
         lc.Index({"codes": np.zeros((4, 8), np.uint8)}, {"d": 8, "d_pad": 8, "m": 8, "deg0": 32, "deg_up": 32,
                                                          "k_reg": 1, "entry": 0, "max_level": 0}, device="cpu")
+
+
+def test_bind_rejects_bad_two_level_views(L):
+    # 2-level codec fields: coarse_k in [0, 65536], an even d_pad, all three arrays, 4-byte aligned codes
+    import paper_1804_09996_amd as lc
+    h = C.c_void_p()
+
+    def coarse():
+        g = lc.IndexView()
+        g.n, g.d, g.d_pad, g.m, g.ksub, g.code_stride = 100, 96, 96, 16, 256, 16
+        g.deg0, g.deg_up, g.k_reg, g.n_beta, g.entry, g.max_level, g.n_up_rows = 32, 32, 16, 256, 0, 0, 0
+        g.m_beta = 1
+        for name in ("centroids", "codes", "adj0", "up_base", "beta", "beta_idx", "coarse_cent", "coarse_codes",
+                     "coarse_norm"):
+            setattr(g, name, 0x1000)
+        g.coarse_k = 64
+        return g
+
+    for field, value in (("coarse_k", -1), ("coarse_k", 65537), ("coarse_cent", None), ("coarse_codes", None),
+                         ("coarse_norm", None), ("coarse_codes", 0x1002)):
+        g = coarse()
+        setattr(g, field, value)
+        assert L.lc_index_bind(C.byref(g), C.byref(h)) == lc.LC_EINVAL, (field, value)
+    g = coarse()
+    g.d, g.d_pad, g.m, g.code_stride, g.proj = 8, 9, 1, 1, 0x1000  # odd d_pad: the first level halves the vector
+    assert L.lc_index_bind(C.byref(g), C.byref(h)) == lc.LC_EINVAL
+    assert L.lc_lut_stride(None) == 0

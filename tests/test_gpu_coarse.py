@@ -1,0 +1,149 @@
+"""2-level residual codec (Sec. 3.3 residual codecs; Sec. 5.1 two-level
+encodings) on the GPU against the oracle, through the C-ABI.
+
+The oracle takes the walk's asymmetric distance by its definition,
+||P y - (c + r)||^2 in float64 with both levels decoded; the GPU sums the
+decomposed form in float32 (the [m][256] inner-product table, the node's two
+first-level entries and its stored term, clamped at 0).  Bars: the short-lists
+of the float32 walk equal the oracle's on at least 90 % of queries (a float32
+near-tie may reorder one), every short-list distance within 1e-4 of the
+oracle's (relative to the largest), top-K EXACT against the oracle's
+refinement of the GPU's short-list, every returned distance within 1e-5
+relative, and the codebook assignment identical on every vector.
+"""
+import numpy as np
+import pytest
+
+import datagen
+import oracle
+from tests import parity
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    assert t.cuda.is_available(), "GPU tests need a GPU"
+    return t
+
+
+_built = {}
+
+
+def _build(m, d, d_pad=None, k=32):
+    key = (m, d, d_pad, k)
+    if key not in _built:
+        kw = {} if d_pad is None else {"d_pad": d_pad}
+        w = datagen.small(name=f"coarse-{m}-{d}", n=1500, nq=24, d=d, m=m, n_train=1024, n_beta=8,
+                          n_beta_train=1500, k_reg=6, ef=40, shortlist=48, topk=10, coarse_k=k, **kw)
+        ix, db, q = oracle.build_workload(w, nthreads=4)
+        _built[key] = (w, ix, db, q)
+    return _built[key]
+
+
+def _oracle_topk(ix, q, cand_ids, cand_n, K):
+    ids = np.full((q.shape[0], K), -1, np.int32)
+    d = np.full((q.shape[0], K), np.inf)
+    for i in range(q.shape[0]):
+        c = cand_ids[i, :max(int(cand_n[i]), 0)]
+        dd = np.array([ix.refined_distance(q[i], int(x)) for x in c])
+        order = np.lexsort((c, dd))[:K]
+        ids[i, :order.size] = c[order]
+        d[i, :order.size] = dd[order]
+    return {"ids": ids, "d": d}
+
+
+@pytest.mark.parametrize("m,d,d_pad", [(8, 32, None), (16, 96, None), (8, 28, 32)])
+def test_two_level_search_matches_oracle(torch, m, d, d_pad):
+    import paper_1804_09996_amd as lc
+    w, ix, db, q = _build(m, d, d_pad)
+    assert ix.coarse_k == 32 and (d_pad is None or ix.proj is not None)
+    print(f"case m {m} d {d} d_pad {w.d_pad}", flush=True)
+    gix = lc.Index.from_index(ix)
+    assert gix.coarse_k == 32 and gix.lut_stride == (m * 256 + 64 + 63) // 64 * 64
+    o = ix.search(q, w.ef, w.shortlist, w.topk)
+    ids, dist, r = gix.query(torch.from_numpy(q), ef=w.ef, ef_max=w.ef, S=w.shortlist, K=w.topk, stats=True)
+    cand, cn = r.cand_ids.cpu().numpy(), r.cand_n.cpu().numpy()
+    adc = r.cand_adc.cpu().numpy()
+    same = [np.array_equal(cand[i], o["cand_ids"][i]) for i in range(q.shape[0])]
+    assert np.mean(same) >= 0.9, np.mean(same)
+    for i in np.flatnonzero(same):
+        n = int(cn[i])
+        scale = float(o["cand_adc"][i, :n].max())
+        np.testing.assert_allclose(adc[i, :n], o["cand_adc"][i, :n], rtol=0, atol=1e-4 * scale)
+        assert np.array_equal(r.stats.cpu().numpy()[i], o["stats"][i])
+    ref = _oracle_topk(ix, q, cand, cn, w.topk)
+    s = parity.summarize(ix, q, ids.cpu().numpy(), dist.cpu().numpy(), ref)
+    print(f"m {m}: walk {np.mean(same):.2f} EXACT {s['exact_frac']:.3f} max rel err {s['max_rel_err']:.1e}")
+    assert s["exact_frac"] == 1.0 and s["max_rel_err"] <= 1e-5
+    gix.close()
+
+
+def test_two_level_tables_layout(torch):
+    # row q: [m][256] entries -2 <z^s, C[s][c]>, then [2][k] entries ||z^h - C1[h][c]||^2, then zeros
+    import paper_1804_09996_amd as lc
+    w, ix, db, q = _build(8, 28, 32)
+    gix = lc.Index.from_index(ix)
+    lut, scale = gix.build_lut(torch.from_numpy(q))
+    assert scale is None and tuple(lut.shape) == (q.shape[0], gix.lut_stride)
+    lut = lut.cpu().numpy().astype(np.float64)
+    h, ds, k = w.d_pad // 2, w.d_pad // w.m, ix.coarse_k
+    for i in range(q.shape[0]):
+        z = ix.proj.astype(np.float64) @ q[i].astype(np.float64)
+        ip = np.concatenate([-2.0 * (ix.centroids[s].astype(np.float64) @ z[s * ds:(s + 1) * ds]) for s in range(w.m)])
+        ct = np.concatenate([((z[None, j * h:(j + 1) * h] - ix.coarse_cent[j].astype(np.float64)) ** 2).sum(1)
+                             for j in range(2)])
+        np.testing.assert_allclose(lut[i, :w.m * 256], ip, rtol=0, atol=1e-5 * np.abs(ip).max())
+        np.testing.assert_allclose(lut[i, w.m * 256:w.m * 256 + 2 * k], ct, rtol=1e-5, atol=1e-6)
+        assert (lut[i, w.m * 256 + 2 * k:] == 0).all()
+    with pytest.raises(lc.LCError):  # the fp16 table form covers the one-level codec only
+        gix.build_lut(torch.from_numpy(q), lut_dtype=lc.LC_LUT_F16)
+    gix.close()
+
+
+def test_two_level_budget_matches_oracle(torch):
+    # the budget T on distance evaluations (Sec. 3.1) on the 2-level walk
+    import paper_1804_09996_amd as lc
+    w, ix, db, q = _build(16, 96)
+    gix = lc.Index.from_index(ix)
+    for T in (20, 75):
+        o = ix.search(q, w.ef, w.shortlist, w.topk, max_evals=T)
+        ids, dist, r = gix.query(torch.from_numpy(q), ef=w.ef, ef_max=w.ef, S=w.shortlist, K=w.topk, stats=True,
+                                 max_evals=T)
+        st = r.stats.cpu().numpy()
+        assert (st[:, 1] <= T).all()
+        same = [np.array_equal(r.cand_ids.cpu().numpy()[i], o["cand_ids"][i]) for i in range(q.shape[0])]
+        assert np.mean(same) >= 0.9
+        for i in np.flatnonzero(same):
+            assert np.array_equal(st[i], o["stats"][i])
+    gix.close()
+
+
+@pytest.mark.parametrize("m,d,d_pad", [(16, 96, None), (8, 28, 32)])
+def test_two_level_assignment_is_identical(torch, m, d, d_pad):
+    # the float64 arg-min of Eq. 7 with the 2-level decoding: the oracle's entry on every vector
+    import paper_1804_09996_amd as lc
+    w, ix, db, q = _build(m, d, d_pad)
+    gix = lc.Index.from_index(ix)
+    got = gix.assign_beta(torch.from_numpy(db)).cpu().numpy()
+    assert np.array_equal(got[:, 0], ix.beta_idx), int((got[:, 0] != ix.beta_idx).sum())
+    gix.close()
+
+
+def test_zero_first_level_gives_the_one_level_results(torch):
+    # one first-level centroid at the origin: same codes, same graph, the one-level search
+    import dataclasses
+    import paper_1804_09996_amd as lc
+    w, ix, db, q = _build(16, 96)
+    one = dataclasses.replace(ix, coarse_cent=None, coarse_codes=None, coarse_norm=None)
+    zero = dataclasses.replace(ix, coarse_cent=np.zeros((2, 1, w.d_pad // 2), np.float32),
+                               coarse_codes=np.zeros((ix.n, 2), np.uint16))
+    zero.coarse_norm = zero.coarse_norms()
+    a, b = lc.Index.from_index(one), lc.Index.from_index(zero)
+    ia, da, ra = a.query(torch.from_numpy(q), ef=w.ef, ef_max=w.ef, S=w.shortlist, K=w.topk)
+    ib, dbb, rb = b.query(torch.from_numpy(q), ef=w.ef, ef_max=w.ef, S=w.shortlist, K=w.topk)
+    assert np.mean(np.all(ia.cpu().numpy() == ib.cpu().numpy(), axis=1)) >= 0.9
+    np.testing.assert_allclose(dbb.cpu().numpy(), da.cpu().numpy(), rtol=1e-5)
+    a.close()
+    b.close()
