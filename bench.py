@@ -32,13 +32,17 @@ def walk_bytes(w, E, D, S):
     (4 m 256), per expansion one adjacency row (4 deg0), per evaluated node
     its code (m), and the short-list written (8 S + 12)."""
     nq = E.shape[0]
-    return float(nq * (4 * w.m * 256 + 8 * S + 12) + 4 * w.deg0 * E.sum() + w.m * D.sum())
+    # 2-level codec: per evaluated node also its first-level codes (4), term (4) and two table entries (8)
+    per_node = w.m + (16 if w.coarse_k else 0)
+    return float(nq * (4 * w.m * 256 + 8 * S + 12) + 4 * w.deg0 * E.sum() + per_node * D.sum())
 
 
-def walk_kernel_name(m, precision, ef, S):
+def walk_kernel_name(m, precision, ef, S, coarse=False):
     """The walk kernel the default schedule launches: the pool in registers up
     to 128 entries, in LDS beyond."""
     t = "half" if precision != "f32" else "float"
+    if coarse:
+        t = "rfloat"  # the 2-level codec's table type
     w_cap = -(-max(ef, S) // 64) * 64
     return f"walk_reg_kernel<{m},{t},2,false>" if w_cap <= 128 else f"walk_kernel<{m},{t},false>"
 
@@ -47,11 +51,12 @@ def refine_bytes(w, cand_n, K):
     """Per candidate: its beta index (1 byte per codebook block), k links
     (4k), k+1 codes (m(k+1)); per query the output (8K)."""
     c = float(np.clip(cand_n, 0, None).sum())
-    return c * (w.m_beta + 4 * w.k_reg + w.m * (w.k_reg + 1)) + cand_n.shape[0] * 8 * K
+    codes = w.m + (4 if w.coarse_k else 0)  # a 2-level code adds its two 16-bit first-level indices
+    return c * (w.m_beta + 4 * w.k_reg + codes * (w.k_reg + 1)) + cand_n.shape[0] * 8 * K
 
 
 def lut_bytes(w, nq):
-    return float(nq) * (4 * w.d + 4 * w.m * 256)
+    return float(nq) * (4 * w.d + 4 * (w.m * 256 + 2 * w.coarse_k))
 
 
 def traffic_from_profiles(kernel_src, precision, ef, S):
@@ -372,6 +377,8 @@ def main():
                     help="regression codebook size (default: the workload's; 1 = one shared beta, the 0-byte form)")
     ap.add_argument("--opq-iters", type=int, default=0,
                     help="learn the rotation ahead of PQ (OPQ) with this many rotation steps (0 = the workload's)")
+    ap.add_argument("--coarse-k", type=int, default=0,
+                    help="2-level residual codec: first-level centroids per half (4096 = PQ2x12; plain form, f32)")
     ap.add_argument("--max-evals", type=int, default=0,
                     help="budget T on level-0 distance evaluations per query (0 = none; plain and both forms)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
@@ -410,6 +417,10 @@ def main():
         w = dataclasses.replace(w, n_beta=args.n_beta)
     if args.opq_iters:
         w = dataclasses.replace(w, opq_iters=args.opq_iters)
+    if args.coarse_k:
+        if args.form != "plain" or args.precision != "f32":
+            raise SystemExit("--coarse-k takes --form plain --precision f32 (the fp16 tables cover the one-level codec)")
+        w = dataclasses.replace(w, coarse_k=args.coarse_k)
     dev = torch.device("cuda:0")
     t0 = time.time()
     ix, db, q = builder.build_workload(w, cache_dir=args.cache, log=log)
@@ -578,6 +589,7 @@ def main():
         "vs_baseline": None, "dtype": "f16" if f16 else "f32", "data": "synthetic",
         "config": {"workload": f"{w.name}: N={w.n} d={w.d} Gaussian mixture ({w.n_comp} components, "
                                f"L2-normalised), " + (f"learned rotation ({w.opq_iters} steps) + " if w.opq_iters else "") +
+                               (f"2-level codec: first level 2x{w.coarse_k} centroids, residual " if w.coarse_k else "") +
                                f"PQ {w.m}x256, level-0 degree {w.deg0}, k={w.k_reg}, " +
                                (f"product beta codebook {w.m_beta} blocks x {w.n_beta}" if w.m_beta > 1
                                 else f"beta codebook {w.n_beta}") +
@@ -592,7 +604,7 @@ def main():
                    "index": f"built on the host by liblc_build from seed {w.seed}"},
         "roofline": {"bound": "hbm", "achieved": wb / (wm * 1e-3) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": wb / (wm * 1e-3) / 1e9 / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": walk_kernel_name(w.m, head["precision"], head["ef"], S_h),
+                     "kernel": walk_kernel_name(w.m, head["precision"], head["ef"], S_h, bool(w.coarse_k)),
                      "algorithmic_bytes_per_launch": wb},
         "kernels_ms": head["kernels_ms"],
         "kernels_GBps_algorithmic": {"build_lut": lb / (head["kernels_ms"]["build_lut"] * 1e-3) / 1e9,

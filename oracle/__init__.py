@@ -233,14 +233,15 @@ def beta_train(x, ids, proj, d_pad, cent, codes, adj0, k_reg, n_beta, init, km_i
     """Regression codebook(s): [n_beta, k+1] for one block, [m_beta, n_beta, k+1]
     for the product codebook (Eq. 9); the loss history likewise per block."""
     x = _c(x, np.float32)
+    cent, codes, adj0 = _c(cent, np.float32), _c(codes, np.uint8), _c(adj0, np.int32)
     ids = _c(ids, np.int64)
     proj = None if proj is None else _c(proj, np.float32)
     init = _c(init, np.int64)
     beta = np.empty((m_beta, n_beta, k_reg + 1), np.float32)
     hist = np.empty((m_beta, em_iters + 1), np.float64)
     rc = _load().orc_beta_train(_ptr(x), _ptr(ids), ids.shape[0], x.shape[1], _ptr(proj), d_pad, cent.shape[0],
-                                cent.shape[1], _ptr(_c(cent, np.float32)), _ptr(_c(codes, np.uint8)), codes.shape[1],
-                                _ptr(_c(adj0, np.int32)), adj0.shape[1], k_reg, n_beta, m_beta, _ptr(init), km_iters,
+                                cent.shape[1], _ptr(cent), _ptr(codes), codes.shape[1],
+                                _ptr(adj0), adj0.shape[1], k_reg, n_beta, m_beta, _ptr(init), km_iters,
                                 em_iters, nthreads, _ptr(beta), _ptr(hist), _cref(_coarse(coarse)))
     if rc != 0:
         raise ValueError(f"orc_beta_train failed ({rc})")
@@ -251,12 +252,13 @@ def beta_train(x, ids, proj, d_pad, cent, codes, adj0, k_reg, n_beta, init, km_i
 
 def beta_shared(x, ids, proj, d_pad, cent, codes, adj0, k_reg, coarse=None):
     x = _c(x, np.float32)
+    cent, codes, adj0 = _c(cent, np.float32), _c(codes, np.uint8), _c(adj0, np.int32)
     ids = _c(ids, np.int64)
     proj = None if proj is None else _c(proj, np.float32)
     beta = np.empty(k_reg + 1, np.float64)
     rc = _load().orc_beta_shared(_ptr(x), _ptr(ids), ids.shape[0], x.shape[1], _ptr(proj), d_pad, cent.shape[0],
-                                 cent.shape[1], _ptr(_c(cent, np.float32)), _ptr(_c(codes, np.uint8)), codes.shape[1],
-                                 _ptr(_c(adj0, np.int32)), adj0.shape[1], k_reg, _ptr(beta), _cref(_coarse(coarse)))
+                                 cent.shape[1], _ptr(cent), _ptr(codes), codes.shape[1],
+                                 _ptr(adj0), adj0.shape[1], k_reg, _ptr(beta), _cref(_coarse(coarse)))
     if rc != 0:
         raise ValueError(f"orc_beta_shared failed ({rc})")
     return beta
@@ -266,13 +268,14 @@ def beta_assign(x, proj, d_pad, cent, codes, adj0, k_reg, beta, nthreads=1, coar
     """Entry per vector: [n] for a [n_beta, k+1] codebook, [n, m_beta] for a
     [m_beta, n_beta, k+1] product codebook."""
     x = _c(x, np.float32)
+    cent, codes, adj0 = _c(cent, np.float32), _c(codes, np.uint8), _c(adj0, np.int32)
     proj = None if proj is None else _c(proj, np.float32)
     beta = _c(beta, np.float32)
     mb = 1 if beta.ndim == 2 else beta.shape[0]
     out = np.empty((x.shape[0], mb), np.uint8)
     rc = _load().orc_beta_assign(_ptr(x), x.shape[0], x.shape[1], _ptr(proj), d_pad, cent.shape[0], cent.shape[1],
-                                 _ptr(_c(cent, np.float32)), _ptr(_c(codes, np.uint8)), codes.shape[1],
-                                 _ptr(_c(adj0, np.int32)), adj0.shape[1], k_reg, beta.shape[-2], mb, _ptr(beta),
+                                 _ptr(cent), _ptr(codes), codes.shape[1],
+                                 _ptr(adj0), adj0.shape[1], k_reg, beta.shape[-2], mb, _ptr(beta),
                                  nthreads, _ptr(out), _cref(_coarse(coarse)))
     if rc != 0:
         raise ValueError(f"orc_beta_assign failed ({rc})")
@@ -352,17 +355,20 @@ class Index:
     def lut(self, y: np.ndarray) -> np.ndarray:
         out = np.empty((self.m, self.ksub), np.float64)
         s = self._struct()
-        _load().orc_lut(C.byref(s), _ptr(_c(y, np.float32)), _ptr(out))
+        y = _c(y, np.float32)
+        _load().orc_lut(C.byref(s), _ptr(y), _ptr(out))
         return out
 
     def refined_distance(self, y: np.ndarray, i: int) -> float:
         s = self._struct()
-        return float(_load().orc_refined_distance(C.byref(s), _ptr(_c(y, np.float32)), int(i)))
+        y = _c(y, np.float32)
+        return float(_load().orc_refined_distance(C.byref(s), _ptr(y), int(i)))
 
     def walk_trace(self, y: np.ndarray, ef_eff: int, cap: int = 1 << 20) -> np.ndarray:
         s = self._struct()
         out = np.empty(cap, np.int32)
-        nt = _load().orc_walk_trace(C.byref(s), _ptr(_c(y, np.float32)), int(ef_eff), _ptr(out), cap)
+        y = _c(y, np.float32)
+        nt = _load().orc_walk_trace(C.byref(s), _ptr(y), int(ef_eff), _ptr(out), cap)
         return out[:nt].copy()
 
     def search(self, q: np.ndarray, ef, S: int, K: int, nthreads: Optional[int] = None, max_evals: int = 0) -> dict:

@@ -121,6 +121,8 @@ def build_index(w, db, train, proj, level_u, pq_init, beta_ids, beta_init, nthre
     L = lib()
     nt = nthreads or threads()
     db, train, proj = _c(db, np.float32), _c(train, np.float32), _c(proj, np.float32)
+    # converted copies are held here for as long as the native calls read them
+    pq_init, level_u, beta_init = _c(pq_init, np.int64), _c(level_u, np.float64), _c(beta_init, np.int64)
     n, d = db.shape
     t0 = time.time()
     if log:
@@ -139,8 +141,8 @@ def build_index(w, db, train, proj, level_u, pq_init, beta_ids, beta_init, nthre
         # 2-level residual codec: first level over the two halves, then the PQ of the residual
         import datagen
         ccent = np.empty((2, ck, w.d_pad // 2), np.float32)
-        _ok(L.lcb_coarse_train(_p(train), train.shape[0], d, _p(proj), w.d_pad, ck,
-                               _p(_c(datagen.coarse_init_ids(w, train.shape[0]), np.int64)), w.pq_iters, nt,
+        cinit = _c(datagen.coarse_init_ids(w, train.shape[0]), np.int64)  # held while the call reads it
+        _ok(L.lcb_coarse_train(_p(train), train.shape[0], d, _p(proj), w.d_pad, ck, _p(cinit), w.pq_iters, nt,
                                _p(ccent)), "lcb_coarse_train")
         tcodes = np.empty((train.shape[0], 2), np.uint16)
         rtrain = np.empty((train.shape[0], w.d_pad), np.float32)
@@ -150,7 +152,7 @@ def build_index(w, db, train, proj, level_u, pq_init, beta_ids, beta_init, nthre
         rdb = np.empty((n, w.d_pad), np.float32)
         _ok(L.lcb_coarse_encode(_p(db), n, d, _p(proj), w.d_pad, ck, _p(ccent), nt, _p(ccodes), _p(rdb)),
             "lcb_coarse_encode")
-        _ok(L.lcb_pq_train(_p(rtrain), rtrain.shape[0], w.d_pad, None, w.d_pad, w.m, _p(_c(pq_init, np.int64)),
+        _ok(L.lcb_pq_train(_p(rtrain), rtrain.shape[0], w.d_pad, None, w.d_pad, w.m, _p(pq_init),
                            w.pq_iters, nt, _p(cent)), "lcb_pq_train")
         _ok(L.lcb_pq_encode(_p(rdb), n, w.d_pad, None, w.d_pad, w.m, _p(cent), nt, _p(codes), cs), "lcb_pq_encode")
         del rdb, rtrain
@@ -159,14 +161,14 @@ def build_index(w, db, train, proj, level_u, pq_init, beta_ids, beta_init, nthre
         _ok(L.lcb_coarse_decode(n, w.d_pad, w.m, _p(cent), _p(codes), cs, ck, _p(ccent), _p(ccodes), nt, _p(rec),
                                 _p(cnorm)), "lcb_coarse_decode")
     else:
-        _ok(L.lcb_pq_train(_p(train), train.shape[0], d, _p(proj), w.d_pad, w.m, _p(_c(pq_init, np.int64)),
+        _ok(L.lcb_pq_train(_p(train), train.shape[0], d, _p(proj), w.d_pad, w.m, _p(pq_init),
                            w.pq_iters, nt, _p(cent)), "lcb_pq_train")
         _ok(L.lcb_pq_encode(_p(db), n, d, _p(proj), w.d_pad, w.m, _p(cent), nt, _p(codes), cs), "lcb_pq_encode")
     t1 = time.time()
     if log:
         log(f"index build: product quantizer done ({t1 - t0:.1f}s)")
     level = np.empty(n, np.int8)
-    rows = int(L.lcb_levels(_p(_c(level_u, np.float64)), n, w.level_ratio, w.max_level_cap, _p(level)))
+    rows = int(L.lcb_levels(_p(level_u), n, w.level_ratio, w.max_level_cap, _p(level)))
     adj0 = np.empty((n, w.deg0), np.int32)
     up_base = np.empty(n, np.int32)
     adj_up = np.empty((max(rows, 1), w.deg_up), np.int32)
@@ -182,7 +184,7 @@ def build_index(w, db, train, proj, level_u, pq_init, beta_ids, beta_init, nthre
     beta = np.empty((w.n_beta, w.k_reg + 1) if mb == 1 else (mb, w.n_beta, w.k_reg + 1), np.float32)
     bids = _c(beta_ids, np.int64)
     _ok(L.lcb_beta_train(_p(db), _p(bids), bids.shape[0], d, _p(proj), w.d_pad, w.m, _p(cent), _p(codes), cs,
-                         _p(adj0), w.deg0, w.k_reg, w.n_beta, mb, _p(_c(beta_init, np.int64)), w.beta_kmeans_iters,
+                         _p(adj0), w.deg0, w.k_reg, w.n_beta, mb, _p(beta_init), w.beta_kmeans_iters,
                          w.em_iters, nt, _p(beta), None, _p(rec)), "lcb_beta_train")
     bidx = np.empty(n if mb == 1 else (n, mb), np.uint8)
     _ok(L.lcb_beta_assign(_p(db), n, d, _p(proj), w.d_pad, w.m, _p(cent), _p(codes), cs, _p(adj0), w.deg0, w.k_reg,
@@ -225,7 +227,8 @@ def opq_train(train, d_pad, m, init_proj, init, opq_iters, km_iters, nthreads=No
     n, d = train.shape
     proj = np.empty((d_pad, d), np.float32)
     hist = np.empty(opq_iters + 1, np.float64)
-    _ok(L.lcb_opq_train(_p(train), n, d, d_pad, m, _p(_c(init_proj, np.float32)), _p(_c(init, np.int64)), opq_iters,
+    init_proj, init = _c(init_proj, np.float32), _c(init, np.int64)  # held while the call reads them
+    _ok(L.lcb_opq_train(_p(train), n, d, d_pad, m, _p(init_proj), _p(init), opq_iters,
                         km_iters, nthreads or threads(), _p(proj), _p(hist)), "lcb_opq_train")
     return proj, hist
 
