@@ -507,6 +507,105 @@ __global__ __launch_bounds__(1024) void refine_f32_generic(RefineArgs a, int m, 
   }
 }
 
+// Refinement for the 2-level codec (float32).  Lane `part` of a candidate's
+// four owns the contiguous coordinates [part Q, part Q + Q): Q / DSUB whole
+// sub-spaces inside one half of the vector, so each neighbour's first-level
+// centroid contributes one contiguous slice of its row.  Neighbours go four at
+// a time so that their loads overlap.  Per coordinate the sum runs over the
+// neighbours in order, the PQ centroid before the first-level one, as in the
+// generic kernel.
+template <int Q, int DSUB>
+__global__ __launch_bounds__(512) void refine_coarse_kernel(RefineArgs a, int m, int staged) {
+  constexpr int NS = Q / DSUB;  // sub-spaces per lane
+  constexpr int DP = 4 * Q;
+  extern __shared__ __align__(16) unsigned char smem[];
+  const size_t cent_bytes = staged ? (size_t(m) * 256 * DSUB * 4 + 15) / 16 * 16 : 0;
+  const float *C = staged ? reinterpret_cast<const float *>(smem) : a.cent;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  unsigned char *wbase = smem + cent_bytes + size_t(wave) * (DP * 4 + a.S_pad * 8);
+  float *yv = reinterpret_cast<float *>(wbase);
+  uint64_t *keys = reinterpret_cast<uint64_t *>(wbase + DP * 4);
+  if (staged)
+    for (int i = threadIdx.x; i < m * 256 * DSUB; i += blockDim.x) reinterpret_cast<float *>(smem)[i] = a.cent[i];
+  __syncthreads();
+  const int part = lane & 3, grp = lane >> 2;
+  const int s0 = part * NS, half = part >> 1;
+  const int spb = m / a.m_beta;  // sub-spaces per codebook block
+  for (int64_t q = int64_t(blockIdx.x) * a.wpb + wave; q < a.nq; q += int64_t(gridDim.x) * a.wpb) {
+    project_query(a, q, yv, lane);
+    wave_sync();
+    const int cn = a.cand_n[q];
+    for (int c0 = 0; c0 < a.S_pad; c0 += 16) {
+      const int c = c0 + grp;
+      int32_t id = candidate_id(a, q, c, cn);
+      for (int jb = 0; id >= 0 && jb < a.m_beta; ++jb)
+        if (a.beta_idx[int64_t(id) * a.m_beta + jb] >= a.n_beta) id = -1;  // malformed input: no candidate
+      float e = 0.f;
+      if (id >= 0) {
+        const int32_t *links = a.adj0 + int64_t(id) * a.deg0;
+        uint32_t bo[NS];  // offset of the beta row of each of the lane's sub-spaces
+#pragma unroll
+        for (int v = 0; v < NS; ++v) {
+          const int jb = (s0 + v) / spb;
+          bo[v] = (uint32_t(jb) * a.n_beta + a.beta_idx[int64_t(id) * a.m_beta + jb]) * uint32_t(a.k_reg + 1);
+        }
+        float acc[Q];
+#pragma unroll
+        for (int i = 0; i < Q; ++i) acc[i] = 0.f;
+        for (int j0 = 0; j0 <= a.k_reg; j0 += 4) {
+          constexpr int NW = (NS + 3) / 4;
+          int32_t g[4];
+          uint32_t cc[4];
+          uint32_t cd[4][NW];  // the lane's code bytes of each neighbour, four to a word
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const int j = j0 + u;
+            int32_t x = j > a.k_reg ? -1 : (j == 0 ? id : links[j - 1]);
+            g[u] = x < 0 || x >= a.n ? -1 : x;  // a missing link is a zero vector
+          }
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            cc[u] = g[u] >= 0 ? a.ccodes[g[u]] : 0u;
+#pragma unroll
+            for (int i = 0; i < NW; ++i) cd[u][i] = 0u;
+#pragma unroll
+            for (int v = 0; v < NS; ++v)
+              cd[u][v >> 2] |= (g[u] >= 0 ? uint32_t(a.codes[size_t(g[u]) * a.code_stride + s0 + v]) : 0u)
+                               << (8 * (v & 3));
+          }
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            if (g[u] < 0) continue;
+            const int j = j0 + u;
+            const float *c1 = a.ccent + (size_t(half) * a.coarse_k + (half ? cc[u] >> 16 : cc[u] & 0xFFFFu)) * (DP / 2) +
+                              (part & 1) * Q;
+#pragma unroll
+            for (int v = 0; v < NS; ++v) {
+              const float w = a.beta[bo[v] + j];
+              const float *cr = C + ((s0 + v) * 256 + int((cd[u][v >> 2] >> (8 * (v & 3))) & 0xFFu)) * DSUB;
+#pragma unroll
+              for (int t = 0; t < DSUB; ++t) acc[v * DSUB + t] += w * cr[t];
+#pragma unroll
+              for (int t = 0; t < DSUB; ++t) acc[v * DSUB + t] += w * c1[v * DSUB + t];
+            }
+          }
+        }
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+          const float df = yv[part * Q + i] - acc[i];
+          e += df * df;
+        }
+      }
+      e = group_sum<4>(e);
+      if (part == 0) keys[c] = id >= 0 ? make_key(e, id) : kKeyMax;
+    }
+    wave_sync();
+    wave_sort(keys, a.S_pad, lane);
+    write_topk(a, q, keys, lane);
+    wave_sync();
+  }
+}
+
 int next_pow2(int x) {
   int p = 1;
   while (p < x) p <<= 1;
@@ -550,11 +649,11 @@ RefineArgs make_args(const lc_index *ix, const float *q, int64_t nq, const int32
 
 // Waves per block and LDS bytes for the staged centroids plus per-wave buffers.
 bool plan_blocks(const lc_index *ix, RefineArgs &a, int cent_elem_bytes, int *lds, int64_t *blocks,
-                 bool stage = true) {
+                 bool stage = true, int max_wpb = 16) {
   const int cent_bytes = stage ? (ix->v.m * 256 * ix->dsub * cent_elem_bytes + 15) / 16 * 16 : 0;
   const int per_wave = ix->v.d_pad * 4 + a.S_pad * 8;
   int wpb = (ix->lds_per_cu - cent_bytes) / per_wave;
-  if (wpb > 16) wpb = 16;
+  if (wpb > max_wpb) wpb = max_wpb;
   if (wpb < 1) return false;
   a.wpb = wpb;
   *lds = cent_bytes + wpb * per_wave;
@@ -603,6 +702,34 @@ int launch_generic(const lc_index *ix, RefineArgs a, hipStream_t st) {
   return hipGetLastError() == hipSuccess ? LC_OK : LC_EHIP;
 }
 
+template <int Q, int DSUB>
+int launch_coarse_q(const lc_index *ix, RefineArgs a, hipStream_t st) {
+  int lds;
+  int64_t blocks;
+  // 8 waves per block: the kernel is built for 512 threads (256 registers a lane)
+  const bool staged = plan_blocks(ix, a, 4, &lds, &blocks, true, 8);
+  if (!staged && !plan_blocks(ix, a, 4, &lds, &blocks, false, 8)) return LC_ENOTSUP;
+  if (hipFuncSetAttribute(reinterpret_cast<const void *>(&refine_coarse_kernel<Q, DSUB>),
+                          hipFuncAttributeMaxDynamicSharedMemorySize, lds) != hipSuccess)
+    return LC_EHIP;
+  hipLaunchKernelGGL((refine_coarse_kernel<Q, DSUB>), dim3(int(blocks)), dim3(64 * a.wpb), lds, st, a, ix->v.m,
+                     int(staged));
+  return hipGetLastError() == hipSuccess ? LC_OK : LC_EHIP;
+}
+
+// 2-level codec: shapes with a quarter of the coordinates per lane (Q = d_pad / 4
+// whole sub-spaces) take refine_coarse_kernel, others the generic kernel.
+int launch_coarse(const lc_index *ix, const RefineArgs &a, hipStream_t st) {
+  const int qd = ix->v.d_pad / 4, ds = ix->dsub;
+  if (ix->v.d_pad % 4 == 0 && qd % ds == 0) {
+#define QSHAPE(QQ, DS) \
+  if (qd == QQ && ds == DS) return launch_coarse_q<QQ, DS>(ix, a, st);
+    QSHAPE(8, 2) QSHAPE(8, 4) QSHAPE(12, 2) QSHAPE(16, 4) QSHAPE(24, 6) QSHAPE(24, 12) QSHAPE(28, 2) QSHAPE(32, 4)
+#undef QSHAPE
+  }
+  return launch_generic(ix, a, st);
+}
+
 }  // namespace
 
 // Specialised shapes (m, dsub, code stride) with 1, 2, 4 or 8 codebook
@@ -622,7 +749,7 @@ int lc_launch_refine(const lc_index *ix, const float *q, int64_t nq, const int32
   // candidate's distance is the float32 one and all are sorted by it, which is the plain kernel
   const bool bf_pass = bf && a.K2 < S;
   const bool spec_mb = a.m_beta == 1 || a.m_beta == 2 || a.m_beta == 4 || a.m_beta == 8;
-  if (a.ccent) return bf_pass ? LC_ENOTSUP : launch_generic(ix, a, st);  // 2-level codec: the float32 kernel
+  if (a.ccent) return bf_pass ? LC_ENOTSUP : launch_coarse(ix, a, st);  // 2-level codec: float32 kernels
 #define SHAPE(MM, DS, CSS)                                                                              \
   if (m == MM && ds == DS && spec_mb)                                                                   \
     return bf_pass ? launch_blocks<MM, DS, CSS, uint16_t>(ix, a, st) : launch_blocks<MM, DS, CSS, float>(ix, a, st);

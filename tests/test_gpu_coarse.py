@@ -54,7 +54,10 @@ def _oracle_topk(ix, q, cand_ids, cand_n, K):
     return {"ids": ids, "d": d}
 
 
-@pytest.mark.parametrize("m,d,d_pad", [(8, 32, None), (16, 96, None), (8, 28, 32)])
+# quarter-vector kernel shapes (d_pad / 4, dsub): (8, 4), (24, 6), (32, 4), (28, 2); m 24 with d 72 has
+# no such kernel (18, 3) and takes the generic float32 refinement
+@pytest.mark.parametrize("m,d,d_pad", [(8, 32, None), (16, 96, None), (8, 28, 32), (32, 128, None), (56, 112, None),
+                                       (24, 72, None)])
 def test_two_level_search_matches_oracle(torch, m, d, d_pad):
     import paper_1804_09996_amd as lc
     w, ix, db, q = _build(m, d, d_pad)
