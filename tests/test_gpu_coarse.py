@@ -150,3 +150,30 @@ def test_zero_first_level_gives_the_one_level_results(torch):
     np.testing.assert_allclose(dbb.cpu().numpy(), da.cpu().numpy(), rtol=1e-5)
     a.close()
     b.close()
+
+
+def test_two_level_batched_form_matches_query(torch):
+    # the batched form (per-query ef, captured step) on a 2-level index: per query the bits of Index.query
+    import paper_1804_09996_amd as lc
+    from paper_1804_09996_amd.batched import BatchedSearcher
+    w, ix, db, q = _build(8, 28, 32)
+    gix = lc.Index.from_index(ix)
+    ef = np.where(np.arange(q.shape[0]) % 3 == 0, 48, 16).astype(np.int32)
+    bs = BatchedSearcher(gix, q.shape[0], 48, 16, 5, precision="f32")
+    bs.set_inputs(q, ef)
+    ids, d = bs.run()
+    ids, d = ids.cpu().numpy(), d.cpu().numpy()
+    for e in (16, 48):
+        sel = np.flatnonzero(ef == e)
+        ri, rd, _ = gix.query(torch.from_numpy(q[sel]), ef=e, ef_max=48, S=16, K=5)
+        assert np.array_equal(ids[sel], ri.cpu().numpy())
+        assert np.array_equal(d[sel].view(np.uint32), rd.cpu().numpy().view(np.uint32))
+    bs.capture()
+    for _ in range(3):
+        gi, gd = bs.run()
+        torch.cuda.synchronize()
+        assert np.array_equal(gi.cpu().numpy(), ids)
+        assert np.array_equal(gd.cpu().numpy().view(np.uint32), d.view(np.uint32))
+        gix.query(torch.from_numpy(q[:7]), ef=16, ef_max=48, S=16, K=5)
+        torch.cuda.synchronize()
+    gix.close()
