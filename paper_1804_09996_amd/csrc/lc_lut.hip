@@ -258,20 +258,100 @@ namespace {
 // entries ||z^h - C1[h][c]||^2, then zero padding up to the row stride.  One
 // thread per table entry, its centroid row read once for the block's queries.
 constexpr int kQR = 8;
+static_assert(kQR == 8, "the query rows are read as two float4");
 
 struct ResLutArgs {
   const float *q, *proj, *cent, *ccent;
   int64_t nq, stride;
   int d, d_pad, m, dsub, k1;
+  int skip_coarse;  // the first-level entries are written by coarse_lut_kernel
   float *lut;
 };
 
+// First-level entries of the 2-level codec on MFMA: ||z - c||^2 =
+// ||z||^2 + ||c||^2 - 2 <z, c> for 64 queries (one 16-query tile per wave) and
+// a chunk of 256 centroids of one half, staged once per block by a coalesced
+// copy.  z = the query's half (queries already projected, or no projection);
+// centroids past k are zero rows, not written.  The halves of unit-norm data
+// have squared norms near 1/2, so the cancellation costs about 1e-7 of that.
+template <int H>
+__global__ __launch_bounds__(256) void coarse_lut_kernel(const float *__restrict__ z, int64_t nq, int zstride,
+                                                          const float *__restrict__ ccent, int k1, int64_t stride,
+                                                          int off, float *__restrict__ lut) {
+  static_assert(H % 4 == 0, "a half of a multiple of 4 coordinates");
+  constexpr int KS = H / 4;
+  __shared__ float4 cc4[256 * H / 4];  // the chunk's centroids, row stride H
+  __shared__ float nc[256];
+  __shared__ float ya[4][16 * H];
+  __shared__ float ny[4][16];
+  const float *cc = reinterpret_cast<const float *>(cc4);
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int nch = (k1 + 255) / 256;
+  const int half = blockIdx.y / nch, c0 = (blockIdx.y % nch) * 256;
+  const int nvalid = k1 - c0 < 256 ? k1 - c0 : 256;
+  const float4 *cs = reinterpret_cast<const float4 *>(ccent + (size_t(half) * k1 + c0) * H);
+  for (int e = tid; e < 256 * H / 4; e += 256)
+    cc4[e] = e < nvalid * H / 4 ? cs[e] : make_float4(0.f, 0.f, 0.f, 0.f);
+  const int64_t q0 = int64_t(blockIdx.x) * 64 + wave * 16;
+  float *yw = ya[wave];
+  for (int e = lane; e < 16 * H; e += 64) {
+    const int i = e / H, t = e % H;
+    const int64_t qi = q0 + i;
+    yw[e] = qi < nq ? z[qi * zstride + half * H + t] : 0.f;
+  }
+  __syncthreads();
+  {
+    float a2 = 0.f;
+#pragma unroll
+    for (int t = 0; t < H; ++t) a2 += cc[tid * H + t] * cc[tid * H + t];
+    nc[tid] = a2;
+  }
+  if (lane < 16) {
+    float a2 = 0.f;
+#pragma unroll
+    for (int t = 0; t < H; ++t) a2 += yw[lane * H + t] * yw[lane * H + t];
+    ny[wave][lane] = a2;
+  }
+  __syncthreads();
+  if (q0 >= nq) return;
+  // v_mfma_f32_16x16x4_f32: lane l supplies A[l % 16][l / 16] and B[l / 16][l % 16]
+  // and receives D[4 (l / 16) + r][l % 16], r = 0..3
+  const int col = lane & 15, kg = lane >> 4;
+  float a[KS];
+#pragma unroll
+  for (int ks = 0; ks < KS; ++ks) a[ks] = yw[col * H + ks * 4 + kg];
+  for (int tile = 0; tile < 16; ++tile) {
+    floatx4 acc = {0.f, 0.f, 0.f, 0.f};
+    const int c = tile * 16 + col;
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks)
+      acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[ks], cc[c * H + ks * 4 + kg], acc, 0, 0, 0);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int64_t qi = q0 + kg * 4 + r;
+      if (qi < nq && c < nvalid)
+        lut[qi * stride + off + int64_t(half) * k1 + c0 + c] = lc::clamp0(ny[wave][kg * 4 + r] + nc[c] - 2.f * acc[r]);
+    }
+  }
+}
+
+template <int H>
+int launch_coarse_lut(const ResLutArgs &a, const float *z, int zstride, hipStream_t st) {
+  const dim3 grid(lc::ceil_div(a.nq, 64), 2 * ((a.k1 + 255) / 256));
+  hipLaunchKernelGGL((coarse_lut_kernel<H>), grid, dim3(256), 0, st, z, a.nq, zstride, a.ccent, a.k1, a.stride,
+                     a.m * 256, a.lut);
+  return hipGetLastError() == hipSuccess ? LC_OK : LC_EHIP;
+}
+
 __global__ __launch_bounds__(256) void lut_res_kernel(ResLutArgs a) {
-  extern __shared__ float zs[];  // [kQR][d_pad]
+  // [d_pad][kQR]: the block's queries side by side, so that one coordinate of all
+  // of them is two 16-byte reads (every lane reads the same address)
+  extern __shared__ float4 zs4[];
+  float *zs = reinterpret_cast<float *>(zs4);
   const int64_t q0 = int64_t(blockIdx.x) * kQR;
   const int nqb = int(a.nq - q0 < kQR ? a.nq - q0 : kQR);
   for (int e = threadIdx.x; e < kQR * a.d_pad; e += blockDim.x) {
-    const int qi = e / a.d_pad, t = e % a.d_pad;
+    const int qi = e % kQR, t = e / kQR;
     float v = 0.f;
     if (qi < nqb) {
       const float *y = a.q + (q0 + qi) * a.d;
@@ -284,6 +364,10 @@ __global__ __launch_bounds__(256) void lut_res_kernel(ResLutArgs a) {
     zs[e] = v;
   }
   __syncthreads();
+  auto zrow = [&](int t, float (&z)[kQR]) {
+    const float4 lo = zs4[t * 2], hi = zs4[t * 2 + 1];
+    z[0] = lo.x, z[1] = lo.y, z[2] = lo.z, z[3] = lo.w, z[4] = hi.x, z[5] = hi.y, z[6] = hi.z, z[7] = hi.w;
+  };
   const int h = a.d_pad / 2, e1 = a.m * 256, e2 = e1 + 2 * a.k1;
   for (int e = threadIdx.x; e < a.stride; e += blockDim.x) {
     float acc[kQR];
@@ -294,19 +378,24 @@ __global__ __launch_bounds__(256) void lut_res_kernel(ResLutArgs a) {
       const float *c = a.cent + int64_t(e) * a.dsub;
       for (int t = 0; t < a.dsub; ++t) {
         const float cv = c[t];
+        float z[kQR];
+        zrow(s * a.dsub + t, z);
 #pragma unroll
-        for (int i = 0; i < kQR; ++i) acc[i] += zs[i * a.d_pad + s * a.dsub + t] * cv;
+        for (int i = 0; i < kQR; ++i) acc[i] += z[i] * cv;
       }
 #pragma unroll
       for (int i = 0; i < kQR; ++i) acc[i] *= -2.f;
     } else if (e < e2) {
+      if (a.skip_coarse) continue;
       const int half = (e - e1) / a.k1;
       const float *c = a.ccent + int64_t(e - e1) * h;
       for (int t = 0; t < h; ++t) {
         const float cv = c[t];
+        float z[kQR];
+        zrow(half * h + t, z);
 #pragma unroll
         for (int i = 0; i < kQR; ++i) {
-          const float df = zs[i * a.d_pad + half * h + t] - cv;
+          const float df = z[i] - cv;
           acc[i] += df * df;
         }
       }
@@ -332,8 +421,21 @@ int launch_res(const lc_index *ix, const float *q, int64_t nq, int dtype, void *
   a.lut = static_cast<float *>(lut);
   const size_t lds = size_t(kQR) * a.d_pad * 4;
   if (lds > 65536) return LC_ENOTSUP;
+  // first-level entries on MFMA when the queries need no projection here and the half has a kernel
+  const int h = a.d_pad / 2;
+  const bool mfma = !a.proj && (h == 16 || h == 24 || h == 32 || h == 36 || h == 48 || h == 56);
+  a.skip_coarse = mfma ? 1 : 0;
   hipLaunchKernelGGL(lut_res_kernel, dim3(lc::ceil_div(nq, kQR)), dim3(256), lds, st, a);
-  return hipGetLastError() == hipSuccess ? LC_OK : LC_EHIP;
+  if (hipGetLastError() != hipSuccess) return LC_EHIP;
+  if (!mfma) return LC_OK;
+  switch (h) {
+    case 16: return launch_coarse_lut<16>(a, q, a.d, st);
+    case 24: return launch_coarse_lut<24>(a, q, a.d, st);
+    case 32: return launch_coarse_lut<32>(a, q, a.d, st);
+    case 36: return launch_coarse_lut<36>(a, q, a.d, st);
+    case 48: return launch_coarse_lut<48>(a, q, a.d, st);
+    default: return launch_coarse_lut<56>(a, q, a.d, st);
+  }
 }
 
 }  // namespace

@@ -83,17 +83,21 @@ def test_two_level_search_matches_oracle(torch, m, d, d_pad):
     gix.close()
 
 
-def test_two_level_tables_layout(torch):
+# (m, d, d_pad, queries projected first): the first-level entries on the VALU with the projection applied
+# in the kernel, else on MFMA (halves of 16 and 48; 32 centroids, one partial chunk of 256)
+@pytest.mark.parametrize("m,d,d_pad,pre", [(8, 28, 32, False), (8, 28, 32, True), (16, 96, None, False)])
+def test_two_level_tables_layout(torch, m, d, d_pad, pre):
     # row q: [m][256] entries -2 <z^s, C[s][c]>, then [2][k] entries ||z^h - C1[h][c]||^2, then zeros
     import paper_1804_09996_amd as lc
-    w, ix, db, q = _build(8, 28, 32)
+    w, ix, db, q = _build(m, d, d_pad)
     gix = lc.Index.from_index(ix)
-    lut, scale = gix.build_lut(torch.from_numpy(q))
+    qt = torch.from_numpy(q)
+    lut, scale = gix.build_lut(gix.project(qt), projected=True) if pre else gix.build_lut(qt)
     assert scale is None and tuple(lut.shape) == (q.shape[0], gix.lut_stride)
     lut = lut.cpu().numpy().astype(np.float64)
     h, ds, k = w.d_pad // 2, w.d_pad // w.m, ix.coarse_k
     for i in range(q.shape[0]):
-        z = ix.proj.astype(np.float64) @ q[i].astype(np.float64)
+        z = q[i].astype(np.float64) if ix.proj is None else ix.proj.astype(np.float64) @ q[i].astype(np.float64)
         ip = np.concatenate([-2.0 * (ix.centroids[s].astype(np.float64) @ z[s * ds:(s + 1) * ds]) for s in range(w.m)])
         ct = np.concatenate([((z[None, j * h:(j + 1) * h] - ix.coarse_cent[j].astype(np.float64)) ** 2).sum(1)
                              for j in range(2)])
