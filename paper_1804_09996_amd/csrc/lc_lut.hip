@@ -269,7 +269,7 @@ struct ResLutArgs {
 };
 
 // First-level entries of the 2-level codec on MFMA: ||z - c||^2 =
-// ||z||^2 + ||c||^2 - 2 <z, c> for 64 queries (one 16-query tile per wave) and
+// ||z||^2 + ||c||^2 - 2 <z, c> for 256 queries (four 16-query tiles per wave) and
 // a chunk of 256 centroids of one half, staged once per block by a coalesced
 // copy.  z = the query's half (queries already projected, or no projection);
 // centroids past k are zero rows, not written.  The halves of unit-norm data
@@ -292,13 +292,6 @@ __global__ __launch_bounds__(256) void coarse_lut_kernel(const float *__restrict
   const float4 *cs = reinterpret_cast<const float4 *>(ccent + (size_t(half) * k1 + c0) * H);
   for (int e = tid; e < 256 * H / 4; e += 256)
     cc4[e] = e < nvalid * H / 4 ? cs[e] : make_float4(0.f, 0.f, 0.f, 0.f);
-  const int64_t q0 = int64_t(blockIdx.x) * 64 + wave * 16;
-  float *yw = ya[wave];
-  for (int e = lane; e < 16 * H; e += 64) {
-    const int i = e / H, t = e % H;
-    const int64_t qi = q0 + i;
-    yw[e] = qi < nq ? z[qi * zstride + half * H + t] : 0.f;
-  }
   __syncthreads();
   {
     float a2 = 0.f;
@@ -306,38 +299,50 @@ __global__ __launch_bounds__(256) void coarse_lut_kernel(const float *__restrict
     for (int t = 0; t < H; ++t) a2 += cc[tid * H + t] * cc[tid * H + t];
     nc[tid] = a2;
   }
-  if (lane < 16) {
-    float a2 = 0.f;
-#pragma unroll
-    for (int t = 0; t < H; ++t) a2 += yw[lane * H + t] * yw[lane * H + t];
-    ny[wave][lane] = a2;
-  }
   __syncthreads();
-  if (q0 >= nq) return;
-  // v_mfma_f32_16x16x4_f32: lane l supplies A[l % 16][l / 16] and B[l / 16][l % 16]
-  // and receives D[4 (l / 16) + r][l % 16], r = 0..3
+  float *yw = ya[wave];
   const int col = lane & 15, kg = lane >> 4;
-  float a[KS];
-#pragma unroll
-  for (int ks = 0; ks < KS; ++ks) a[ks] = yw[col * H + ks * 4 + kg];
-  for (int tile = 0; tile < 16; ++tile) {
-    floatx4 acc = {0.f, 0.f, 0.f, 0.f};
-    const int c = tile * 16 + col;
-#pragma unroll
-    for (int ks = 0; ks < KS; ++ks)
-      acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[ks], cc[c * H + ks * 4 + kg], acc, 0, 0, 0);
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int64_t qi = q0 + kg * 4 + r;
-      if (qi < nq && c < nvalid)
-        lut[qi * stride + off + int64_t(half) * k1 + c0 + c] = lc::clamp0(ny[wave][kg * 4 + r] + nc[c] - 2.f * acc[r]);
+  for (int qt = 0; qt < 4; ++qt) {
+    const int64_t q0 = int64_t(blockIdx.x) * 256 + wave * 64 + qt * 16;
+    if (q0 >= nq) break;
+    for (int e = lane; e < 16 * H; e += 64) {
+      const int i = e / H, t = e % H;
+      const int64_t qi = q0 + i;
+      yw[e] = qi < nq ? z[qi * zstride + half * H + t] : 0.f;
     }
+    lc::wave_sync();
+    if (lane < 16) {
+      float a2 = 0.f;
+#pragma unroll
+      for (int t = 0; t < H; ++t) a2 += yw[lane * H + t] * yw[lane * H + t];
+      ny[wave][lane] = a2;
+    }
+    lc::wave_sync();
+    // v_mfma_f32_16x16x4_f32: lane l supplies A[l % 16][l / 16] and B[l / 16][l % 16]
+    // and receives D[4 (l / 16) + r][l % 16], r = 0..3
+    float a[KS];
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) a[ks] = yw[col * H + ks * 4 + kg];
+    for (int tile = 0; tile < 16; ++tile) {
+      floatx4 acc = {0.f, 0.f, 0.f, 0.f};
+      const int c = tile * 16 + col;
+#pragma unroll
+      for (int ks = 0; ks < KS; ++ks)
+        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[ks], cc[c * H + ks * 4 + kg], acc, 0, 0, 0);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t qi = q0 + kg * 4 + r;
+        if (qi < nq && c < nvalid)
+          lut[qi * stride + off + int64_t(half) * k1 + c0 + c] = lc::clamp0(ny[wave][kg * 4 + r] + nc[c] - 2.f * acc[r]);
+      }
+    }
+    lc::wave_sync();  // yw and ny are rewritten for the next tile
   }
 }
 
 template <int H>
 int launch_coarse_lut(const ResLutArgs &a, const float *z, int zstride, hipStream_t st) {
-  const dim3 grid(lc::ceil_div(a.nq, 64), 2 * ((a.k1 + 255) / 256));
+  const dim3 grid(lc::ceil_div(a.nq, 256), 2 * ((a.k1 + 255) / 256));
   hipLaunchKernelGGL((coarse_lut_kernel<H>), grid, dim3(256), 0, st, z, a.nq, zstride, a.ccent, a.k1, a.stride,
                      a.m * 256, a.lut);
   return hipGetLastError() == hipSuccess ? LC_OK : LC_EHIP;
