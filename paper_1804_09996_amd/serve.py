@@ -52,11 +52,13 @@ class Request:
         return self.done - self.arrival
 
 
-def query_bytes(m: int, S: int, K: int, d: int, lut_bytes: int = 2, d_proj: int = 0) -> int:
+def query_bytes(m: int, S: int, K: int, d: int, lut_bytes: int = 2, d_proj: int = 0, lut_entries: int = 0) -> int:
     """Device bytes one query holds while in flight: its table (+ scales),
     pool output (ids + distances), results, the query itself (and its
-    projection, d_proj values, when the index has one) and its ef."""
-    return m * 256 * lut_bytes + 4 * m + 8 * S + 4 + 8 * K + 4 * d + 4 * d_proj + 4
+    projection, d_proj values, when the index has one) and its ef.
+    ``lut_entries``: table entries per query when not m * 256 (the 2-level
+    codec's row, Index.lut_stride)."""
+    return (lut_entries or m * 256) * lut_bytes + 4 * m + 8 * S + 4 + 8 * K + 4 * d + 4 * d_proj + 4
 
 
 class Scheduler:

@@ -181,3 +181,24 @@ def test_two_level_batched_form_matches_query(torch):
         gix.query(torch.from_numpy(q[:7]), ef=16, ef_max=48, S=16, K=5)
         torch.cuda.synchronize()
     gix.close()
+
+
+def test_two_level_serving_same_alone_and_in_the_mix(torch):
+    # the serving loop on a 2-level index (float32 tables of lut_stride entries): a request's results do not
+    # depend on the batch it rides in
+    import paper_1804_09996_amd as lc
+    from paper_1804_09996_amd import serve
+    w, ix, db, q = _build(8, 28, 32)
+    gix = lc.Index.from_index(ix)
+    S, K, ef_max = 16, 5, 64
+    reqs = serve.poisson_requests(w.d, q, rate_rps=4000.0, n_requests=20, seed=5, efs=(16, 64), max_batch=8)
+    eng = serve.GpuEngine(gix, n_slots=3, slot_queries=32, ef_max=ef_max, S=S, K=K, precision="f32")
+    bpq = serve.query_bytes(w.m, S, K, w.d, lut_bytes=4, d_proj=w.d_pad, lut_entries=gix.lut_stride)
+    stats = serve.serve(eng, serve.Scheduler(3, 32, mem_budget=64 * bpq, bytes_per_query=bpq), reqs)
+    torch.cuda.synchronize()
+    assert stats["requests"] == 20
+    for r in reqs:
+        ids, d, _ = gix.query(torch.from_numpy(r.queries), ef=r.ef, ef_max=ef_max, S=S, K=K)
+        assert np.array_equal(r.ids, ids.cpu().numpy()), r.rid
+        assert np.array_equal(r.dist.view(np.uint32), d.cpu().numpy().view(np.uint32)), r.rid
+    gix.close()
