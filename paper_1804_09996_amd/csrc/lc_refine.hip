@@ -514,13 +514,16 @@ __global__ __launch_bounds__(1024) void refine_f32_generic(RefineArgs a, int m, 
 // a time so that their loads overlap.  Per coordinate the sum runs over the
 // neighbours in order, the PQ centroid before the first-level one, as in the
 // generic kernel.
-template <int Q, int DSUB>
-__global__ __launch_bounds__(512) void refine_coarse_kernel(RefineArgs a, int m, int staged) {
+// STAGED: the PQ centroids in LDS (a compile-time choice, so that their reads
+// are LDS reads rather than generic ones that also wait on global loads).
+template <int Q, int DSUB, bool STAGED>
+__global__ __launch_bounds__(512) void refine_coarse_kernel(RefineArgs a, int m) {
   constexpr int NS = Q / DSUB;  // sub-spaces per lane
   constexpr int DP = 4 * Q;
   extern __shared__ __align__(16) unsigned char smem[];
+  const bool staged = STAGED;
   const size_t cent_bytes = staged ? (size_t(m) * 256 * DSUB * 4 + 15) / 16 * 16 : 0;
-  const float *C = staged ? reinterpret_cast<const float *>(smem) : a.cent;
+  const float *C = STAGED ? reinterpret_cast<const float *>(smem) : a.cent;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   unsigned char *wbase = smem + cent_bytes + size_t(wave) * (DP * 4 + a.S_pad * 8);
   float *yv = reinterpret_cast<float *>(wbase);
@@ -709,11 +712,15 @@ int launch_coarse_q(const lc_index *ix, RefineArgs a, hipStream_t st) {
   // 8 waves per block: the kernel is built for 512 threads (256 registers a lane)
   const bool staged = plan_blocks(ix, a, 4, &lds, &blocks, true, 8);
   if (!staged && !plan_blocks(ix, a, 4, &lds, &blocks, false, 8)) return LC_ENOTSUP;
-  if (hipFuncSetAttribute(reinterpret_cast<const void *>(&refine_coarse_kernel<Q, DSUB>),
-                          hipFuncAttributeMaxDynamicSharedMemorySize, lds) != hipSuccess)
-    return LC_EHIP;
-  hipLaunchKernelGGL((refine_coarse_kernel<Q, DSUB>), dim3(int(blocks)), dim3(64 * a.wpb), lds, st, a, ix->v.m,
-                     int(staged));
+  const void *fn = staged ? reinterpret_cast<const void *>(&refine_coarse_kernel<Q, DSUB, true>)
+                          : reinterpret_cast<const void *>(&refine_coarse_kernel<Q, DSUB, false>);
+  if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, lds) != hipSuccess) return LC_EHIP;
+  if (staged)
+    hipLaunchKernelGGL((refine_coarse_kernel<Q, DSUB, true>), dim3(int(blocks)), dim3(64 * a.wpb), lds, st, a,
+                       ix->v.m);
+  else
+    hipLaunchKernelGGL((refine_coarse_kernel<Q, DSUB, false>), dim3(int(blocks)), dim3(64 * a.wpb), lds, st, a,
+                       ix->v.m);
   return hipGetLastError() == hipSuccess ? LC_OK : LC_EHIP;
 }
 
