@@ -446,11 +446,13 @@ __global__ __launch_bounds__(1024) void refine_kernel(RefineArgs a) {
 // its sub-spaces one at a time and re-reads the code byte of each neighbour.
 // staged = 0: the centroids do not fit LDS and are read from global memory
 // (cached); the arithmetic is the same.
-__global__ __launch_bounds__(1024) void refine_f32_generic(RefineArgs a, int m, int dsub, int staged) {
+template <bool STAGED>  // the centroids in LDS: read with LDS loads
+__global__ __launch_bounds__(1024) void refine_f32_generic(RefineArgs a, int m, int dsub) {
   const int DP = m * dsub;
   extern __shared__ __align__(16) unsigned char smem[];
+  const bool staged = STAGED;
   const size_t cent_bytes = staged ? (size_t(m) * 256 * dsub * 4 + 15) / 16 * 16 : 0;
-  const float *C = staged ? reinterpret_cast<const float *>(smem) : a.cent;
+  const float *C = STAGED ? reinterpret_cast<const float *>(smem) : a.cent;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   unsigned char *wbase = smem + cent_bytes + size_t(wave) * (DP * 4 + a.S_pad * 8);
   float *yv = reinterpret_cast<float *>(wbase);
@@ -697,11 +699,13 @@ int launch_generic(const lc_index *ix, RefineArgs a, hipStream_t st) {
   // centroids in LDS when they fit beside the per-wave buffers, else read from global memory
   const bool staged = plan_blocks(ix, a, 4, &lds, &blocks);
   if (!staged && !plan_blocks(ix, a, 4, &lds, &blocks, false)) return LC_ENOTSUP;
-  if (hipFuncSetAttribute(reinterpret_cast<const void *>(&refine_f32_generic),
-                          hipFuncAttributeMaxDynamicSharedMemorySize, lds) != hipSuccess)
-    return LC_EHIP;
-  hipLaunchKernelGGL(refine_f32_generic, dim3(int(blocks)), dim3(64 * a.wpb), lds, st, a, ix->v.m, ix->dsub,
-                     int(staged));
+  const void *fn = staged ? reinterpret_cast<const void *>(&refine_f32_generic<true>)
+                          : reinterpret_cast<const void *>(&refine_f32_generic<false>);
+  if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, lds) != hipSuccess) return LC_EHIP;
+  if (staged)
+    hipLaunchKernelGGL(refine_f32_generic<true>, dim3(int(blocks)), dim3(64 * a.wpb), lds, st, a, ix->v.m, ix->dsub);
+  else
+    hipLaunchKernelGGL(refine_f32_generic<false>, dim3(int(blocks)), dim3(64 * a.wpb), lds, st, a, ix->v.m, ix->dsub);
   return hipGetLastError() == hipSuccess ? LC_OK : LC_EHIP;
 }
 
