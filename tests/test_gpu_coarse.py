@@ -202,3 +202,28 @@ def test_two_level_serving_same_alone_and_in_the_mix(torch):
         assert np.array_equal(r.ids, ids.cpu().numpy()), r.rid
         assert np.array_equal(r.dist.view(np.uint32), d.cpu().numpy().view(np.uint32)), r.rid
     gix.close()
+
+
+def test_two_level_two_chunks_of_first_level_centroids(torch):
+    # k = 300: the MFMA first-level tables in two chunks (256 and 44 centroids); values and search
+    import paper_1804_09996_amd as lc
+    w, ix, db, q = _build(16, 96, None, k=300)
+    assert ix.coarse_k == 300
+    gix = lc.Index.from_index(ix)
+    lut, _ = gix.build_lut(torch.from_numpy(q))
+    lut = lut.cpu().numpy().astype(np.float64)
+    h, base = w.d_pad // 2, w.m * 256
+    for i in range(q.shape[0]):
+        z = q[i].astype(np.float64)
+        ct = np.concatenate([((z[None, j * h:(j + 1) * h] - ix.coarse_cent[j].astype(np.float64)) ** 2).sum(1)
+                             for j in range(2)])
+        np.testing.assert_allclose(lut[i, base:base + 600], ct, rtol=1e-5, atol=1e-6)
+        assert (lut[i, base + 600:] == 0).all()
+    o = ix.search(q, w.ef, w.shortlist, w.topk)
+    ids, dist, r = gix.query(torch.from_numpy(q), ef=w.ef, ef_max=w.ef, S=w.shortlist, K=w.topk, stats=True)
+    cand = r.cand_ids.cpu().numpy()
+    assert np.mean([np.array_equal(cand[i], o["cand_ids"][i]) for i in range(q.shape[0])]) >= 0.9
+    ref = _oracle_topk(ix, q, cand, r.cand_n.cpu().numpy(), w.topk)
+    s = parity.summarize(ix, q, ids.cpu().numpy(), dist.cpu().numpy(), ref)
+    assert s["exact_frac"] == 1.0 and s["max_rel_err"] <= 1e-5
+    gix.close()
