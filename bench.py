@@ -42,7 +42,7 @@ def walk_kernel_name(m, precision, ef, S, coarse=False):
     to 128 entries, in LDS beyond."""
     t = "half" if precision != "f32" else "float"
     if coarse:
-        t = "rfloat"  # the 2-level codec's table type
+        t = "rhalf" if precision != "f32" else "rfloat"  # the 2-level codec's table types
     w_cap = -(-max(ef, S) // 64) * 64
     return f"walk_reg_kernel<{m},{t},2,false>" if w_cap <= 128 else f"walk_kernel<{m},{t},false>"
 
@@ -378,7 +378,7 @@ def main():
     ap.add_argument("--opq-iters", type=int, default=0,
                     help="learn the rotation ahead of PQ (OPQ) with this many rotation steps (0 = the workload's)")
     ap.add_argument("--coarse-k", type=int, default=0,
-                    help="2-level residual codec: first-level centroids per half (4096 = PQ2x12; plain form, f32)")
+                    help="2-level residual codec: first-level centroids per half (4096 = PQ2x12; plain form, f32 or f16)")
     ap.add_argument("--max-evals", type=int, default=0,
                     help="budget T on level-0 distance evaluations per query (0 = none; plain and both forms)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
@@ -418,8 +418,9 @@ def main():
     if args.opq_iters:
         w = dataclasses.replace(w, opq_iters=args.opq_iters)
     if args.coarse_k:
-        if args.form != "plain" or args.precision != "f32":
-            raise SystemExit("--coarse-k takes --form plain --precision f32 (the fp16 tables cover the one-level codec)")
+        if args.form != "plain" or args.precision == "f16+bf16":
+            raise SystemExit("--coarse-k takes --form plain with --precision f32 or f16 (the bf16 refinement covers "
+                             "the one-level codec)")
         w = dataclasses.replace(w, coarse_k=args.coarse_k)
     dev = torch.device("cuda:0")
     t0 = time.time()

@@ -113,10 +113,11 @@ typedef struct lc_index lc_index;
 int lc_index_bind(const lc_index_view *view, lc_index **out);
 void lc_index_release(lc_index *ix);
 
-/* Entries per query of a distance table: m * 256 for the one-level codec;
- * for the 2-level codec m * 256 + 2 * coarse_k rounded up to a multiple of 64
- * (table layout below).  0 for a NULL index. */
-int64_t lc_lut_stride(const lc_index *ix);
+/* Elements of lut_dtype per query row of a distance table: m * 256 for the
+ * one-level codec; for the 2-level codec the row holds m * 256 entries of
+ * lut_dtype, then 2 * coarse_k float32 entries, and is padded to a multiple
+ * of 256 bytes (layout below).  0 for a NULL index or another type. */
+int64_t lc_lut_stride(const lc_index *ix, int lut_dtype);
 
 /* Distance tables, Sec. 4.1 (asymmetric distances):
  *   LUT[q][s][c] = || (P y_q)^s - C[s][c] ||^2,  s < m, c < 256.
@@ -126,13 +127,15 @@ int64_t lc_lut_stride(const lc_index *ix);
  *      rounded to nearest, with lut_scale f32 [nq][m] a power of two per
  *      (query, sub-space) that maps the largest entry of the row to at most
  *      2^15 (precision form; lut_scale is NULL for F32).
- * 2-level codec (coarse_k > 0; LC_LUT_F32 only, else LC_ENOTSUP): with
- * z = P y_q, c the first-level and r the second-level reconstruction,
+ * 2-level codec (coarse_k > 0): with z = P y_q, c the first-level and r the
+ * second-level reconstruction,
  * ||z - c - r||^2 = ||z^0 - c^0||^2 + ||z^1 - c^1||^2 - 2 <z, r> + coarse_norm,
- * so row q of lut (lc_lut_stride entries) holds [m][256] entries
- * -2 <z^s, C[s][c]>, then [2][coarse_k] entries ||z^h - C1[h][c]||^2, then
- * padding; lc_search adds a node's two first-level entries and its
- * coarse_norm to the sum over its codes, and clamps the result at 0.
+ * so row q of lut (lc_lut_stride(ix, lut_dtype) elements) holds [m][256]
+ * entries -2 <z^s, C[s][c]> (LC_LUT_F16: divided by lut_scale[q][s], a power
+ * of two mapping the row's largest magnitude to at most 2^15), then
+ * [2][coarse_k] float32 entries ||z^h - C1[h][c]||^2, then zero padding;
+ * lc_search adds a node's two first-level entries and its coarse_norm to the
+ * sum over its codes, and clamps the result at 0.
  * nq == 0 is a no-op. */
 int lc_build_lut(const lc_index *ix, const float *q, int64_t nq, int lut_dtype, void *lut,
                  float *lut_scale, void *stream);

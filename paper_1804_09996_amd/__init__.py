@@ -99,7 +99,7 @@ def lib():
         L.lc_project_queries.argtypes = [p, p, i64, p, p]
         L.lc_build_lut_projected.argtypes = [p, p, i64, C.c_int, p, p, p]
         L.lc_refine_projected.argtypes = [p, p, i64, p, p, i32, i32, C.c_int, p, p, p]
-        L.lc_lut_stride.argtypes = [p]
+        L.lc_lut_stride.argtypes = [p, C.c_int]
         L.lc_lut_stride.restype = i64
         _lib = L
     return _lib
@@ -210,7 +210,8 @@ class Index:
         self.n, self.m, self.d, self.d_pad = v.n, v.m, v.d, v.d_pad
         self.k_reg = v.k_reg
         self.coarse_k = v.coarse_k
-        self.lut_stride = int(L.lc_lut_stride(h))
+        self.lut_stride = int(L.lc_lut_stride(h, LC_LUT_F32))      # float32 table: floats per row
+        self.lut_stride_f16 = int(L.lc_lut_stride(h, LC_LUT_F16))  # fp16 table: 16-bit elements per row
         self._ws = None
 
     @classmethod
@@ -236,6 +237,11 @@ class Index:
         except Exception:
             pass
 
+    def refine_mode(self, precision: str) -> int:
+        """Refinement for a precision name: "f16" is the bf16 refinement with the
+        exact fp32 re-score, except on a 2-level index (float32 refinement)."""
+        return LC_REFINE_BF16_RESCORE if precision == "f16" and not self.coarse_k else LC_REFINE_F32
+
     # -- the three calls of the path ---------------------------------------
     @property
     def has_projection(self) -> bool:
@@ -260,7 +266,8 @@ class Index:
             lut = torch.empty(shape, dtype=torch.float32, device=self.device)
             scale = None
         else:
-            lut = torch.empty((nq, self.m, 256), dtype=torch.float16, device=self.device)
+            shape = (nq, self.lut_stride_f16) if self.coarse_k else (nq, self.m, 256)
+            lut = torch.empty(shape, dtype=torch.float16, device=self.device)
             scale = torch.empty((nq, self.m), dtype=torch.float32, device=self.device)
         fn = lib().lc_build_lut_projected if projected else lib().lc_build_lut
         _check(fn(self.handle, _ptr(q), nq, lut_dtype, _ptr(lut), _ptr(scale), _stream(torch, self.device)),
@@ -350,13 +357,13 @@ class Index:
               sched: Optional[Schedule] = None, precision: str = "f32", max_evals: int = 0):
         """The whole path: tables, walk and short-list, refinement and top-K.
         ``precision="f16"`` selects the fp16 table and the bf16 refinement
-        with exact fp32 re-scoring of the final candidates."""
+        with exact fp32 re-scoring of the final candidates (on a 2-level index
+        the fp16 table and the float32 refinement)."""
         lp = precision == "f16"
         pj = self.has_projection  # project the batch once for the tables and the refinement
         if pj:
             q = self.project(q)
         lut, scale = self.build_lut(q, LC_LUT_F16 if lp else LC_LUT_F32, projected=pj)
         r = self.search(lut, scale, ef=ef, ef_max=ef_max, S=S, stats=stats, sched=sched, max_evals=max_evals)
-        ids, d = self.refine(q, r.cand_ids, r.cand_n, K, LC_REFINE_BF16_RESCORE if lp else LC_REFINE_F32,
-                             projected=pj)
+        ids, d = self.refine(q, r.cand_ids, r.cand_n, K, self.refine_mode(precision), projected=pj)
         return ids, d, r

@@ -23,7 +23,7 @@ from typing import List, Optional, Sequence
 
 import numpy as np
 
-from . import LC_LUT_F16, LC_LUT_F32, LC_REFINE_BF16_RESCORE, LC_REFINE_F32, SearchResult, _check, _stream, autotune, \
+from . import LC_LUT_F16, LC_LUT_F32, SearchResult, _check, _stream, autotune, \
     lib
 
 
@@ -66,7 +66,7 @@ class BatchedSearcher:
         self.torch, self.gix = torch, gix
         self.nq, self.ef_max, self.S, self.K = nq, ef_max, S, K
         self.lut_dtype = LC_LUT_F16 if precision == "f16" else LC_LUT_F32
-        self.refine_p = LC_REFINE_BF16_RESCORE if precision == "f16" else LC_REFINE_F32
+        self.refine_p = gix.refine_mode(precision)
         dev = gix.device
         # the batch in (class, longest ef first) order, and the map back to query order
         self.q = torch.empty((nq, gix.d), dtype=torch.float32, device=dev)

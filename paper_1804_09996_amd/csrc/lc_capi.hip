@@ -76,7 +76,10 @@ int lc_index_bind(const lc_index_view *v, lc_index **out) {
 
 void lc_index_release(lc_index *ix) { delete ix; }
 
-int64_t lc_lut_stride(const lc_index *ix) { return ix ? lc_lut_entries(ix) : 0; }
+int64_t lc_lut_stride(const lc_index *ix, int lut_dtype) {
+  if (!ix || (lut_dtype != LC_LUT_F32 && lut_dtype != LC_LUT_F16)) return 0;
+  return lc_lut_row_bytes(ix, lut_dtype) / (lut_dtype == LC_LUT_F16 ? 2 : 4);
+}
 
 namespace {
 int build_lut(const lc_index *ix, const float *q, int64_t nq, int lut_dtype, void *lut, float *lut_scale,

@@ -77,13 +77,16 @@ inline int ceil_div(int64_t a, int64_t b) { return int((a + b - 1) / b); }
 
 }  // namespace lc
 
-// Entries per query of a distance table: m * 256, or for the 2-level codec
-// m * 256 + 2 * coarse_k rounded up to a multiple of 64.
-inline int64_t lc_lut_entries(const lc_index *ix) {
-  const int64_t base = int64_t(ix->v.m) * 256;
+// Bytes of one query's distance-table row: m * 256 entries of 4 (F32) or 2
+// (F16) bytes; for the 2-level codec then 2 * coarse_k float32 first-level
+// entries, the row padded to a multiple of 256 bytes.
+inline int64_t lc_lut_row_bytes(const lc_index *ix, int dtype) {
+  const int64_t base = int64_t(ix->v.m) * 256 * (dtype == LC_LUT_F16 ? 2 : 4);
   if (ix->v.coarse_k <= 0) return base;
-  return (base + 2 * int64_t(ix->v.coarse_k) + 63) / 64 * 64;
+  return (base + 8 * int64_t(ix->v.coarse_k) + 255) / 256 * 256;
 }
+// Float32 entries per row (the float32 table).
+inline int64_t lc_lut_entries(const lc_index *ix) { return lc_lut_row_bytes(ix, LC_LUT_F32) / 4; }
 
 // Launchers (return LC_* codes).
 int lc_launch_project(const lc_index *ix, const float *q, int64_t nq, float *out, hipStream_t st);

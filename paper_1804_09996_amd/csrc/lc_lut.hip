@@ -262,10 +262,13 @@ static_assert(kQR == 8, "the query rows are read as two float4");
 
 struct ResLutArgs {
   const float *q, *proj, *cent, *ccent;
-  int64_t nq, stride;
+  int64_t nq, row_bytes, row_floats;
   int d, d_pad, m, dsub, k1;
+  int coff;         // float offset of the first-level entries in a row
+  int f16;          // inner-product entries as fp16 with a power-of-two scale per row
   int skip_coarse;  // the first-level entries are written by coarse_lut_kernel
-  float *lut;
+  unsigned char *lut;
+  float *scale;     // [nq][m] (f16)
 };
 
 // First-level entries of the 2-level codec on MFMA: ||z - c||^2 =
@@ -343,8 +346,8 @@ __global__ __launch_bounds__(256) void coarse_lut_kernel(const float *__restrict
 template <int H>
 int launch_coarse_lut(const ResLutArgs &a, const float *z, int zstride, hipStream_t st) {
   const dim3 grid(lc::ceil_div(a.nq, 256), 2 * ((a.k1 + 255) / 256));
-  hipLaunchKernelGGL((coarse_lut_kernel<H>), grid, dim3(256), 0, st, z, a.nq, zstride, a.ccent, a.k1, a.stride,
-                     a.m * 256, a.lut);
+  hipLaunchKernelGGL((coarse_lut_kernel<H>), grid, dim3(256), 0, st, z, a.nq, zstride, a.ccent, a.k1, a.row_floats,
+                     a.coff, reinterpret_cast<float *>(a.lut));
   return hipGetLastError() == hipSuccess ? LC_OK : LC_EHIP;
 }
 
@@ -352,10 +355,12 @@ __global__ __launch_bounds__(256) void lut_res_kernel(ResLutArgs a) {
   // [d_pad][kQR]: the block's queries side by side, so that one coordinate of all
   // of them is two 16-byte reads (every lane reads the same address)
   extern __shared__ float4 zs4[];
+  __shared__ float red[4][kQR];
   float *zs = reinterpret_cast<float *>(zs4);
   const int64_t q0 = int64_t(blockIdx.x) * kQR;
   const int nqb = int(a.nq - q0 < kQR ? a.nq - q0 : kQR);
-  for (int e = threadIdx.x; e < kQR * a.d_pad; e += blockDim.x) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  for (int e = tid; e < kQR * a.d_pad; e += blockDim.x) {
     const int qi = e % kQR, t = e / kQR;
     float v = 0.f;
     if (qi < nqb) {
@@ -373,27 +378,60 @@ __global__ __launch_bounds__(256) void lut_res_kernel(ResLutArgs a) {
     const float4 lo = zs4[t * 2], hi = zs4[t * 2 + 1];
     z[0] = lo.x, z[1] = lo.y, z[2] = lo.z, z[3] = lo.w, z[4] = hi.x, z[5] = hi.y, z[6] = hi.z, z[7] = hi.w;
   };
-  const int h = a.d_pad / 2, e1 = a.m * 256, e2 = e1 + 2 * a.k1;
-  for (int e = threadIdx.x; e < a.stride; e += blockDim.x) {
+  auto row = [&](int i) { return a.lut + (q0 + i) * a.row_bytes; };
+  // inner-product rows, one row of 256 entries per pass (one entry per thread)
+  for (int s = 0; s < a.m; ++s) {
+    const int e = s * 256 + tid;
     float acc[kQR];
 #pragma unroll
     for (int i = 0; i < kQR; ++i) acc[i] = 0.f;
-    if (e < e1) {
-      const int s = e >> 8;
-      const float *c = a.cent + int64_t(e) * a.dsub;
-      for (int t = 0; t < a.dsub; ++t) {
-        const float cv = c[t];
-        float z[kQR];
-        zrow(s * a.dsub + t, z);
+    const float *c = a.cent + int64_t(e) * a.dsub;
+    for (int t = 0; t < a.dsub; ++t) {
+      const float cv = c[t];
+      float z[kQR];
+      zrow(s * a.dsub + t, z);
 #pragma unroll
-        for (int i = 0; i < kQR; ++i) acc[i] += z[i] * cv;
+      for (int i = 0; i < kQR; ++i) acc[i] += z[i] * cv;
+    }
+#pragma unroll
+    for (int i = 0; i < kQR; ++i) acc[i] *= -2.f;
+    if (!a.f16) {
+      for (int i = 0; i < nqb; ++i) reinterpret_cast<float *>(row(i))[e] = acc[i];
+      continue;
+    }
+    // the row's largest magnitude per query: over the wave, then over the four waves
+    float mx[kQR];
+#pragma unroll
+    for (int i = 0; i < kQR; ++i) {
+      mx[i] = fabsf(acc[i]);
+      for (int o = 32; o >= 1; o >>= 1) mx[i] = fmaxf(mx[i], __shfl_xor(mx[i], o));
+    }
+    if (lane == 0)
+#pragma unroll
+      for (int i = 0; i < kQR; ++i) red[wave][i] = mx[i];
+    __syncthreads();
+    for (int i = 0; i < nqb; ++i) {
+      const float m4 = fmaxf(fmaxf(red[0][i], red[1][i]), fmaxf(red[2][i], red[3][i]));
+      int ex = 0;
+      if (m4 > 0.f) {
+        frexpf(m4 * (1.f / 32768.f), &ex);  // m4 / 2^15 = f * 2^ex, f in [0.5, 1)
+        ex = ex < -100 ? -100 : (ex > 100 ? 100 : ex);
       }
+      reinterpret_cast<__half *>(row(i))[e] = __float2half_rn(acc[i] * ldexpf(1.f, -ex));
+      if (tid == 0) a.scale[(q0 + i) * a.m + s] = ldexpf(1.f, ex);
+    }
+    __syncthreads();  // red is rewritten for the next row
+  }
+  // first-level entries (unless on MFMA) and the padding, float32
+  const int h = a.d_pad / 2;
+  for (int e = tid; e < a.row_floats - a.coff; e += blockDim.x) {
+    float acc[kQR];
 #pragma unroll
-      for (int i = 0; i < kQR; ++i) acc[i] *= -2.f;
-    } else if (e < e2) {
+    for (int i = 0; i < kQR; ++i) acc[i] = 0.f;
+    if (e < 2 * a.k1) {
       if (a.skip_coarse) continue;
-      const int half = (e - e1) / a.k1;
-      const float *c = a.ccent + int64_t(e - e1) * h;
+      const int half = e / a.k1;
+      const float *c = a.ccent + int64_t(e) * h;
       for (int t = 0; t < h; ++t) {
         const float cv = c[t];
         float z[kQR];
@@ -405,25 +443,30 @@ __global__ __launch_bounds__(256) void lut_res_kernel(ResLutArgs a) {
         }
       }
     }
-    for (int i = 0; i < nqb; ++i) a.lut[(q0 + i) * a.stride + e] = acc[i];
+    for (int i = 0; i < nqb; ++i) reinterpret_cast<float *>(row(i))[a.coff + e] = acc[i];
   }
 }
 
-int launch_res(const lc_index *ix, const float *q, int64_t nq, int dtype, void *lut, bool projected, hipStream_t st) {
-  if (dtype != LC_LUT_F32) return LC_ENOTSUP;
+int launch_res(const lc_index *ix, const float *q, int64_t nq, int dtype, void *lut, float *scale, bool projected,
+               hipStream_t st) {
+  if (dtype == LC_LUT_F16 && !scale) return LC_EINVAL;
   ResLutArgs a;
   a.q = q;
   a.proj = projected ? nullptr : ix->v.proj;
   a.cent = ix->v.centroids;
   a.ccent = ix->v.coarse_cent;
   a.nq = nq;
-  a.stride = lc_lut_entries(ix);
+  a.row_bytes = lc_lut_row_bytes(ix, dtype);
+  a.row_floats = a.row_bytes / 4;
+  a.f16 = dtype == LC_LUT_F16;
+  a.coff = ix->v.m * 256 * (a.f16 ? 2 : 4) / 4;
+  a.scale = scale;
   a.d = projected ? ix->v.d_pad : ix->v.d;
   a.d_pad = ix->v.d_pad;
   a.m = ix->v.m;
   a.dsub = ix->dsub;
   a.k1 = ix->v.coarse_k;
-  a.lut = static_cast<float *>(lut);
+  a.lut = static_cast<unsigned char *>(lut);
   const size_t lds = size_t(kQR) * a.d_pad * 4;
   if (lds > 65536) return LC_ENOTSUP;
   // first-level entries on MFMA when the queries need no projection here and the half has a kernel
@@ -449,7 +492,7 @@ int lc_launch_lut(const lc_index *ix, const float *q, int64_t nq, int dtype, voi
                   bool projected, hipStream_t st) {
   if (dtype != LC_LUT_F32 && dtype != LC_LUT_F16) return LC_ENOTSUP;
   if (nq > int64_t(0x7FFFFFFF) * 16) return LC_EINVAL;
-  if (ix->v.coarse_k > 0) return launch_res(ix, q, nq, dtype, lut, projected, st);
+  if (ix->v.coarse_k > 0) return launch_res(ix, q, nq, dtype, lut, scale, projected, st);
   hipError_t e;
   switch (ix->dsub) {
 #define CASE(DS) \

@@ -80,16 +80,23 @@ __device__ __forceinline__ float lut_at(const __half *lut, const float *sc, int 
 }
 
 // Table of the 2-level codec (Sec. 5.1): its [m][256] part holds
-// -2 <z^s, C[s][c]>; a node's key adds its two first-level entries (read from
-// the query's table in global memory) and its stored term, clamped at 0.
+// -2 <z^s, C[s][c]> (rfloat: float32; rhalf: fp16 times its row's power-of-two
+// scale); a node's key adds its two first-level entries (float32, read from the
+// query's table row in global memory) and its stored term, clamped at 0.
 struct rfloat {
   float v;
+};
+struct rhalf {
+  __half v;
 };
 __device__ __forceinline__ float lut_at(const rfloat *lut, const float *, int s, uint32_t c) {
   return lut[s * 256 + c].v;
 }
+__device__ __forceinline__ float lut_at(const rhalf *lut, const float *sc, int s, uint32_t c) {
+  return __half2float(lut[s * 256 + c].v) * sc[s];
+}
 template <typename T>
-constexpr bool kRes = std::is_same<T, rfloat>::value;
+constexpr bool kRes = std::is_same<T, rfloat>::value || std::is_same<T, rhalf>::value;
 
 // First-level entries of node id plus its stored term (2-level codec).
 __device__ __forceinline__ float coarse_term(const WalkArgs &a, const float *ctab, int32_t id) {
@@ -865,7 +872,8 @@ __global__ __launch_bounds__(64) void walk_kernel(WalkArgs a) {
       // stage the table (and its row scales), clear the visited table
       const float4 *src = reinterpret_cast<const float4 *>(static_cast<const T *>(a.lut) + q * a.lut_stride);
       [[maybe_unused]] const float *ctab =
-          kRes<T> ? reinterpret_cast<const float *>(a.lut) + q * a.lut_stride + M * 256 : nullptr;
+          kRes<T> ? reinterpret_cast<const float *>(static_cast<const T *>(a.lut) + q * a.lut_stride + M * 256)
+                  : nullptr;
       for (int i = lane; i < kLutBytes / 16; i += 64) reinterpret_cast<float4 *>(lut)[i] = src[i];
       if (sizeof(T) == 2)
         for (int i = lane; i < M; i += 64) sc[i] = a.scale[q * M + i];
@@ -1126,7 +1134,8 @@ __global__ __launch_bounds__(64) void walk_reg_kernel(WalkArgs a) {
       // stage the table, take its row scales into registers, clear the visited table
       const float4 *src = reinterpret_cast<const float4 *>(static_cast<const T *>(a.lut) + q * a.lut_stride);
       [[maybe_unused]] const float *ctab =
-          kRes<T> ? reinterpret_cast<const float *>(a.lut) + q * a.lut_stride + M * 256 : nullptr;
+          kRes<T> ? reinterpret_cast<const float *>(static_cast<const T *>(a.lut) + q * a.lut_stride + M * 256)
+                  : nullptr;
       for (int i = lane; i < kLutBytes / 16; i += 64) reinterpret_cast<float4 *>(lut)[i] = src[i];
       float scr[sizeof(T) == 2 ? M : 1];
 #pragma unroll
@@ -1335,7 +1344,8 @@ __global__ __launch_bounds__(64) void walk_cache_kernel(WalkArgs a) {
 
       const float4 *src = reinterpret_cast<const float4 *>(static_cast<const T *>(a.lut) + q * a.lut_stride);
       [[maybe_unused]] const float *ctab =
-          kRes<T> ? reinterpret_cast<const float *>(a.lut) + q * a.lut_stride + M * 256 : nullptr;
+          kRes<T> ? reinterpret_cast<const float *>(static_cast<const T *>(a.lut) + q * a.lut_stride + M * 256)
+                  : nullptr;
       for (int i = lane; i < kLutBytes / 16; i += 64) reinterpret_cast<float4 *>(lut)[i] = src[i];
       if (sizeof(T) == 2)
         for (int i = lane; i < M; i += 64) sc[i] = a.scale[q * M + i];
@@ -1627,7 +1637,7 @@ int launch_m(const lc_index *ix, const void *lut, const float *scale, int64_t nq
   a.ccodes = reinterpret_cast<const uint32_t *>(ix->v.coarse_codes);
   a.cnorm = ix->v.coarse_norm;
   a.coarse_k = ix->v.coarse_k;
-  a.lut_stride = lc_lut_entries(ix);
+  a.lut_stride = lc_lut_row_bytes(ix, sizeof(T) == 2 ? LC_LUT_F16 : LC_LUT_F32) / int64_t(sizeof(T));
   return max_d > 0 ? launch_kernel<M, T, true>(p, sc, a, st) : launch_kernel<M, T, false>(p, sc, a, st);
 }
 
@@ -1657,13 +1667,14 @@ int lc_launch_walk(const lc_index *ix, const void *lut, int dtype, const float *
   if (dtype != LC_LUT_F32 && dtype != LC_LUT_F16) return LC_ENOTSUP;
   if (!valid_schedule(sched)) return LC_EINVAL;
   const lc_schedule *sc = sched ? sched : &kDefaultSchedule;
-  if (ix->v.coarse_k > 0) {  // 2-level codec: float32 tables only
-    if (dtype != LC_LUT_F32) return LC_ENOTSUP;
+  if (ix->v.coarse_k > 0) {  // 2-level codec
     switch (ix->v.m) {
-#define CASE(MM)                                                                                       \
-  case MM:                                                                                             \
-    return launch_m<MM, rfloat>(ix, lut, scale, nq, ef, ef_max, S, max_d, order, cand_ids, cand_adc, cand_n, \
-                                stats, ws, ws_bytes, sc, st);
+#define CASE(MM)                                                                                              \
+  case MM:                                                                                                    \
+    return dtype == LC_LUT_F32 ? launch_m<MM, rfloat>(ix, lut, scale, nq, ef, ef_max, S, max_d, order,       \
+                                                      cand_ids, cand_adc, cand_n, stats, ws, ws_bytes, sc, st) \
+                               : launch_m<MM, rhalf>(ix, lut, scale, nq, ef, ef_max, S, max_d, order,        \
+                                                     cand_ids, cand_adc, cand_n, stats, ws, ws_bytes, sc, st);
       LC_FOR_EACH_M(CASE)
 #undef CASE
       default: return LC_ENOTSUP;

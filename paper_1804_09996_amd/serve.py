@@ -124,7 +124,7 @@ class GpuEngine:
         self.gix, self.ef_max, self.S, self.K = gix, ef_max, S, K
         self.sched = sched
         self.lut_dtype = lc.LC_LUT_F16 if precision == "f16" else lc.LC_LUT_F32
-        self.refine_p = lc.LC_REFINE_BF16_RESCORE if precision == "f16" else lc.LC_REFINE_F32
+        self.refine_p = gix.refine_mode(precision)
         dev = gix.device
         Q, d, m = slot_queries, gix.d, gix.m
         # an index with a projection projects each batch once, for the tables and the refinement, as
@@ -143,7 +143,8 @@ class GpuEngine:
                 "q": torch.empty((Q, d), dtype=torch.float32, device=dev),
                 "qp": torch.empty((Q, gix.d_pad) if self.projected else (1,), dtype=torch.float32, device=dev),
                 "ef": torch.empty(Q, dtype=torch.int32, device=dev),
-                "lut": torch.empty((Q, gix.lut_stride) if gix.coarse_k else (Q, m, 256), dtype=lut_t, device=dev),
+                "lut": torch.empty(((Q, gix.lut_stride_f16 if precision == "f16" else gix.lut_stride) if gix.coarse_k
+                                    else (Q, m, 256)), dtype=lut_t, device=dev),
                 "scale": torch.empty((Q, m), dtype=torch.float32, device=dev),
                 "cand_ids": torch.empty((Q, S), dtype=torch.int32, device=dev),
                 "cand_adc": torch.empty((Q, S), dtype=torch.float32, device=dev),

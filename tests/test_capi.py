@@ -145,4 +145,4 @@ def test_bind_rejects_bad_two_level_views(L):
     g = coarse()
     g.d, g.d_pad, g.m, g.code_stride, g.proj = 8, 9, 1, 1, 0x1000  # odd d_pad: the first level halves the vector
     assert L.lc_index_bind(C.byref(g), C.byref(h)) == lc.LC_EINVAL
-    assert L.lc_lut_stride(None) == 0
+    assert L.lc_lut_stride(None, 0) == 0

@@ -104,8 +104,21 @@ def test_two_level_tables_layout(torch, m, d, d_pad, pre):
         np.testing.assert_allclose(lut[i, :w.m * 256], ip, rtol=0, atol=1e-5 * np.abs(ip).max())
         np.testing.assert_allclose(lut[i, w.m * 256:w.m * 256 + 2 * k], ct, rtol=1e-5, atol=1e-6)
         assert (lut[i, w.m * 256 + 2 * k:] == 0).all()
-    with pytest.raises(lc.LCError):  # the fp16 table form covers the one-level codec only
-        gix.build_lut(torch.from_numpy(q), lut_dtype=lc.LC_LUT_F16)
+    # fp16 form: the inner-product entries times their row's power-of-two scale within fp16 rounding of the
+    # row's largest magnitude, the first-level entries float32 after them (byte offset m * 512)
+    q16 = gix.project(qt) if pre else qt
+    l16, sc = gix.build_lut(q16, lut_dtype=lc.LC_LUT_F16, projected=pre)
+    assert tuple(l16.shape) == (q.shape[0], gix.lut_stride_f16) and tuple(sc.shape) == (q.shape[0], w.m)
+    raw = l16.cpu().numpy().view(np.uint8)
+    sc = sc.cpu().numpy().astype(np.float64)
+    assert np.all(np.log2(sc) == np.round(np.log2(sc)))
+    for i in range(q.shape[0]):
+        ip16 = raw[i, :w.m * 512].view(np.float16).astype(np.float64).reshape(w.m, 256) * sc[i][:, None]
+        ref = lut[i, :w.m * 256].reshape(w.m, 256)
+        for s in range(w.m):
+            assert np.abs(ip16[s] - ref[s]).max() <= 2.0 ** -10 * np.abs(ref[s]).max() + 1e-6
+        ct16 = raw[i, w.m * 512:w.m * 512 + 8 * k].view(np.float32).astype(np.float64)
+        np.testing.assert_array_equal(ct16, lut[i, w.m * 256:w.m * 256 + 2 * k])
     gix.close()
 
 
@@ -225,5 +238,26 @@ def test_two_level_two_chunks_of_first_level_centroids(torch):
     assert np.mean([np.array_equal(cand[i], o["cand_ids"][i]) for i in range(q.shape[0])]) >= 0.9
     ref = _oracle_topk(ix, q, cand, r.cand_n.cpu().numpy(), w.topk)
     s = parity.summarize(ix, q, ids.cpu().numpy(), dist.cpu().numpy(), ref)
+    assert s["exact_frac"] == 1.0 and s["max_rel_err"] <= 1e-5
+    gix.close()
+
+
+@pytest.mark.parametrize("m,d,d_pad", [(16, 96, None), (8, 28, 32)])
+def test_two_level_fp16_tables(torch, m, d, d_pad):
+    # fp16 inner-product entries (the precision form on the 2-level codec): the walk takes its own
+    # short-list; its refinement is the oracle's to the same bars, and the short-lists stay close to float32's
+    import paper_1804_09996_amd as lc
+    w, ix, db, q = _build(m, d, d_pad)
+    gix = lc.Index.from_index(ix)
+    i32, d32, r32 = gix.query(torch.from_numpy(q), ef=w.ef, ef_max=w.ef, S=w.shortlist, K=w.topk)
+    ids, dist, r = gix.query(torch.from_numpy(q), ef=w.ef, ef_max=w.ef, S=w.shortlist, K=w.topk, precision="f16")
+    cand, cn = r.cand_ids.cpu().numpy(), r.cand_n.cpu().numpy()
+    c32 = r32.cand_ids.cpu().numpy()
+    overlap = np.mean([np.intersect1d(cand[i][cand[i] >= 0], c32[i][c32[i] >= 0]).size / max(1, int(cn[i]))
+                       for i in range(q.shape[0])])
+    assert overlap >= 0.9, overlap
+    ref = _oracle_topk(ix, q, cand, cn, w.topk)
+    s = parity.summarize(ix, q, ids.cpu().numpy(), dist.cpu().numpy(), ref)
+    print(f"m {m} fp16: short-list overlap with float32 {overlap:.3f} EXACT {s['exact_frac']:.3f}")
     assert s["exact_frac"] == 1.0 and s["max_rel_err"] <= 1e-5
     gix.close()
