@@ -251,7 +251,10 @@ int lc_search_budget(const lc_index *ix, const void *lut, int lut_dtype, const f
  * Requires 1 <= K <= S.  The centroids are staged in LDS when they fit
  * (d_pad x 256 values beside the per-wave buffers), else the float32 kernel
  * reads them from global memory; LC_ENOTSUP for the precision form on a
- * shape without a specialised kernel. */
+ * shape without a specialised kernel.  2-level codec: q(g) decodes both
+ * levels (the first-level centroid of each half plus the PQ residual), in
+ * float32 only (the precision form returns LC_ENOTSUP when its re-score does
+ * not cover the whole short-list). */
 int lc_refine(const lc_index *ix, const float *q, int64_t nq, const int32_t *cand_ids,
               const int32_t *cand_n, int32_t S, int32_t K, int precision, int32_t *out_ids,
               float *out_d, void *stream);

@@ -23,6 +23,10 @@
  *                                    product codebook of Eq. 9; m_beta = 1 is
  *                                    the single codebook of Eq. 5-8)
  *   beta_idx[n][m_beta] u8           selected entry per vector and block
+ *   coarse  (optional)               2-level codec (Sec. 5.1): first-level
+ *                                    centroids [2][k][d_pad/2] f32 and codes
+ *                                    [n][2] u16; the PQ codes then encode the
+ *                                    residual
  *
  * Parity: unpinned functions are marked "parity unpinned" below; every other
  * function is pinned by a CPU test against a closed form, brute force or a
