@@ -224,7 +224,7 @@ int lc_search_sched(const lc_index *ix, const void *lut, int lut_dtype, const fl
                     size_t ws_bytes, const lc_schedule *sched, void *stream);
 
 /* lc_search_sched with the paper's budget T on distance computations (Sec.
- * 3.1, "the number of comparisons after which the search is stopped"):
+ * 3.1: the walk stops once it has compared the query with T nodes):
  * max_evals > 0 ends a query's level-0 walk right after its max_evals-th
  * distance evaluation, so D = min(max_evals, D of the unbounded walk); the
  * links of that last expansion past the budget are not evaluated, and the

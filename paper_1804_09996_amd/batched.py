@@ -1,8 +1,11 @@
 """Batched form: one large batch of queries with per-query efSearch.
 
 The whole path for the batch (tables, walk, refinement) runs on static device
-buffers and is captured once in a HIP graph; each step copies the queries and
-their ef into the static inputs and replays the graph.  The walk is the
+buffers and is captured in a HIP graph; each step copies the queries and
+their ef into the static inputs and replays the graph.  A batch whose ef
+values change the class rows, a class's largest pool or a workspace is
+recorded again before its first replay, so a captured launch never meets a
+query beyond its pool or a freed workspace.  The walk is the
 persistent kernel: resident slots take queries from an atomic counter, longest
 ef first, so the long walks start early and the short ones fill the tail.
 
@@ -98,13 +101,26 @@ class BatchedSearcher:
     def _apply(self):
         torch = self.torch
         ef = self._host_ef
-        perm, self.ranges = class_permutation(ef, self.S, self.limits)
+        perm, ranges = class_permutation(ef, self.S, self.limits)
         inv = np.empty_like(perm)
         inv[perm] = np.arange(perm.size)
+        if self.graph is not None:
+            # a replay still in flight reads the static inputs and workspaces
+            torch.cuda.synchronize(self.gix.device)
         self.q.copy_(torch.from_numpy(self._host_q[perm]))
         self.ef.copy_(torch.from_numpy(ef[perm]))
         self.inv.copy_(torch.from_numpy(inv))
+        old_ranges, old_ws = self.ranges, list(self.ws)
+        self.ranges = ranges
         self._size_lanes()
+        if self.graph is not None and (ranges != old_ranges or len(old_ws) != len(self.ws)
+                                       or any(a is not b for a, b in zip(old_ws, self.ws))):
+            # the captured launches hold the old class rows, pool limits and workspaces: record the step
+            # again for the new ones (the old graph and workspaces are released only after that)
+            retired = (self.graph, old_ws)
+            self.graph = None
+            self.capture()
+            del retired
 
     def _size_lanes(self):
         torch, gix = self.torch, self.gix
@@ -119,7 +135,8 @@ class BatchedSearcher:
         self.ws = ws
 
     def set_classes(self, limits: Sequence[int]):
-        """Pool limits of the ef classes (ascending); re-permutes the batch."""
+        """Pool limits of the ef classes (ascending); re-permutes the batch
+        (and records the captured step again when its classes change)."""
         self.limits = sorted(int(x) for x in limits)
         if self._host_ef is not None:
             self._apply()

@@ -158,6 +158,9 @@ class GpuEngine:
                 "h_d": torch.empty((Q, K), dtype=torch.float32).pin_memory(),
                 "event": None, "n": 0,
             })
+        # the workspaces are zero-filled on the allocating stream; every slot stream must see that
+        # before its first launch reads them
+        torch.cuda.current_stream(dev).synchronize()
 
     def launch(self, slot: int, batch: List[Request]):
         torch, lc, C = self.torch, self.lc, self.lc.C

@@ -4,12 +4,13 @@ encodings) on the GPU against the oracle, through the C-ABI.
 The oracle takes the walk's asymmetric distance by its definition,
 ||P y - (c + r)||^2 in float64 with both levels decoded; the GPU sums the
 decomposed form in float32 (the [m][256] inner-product table, the node's two
-first-level entries and its stored term, clamped at 0).  Bars: the short-lists
-of the float32 walk equal the oracle's on at least 90 % of queries (a float32
-near-tie may reorder one), every short-list distance within 1e-4 of the
-oracle's (relative to the largest), top-K EXACT against the oracle's
-refinement of the GPU's short-list, every returned distance within 1e-5
-relative, and the codebook assignment identical on every vector.
+first-level entries and its stored term, clamped at 0).  Bars: the short-lists,
+E and D of the float32 walk equal the oracle's on every query, every
+short-list distance within 1e-5 relative of the oracle's, top-K EXACT against
+the oracle's refinement of the GPU's short-list, every returned distance
+within 1e-5 relative, and the codebook assignment identical on every vector.
+The fp16 tables are an approximation by design: their walk is held to a
+short-list overlap with float32's, and its refinement to the oracle's bars.
 """
 import numpy as np
 import pytest
@@ -70,11 +71,10 @@ def test_two_level_search_matches_oracle(torch, m, d, d_pad):
     cand, cn = r.cand_ids.cpu().numpy(), r.cand_n.cpu().numpy()
     adc = r.cand_adc.cpu().numpy()
     same = [np.array_equal(cand[i], o["cand_ids"][i]) for i in range(q.shape[0])]
-    assert np.mean(same) >= 0.9, np.mean(same)
+    assert np.mean(same) == 1.0, np.mean(same)
     for i in np.flatnonzero(same):
         n = int(cn[i])
-        scale = float(o["cand_adc"][i, :n].max())
-        np.testing.assert_allclose(adc[i, :n], o["cand_adc"][i, :n], rtol=0, atol=1e-4 * scale)
+        np.testing.assert_allclose(adc[i, :n], o["cand_adc"][i, :n], rtol=1e-5)
         assert np.array_equal(r.stats.cpu().numpy()[i], o["stats"][i])
     ref = _oracle_topk(ix, q, cand, cn, w.topk)
     s = parity.summarize(ix, q, ids.cpu().numpy(), dist.cpu().numpy(), ref)
@@ -134,7 +134,7 @@ def test_two_level_budget_matches_oracle(torch):
         st = r.stats.cpu().numpy()
         assert (st[:, 1] <= T).all()
         same = [np.array_equal(r.cand_ids.cpu().numpy()[i], o["cand_ids"][i]) for i in range(q.shape[0])]
-        assert np.mean(same) >= 0.9
+        assert np.mean(same) == 1.0
         for i in np.flatnonzero(same):
             assert np.array_equal(st[i], o["stats"][i])
     gix.close()
@@ -163,7 +163,11 @@ def test_zero_first_level_gives_the_one_level_results(torch):
     a, b = lc.Index.from_index(one), lc.Index.from_index(zero)
     ia, da, ra = a.query(torch.from_numpy(q), ef=w.ef, ef_max=w.ef, S=w.shortlist, K=w.topk)
     ib, dbb, rb = b.query(torch.from_numpy(q), ef=w.ef, ef_max=w.ef, S=w.shortlist, K=w.topk)
-    assert np.mean(np.all(ia.cpu().numpy() == ib.cpu().numpy(), axis=1)) >= 0.9
+    # both GPU forms against the oracle's one-level search of the same codes (EXACT on every query)
+    o = one.search(q, w.ef, w.shortlist, w.topk)
+    for ids_, d_ in ((ia, da), (ib, dbb)):
+        s = parity.summarize(one, q, ids_.cpu().numpy(), d_.cpu().numpy(), o)
+        assert s["exact_frac"] == 1.0 and s["max_rel_err"] <= 1e-5
     np.testing.assert_allclose(dbb.cpu().numpy(), da.cpu().numpy(), rtol=1e-5)
     a.close()
     b.close()
@@ -235,7 +239,7 @@ def test_two_level_two_chunks_of_first_level_centroids(torch):
     o = ix.search(q, w.ef, w.shortlist, w.topk)
     ids, dist, r = gix.query(torch.from_numpy(q), ef=w.ef, ef_max=w.ef, S=w.shortlist, K=w.topk, stats=True)
     cand = r.cand_ids.cpu().numpy()
-    assert np.mean([np.array_equal(cand[i], o["cand_ids"][i]) for i in range(q.shape[0])]) >= 0.9
+    assert np.mean([np.array_equal(cand[i], o["cand_ids"][i]) for i in range(q.shape[0])]) == 1.0
     ref = _oracle_topk(ix, q, cand, r.cand_n.cpu().numpy(), w.topk)
     s = parity.summarize(ix, q, ids.cpu().numpy(), dist.cpu().numpy(), ref)
     assert s["exact_frac"] == 1.0 and s["max_rel_err"] <= 1e-5

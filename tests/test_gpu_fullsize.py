@@ -41,7 +41,7 @@ def test_full_batch_against_oracle_sample(c2):
     s = parity.summarize(oix, q[sample], ids, d, o)
     walk_same = np.mean([np.array_equal(st[i], o["stats"][i]) for i in range(len(sample))])
     print(f"1M: EXACT {s['exact_frac']:.4f}, (E,D) identical {walk_same:.4f}, max rel err {s['max_rel_err']:.2e}")
-    assert s["exact_frac"] >= 0.999
+    assert s["exact_frac"] == 1.0 and walk_same == 1.0
     assert s["max_rel_err"] <= 1e-5
 
 
@@ -52,6 +52,6 @@ def test_largest_pool_on_a_sample(c2):
     ids, d, r = gix.query(qd[:24], ef=ef, ef_max=ef, S=w.shortlist, K=w.topk, stats=True)
     o = oix.search(q[:24], ef, w.shortlist, w.topk)
     same = np.mean([np.array_equal(r.stats.cpu().numpy()[i], o["stats"][i]) for i in range(24)])
-    assert same >= 0.95
+    assert same == 1.0
     s = parity.summarize(oix, q[:24], ids.cpu().numpy(), d.cpu().numpy(), o)
-    assert s["exact_frac"] >= 0.95 and s["max_rel_err"] <= 1e-5
+    assert s["exact_frac"] == 1.0 and s["max_rel_err"] <= 1e-5
