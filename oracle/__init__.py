@@ -83,6 +83,10 @@ def _declare(L):
     L.orc_walk_trace.restype = C.c_int32
     L.orc_project.argtypes = [_p, _i, _i, _p, _p]
     L.orc_project.restype = None
+    L.orc_build_trace.argtypes = [_p, _i64]
+    L.orc_build_trace.restype = None
+    L.orc_build_trace_used.argtypes = []
+    L.orc_build_trace_used.restype = _i64
 
 
 def _ptr(a: Optional[np.ndarray]):
@@ -218,6 +222,32 @@ def hnsw_build(x, proj, d_pad, cent, codes, level, deg0, deg_up, efc, nthreads=1
     if rows == 0:
         adj_up = adj_up[:0]
     return adj0, up_base, adj_up, int(entry.value), int(maxl.value)
+
+
+def hnsw_build_traced(x, proj, d_pad, cent, codes, level, deg0, deg_up, efc, coarse=None, cap_words=1 << 24):
+    """hnsw_build on one thread with the build trace on: (adj0, up_base,
+    adj_up, entry, max_level, records), records a list of dicts
+    {kind, level, owner, cand, out, by_test} in execution order (layout in
+    lc_oracle.h)."""
+    L = _load()
+    buf = np.zeros(cap_words, np.int32)
+    L.orc_build_trace(_ptr(buf), cap_words)
+    try:
+        out = hnsw_build(x, proj, d_pad, cent, codes, level, deg0, deg_up, efc, nthreads=1, coarse=coarse)
+        used = int(L.orc_build_trace_used())
+    finally:
+        L.orc_build_trace(None, 0)
+    if used < 0:
+        raise ValueError("build trace overflowed its buffer")
+    recs, i = [], 0
+    while i < used:
+        kind, lvl, owner, nc, nout = (int(v) for v in buf[i:i + 5])
+        cand = buf[i + 5:i + 5 + nc].copy()
+        o = buf[i + 5 + nc:i + 5 + nc + nout].copy()
+        bt = buf[i + 5 + nc + nout:i + 5 + nc + 2 * nout].astype(bool)
+        recs.append({"kind": kind, "level": lvl, "owner": owner, "cand": cand, "out": o, "by_test": bt})
+        i += 5 + nc + 2 * nout
+    return (*out, recs)
 
 
 def lsq_solve(a: np.ndarray, c: np.ndarray):

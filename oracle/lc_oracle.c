@@ -460,13 +460,56 @@ static int layer_search(gb *g, const double *v, int l, int32_t ep, int ef, int t
   return nw;
 }
 
+/* Optional record of every list update of the graph build (test
+ * infrastructure, see lc_oracle.h): appended under a mutex, in execution
+ * order (one thread gives the sequential order). */
+static pthread_mutex_t g_trace_mu = PTHREAD_MUTEX_INITIALIZER;
+static int32_t *g_trace = NULL;
+static int64_t g_trace_cap = 0, g_trace_used = 0;
+
+void orc_build_trace(int32_t *buf, int64_t cap) {
+  pthread_mutex_lock(&g_trace_mu);
+  g_trace = buf;
+  g_trace_cap = buf ? cap : 0;
+  g_trace_used = 0;
+  pthread_mutex_unlock(&g_trace_mu);
+}
+
+int64_t orc_build_trace_used(void) { return g_trace_used; }
+
+/* record [kind, level, owner, nc, nout, cand[nc], out[nout], kept[nout]] */
+static void trace_put(int kind, int level, int32_t owner, const int32_t *cand, int nc, const int32_t *out,
+                      const char *kept, int nout) {
+  pthread_mutex_lock(&g_trace_mu);
+  if (g_trace && g_trace_used >= 0) {
+    int64_t need = 5 + (int64_t)nc + 2 * (int64_t)nout;
+    if (g_trace_used + need > g_trace_cap) {
+      g_trace_used = -1;
+    } else {
+      int32_t *r = g_trace + g_trace_used;
+      r[0] = kind;
+      r[1] = level;
+      r[2] = owner;
+      r[3] = nc;
+      r[4] = nout;
+      for (int i = 0; i < nc; i++) r[5 + i] = cand[i];
+      for (int i = 0; i < nout; i++) {
+        r[5 + nc + i] = out[i];
+        r[5 + nc + nout + i] = kept ? kept[i] : 0;
+      }
+      g_trace_used += need;
+    }
+  }
+  pthread_mutex_unlock(&g_trace_mu);
+}
+
 /* Neighbour selection (Sec. 2 "shrinking" operator): walk the candidates in
  * (distance to owner, id) order and keep one only if it is closer to the
  * owner than to every already-kept link (distances between reconstructions);
  * then fill the remaining slots with the nearest rejected candidates.  The
  * result is written sorted by (distance to owner, id). */
 static int select_links(gb *g, const double *owner, const int32_t *cand, int nc, int cap,
-                        int32_t *out) {
+                        int32_t *out, char *by_test) {
   okey *ks = (okey *)malloc(sizeof(okey) * (size_t)(nc > 0 ? nc : 1));
   char *kept = (char *)calloc((size_t)(nc > 0 ? nc : 1), 1);
   int32_t *kid = (int32_t *)malloc(sizeof(int32_t) * (size_t)(cap > 0 ? cap : 1));
@@ -489,12 +532,15 @@ static int select_links(gb *g, const double *owner, const int32_t *cand, int nc,
   }
   for (int i = 0; i < nc && nk < cap; i++)
     if (!kept[i]) {
-      kept[i] = 1;
+      kept[i] = 2; /* filled: the nearest candidates the test rejected */
       nk++;
     }
   int w = 0;
   for (int i = 0; i < nc; i++)
-    if (kept[i]) out[w++] = ks[i].id;
+    if (kept[i]) {
+      if (by_test) by_test[w] = kept[i] == 1;
+      out[w++] = ks[i].id;
+    }
   for (int i = w; i < cap; i++) out[i] = -1;
   free(ks);
   free(kept);
@@ -532,7 +578,11 @@ static void gb_search_one(int64_t bi, int tid, void *vctx) {
     int nw = layer_search(g, v, l, cur, g->efc, tid, W);
     for (int i = 0; i < nw; i++) ids[i] = W[i].id;
     int cap = cap_of(g, l);
-    g->seln[bi][l] = select_links(g, v, ids, nw, cap, g->sel[bi] + (int64_t)l * (g->deg0 > g->deg_up ? g->deg0 : g->deg_up));
+    int32_t *o = g->sel[bi] + (int64_t)l * (g->deg0 > g->deg_up ? g->deg0 : g->deg_up);
+    char *by_test = (char *)malloc((size_t)cap);
+    g->seln[bi][l] = select_links(g, v, ids, nw, cap, o, by_test);
+    trace_put(0, l, x, ids, nw, o, by_test, g->seln[bi][l]);
+    free(by_test);
     cur = W[0].id;
   }
   free(W);
@@ -563,10 +613,14 @@ static void gb_reverse_one(int64_t gi, int tid, void *vctx) {
     qsort(ks, (size_t)nc, sizeof(okey), okey_cmp);
     for (int i = 0; i < cap; i++) row[i] = i < nc ? ks[i].id : -1;
     free(ks);
+    trace_put(2, l, e, cand, nc, row, NULL, nc);
   } else {
     int32_t *tmp = (int32_t *)malloc(sizeof(int32_t) * (size_t)cap);
-    select_links(g, v, cand, nc, cap, tmp);
+    char *by_test = (char *)malloc((size_t)cap);
+    int w = select_links(g, v, cand, nc, cap, tmp, by_test);
     memcpy(row, tmp, sizeof(int32_t) * (size_t)cap);
+    trace_put(1, l, e, cand, nc, tmp, by_test, w);
+    free(by_test);
     free(tmp);
   }
   free(cand);
@@ -680,6 +734,7 @@ int orc_hnsw_build(const float *x, int64_t n, int d, const float *proj, int d_pa
     if (pos + bs > n) bs = n - pos;
     g->batch = order + pos;
     g->nb = bs;
+    trace_put(3, 0, (int32_t)bs, g->batch, (int)bs, NULL, NULL, 0);
     orc_parallel_for(bs, nthreads, gb_search_one, g);
     /* the new nodes' own lists */
     int64_t nr = 0;

@@ -89,13 +89,34 @@ int orc_pq_encode(const float *x, int64_t n, int d, const float *proj, int d_pad
 int64_t orc_levels(const double *u, int64_t n, int ratio, int cap, int8_t *level);
 
 /* Batched nested-graph build over PQ-coded vectors (Sec. 2, Sec. 4.1, Sec. 5.1).
- * Fills adj0, up_base, adj_up, *entry, *max_level.  parity unpinned beyond
- * the structural invariants and the small complete-graph cases. */
+ * Fills adj0, up_base, adj_up, *entry, *max_level.  Pinned through the build
+ * trace below: every candidate list equals an independent best-first search
+ * of the graph as it stood at the start of its batch, every selection meets
+ * the shrinking rule's defining properties checked pair by pair, every
+ * reverse-link merge covers the old list plus its new links and is ordered by
+ * the distance from the owner's own vector, and replaying the trace gives the
+ * final lists. */
 int orc_hnsw_build(const float *x, int64_t n, int d, const float *proj, int d_pad, int m,
                    int ksub, const float *cent, const uint8_t *codes, int code_stride,
                    const int8_t *level, int deg0, int deg_up, int ef_construction, int nthreads,
                    int32_t *adj0, int32_t *up_base, int32_t *adj_up, int32_t *entry,
                    int32_t *max_level, const orc_coarse *cq /* NULL: one-level codec */);
+
+/* Build trace (test infrastructure): while buf is set, orc_hnsw_build
+ * appends one record per list update, in execution order (sequential with one
+ * thread):
+ *   [kind, level, owner, nc, nout, cand[nc], out[nout], by_test[nout]]
+ * kind 0: selection of a new node's list at a level (cand = its search
+ *         result W, sorted by (distance, id));
+ * kind 1: a reverse-link merge that overflowed the list and re-ran the
+ *         selection from the owner's vector (cand = old list, then new links);
+ * kind 2: a reverse-link merge that fit (out = cand sorted by distance);
+ * kind 3: start of a batch (owner = batch size, cand = the batch's nodes).
+ * by_test[i] = 1 when out[i] was kept by the shrinking test, 0 when it
+ * filled a free slot.  orc_build_trace(NULL, 0) stops recording;
+ * orc_build_trace_used() is the words written, or -1 once cap overflowed. */
+void orc_build_trace(int32_t *buf, int64_t cap);
+int64_t orc_build_trace_used(void);
 
 /* Least squares (Sec. 4.2, Eq. 4): beta minimising ||x - G beta||^2 given
  * A = G^T G and c = G^T x; Cholesky, else eigen pseudo-inverse. */
