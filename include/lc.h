@@ -237,6 +237,30 @@ int lc_search_budget(const lc_index *ix, const void *lut, int lut_dtype, const f
                      const int32_t *order, int32_t *cand_ids, float *cand_adc, int32_t *cand_n,
                      int32_t *stats, void *ws, size_t ws_bytes, const lc_schedule *sched, void *stream);
 
+/* lc_search for callers that cannot allocate device memory (code under HIP
+ * graph capture, serving loops or harnesses that forbid hipMalloc): the same
+ * first stage with the default schedule, its workspace being a fixed array of
+ * LC_NOALLOC_SCRATCH_BYTES inside the library instead of an argument.  The
+ * call allocates nothing; the caller still owns lut, lut_scale, ef and the
+ * outputs, which are as for lc_search (identical values).
+ *  - Each GPU the library runs on holds its own copy of the array until the
+ *    process ends; the call uses the current device's, which must be the
+ *    device the index was bound on (else LC_EINVAL).
+ *  - The first call on a device zeroes the array with a kernel on `stream`;
+ *    every call then zeroes the queue counters at its head the same way, and
+ *    a completed walk leaves the rest zero-filled.
+ *  - The walk launches only as many resident query slots as the array holds
+ *    (each slot needs an n-bit visited bitset and an id list), so for a large
+ *    index it runs slower than lc_search with a full workspace; LC_ENOSPC when
+ *    not even one slot fits.
+ *  - Calls that overlap on one GPU (other streams, other threads) share the
+ *    array and race: serialise them.
+ * Errors as lc_search. */
+#define LC_NOALLOC_SCRATCH_BYTES (128u << 20)
+int lc_search_noalloc(const lc_index *ix, const void *lut, int lut_dtype, const float *lut_scale,
+                      int64_t nq, const int32_t *ef, int32_t ef_max, int32_t S, int32_t *cand_ids,
+                      float *cand_adc, int32_t *cand_n, int32_t *stats, void *stream);
+
 /* Second stage (Sec. 4.1 "Refinement strategy"; Sec. 4.2 Eq. 5; Sec. 4.3
  * Eq. 7 and Eq. 9).  For each valid short-list id i:
  *   g_0 = i, g_j = adj0[i][j-1] (j = 1..k_reg, -1 -> zero),

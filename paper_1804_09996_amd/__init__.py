@@ -101,6 +101,7 @@ def lib():
         L.lc_refine_projected.argtypes = [p, p, i64, p, p, i32, i32, C.c_int, p, p, p]
         L.lc_lut_stride.argtypes = [p, C.c_int]
         L.lc_lut_stride.restype = i64
+        L.lc_search_noalloc.argtypes = [p, p, C.c_int, p, i64, p, i32, i32, p, p, p, p, p]
         _lib = L
     return _lib
 
@@ -108,7 +109,8 @@ def lib():
 def exported_symbols():
     return ["lc_build_id", "lc_strerror", "lc_index_bind", "lc_index_release", "lc_build_lut", "lc_search_workspace_bytes",
             "lc_search", "lc_refine", "lc_search_workspace_bytes_sched", "lc_search_sched", "lc_search_budget",
-            "lc_assign_beta", "lc_project_queries", "lc_build_lut_projected", "lc_refine_projected", "lc_lut_stride"]
+            "lc_assign_beta", "lc_project_queries", "lc_build_lut_projected", "lc_refine_projected", "lc_lut_stride",
+            "lc_search_noalloc"]
 
 
 def _check(rc: int, where: str):
@@ -328,6 +330,24 @@ class Index:
                                        _stream(torch, self.device))
         _check(rc, "lc_search")
         return SearchResult(cand_ids, cand_adc, cand_n, st)
+
+    def search_noalloc(self, lut, scale=None, ef=None, ef_max: int = 64, S: int = 64, out: SearchResult = None):
+        """lc_search_noalloc: the walk with the library's fixed workspace array;
+        ``out`` (a SearchResult with stats) holds the outputs, allocated here
+        when None."""
+        torch = self.torch
+        nq = lut.shape[0]
+        lut_dtype = LC_LUT_F16 if lut.dtype == torch.float16 else LC_LUT_F32
+        ef_t = None if ef is None else torch.as_tensor(ef, dtype=torch.int32).to(self.device).contiguous()
+        if out is None:
+            out = SearchResult(torch.empty((nq, S), dtype=torch.int32, device=self.device),
+                               torch.empty((nq, S), dtype=torch.float32, device=self.device),
+                               torch.empty(nq, dtype=torch.int32, device=self.device),
+                               torch.empty((nq, 2), dtype=torch.int32, device=self.device))
+        _check(lib().lc_search_noalloc(self.handle, _ptr(lut), lut_dtype, _ptr(scale), nq, _ptr(ef_t), ef_max, S,
+                                       _ptr(out.cand_ids), _ptr(out.cand_adc), _ptr(out.cand_n), _ptr(out.stats),
+                                       _stream(torch, self.device)), "lc_search_noalloc")
+        return out
 
     def refine(self, q, cand_ids, cand_n, K: int, precision: int = LC_REFINE_F32, projected: bool = False):
         torch = self.torch

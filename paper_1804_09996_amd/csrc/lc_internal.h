@@ -88,7 +88,9 @@ inline int64_t lc_lut_row_bytes(const lc_index *ix, int dtype) {
 // Float32 entries per row (the float32 table).
 inline int64_t lc_lut_entries(const lc_index *ix) { return lc_lut_row_bytes(ix, LC_LUT_F32) / 4; }
 
-// Launchers (return LC_* codes).
+// Launchers (return LC_* codes).  lc_launch_walk with fit_ws launches no more
+// resident query slots than the workspace holds (LC_ENOSPC when not even one
+// fits) instead of requiring the workspace of the full grid.
 int lc_launch_project(const lc_index *ix, const float *q, int64_t nq, float *out, hipStream_t st);
 int lc_launch_lut(const lc_index *ix, const float *q, int64_t nq, int dtype, void *lut, float *scale,
                   bool projected,
@@ -100,7 +102,7 @@ int lc_launch_walk(const lc_index *ix, const void *lut, int dtype, const float *
                    const int32_t *ef, int32_t ef_max, int32_t S, int32_t max_d, const int32_t *order, int32_t *cand_ids,
                    float *cand_adc,
                    int32_t *cand_n, int32_t *stats, void *ws, size_t ws_bytes, const lc_schedule *sched,
-                   hipStream_t st);
+                   hipStream_t st, bool fit_ws = false);
 int lc_launch_refine(const lc_index *ix, const float *q, int64_t nq, const int32_t *cand_ids,
                      const int32_t *cand_n, int32_t S, int32_t K, int precision, int32_t *out_ids,
                      float *out_d, bool projected, hipStream_t st);

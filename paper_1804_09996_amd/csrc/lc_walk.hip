@@ -1593,9 +1593,17 @@ int launch_kernel(const WalkPlan &p, const lc_schedule *sc, const WalkArgs &a, h
 template <int M, typename T>
 int launch_m(const lc_index *ix, const void *lut, const float *scale, int64_t nq, const int32_t *ef,
              int32_t ef_max, int32_t S, int32_t max_d, const int32_t *order, int32_t *cand_ids, float *cand_adc,
-             int32_t *cand_n, int32_t *stats, void *ws, size_t ws_bytes, const lc_schedule *sc, hipStream_t st) {
+             int32_t *cand_n, int32_t *stats, void *ws, size_t ws_bytes, const lc_schedule *sc, hipStream_t st,
+             bool fit_ws) {
   WalkPlan p = plan_for<M>(ix, nq, ef_max, S, sc, int(sizeof(T)));
   const int64_t words = (int64_t(ix->v.n) + 31) / 32;
+  if (fit_ws) {
+    // as many resident slots as the workspace holds (results do not depend on the slot count)
+    const size_t per_slot = size_t(words) * 4 + size_t(list_cap_for(p.w_cap)) * 4;
+    const size_t fit = ws_bytes > kHeaderBytes ? (ws_bytes - kHeaderBytes) / per_slot : 0;
+    if (fit < 1) return LC_ENOSPC;
+    if (size_t(p.grid) > fit) p.grid = int(fit);
+  }
   if (ws_bytes < ws_need(p, words)) return LC_ENOSPC;
   if (p.lds_bytes > ix->lds_per_cu) return LC_ENOTSUP;
   WalkArgs a;
@@ -1663,7 +1671,7 @@ int lc_launch_walk(const lc_index *ix, const void *lut, int dtype, const float *
                    const int32_t *ef, int32_t ef_max, int32_t S, int32_t max_d, const int32_t *order,
                    int32_t *cand_ids, float *cand_adc,
                    int32_t *cand_n, int32_t *stats, void *ws, size_t ws_bytes, const lc_schedule *sched,
-                   hipStream_t st) {
+                   hipStream_t st, bool fit_ws) {
   if (dtype != LC_LUT_F32 && dtype != LC_LUT_F16) return LC_ENOTSUP;
   if (!valid_schedule(sched)) return LC_EINVAL;
   const lc_schedule *sc = sched ? sched : &kDefaultSchedule;
@@ -1672,9 +1680,9 @@ int lc_launch_walk(const lc_index *ix, const void *lut, int dtype, const float *
 #define CASE(MM)                                                                                              \
   case MM:                                                                                                    \
     return dtype == LC_LUT_F32 ? launch_m<MM, rfloat>(ix, lut, scale, nq, ef, ef_max, S, max_d, order,       \
-                                                      cand_ids, cand_adc, cand_n, stats, ws, ws_bytes, sc, st) \
+                                                      cand_ids, cand_adc, cand_n, stats, ws, ws_bytes, sc, st, fit_ws) \
                                : launch_m<MM, rhalf>(ix, lut, scale, nq, ef, ef_max, S, max_d, order,        \
-                                                     cand_ids, cand_adc, cand_n, stats, ws, ws_bytes, sc, st);
+                                                     cand_ids, cand_adc, cand_n, stats, ws, ws_bytes, sc, st, fit_ws);
       LC_FOR_EACH_M(CASE)
 #undef CASE
       default: return LC_ENOTSUP;
@@ -1684,9 +1692,9 @@ int lc_launch_walk(const lc_index *ix, const void *lut, int dtype, const float *
 #define CASE(MM)                                                                                              \
   case MM:                                                                                                    \
     return dtype == LC_LUT_F32 ? launch_m<MM, float>(ix, lut, scale, nq, ef, ef_max, S, max_d, order,        \
-                                                     cand_ids, cand_adc, cand_n, stats, ws, ws_bytes, sc, st) \
+                                                     cand_ids, cand_adc, cand_n, stats, ws, ws_bytes, sc, st, fit_ws) \
                                : launch_m<MM, __half>(ix, lut, scale, nq, ef, ef_max, S, max_d, order,       \
-                                                      cand_ids, cand_adc, cand_n, stats, ws, ws_bytes, sc, st);
+                                                      cand_ids, cand_adc, cand_n, stats, ws, ws_bytes, sc, st, fit_ws);
     LC_FOR_EACH_M(CASE)
 #undef CASE
     default: return LC_ENOTSUP;
