@@ -22,6 +22,7 @@ from __future__ import annotations
 
 import dataclasses
 import hashlib
+import os
 from typing import Optional
 
 import numpy as np
@@ -147,20 +148,36 @@ def _gmm_params(w: Workload):
     return means, np.sqrt(t ** -2.0), q
 
 
+def _chunks(n: int, chunk: int, fill) -> None:
+    """Run fill(c0, c1) over the chunks of range(n); chunks draw from their
+    own sub-streams, so they run on a thread pool (numpy releases the GIL in
+    its generators and matrix products) and the result does not depend on it."""
+    starts = list(range(0, n, chunk))
+    if len(starts) <= 1:
+        for c0 in starts:
+            fill(c0, min(n, c0 + chunk))
+        return
+    from concurrent.futures import ThreadPoolExecutor
+    with ThreadPoolExecutor(max_workers=max(1, min(16, os.cpu_count() or 1, len(starts)))) as ex:
+        list(ex.map(lambda c0: fill(c0, min(n, c0 + chunk)), starts))
+
+
 def gmm(w: Workload, n: int, stream: str, chunk: int = 1 << 18) -> np.ndarray:
     """``x = R (mu_c + eps)`` with c uniform over the components,
     ``mu_c ~ N(0, diag(t^-1))``, ``eps ~ N(0, diag(t^-2))`` and ``R`` a seeded
     rotation; drawn in float64, L2-normalised, rounded to float32."""
     means, noise_sd, rot = _gmm_params(w)
     out = np.empty((n, w.d), dtype=np.float32)
-    for c0 in range(0, n, chunk):
-        c1 = min(n, c0 + chunk)
+
+    def fill(c0, c1):
         g = rng(w.seed, stream, c0 // chunk)
         comp = g.integers(0, w.n_comp, size=c1 - c0)
         x = means[comp] + g.standard_normal((c1 - c0, w.d)) * noise_sd[None, :]
         x = x @ rot.T
         x /= np.linalg.norm(x, axis=1, keepdims=True)
         out[c0:c1] = x
+
+    _chunks(n, chunk, fill)
     return out
 
 
@@ -172,12 +189,14 @@ def int128(w: Workload, n: int, stream: str, chunk: int = 1 << 18) -> np.ndarray
     is_exp = np.zeros(w.d, dtype=bool)
     is_exp[dims] = True
     out = np.empty((n, w.d), dtype=np.float32)
-    for c0 in range(0, n, chunk):
-        c1 = min(n, c0 + chunk)
+
+    def fill(c0, c1):
         g = rng(w.seed, stream, c0 // chunk)
         e = np.minimum(np.floor(g.exponential(20.0, size=(c1 - c0, w.d))), 255.0)
         u = np.floor(256.0 * g.random(size=(c1 - c0, w.d)))
         out[c0:c1] = np.where(is_exp[None, :], e, u).astype(np.float32)
+
+    _chunks(n, chunk, fill)
     return out
 
 

@@ -319,6 +319,57 @@ int lc_refine_projected(const lc_index *ix, const float *qp, int64_t nq, const i
 int lc_assign_beta(const lc_index *ix, const float *x, int64_t n0, int64_t count, uint8_t *out,
                    void *stream);
 
+/* ---- Index build on the GPU (steps before the search path) -------------- */
+
+/* The projection the builder applies to database vectors: xp[i][r] =
+ * float(sum_t double(proj[r][t]) * double(x[i][t])), t ascending in float64 (a
+ * copy when proj is NULL, which requires d_pad == d).  x f32 [n][d], xp f32
+ * [n][d_pad], device.  Errors: LC_EINVAL. */
+int lc_project_exact(const float *x, int64_t n, int d, const float *proj, int d_pad, float *xp, void *stream);
+
+/* Product-quantizer encoding (Sec. 3.3, Sec. 4.1): codes[i][s] = the c
+ * minimising ||xp_i^s - C[s][c]||^2, each distance a float32 sum over the
+ * sub-space's coordinates in order, the lowest c on ties; bytes m..code_stride-1
+ * of a row are zero.  xp f32 [n][d_pad], centroids f32 [m][256][d_pad/m], codes
+ * u8 [n][code_stride], device.  Errors: LC_EINVAL; LC_ENOTSUP for d_pad/m > 16. */
+int lc_pq_encode(const float *xp, int64_t n, int d_pad, int m, const float *centroids, uint8_t *codes,
+                 int code_stride, void *stream);
+
+/* Workspace bytes of lc_graph_insert for batches of at most max_count nodes
+ * (0 for bad arguments or ef_construction > 64). */
+size_t lc_graph_insert_workspace_bytes(const lc_index *ix, int32_t max_count, int32_t ef_construction);
+
+/* One batch of the graph build (Sec. 5.1: nodes added in batches, each
+ * searched against the graph as it stood when the batch began, then linked)
+ * for nodes of level 0.  For every node x of nodes[0..count):
+ *   1. search: greedy descent from `entry` on the upper levels, then the
+ *      level-0 walk of lc_search with ef = S = ef_construction, on the table
+ *      ||xp_x^s - C[s][c]||^2 (float32 sums in coordinate order; Sec. 4.1
+ *      asymmetric distances from the raw vector);
+ *   2. x's list (deg0 entries, -1 padded): over the candidates in (distance,
+ *      id) order, the shrinking rule of Sec. 2 keeps e if d(x, e) < d(e, s)
+ *      for every link s kept before it, d(e, s) = ||q(e) - q(s)||^2 summed
+ *      over the sub-spaces in order; free slots take the nearest rejected
+ *      candidates;
+ *   3. reverse links: every y in x's list gets x; y's list and its new links,
+ *      ordered by (||xp_y - q(.)||^2, id), are kept whole when they fit deg0
+ *      and re-shrunk by the rule of step 2 otherwise.
+ * With these float orders (no fused multiply-add) the lists are those of the
+ * host builder (lcb_graph_build) given the same arrays.
+ * ix:    the index being built (its adj0 is adj0; codes, centroids, up_base,
+ *        adj_up, entry and max_level as for lc_search; one-level PQ only).
+ * adj0:  i32 [n][deg0] device, modified in place; must be the view's adj0.
+ * xp:    f32 [n][d_pad] projected database vectors (lc_project_exact).
+ * nodes: i32 [count] device, the batch (level-0 nodes not yet linked).
+ * ws:    at least lc_graph_insert_workspace_bytes(ix, max_count,
+ *        ef_construction) bytes, zero-filled before the first call; every
+ *        call leaves it zero-filled where that matters.
+ * Requires 0 <= count <= max_count, 1 <= ef_construction <= 64 (LC_ENOTSUP
+ * above), d_pad * 1 KB of centroids plus 16 vectors within one compute unit's
+ * LDS (LC_ENOTSUP otherwise), coarse_k == 0 (LC_ENOTSUP). */
+int lc_graph_insert(const lc_index *ix, int32_t *adj0, const float *xp, const int32_t *nodes, int32_t count,
+                    int32_t max_count, int32_t ef_construction, void *ws, size_t ws_bytes, void *stream);
+
 const char *lc_strerror(int code);
 
 /* Identity of the build: a hex sha1 over this header and the library's

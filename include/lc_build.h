@@ -73,6 +73,18 @@ int lcb_graph_build(const float *x, int64_t n, int d, const float *proj, int d_p
                     int32_t *adj0, int32_t *up_base, int32_t *adj_up, int32_t *entry,
                     int32_t *max_level, const float *rec);
 
+/* lcb_graph_build with upper_only = 1: the same batches, stopped before the
+ * first batch that starts with a level-0 node (every later node is then a
+ * level-0 node, so the rest of the build only searches and links level 0:
+ * lc_graph_insert on the GPU continues it from *next_pos, the position in the
+ * insertion order where it stopped, with the same batch sizes).  upper_only = 0
+ * is lcb_graph_build; *next_pos (if given) is then n. */
+int lcb_graph_build_part(const float *x, int64_t n, int d, const float *proj, int d_pad, int m,
+                         const float *centroids, const uint8_t *codes, int code_stride,
+                         const int8_t *level, int deg0, int deg_up, int ef_construction, int nthreads,
+                         int32_t *adj0, int32_t *up_base, int32_t *adj_up, int32_t *entry,
+                         int32_t *max_level, const float *rec, int upper_only, int64_t *next_pos);
+
 /* Regression codebook (Sec. 4.3, Eq. 6-8) in float64 on the training ids:
  * per-vector least squares initialises a k-means (km_iters), then em_iters
  * rounds of assignment (Eq. 7) and per-cluster least squares (Eq. 8).  With

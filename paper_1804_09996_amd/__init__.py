@@ -102,6 +102,11 @@ def lib():
         L.lc_lut_stride.argtypes = [p, C.c_int]
         L.lc_lut_stride.restype = i64
         L.lc_search_noalloc.argtypes = [p, p, C.c_int, p, i64, p, i32, i32, p, p, p, p, p]
+        L.lc_project_exact.argtypes = [p, i64, C.c_int, p, C.c_int, p, p]
+        L.lc_pq_encode.argtypes = [p, i64, C.c_int, C.c_int, p, p, C.c_int, p]
+        L.lc_graph_insert_workspace_bytes.argtypes = [p, i32, i32]
+        L.lc_graph_insert_workspace_bytes.restype = sz
+        L.lc_graph_insert.argtypes = [p, p, p, p, i32, i32, i32, p, sz, p]
         _lib = L
     return _lib
 
@@ -110,7 +115,8 @@ def exported_symbols():
     return ["lc_build_id", "lc_strerror", "lc_index_bind", "lc_index_release", "lc_build_lut", "lc_search_workspace_bytes",
             "lc_search", "lc_refine", "lc_search_workspace_bytes_sched", "lc_search_sched", "lc_search_budget",
             "lc_assign_beta", "lc_project_queries", "lc_build_lut_projected", "lc_refine_projected", "lc_lut_stride",
-            "lc_search_noalloc"]
+            "lc_search_noalloc", "lc_project_exact", "lc_pq_encode", "lc_graph_insert_workspace_bytes",
+            "lc_graph_insert"]
 
 
 def _check(rc: int, where: str):

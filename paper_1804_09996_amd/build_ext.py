@@ -15,7 +15,8 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 
-HIP_SOURCES = ["lc_capi.hip", "lc_lut.hip", "lc_walk.hip", "lc_refine.hip", "lc_assign.hip", "lc_noalloc.hip"]
+HIP_SOURCES = ["lc_capi.hip", "lc_lut.hip", "lc_walk.hip", "lc_refine.hip", "lc_assign.hip", "lc_noalloc.hip",
+               "lc_graph.hip"]
 BUILD_SOURCES = ["lc_builder.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -33,6 +33,7 @@ def lib():
         L.lcb_levels.argtypes = [p, i64, i, i, p]
         L.lcb_levels.restype = i64
         L.lcb_graph_build.argtypes = [p, i64, i, p, i, i, p, p, i, p, i, i, i, i, p, p, p, p, p, p]
+        L.lcb_graph_build_part.argtypes = [p, i64, i, p, i, i, p, p, i, p, i, i, i, i, p, p, p, p, p, p, i, p]
         L.lcb_beta_train.argtypes = [p, p, i64, i, p, i, i, p, p, i, p, i, i, i, i, p, i, i, i, p, p, p]
         L.lcb_beta_assign.argtypes = [p, i64, i, p, i, i, p, p, i, p, i, i, i, i, p, i, p, p]
         L.lcb_coarse_train.argtypes = [p, i64, i, p, i, i, p, i, i, p]

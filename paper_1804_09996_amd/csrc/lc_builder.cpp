@@ -527,6 +527,15 @@ int lcb_graph_build(const float *x, int64_t n, int d, const float *proj, int d_p
                     const float *centroids, const uint8_t *codes, int code_stride, const int8_t *level,
                     int deg0, int deg_up, int ef_construction, int nthreads, int32_t *adj0, int32_t *up_base,
                     int32_t *adj_up, int32_t *entry, int32_t *max_level, const float *rec) {
+  return lcb_graph_build_part(x, n, d, proj, d_pad, m, centroids, codes, code_stride, level, deg0, deg_up,
+                              ef_construction, nthreads, adj0, up_base, adj_up, entry, max_level, rec, 0, nullptr);
+}
+
+int lcb_graph_build_part(const float *x, int64_t n, int d, const float *proj, int d_pad, int m,
+                         const float *centroids, const uint8_t *codes, int code_stride, const int8_t *level,
+                         int deg0, int deg_up, int ef_construction, int nthreads, int32_t *adj0, int32_t *up_base,
+                         int32_t *adj_up, int32_t *entry, int32_t *max_level, const float *rec, int upper_only,
+                         int64_t *next_pos) {
   if (n < 1 || m < 1 || d_pad % m || deg0 < 1 || deg0 > 64 || deg_up < 1 || deg_up > 64 || ef_construction < 1)
     return -1;
   if (nthreads < 1) nthreads = 1;
@@ -598,6 +607,7 @@ int lcb_graph_build(const float *x, int64_t n, int d, const float *proj, int d_p
   Progress prog("graph");
   int64_t pos = 1;
   while (pos < n) {
+    if (upper_only && level[order[pos]] == 0) break;  // the rest are level-0 nodes
     prog.tick(pos, n);
     int64_t bs = std::max<int64_t>(1, std::min<int64_t>(bmax, pos / 16));
     if (pos + bs > n) bs = n - pos;
@@ -675,6 +685,7 @@ int lcb_graph_build(const float *x, int64_t n, int d, const float *proj, int d_p
   }
   *entry = B.entry;
   *max_level = B.max_level;
+  if (next_pos) *next_pos = pos;
   return 0;
 }
 

@@ -137,3 +137,50 @@ def test_builder_two_level_codec_matches_oracle(nthreads):
     assert np.all(bix.adj0 == oix.adj0, axis=1).mean() >= 0.99
     np.testing.assert_allclose(bix.beta, oix.beta, rtol=1e-3, atol=1e-4)
     assert (bix.beta_idx == oix.beta_idx).mean() >= 0.99
+
+
+def test_partial_build_stops_before_the_level0_batches():
+    # the host part of the GPU build: the same batches as the full build up to the first batch that starts
+    # with a level-0 node; its upper-level lists are already final, and no later node is linked yet
+    import ctypes as C
+    from paper_1804_09996_amd import builder, gpu_build
+    w = datagen.small(name="part", n=2500, nq=4, d=24, m=4, n_train=2048, pq_iters=4)
+    db, train = datagen.vectors(w, "db"), datagen.vectors(w, "train")
+    full = builder.build_index(w, db, train, None, datagen.level_uniforms(w), datagen.pq_init_ids(w, train.shape[0]),
+                               datagen.beta_train_ids(w), datagen.beta_init_ids(w, min(w.n, w.n_beta_train)), 2)
+    L = builder.lib()
+    p_ = builder._p
+    n, cs = w.n, full.codes.shape[1]
+    level = np.ascontiguousarray(full.level)
+    rows = int(level.astype(np.int64).sum())
+    adj0 = np.empty((n, w.deg0), np.int32)
+    up_base = np.empty(n, np.int32)
+    adj_up = np.empty((max(rows, 1), w.deg_up), np.int32)
+    entry, maxl, nxt = C.c_int32(), C.c_int32(), C.c_int64()
+    codes = np.ascontiguousarray(full.codes)
+    cent = np.ascontiguousarray(full.centroids)
+    rc = L.lcb_graph_build_part(p_(db), n, w.d, None, w.d_pad, w.m, p_(cent), p_(codes), cs, p_(level), w.deg0,
+                                w.deg_up, w.ef_construction, 2, p_(adj0), p_(up_base), p_(adj_up), C.byref(entry),
+                                C.byref(maxl), None, 1, C.byref(nxt))
+    assert rc == 0
+    order = np.concatenate([np.flatnonzero(level == l) for l in range(int(level.max()), -1, -1)])
+    n_up = int((level > 0).sum())
+    starts = [p for p, _ in gpu_build.batch_schedule(n, 1)]
+    assert nxt.value in starts and nxt.value >= n_up and nxt.value - 1 < n_up + max(1, nxt.value // 16)
+    assert all(level[order[p]] > 0 for p in starts if p < nxt.value)
+    assert np.array_equal(adj_up[:rows], full.adj_up)
+    later = order[nxt.value:]
+    assert np.all(adj0[later] == -1) and not np.isin(later, adj0).any()
+    assert (entry.value, maxl.value) == (full.entry, full.max_level)
+
+
+def test_batch_schedule():
+    from paper_1804_09996_amd import gpu_build
+    s = gpu_build.batch_schedule(100_000, 1)
+    assert s[0] == (1, 1) and s[15] == (16, 1) and s[16] == (17, 1) and s[17] == (18, 1)
+    pos = 1
+    for p, b in s:
+        assert p == pos and b == max(1, min(4096, p // 16)) or p + b == 100_000
+        pos += b
+    assert pos == 100_000
+    assert gpu_build.batch_schedule(10, 10) == []
