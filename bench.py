@@ -1,9 +1,12 @@
 """Benchmark of the Link & Code search path on one MI355X.
 
-One step = the whole path (tables, walk + short-list, refinement + top-K) over
-one batch of queries already resident in HBM.  Prints one JSON line.
+Default: the serving workload (20M vectors, PQ 56, k = 32): requests served by
+continuous batching with fp16 tables against the plain float32 path at the
+same 1-recall@1; one step = one backlog of requests, each request the whole
+path (tables, walk + short-list, refinement + top-K) over its queries, already
+resident in HBM.  Prints one JSON line.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload C2-1M]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--form serve|both|plain|batched|assign]
 """
 import argparse
 import dataclasses
@@ -75,20 +78,32 @@ def traffic_from_profiles(kernel_src, precision, ef, S):
     return t.get("bytes_per_launch")
 
 
-def ground_truth(torch, db, q, dev):
+def ground_truth(torch, db, q, dev, q_chunk=512, db_chunk=1 << 21):
     """Exact nearest neighbour (raw vectors, squared L2, lowest id on ties):
-    float32 candidates on the GPU, decided in float64 on the host."""
+    the 8 best of every query by float32 products on the GPU (database in
+    chunks), decided in float64 on the host."""
     dbt = torch.from_numpy(db).to(dev)
     nrm = (dbt * dbt).sum(1)
     gt = np.empty(q.shape[0], np.int64)
-    for c0 in range(0, q.shape[0], 1024):
-        qt = torch.from_numpy(q[c0:c0 + 1024]).to(dev)
-        d = nrm[None, :] - 2.0 * qt @ dbt.T
-        cand = torch.topk(d, 8, dim=1, largest=False).indices.cpu().numpy()
+    for c0 in range(0, q.shape[0], q_chunk):
+        qt = torch.from_numpy(q[c0:c0 + q_chunk]).to(dev)
+        best_d = best_i = None
+        for b0 in range(0, db.shape[0], db_chunk):
+            d = nrm[None, b0:b0 + db_chunk] - 2.0 * qt @ dbt[b0:b0 + db_chunk].T
+            v, i = torch.topk(d, min(8, d.shape[1]), dim=1, largest=False)
+            i = i + b0
+            if best_d is None:
+                best_d, best_i = v, i
+            else:
+                v2, j = torch.topk(torch.cat([best_d, v], 1), min(8, best_d.shape[1] + v.shape[1]), dim=1,
+                                   largest=False)
+                best_d, best_i = v2, torch.gather(torch.cat([best_i, i], 1), 1, j)
+        cand = best_i.cpu().numpy()
         for i in range(cand.shape[0]):
             cd = ((db[cand[i]].astype(np.float64) - q[c0 + i].astype(np.float64)) ** 2).sum(1)
             o = np.lexsort((cand[i], cd))
             gt[c0 + i] = cand[i][o[0]]
+    del dbt, nrm
     return gt
 
 
@@ -171,7 +186,7 @@ def bench_batched(args):
     from paper_1804_09996_amd import builder
     from paper_1804_09996_amd.batched import BatchedSearcher
 
-    w = datagen.WORKLOADS[args.workload if args.workload != "C2-1M" else "C4-10M"]
+    w = datagen.WORKLOADS[args.workload if args.workload not in ("C2-1M", "C5-20M") else "C4-10M"]
     dev = torch.device("cuda:0")
     t0 = time.time()
     ix, db, q = builder.build_workload(w, cache_dir=args.cache, log=log)
@@ -293,63 +308,304 @@ def bench_assign(args):
                       "host_builder": {"vectors": ns, "seconds": cpu_s, "vectors_per_s": ns / cpu_s, "threads": nt}}))
 
 
-def bench_serve(args):
-    """Serving form: Poisson arrivals of requests (batch size log-uniform
-    1..1024, ef in {32, 64, 128, 256}) at fractions of the measured
-    saturation throughput; fp16 tables, bf16 refinement; p50/p99 latency."""
-    import dataclasses
+def host_cores():
+    """Host cores this process may use: its CPU affinity, cut to the cgroup's
+    CPU quota when one is set."""
+    n = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    try:
+        quota, period = open("/sys/fs/cgroup/cpu.max").read().split()[:2]
+        if quota != "max":
+            n = min(n, max(1, int(float(quota) / float(period))))
+    except (OSError, ValueError):
+        pass
+    return max(1, n)
 
+
+SERVE_MIX = (32, 64, 128, 256)  # efSearch of the serving workload's requests
+
+
+def serve_walk_bytes(m, S, E, D):
+    """Algorithmic bytes of one fp16-table walk launch: per query the table
+    (2 m 256) and its row scales (4 m), per expansion one adjacency row (128),
+    per evaluated node its code (m), the short-list written (8 S + 12)."""
+    nq = E.shape[0]
+    return float(nq * (2 * m * 256 + 4 * m + 8 * S + 12) + 128 * E.sum() + m * D.sum())
+
+
+def bench_serve(args):
+    """The serving workload: a resident index, requests (a batch of queries,
+    one efSearch each) served by continuous batching with fp16 tables, against
+    the plain float32 path at the same 1-recall@1.
+
+    Phases, in order: (1) the index build (GPU steps), (2) exact nearest
+    neighbours of the query pool, (3) the walk alone on one stream (its kernel
+    time and roofline), (4) the plain float32 path on fixed batches over an ef
+    grid, (5) the served fp16 form at saturation over scaled ef mixes, (6) the
+    timed steps: W + K backlogs of requests with the workload's ef mix, (7)
+    Poisson loads at fractions of saturation (latency), (8) the oracle on the
+    host cores (baseline and sampled parity)."""
     import torch
 
     import datagen
     import paper_1804_09996_amd as lc
-    from paper_1804_09996_amd import builder, serve
+    from paper_1804_09996_amd import gpu_build, serve
 
     w = datagen.WORKLOADS[args.workload if args.workload != "C2-1M" else "C5-20M"]
-    if not args.n and w.n > 2_000_000:
-        args.n = 2_000_000  # the host builder needs far longer than one run for 20M vectors of 56-byte codes
     if args.n:
-        w = dataclasses.replace(w, name=f"{w.name.split('-')[0]}-{args.n // 1_000_000}M", n=args.n)
+        w = dataclasses.replace(w, name=f"{w.name.split('-')[0]}-{args.n / 1e6:g}M", n=args.n)
     dev = torch.device("cuda:0")
+    # (1) the index: data-parallel build steps on the GPU
     t0 = time.time()
-    ix, db, q = builder.build_workload(w, cache_dir=args.cache, log=log)
-    log(f"index ready in {time.time() - t0:.1f}s (n={ix.n}, max_level={ix.max_level})")
+    build_t = {}
+    ix, db, _ = gpu_build.build_workload_gpu(w, device=dev, log=log, timings=build_t)
+    build_t["data_and_build_s"] = time.time() - t0
+    pool = datagen.vectors(dataclasses.replace(w, nq=args.pool), "query")
+    # (2) ground truth of every pool query
+    t1 = time.time()
+    gt = ground_truth(torch, db, pool, dev)
+    log(f"ground truth of {pool.shape[0]} queries in {time.time() - t1:.1f}s")
     gix = lc.Index.from_index(ix, device=dev)
-    S, K, ef_max = 32, w.topk, 256
-    slot_q, n_slots = 2048, 4
-    bpq = serve.query_bytes(w.m, S, K, w.d, d_proj=w.d_pad if ix.proj is not None else 0)
-    budget = n_slots * slot_q * bpq
-    eng = serve.GpuEngine(gix, n_slots=n_slots, slot_queries=slot_q, ef_max=ef_max, S=S, K=K, precision="f16")
-    # saturation: a backlog of requests all present at t = 0
-    # saturation: a backlog of 1000 requests (~150k queries) all present at t = 0, run three times (the
-    # first also warms the slots); the median of the three
-    sat_runs = []
-    for k in range(3):
-        sat_reqs = serve.poisson_requests(w.d, q, 1e9, 1000, w.seed + 1)
-        for r in sat_reqs:
+    del db
+    S, K, ef_max = args.serve_shortlist, w.topk, 512
+    m = w.m
+    qd = torch.from_numpy(pool).to(dev)
+    nq = pool.shape[0]
+    mix_ef = np.asarray(SERVE_MIX)[datagen.rng(w.seed, "EF").integers(0, len(SERVE_MIX), nq)].astype(np.int32)
+
+    # (3) the dominant kernel alone: fp16-table walk over the pool with the workload's ef mix, one stream.
+    # These are the first launches of this kernel in the process (the build's walks use float32 tables).
+    qp = gix.project(qd)
+    lut16, sc16 = gix.build_lut(qp, lc.LC_LUT_F16, projected=True)
+    ef_t = torch.from_numpy(mix_ef).to(dev)
+    ws1 = gix.workspace(nq, int(mix_ef.max()), S)
+    reps = max(5, args.steps // 2)
+    durs = []
+    for k in range(reps + 1):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        r1 = gix.search(lut16, sc16, ef=ef_t, ef_max=int(mix_ef.max()), S=S, stats=True, ws=ws1)
+        b.record()
+        b.synchronize()
+        if k:
+            durs.append(a.elapsed_time(b))
+    st1 = r1.stats.cpu().numpy()
+    E1, D1 = st1[:, 0].astype(np.int64), st1[:, 1].astype(np.int64)
+    wb = serve_walk_bytes(m, S, E1, D1)
+    walk_ms = float(np.mean(durs))
+    kname = walk_kernel_name(m, "f16", int(mix_ef.max()), S)
+    log(f"walk alone: {kname} {walk_ms:.3f} ms for {nq} queries, {wb / (walk_ms * 1e-3) / 1e9:.0f} GB/s algorithmic")
+    del ws1, lut16, sc16, qp
+
+    # (4) the plain float32 path: tables, walk, refinement on fixed batches of the pool, three streams
+    side = [torch.cuda.Stream(device=dev) for _ in range(3)]
+    wsb = {}
+
+    def plain_point(ef_, steps):
+        """ef_: one efSearch for every query, or an array of per-query values."""
+        per_q = not np.isscalar(ef_)
+        ef_top = int(np.max(ef_)) if per_q else int(ef_)
+        ef_dev = torch.from_numpy(np.asarray(ef_, np.int32)).to(dev) if per_q else None
+        lanes = []
+        for i, st_ in enumerate(side):
+            nb = gix.workspace_bytes(nq, max(ef_top, S), S)
+            if wsb.get(i) is None or wsb[i].numel() < nb:
+                wsb[i] = torch.zeros(nb, dtype=torch.uint8, device=dev)
+            lanes.append((st_, wsb[i]))
+        torch.cuda.synchronize()
+
+        def step(k):
+            st_, ws_ = lanes[k % len(lanes)]
+            with torch.cuda.stream(st_):
+                qx = gix.project(qd)
+                lut, _ = gix.build_lut(qx, lc.LC_LUT_F32, projected=True)
+                r = gix.search(lut, None, ef=ef_dev, ef_max=ef_top, S=S, stats=False, ws=ws_)
+                return gix.refine(qx, r.cand_ids, r.cand_n, K, lc.LC_REFINE_F32, projected=True)
+
+        for k in range(len(lanes)):
+            step(k)
+        torch.cuda.synchronize()
+        t_ = time.perf_counter()
+        for k in range(steps):
+            ids_, d_ = step(k)
+        torch.cuda.synchronize()
+        wall_ = time.perf_counter() - t_
+        ids_np = ids_.cpu().numpy()
+        return {"ef": (None if per_q else ef_), "S": S, "qps": nq * steps / wall_,
+                "R@1": recall(ids_np, gt, 1), "R@10": recall(ids_np, gt, 10)}, ids_np, d_.cpu().numpy()
+
+    # the same requests' queries with their own ef (the workload's mix, scaled for the curve) ...
+    scales = (0.25, 0.5, 1.0, 2.0)
+    plain_curve, plain_res = [], {}
+    for sc_ in scales:
+        efq = np.maximum(1, (mix_ef * sc_).astype(np.int32))
+        pt, _, _ = plain_point(efq, max(3, args.steps // 4))
+        pt.update({"ef_mix": [max(1, int(e * sc_)) for e in SERVE_MIX]})
+        plain_curve.append(pt)
+        log(f"plain fp32 ef mix x{sc_}: R@1 {pt['R@1']:.4f} R@10 {pt['R@10']:.4f} {pt['qps']:.0f} queries/s")
+    # ... and one ef for every query (the cheapest way to a given recall on this pool)
+    uniform_curve = []
+    for ef_ in (32, 48, 64, 96, 128, 192, 256):
+        pt, ids_np, d_np = plain_point(ef_, max(3, args.steps // 4))
+        uniform_curve.append(pt)
+        plain_res[ef_] = (ids_np, d_np)
+        log(f"plain fp32 ef {ef_}: R@1 {pt['R@1']:.4f} R@10 {pt['R@10']:.4f} {pt['qps']:.0f} queries/s")
+    del wsb
+
+    # (5) + (6) the served fp16 form
+    n_slots, slot_q = 4, 2048
+    bpq = serve.query_bytes(m, S, K, w.d, d_proj=w.d_pad)
+    budget = int(0.75 * n_slots * slot_q) * bpq  # below the slots' capacity: admission also waits on memory
+    eng = serve.GpuEngine(gix, n_slots=n_slots, slot_queries=slot_q, ef_max=ef_max, S=S, K=K, precision="f16",
+                          record_walks=True)
+
+    def served_recall(reqs):
+        hit1 = hit10 = tot = 0
+        for r in reqs:
+            g_ = gt[r.qidx]
+            hit1 += int((r.ids[:, :1] == g_[:, None]).any(1).sum())
+            hit10 += int((r.ids[:, :10] == g_[:, None]).any(1).sum())
+            tot += r.size
+        return hit1 / tot, hit10 / tot
+
+    def backlog(efs, n_req, seed):
+        reqs = serve.poisson_requests(w.d, pool, 1e9, n_req, seed, efs=efs)
+        for r in reqs:
             r.arrival = 0.0
-        sat_runs.append(serve.serve(eng, serve.Scheduler(n_slots, slot_q, budget, bpq), sat_reqs))
-        log(f"saturation run {k}: {sat_runs[-1]['qps']:.0f} queries/s")
-    sat = sorted(sat_runs, key=lambda r_: r_["qps"])[1]
-    mean_batch = float(np.mean([r.size for r in sat_reqs]))
-    runs = []
-    for frac in [float(x) for x in args.loads.split(",")]:
-        rate = frac * sat["qps"] / mean_batch
-        reqs = serve.poisson_requests(w.d, q, rate, 400, w.seed + 2)
         res = serve.serve(eng, serve.Scheduler(n_slots, slot_q, budget, bpq), reqs)
+        res["R@1"], res["R@10"] = served_recall(reqs)
+        return res, reqs
+
+    served_curve = []
+    for scale in scales:
+        efs = tuple(max(1, int(e * scale)) for e in SERVE_MIX)
+        res, _ = backlog(efs, args.step_requests * 4, w.seed + 11)
+        served_curve.append({"efs": list(efs), "qps": res["qps"], "R@1": res["R@1"], "R@10": res["R@10"],
+                             "p50_ms": res["latency_ms_p50"], "p99_ms": res["latency_ms_p99"]})
+        log(f"served fp16 ef mix {efs}: R@1 {res['R@1']:.4f} R@10 {res['R@10']:.4f} {res['qps']:.0f} queries/s")
+
+    # the timed steps: each a backlog of step_requests requests (the workload's ef mix) at t = 0
+    for k in range(args.warmup):
+        backlog(SERVE_MIX, args.step_requests, w.seed + 100 + k)
+    eng.walk_log.clear()
+    torch.cuda.synchronize()
+    steps_out, all_reqs = [], []
+    t_ = time.perf_counter()
+    for k in range(args.steps):
+        res, reqs = backlog(SERVE_MIX, args.step_requests, w.seed + 200 + k)
+        steps_out.append(res)
+        all_reqs += reqs
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t_
+    served_q = sum(r_["queries"] for r_ in steps_out)
+    value = served_q / wall
+    r1_head, r10_head = served_recall(all_reqs)
+    timed_walks = list(eng.walk_log)
+    log(f"served fp16 timed: {value:.0f} queries/s over {args.steps} steps, R@1 {r1_head:.4f}")
+
+    # (7) latency at offered loads
+    mean_batch = float(np.mean([r.size for r in all_reqs]))
+    loads = []
+    for frac in [float(x) for x in args.loads.split(",")]:
+        rate = frac * value / mean_batch
+        reqs = serve.poisson_requests(w.d, pool, rate, args.load_requests, w.seed + 2)
+        res = serve.serve(eng, serve.Scheduler(n_slots, slot_q, budget, bpq), reqs)
+        res["R@1"], res["R@10"] = served_recall(reqs)
         res.update({"offered_load_frac": frac, "offered_qps": rate * mean_batch, "request_rate": rate})
-        runs.append(res)
-        log(f"load {frac}: {res}")
-    head = runs[-1]
-    out = {"metric": METRIC, "value": head["qps"], "unit": "queries/s", "n_gpus": 1, "steps": len(runs),
-           "warmup": 1, "ms_per_step": None, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-           "dtype": "f16", "data": "synthetic",
-           "config": {"workload": f"{w.name}: N={w.n} d={w.d}->{w.d_pad} (rotation), PQ {w.m}x256, k={w.k_reg}, "
-                                  f"resident index; Poisson requests, batch round(exp(U(0, ln1024))), ef in "
-                                  f"{{32,64,128,256}}, short-list {S}, top-{K}; fp16 tables, bf16 refinement, fp32 "
-                                  f"re-score; {n_slots} slots x {slot_q} queries, memory budget {budget} B"},
-           "latency_ms": {"p50": head["latency_ms_p50"], "p99": head["latency_ms_p99"]},
-           "saturation_qps": sat["qps"], "saturation_runs_qps": [r_["qps"] for r_ in sat_runs], "loads": runs}
+        loads.append(res)
+        log(f"load {frac}: {res['qps']:.0f} queries/s p50 {res['latency_ms_p50']:.2f} ms p99 "
+            f"{res['latency_ms_p99']:.2f} ms")
+
+    # the plain path at the served form's recall (linear between its grid points)
+    q_plain_r1 = interp_at([(c["R@1"], c["qps"]) for c in plain_curve], r1_head)
+    q_plain_r10 = interp_at([(c["R@10"], c["qps"]) for c in plain_curve], r10_head)
+    q_unif_r1 = interp_at([(c["R@1"], c["qps"]) for c in uniform_curve], r1_head)
+    # served walks of the timed steps: their launch durations on the slot streams (overlapping launches)
+    lw = [x for x in timed_walks if "stats" in x]
+    served_walk = None
+    if lw:
+        sb = sum(serve_walk_bytes(m, S, x["stats"][:, 0].astype(np.int64), x["stats"][:, 1].astype(np.int64))
+                 for x in lw)
+        sd = sum(x["a"].elapsed_time(x["b"]) for x in lw)
+        served_walk = {"launches": len(lw), "mean_launch_ms": sd / len(lw), "bytes": sb,
+                       "GBps_per_launch_time": sb / (sd * 1e-3) / 1e9,
+                       "note": "launches overlap over the slots' streams; each launch's time includes the others'"}
+
+    out = {"metric": METRIC, "value": value, "unit": "queries/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": wall / args.steps * 1e3, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f16", "data": "synthetic",
+           "config": {"workload": f"{w.name}: N={w.n} d={w.d}->{w.d_pad} (seeded orthonormal projection), Gaussian "
+                                  f"mixture ({w.n_comp} components, L2-normalised), PQ {w.m}x256, level-0 degree "
+                                  f"{w.deg0}, k={w.k_reg}, beta codebook {w.n_beta}; resident index built by "
+                                  f"gpu_build; requests of round(exp(U(0, ln1024))) queries, efSearch uniform over "
+                                  f"{list(SERVE_MIX)}, short-list {S}, top-{K}; served by continuous batching "
+                                  f"({n_slots} slots x {slot_q} queries, each on its own stream, memory budget "
+                                  f"{budget} B = 75 % of the slots' capacity) with fp16 tables, bf16 refinement "
+                                  f"and the exact fp32 re-score; a step = a backlog of {args.step_requests} "
+                                  f"requests present at t = 0, served to completion",
+                      "n": w.n, "queries_per_step": served_q / args.steps, "requests_per_step": args.step_requests,
+                      "query_pool": nq},
+           "recall": {"R@1": r1_head, "R@10": r10_head},
+           "plain_fp32": {"qps_at_same_R@1": q_plain_r1, "qps_at_same_R@10": q_plain_r10,
+                          "form": "plain float32 path (tables, walk, refinement, fp32) on fixed batches of the "
+                                  f"{nq}-query pool, each query with its request's ef (the workload's mix, scaled "
+                                  f"x{list(scales)} for the curve), short-list {S}, consecutive batches over three "
+                                  "streams",
+                          "curve": plain_curve,
+                          "one_ef_for_all": {"qps_at_same_R@1": q_unif_r1, "curve": uniform_curve,
+                                             "note": "every query with the same ef: a different workload (no "
+                                                     "request asks for its own ef), shown for context"}},
+           "served_fp16_over_plain_fp32_at_same_R@1": None if not q_plain_r1 else value / q_plain_r1,
+           "served_fp16_over_plain_fp32_at_same_R@10": None if not q_plain_r10 else value / q_plain_r10,
+           "served_fp16_curve": served_curve,
+           "latency_ms": {"p50": loads[-1]["latency_ms_p50"], "p99": loads[-1]["latency_ms_p99"],
+                          "offered_load_frac": loads[-1]["offered_load_frac"]} if loads else None,
+           "loads": loads,
+           "roofline": {"bound": "hbm", "achieved": wb / (walk_ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,
+                        "unit": "GB/s", "frac": wb / (walk_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, "traffic": None,
+                        "kernel": kname, "algorithmic_bytes_per_launch": wb, "launch_ms": walk_ms,
+                        "launches": reps, "queries_per_launch": nq,
+                        "measured": "one stream, the walk alone on the query pool with the workload's ef mix "
+                                    "(these are the process's first launches of this kernel after one warm-up)",
+                        "walk_mean_E": float(E1.mean()), "walk_mean_D": float(D1.mean())},
+           "served_walk_launches": served_walk,
+           "index_build": build_t}
+    if not args.no_cpu_baseline:
+        import oracle
+        from tests import parity
+        oix = oracle.Index(n=ix.n, d=ix.d, d_pad=ix.d_pad, m=ix.m, deg0=ix.deg0, deg_up=ix.deg_up, k_reg=ix.k_reg,
+                           n_beta=ix.n_beta, entry=ix.entry, max_level=ix.max_level, proj=ix.proj,
+                           centroids=ix.centroids, codes=ix.codes, adj0=ix.adj0, level=ix.level,
+                           up_base=ix.up_base, adj_up=ix.adj_up, beta=ix.beta, beta_idx=ix.beta_idx,
+                           m_beta=ix.m_beta)
+        nt = host_cores()
+        # parity: the plain fp32 path at ef 128 against the oracle on a seeded sample of the pool
+        ef_p = 128
+        samp = np.sort(datagen.sample_ids(w.seed, "MISC", nq, args.parity_queries, sub=3))
+        t2 = time.time()
+        o = oix.search(pool[samp], ef_p, S, K, nthreads=nt)
+        dt_par = time.time() - t2
+        ids_p, d_p = plain_res[ef_p]
+        sm = parity.summarize(oix, pool[samp], ids_p[samp], d_p[samp], o)
+        out["parity_sample"] = {"form": f"plain fp32, ef {ef_p}, short-list {S}, top-{K}", "queries": len(samp),
+                                "exact_frac": sm["exact_frac"], "strict_frac": sm["strict_frac"],
+                                "max_rel_dist_err": sm["max_rel_err"]}
+        # the oracle as a baseline: all host cores, the workload's ef mix, about cpu_seconds of work
+        per_q = dt_par * nt / len(samp)
+        n_b = int(min(nq, max(nt, args.cpu_seconds * nt / max(per_q, 1e-6))))
+        t3 = time.time()
+        oix.search(pool[:n_b], mix_ef[:n_b], S, K, nthreads=nt)
+        dt = time.time() - t3
+        n1 = min(200, nq)
+        t4 = time.time()
+        oix.search(pool[:n1], mix_ef[:n1], S, K, nthreads=1)
+        ms1 = (time.time() - t4) / n1 * 1e3
+        out["cpu_baseline"] = {"value": n_b / dt, "unit": "queries/s", "cores": nt, "kind": "oracle",
+                               "sample": f"first {n_b} pool queries with the workload's ef mix, float64 oracle "
+                                         f"search (tables, walk, refinement, top-{K}) on the same index, {nt} "
+                                         f"threads, {dt:.1f} s",
+                               "single_thread_ms_per_query": ms1,
+                               "single_thread_sample": f"first {n1} pool queries, 1 thread",
+                               "cpu_model": cpu_model(), "os_cpu_count": os.cpu_count()}
     print(json.dumps(out), flush=True)
 
 
@@ -358,10 +614,16 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=30)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="C2-1M")
-    ap.add_argument("--form", choices=("both", "plain", "batched", "serve", "assign"), default="both")
-    ap.add_argument("--n", type=int, default=0, help="override the database size (serving form)")
+    ap.add_argument("--workload", default="C5-20M")
+    ap.add_argument("--form", choices=("serve", "both", "plain", "batched", "assign"), default="serve")
+    ap.add_argument("--n", type=int, default=0, help="override the database size (serving form; named in the line)")
     ap.add_argument("--loads", default="0.5,0.8", help="offered loads as fractions of saturation (serving form)")
+    ap.add_argument("--load-requests", type=int, default=5000, help="requests per offered load (serving form)")
+    ap.add_argument("--step-requests", type=int, default=250, help="requests per timed step (serving form)")
+    ap.add_argument("--pool", type=int, default=10_000, help="query pool with exact neighbours (serving form)")
+    ap.add_argument("--serve-shortlist", type=int, default=32, help="short-list size (serving form)")
+    ap.add_argument("--parity-queries", type=int, default=600, help="oracle parity sample (serving form)")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0, help="oracle baseline work (serving form)")
     ap.add_argument("--cache", default=os.environ.get("LC_INDEX_CACHE", os.path.join("/tmp", "lc_index_cache")))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--streams", type=int, default=3,
@@ -410,7 +672,7 @@ def main():
         return bench_serve(args)
     if args.form == "assign":
         return bench_assign(args)
-    w = datagen.WORKLOADS[args.workload]
+    w = datagen.WORKLOADS[args.workload if args.workload != "C5-20M" else "C2-1M"]
     if args.m_beta != 1:
         w = dataclasses.replace(w, m_beta=args.m_beta)
     if args.n_beta:

@@ -121,9 +121,15 @@ def build_index_gpu(w, db, train, proj, level_u, pq_init, beta_ids, beta_init, d
             ws = torch.zeros(nb, dtype=torch.uint8, device=dev)
             adj0_g = gix.t["adj0"]
             base = nodes_g.data_ptr()
-            for pos, bs in sched:
+            last = time.time()
+            for k, (pos, bs) in enumerate(sched):
                 _check(L.lc_graph_insert(gix.handle, adj0_g.data_ptr(), xp_g.data_ptr(), base + 4 * (pos - n_up), bs,
                                          max_count, w.ef_construction, ws.data_ptr(), nb, st), "lc_graph_insert")
+                if log and time.time() - last > 10.0 and k % 64 == 0:
+                    torch.cuda.synchronize(dev)
+                    last = time.time()
+                    log(f"index build: GPU graph batch {k} / {len(sched)} (position {pos} of {n}, "
+                        f"{last - t3:.0f} s)")
             adj0 = adj0_g.cpu().numpy()
             del ws, nodes_g
         gix.close()

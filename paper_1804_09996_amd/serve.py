@@ -42,6 +42,7 @@ class Request:
     slot: int = -1
     ids: Optional[np.ndarray] = None
     dist: Optional[np.ndarray] = None
+    qidx: Optional[np.ndarray] = None  # rows of the query pool the request carries
 
     @property
     def size(self) -> int:
@@ -74,6 +75,7 @@ class Scheduler:
         self.in_flight: Dict[int, List[Request]] = {}
         self.mem_used = 0
         self.max_mem_used = 0
+        self.mem_waits = 0  # admissions cut short by the memory budget while the slot had room
 
     def arrive(self, req: Request):
         if req.size > self.slot_queries or req.size * self.bpq > self.mem_budget:
@@ -89,7 +91,10 @@ class Scheduler:
         while self.pending:
             r = self.pending[0]
             need = r.size * self.bpq
-            if nq + r.size > self.slot_queries or self.mem_used + need > self.mem_budget:
+            if nq + r.size > self.slot_queries:
+                break
+            if self.mem_used + need > self.mem_budget:
+                self.mem_waits += 1
                 break
             self.pending.popleft()
             batch.append(r)
@@ -116,13 +121,17 @@ class GpuEngine:
     """Launches the search path for one slot on its own stream."""
 
     def __init__(self, gix, n_slots: int, slot_queries: int, ef_max: int, S: int, K: int,
-                 precision: str = "f16", sched=None):
+                 precision: str = "f16", sched=None, record_walks: bool = False):
         import torch
 
         import paper_1804_09996_amd as lc
         self.torch, self.lc = torch, lc
         self.gix, self.ef_max, self.S, self.K = gix, ef_max, S, K
         self.sched = sched
+        # record_walks: HIP events around every walk launch on its slot stream and the (E, D) counts of its
+        # queries, for the walk's launch durations and algorithmic bytes (walk_log: one dict per launch)
+        self.record_walks = record_walks
+        self.walk_log: List[dict] = []
         self.lut_dtype = lc.LC_LUT_F16 if precision == "f16" else lc.LC_LUT_F32
         self.refine_p = gix.refine_mode(precision)
         dev = gix.device
@@ -151,9 +160,13 @@ class GpuEngine:
                 "cand_n": torch.empty(Q, dtype=torch.int32, device=dev),
                 "ids": torch.empty((Q, K), dtype=torch.int32, device=dev),
                 "d": torch.empty((Q, K), dtype=torch.float32, device=dev),
+                "stats": torch.empty((Q, 2), dtype=torch.int32, device=dev),
+                "h_stats": torch.empty((Q, 2), dtype=torch.int32).pin_memory(),
                 "ws": torch.zeros(max(int(ws_bytes), 1), dtype=torch.uint8, device=dev),
                 "h_q": torch.empty((Q, d), dtype=torch.float32).pin_memory(),
                 "h_ef": torch.empty(Q, dtype=torch.int32).pin_memory(),
+                "order": torch.empty(Q, dtype=torch.int32, device=dev),
+                "h_order": torch.empty(Q, dtype=torch.int32).pin_memory(),
                 "h_ids": torch.empty((Q, K), dtype=torch.int32).pin_memory(),
                 "h_d": torch.empty((Q, K), dtype=torch.float32).pin_memory(),
                 "event": None, "n": 0,
@@ -171,6 +184,9 @@ class GpuEngine:
             s["h_ef"][n:n + r.size].fill_(int(r.ef))
             n += r.size
         s["n"] = n
+        # the walk's slots take the batch's queries longest ef first, so the long walks do not start last
+        efs = s["h_ef"][:n].numpy()
+        s["h_order"][:n].copy_(torch.from_numpy(np.argsort(-efs, kind="stable").astype(np.int32)))
         # the launch is sized for the batch's own largest ef (a pool of at most
         # 128 entries is held in registers); the slot's workspace covers ef_max
         ef_launch = max(int(r.ef) for r in batch)
@@ -179,6 +195,7 @@ class GpuEngine:
         with torch.cuda.stream(st):
             s["q"][:n].copy_(s["h_q"][:n], non_blocking=True)
             s["ef"][:n].copy_(s["h_ef"][:n], non_blocking=True)
+            s["order"][:n].copy_(s["h_order"][:n], non_blocking=True)
             sp = C.c_void_p(st.cuda_stream)
             scale = s["scale"].data_ptr() if self.lut_dtype == lc.LC_LUT_F16 else None
             proj = self.projected
@@ -189,10 +206,22 @@ class GpuEngine:
             else:
                 lc._check(L.lc_build_lut(h, s["q"].data_ptr(), n, self.lut_dtype, s["lut"].data_ptr(), scale, sp),
                           "lc_build_lut")
+            rec = None
+            if self.record_walks:
+                rec = {"slot": slot, "n": n, "ef_launch": ef_launch, "a": torch.cuda.Event(enable_timing=True),
+                       "b": torch.cuda.Event(enable_timing=True)}
+                rec["a"].record(st)
             lc._check(L.lc_search_sched(h, s["lut"].data_ptr(), self.lut_dtype, scale, n, s["ef"].data_ptr(),
-                                        ef_launch, self.S, None, s["cand_ids"].data_ptr(), s["cand_adc"].data_ptr(),
-                                        s["cand_n"].data_ptr(), None, s["ws"].data_ptr(), s["ws"].numel(),
+                                        ef_launch, self.S, s["order"].data_ptr(), s["cand_ids"].data_ptr(),
+                                        s["cand_adc"].data_ptr(),
+                                        s["cand_n"].data_ptr(), s["stats"].data_ptr() if rec else None,
+                                        s["ws"].data_ptr(), s["ws"].numel(),
                                         None if self.sched is None else C.byref(self.sched), sp), "lc_search")
+            if rec is not None:
+                rec["b"].record(st)
+                s["h_stats"][:n].copy_(s["stats"][:n], non_blocking=True)
+                self.walk_log.append(rec)
+            s["rec"] = rec
             refine = L.lc_refine_projected if proj else L.lc_refine
             qin = s["qp"] if proj else s["q"]
             lc._check(refine(h, qin.data_ptr(), n, s["cand_ids"].data_ptr(), s["cand_n"].data_ptr(), self.S, self.K,
@@ -211,6 +240,9 @@ class GpuEngine:
 
     def deliver(self, slot: int, batch: List[Request]):
         s = self.slots[slot]
+        rec = s.get("rec")
+        if rec is not None:
+            rec["stats"] = s["h_stats"][:rec["n"]].numpy().copy()
         n = 0
         for r in batch:
             r.ids = s["h_ids"][n:n + r.size].numpy().copy()
@@ -260,7 +292,8 @@ def serve(engine, sched: Scheduler, requests: List[Request], clock: Callable[[],
     nqs = sum(r.size for r in finished)
     return {"requests": len(finished), "queries": nqs, "wall_s": wall, "qps": nqs / wall if wall > 0 else 0.0,
             "latency_ms_p50": float(np.percentile(lat, 50)), "latency_ms_p99": float(np.percentile(lat, 99)),
-            "latency_ms_mean": float(lat.mean()), "max_mem_used": sched.max_mem_used}
+            "latency_ms_mean": float(lat.mean()), "max_mem_used": sched.max_mem_used,
+            "mem_waits": sched.mem_waits}
 
 
 def poisson_requests(d: int, queries: np.ndarray, rate_rps: float, n_requests: int, seed: int,
@@ -278,5 +311,5 @@ def poisson_requests(d: int, queries: np.ndarray, rate_rps: float, n_requests: i
         t += float(gaps[k])
         idx = (pos + np.arange(sizes[k])) % queries.shape[0]
         pos = (pos + sizes[k]) % queries.shape[0]
-        out.append(Request(rid=k, queries=np.ascontiguousarray(queries[idx]), ef=int(efv[k]), arrival=t))
+        out.append(Request(rid=k, queries=np.ascontiguousarray(queries[idx]), ef=int(efv[k]), arrival=t, qidx=idx))
     return out
