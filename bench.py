@@ -394,7 +394,35 @@ def bench_serve(args):
     walk_ms = float(np.mean(durs))
     kname = walk_kernel_name(m, "f16", int(mix_ef.max()), S)
     log(f"walk alone: {kname} {walk_ms:.3f} ms for {nq} queries, {wb / (walk_ms * 1e-3) / 1e9:.0f} GB/s algorithmic")
-    del ws1, lut16, sc16, qp
+
+    # every kernel of the path on the same batch, one stream (median of reps)
+    def timed(fn, reps_=5):
+        ts = []
+        for k in range(reps_ + 1):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            fn()
+            b.record()
+            b.synchronize()
+            if k:
+                ts.append(a.elapsed_time(b))
+        return float(np.median(ts))
+
+    kern = {"project": timed(lambda: gix.project(qd)),
+            "build_lut_f16": timed(lambda: gix.build_lut(qp, lc.LC_LUT_F16, projected=True)),
+            "build_lut_f32": timed(lambda: gix.build_lut(qp, lc.LC_LUT_F32, projected=True)),
+            "walk_f16": walk_ms}
+    lut32, _ = gix.build_lut(qp, lc.LC_LUT_F32, projected=True)
+    kern["walk_f32"] = timed(lambda: gix.search(lut32, None, ef=ef_t, ef_max=int(mix_ef.max()), S=S, stats=False,
+                                                ws=ws1))
+    for name, prec in (("refine_f32", lc.LC_REFINE_F32), ("refine_bf16_rescore", lc.LC_REFINE_BF16_RESCORE)):
+        kern[name] = timed(lambda: gix.refine(qp, r1.cand_ids, r1.cand_n, K, prec, projected=True))
+    served_refine = args.serve_refine
+    if served_refine == "auto":
+        served_refine = "bf16" if kern["refine_bf16_rescore"] < kern["refine_f32"] else "f32"
+    log("one-stream kernel times (ms, " + f"{nq} queries): " + ", ".join(f"{k} {v:.3f}" for k, v in kern.items())
+        + f"; served refinement: {served_refine}")
+    del ws1, lut16, sc16, qp, lut32
 
     # (4) the plain float32 path: tables, walk, refinement on fixed batches of the pool, three streams
     side = [torch.cuda.Stream(device=dev) for _ in range(3)]
@@ -452,11 +480,12 @@ def bench_serve(args):
     del wsb
 
     # (5) + (6) the served fp16 form
-    n_slots, slot_q = 4, 2048
+    n_slots, slot_q = args.slots, args.slot_queries
     bpq = serve.query_bytes(m, S, K, w.d, d_proj=w.d_pad)
     budget = int(0.75 * n_slots * slot_q) * bpq  # below the slots' capacity: admission also waits on memory
     eng = serve.GpuEngine(gix, n_slots=n_slots, slot_queries=slot_q, ef_max=ef_max, S=S, K=K, precision="f16",
-                          record_walks=True)
+                          record_walks=True,
+                          refine=lc.LC_REFINE_BF16_RESCORE if served_refine == "bf16" else lc.LC_REFINE_F32)
 
     def served_recall(reqs):
         hit1 = hit10 = tot = 0
@@ -483,22 +512,19 @@ def bench_serve(args):
                              "p50_ms": res["latency_ms_p50"], "p99_ms": res["latency_ms_p99"]})
         log(f"served fp16 ef mix {efs}: R@1 {res['R@1']:.4f} R@10 {res['R@10']:.4f} {res['qps']:.0f} queries/s")
 
-    # the timed steps: each a backlog of step_requests requests (the workload's ef mix) at t = 0
-    for k in range(args.warmup):
-        backlog(SERVE_MIX, args.step_requests, w.seed + 100 + k)
+    # the timed steps: K steps of step_requests requests each (the workload's ef mix), all present at t = 0
+    # and served back to back by the loop (as the plain path's batches follow each other on its streams)
+    if args.warmup:
+        backlog(SERVE_MIX, args.warmup * args.step_requests, w.seed + 100)
     eng.walk_log.clear()
     torch.cuda.synchronize()
-    steps_out, all_reqs = [], []
     t_ = time.perf_counter()
-    for k in range(args.steps):
-        res, reqs = backlog(SERVE_MIX, args.step_requests, w.seed + 200 + k)
-        steps_out.append(res)
-        all_reqs += reqs
+    res_t, all_reqs = backlog(SERVE_MIX, args.steps * args.step_requests, w.seed + 200)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t_
-    served_q = sum(r_["queries"] for r_ in steps_out)
+    served_q = res_t["queries"]
     value = served_q / wall
-    r1_head, r10_head = served_recall(all_reqs)
+    r1_head, r10_head = res_t["R@1"], res_t["R@10"]
     timed_walks = list(eng.walk_log)
     log(f"served fp16 timed: {value:.0f} queries/s over {args.steps} steps, R@1 {r1_head:.4f}")
 
@@ -539,10 +565,11 @@ def bench_serve(args):
                                   f"gpu_build; requests of round(exp(U(0, ln1024))) queries, efSearch uniform over "
                                   f"{list(SERVE_MIX)}, short-list {S}, top-{K}; served by continuous batching "
                                   f"({n_slots} slots x {slot_q} queries, each on its own stream, memory budget "
-                                  f"{budget} B = 75 % of the slots' capacity) with fp16 tables, bf16 refinement "
-                                  f"and the exact fp32 re-score; a step = a backlog of {args.step_requests} "
-                                  f"requests present at t = 0, served to completion",
+                                  f"{budget} B = 75 % of the slots' capacity) with fp16 tables and the "
+                                  f"{served_refine} refinement; a step = {args.step_requests} requests; the K "
+                                  f"timed steps' requests are present at t = 0 and served back to back",
                       "n": w.n, "queries_per_step": served_q / args.steps, "requests_per_step": args.step_requests,
+                      "refinement": served_refine,
                       "query_pool": nq},
            "recall": {"R@1": r1_head, "R@10": r10_head},
            "plain_fp32": {"qps_at_same_R@1": q_plain_r1, "qps_at_same_R@10": q_plain_r10,
@@ -568,6 +595,7 @@ def bench_serve(args):
                                     "(these are the process's first launches of this kernel after one warm-up)",
                         "walk_mean_E": float(E1.mean()), "walk_mean_D": float(D1.mean())},
            "served_walk_launches": served_walk,
+           "one_stream_kernels_ms": kern,
            "index_build": build_t}
     if not args.no_cpu_baseline:
         import oracle
@@ -593,16 +621,21 @@ def bench_serve(args):
         per_q = dt_par * nt / len(samp)
         n_b = int(min(nq, max(nt, args.cpu_seconds * nt / max(per_q, 1e-6))))
         t3 = time.time()
-        oix.search(pool[:n_b], mix_ef[:n_b], S, K, nthreads=nt)
+        passes = 0
+        while True:  # the sample repeated until about cpu_seconds of work
+            oix.search(pool[:n_b], mix_ef[:n_b], S, K, nthreads=nt)
+            passes += 1
+            if time.time() - t3 >= args.cpu_seconds or passes >= 50:
+                break
         dt = time.time() - t3
         n1 = min(200, nq)
         t4 = time.time()
         oix.search(pool[:n1], mix_ef[:n1], S, K, nthreads=1)
         ms1 = (time.time() - t4) / n1 * 1e3
-        out["cpu_baseline"] = {"value": n_b / dt, "unit": "queries/s", "cores": nt, "kind": "oracle",
-                               "sample": f"first {n_b} pool queries with the workload's ef mix, float64 oracle "
-                                         f"search (tables, walk, refinement, top-{K}) on the same index, {nt} "
-                                         f"threads, {dt:.1f} s",
+        out["cpu_baseline"] = {"value": n_b * passes / dt, "unit": "queries/s", "cores": nt, "kind": "oracle",
+                               "sample": f"first {n_b} pool queries with the workload's ef mix ({passes} passes), "
+                                         f"float64 oracle search (tables, walk, refinement, top-{K}) on the same "
+                                         f"index, {nt} threads, {dt:.1f} s",
                                "single_thread_ms_per_query": ms1,
                                "single_thread_sample": f"first {n1} pool queries, 1 thread",
                                "cpu_model": cpu_model(), "os_cpu_count": os.cpu_count()}
@@ -622,6 +655,11 @@ def main():
     ap.add_argument("--step-requests", type=int, default=250, help="requests per timed step (serving form)")
     ap.add_argument("--pool", type=int, default=10_000, help="query pool with exact neighbours (serving form)")
     ap.add_argument("--serve-shortlist", type=int, default=32, help="short-list size (serving form)")
+    ap.add_argument("--slots", type=int, default=6, help="serving slots (each with its own streams; serving form)")
+    ap.add_argument("--slot-queries", type=int, default=4096, help="queries per serving slot (serving form)")
+    ap.add_argument("--serve-refine", choices=("auto", "f32", "bf16"), default="auto",
+                    help="served refinement: fp32, bf16 with the fp32 re-score, or the faster of the two on the "
+                         "one-stream measurement (serving form)")
     ap.add_argument("--parity-queries", type=int, default=600, help="oracle parity sample (serving form)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="oracle baseline work (serving form)")
     ap.add_argument("--cache", default=os.environ.get("LC_INDEX_CACHE", os.path.join("/tmp", "lc_index_cache")))

@@ -121,7 +121,8 @@ class GpuEngine:
     """Launches the search path for one slot on its own stream."""
 
     def __init__(self, gix, n_slots: int, slot_queries: int, ef_max: int, S: int, K: int,
-                 precision: str = "f16", sched=None, record_walks: bool = False):
+                 precision: str = "f16", sched=None, record_walks: bool = False, refine: Optional[int] = None,
+                 split: bool = True):
         import torch
 
         import paper_1804_09996_amd as lc
@@ -132,8 +133,11 @@ class GpuEngine:
         # queries, for the walk's launch durations and algorithmic bytes (walk_log: one dict per launch)
         self.record_walks = record_walks
         self.walk_log: List[dict] = []
+        # split: a batch's queries whose pool fits registers (<= 128 entries) are walked by their own launch,
+        # concurrently with the larger pools' launch (each with its own workspace)
+        self.split = split
         self.lut_dtype = lc.LC_LUT_F16 if precision == "f16" else lc.LC_LUT_F32
-        self.refine_p = gix.refine_mode(precision)
+        self.refine_p = gix.refine_mode(precision) if refine is None else int(refine)
         dev = gix.device
         Q, d, m = slot_queries, gix.d, gix.m
         # an index with a projection projects each batch once, for the tables and the refinement, as
@@ -147,6 +151,9 @@ class GpuEngine:
             ws_bytes = max(lc.lib().lc_search_workspace_bytes_sched(gix.handle, Q, e, S,
                                                                     None if sched is None else lc.C.byref(sched))
                            for e in sorted(set(range(64, ef_max, 64)) | {1, ef_max}))
+            ws2_bytes = max(lc.lib().lc_search_workspace_bytes_sched(gix.handle, Q, e, S,
+                                                                     None if sched is None else lc.C.byref(sched))
+                            for e in (1, 64, 128))
             self.slots.append({
                 "stream": torch.cuda.Stream(device=dev),
                 "q": torch.empty((Q, d), dtype=torch.float32, device=dev),
@@ -163,10 +170,10 @@ class GpuEngine:
                 "stats": torch.empty((Q, 2), dtype=torch.int32, device=dev),
                 "h_stats": torch.empty((Q, 2), dtype=torch.int32).pin_memory(),
                 "ws": torch.zeros(max(int(ws_bytes), 1), dtype=torch.uint8, device=dev),
+                "ws2": torch.zeros(max(int(ws2_bytes), 1) if split else 1, dtype=torch.uint8, device=dev),
+                "stream2": torch.cuda.Stream(device=dev),
                 "h_q": torch.empty((Q, d), dtype=torch.float32).pin_memory(),
                 "h_ef": torch.empty(Q, dtype=torch.int32).pin_memory(),
-                "order": torch.empty(Q, dtype=torch.int32, device=dev),
-                "h_order": torch.empty(Q, dtype=torch.int32).pin_memory(),
                 "h_ids": torch.empty((Q, K), dtype=torch.int32).pin_memory(),
                 "h_d": torch.empty((Q, K), dtype=torch.float32).pin_memory(),
                 "event": None, "n": 0,
@@ -175,27 +182,51 @@ class GpuEngine:
         # before its first launch reads them
         torch.cuda.current_stream(dev).synchronize()
 
+    def _walk(self, s, st, row0, rows, ef_launch, ws):
+        """One walk launch over rows [row0, row0 + rows) of the slot's batch."""
+        lc, C = self.lc, self.lc.C
+        L, h = lc.lib(), self.gix.handle
+        lut_row = s["lut"][0].numel() * s["lut"].element_size()
+        rec = None
+        if self.record_walks:
+            rec = {"n": rows, "row0": row0, "ef_launch": ef_launch, "a": self.torch.cuda.Event(enable_timing=True),
+                   "b": self.torch.cuda.Event(enable_timing=True)}
+            rec["a"].record(st)
+        scale = s["scale"].data_ptr() + 4 * self.gix.m * row0 if self.lut_dtype == lc.LC_LUT_F16 else None
+        lc._check(L.lc_search_sched(h, s["lut"].data_ptr() + lut_row * row0, self.lut_dtype, scale, rows,
+                                    s["ef"].data_ptr() + 4 * row0, ef_launch, self.S, None,
+                                    s["cand_ids"].data_ptr() + 4 * self.S * row0,
+                                    s["cand_adc"].data_ptr() + 4 * self.S * row0, s["cand_n"].data_ptr() + 4 * row0,
+                                    s["stats"].data_ptr() + 8 * row0 if rec else None, ws.data_ptr(), ws.numel(),
+                                    None if self.sched is None else C.byref(self.sched), C.c_void_p(st.cuda_stream)),
+                  "lc_search")
+        if rec is not None:
+            rec["b"].record(st)
+            s["recs"].append(rec)
+            self.walk_log.append(rec)
+
     def launch(self, slot: int, batch: List[Request]):
         torch, lc, C = self.torch, self.lc, self.lc.C
         s = self.slots[slot]
+        # requests longest ef first: the walk's slots take the long walks first, and the batch splits into
+        # two contiguous classes (pools above 128 entries, then pools in registers)
+        batch = sorted(batch, key=lambda r: -r.ef)
+        s["batch"] = batch
         n = 0
+        n_big = 0
         for r in batch:
             s["h_q"][n:n + r.size].copy_(torch.from_numpy(r.queries))
             s["h_ef"][n:n + r.size].fill_(int(r.ef))
             n += r.size
+            if self._pool(r.ef) > 128:
+                n_big = n
         s["n"] = n
-        # the walk's slots take the batch's queries longest ef first, so the long walks do not start last
-        efs = s["h_ef"][:n].numpy()
-        s["h_order"][:n].copy_(torch.from_numpy(np.argsort(-efs, kind="stable").astype(np.int32)))
-        # the launch is sized for the batch's own largest ef (a pool of at most
-        # 128 entries is held in registers); the slot's workspace covers ef_max
-        ef_launch = max(int(r.ef) for r in batch)
+        s["recs"] = []
         L, h = lc.lib(), self.gix.handle
         st = s["stream"]
         with torch.cuda.stream(st):
             s["q"][:n].copy_(s["h_q"][:n], non_blocking=True)
             s["ef"][:n].copy_(s["h_ef"][:n], non_blocking=True)
-            s["order"][:n].copy_(s["h_order"][:n], non_blocking=True)
             sp = C.c_void_p(st.cuda_stream)
             scale = s["scale"].data_ptr() if self.lut_dtype == lc.LC_LUT_F16 else None
             proj = self.projected
@@ -206,22 +237,20 @@ class GpuEngine:
             else:
                 lc._check(L.lc_build_lut(h, s["q"].data_ptr(), n, self.lut_dtype, s["lut"].data_ptr(), scale, sp),
                           "lc_build_lut")
-            rec = None
-            if self.record_walks:
-                rec = {"slot": slot, "n": n, "ef_launch": ef_launch, "a": torch.cuda.Event(enable_timing=True),
-                       "b": torch.cuda.Event(enable_timing=True)}
-                rec["a"].record(st)
-            lc._check(L.lc_search_sched(h, s["lut"].data_ptr(), self.lut_dtype, scale, n, s["ef"].data_ptr(),
-                                        ef_launch, self.S, s["order"].data_ptr(), s["cand_ids"].data_ptr(),
-                                        s["cand_adc"].data_ptr(),
-                                        s["cand_n"].data_ptr(), s["stats"].data_ptr() if rec else None,
-                                        s["ws"].data_ptr(), s["ws"].numel(),
-                                        None if self.sched is None else C.byref(self.sched), sp), "lc_search")
-            if rec is not None:
-                rec["b"].record(st)
-                s["h_stats"][:n].copy_(s["stats"][:n], non_blocking=True)
-                self.walk_log.append(rec)
-            s["rec"] = rec
+            ef_top = int(batch[0].ef)
+            if self.split and 0 < n_big < n:
+                # the two classes concurrently: the large pools on the slot's second stream
+                st2 = s["stream2"]
+                st2.wait_stream(st)
+                self._walk(s, st2, 0, n_big, ef_top, s["ws"])
+                ef_small = max(int(r.ef) for r in batch if self._pool(r.ef) <= 128)
+                self._walk(s, st, n_big, n - n_big, ef_small, s["ws2"])
+                st.wait_stream(st2)
+            else:
+                self._walk(s, st, 0, n, ef_top, s["ws"])
+            for rec in s["recs"]:
+                s["h_stats"][rec["row0"]:rec["row0"] + rec["n"]].copy_(
+                    s["stats"][rec["row0"]:rec["row0"] + rec["n"]], non_blocking=True)
             refine = L.lc_refine_projected if proj else L.lc_refine
             qin = s["qp"] if proj else s["q"]
             lc._check(refine(h, qin.data_ptr(), n, s["cand_ids"].data_ptr(), s["cand_n"].data_ptr(), self.S, self.K,
@@ -232,6 +261,10 @@ class GpuEngine:
             ev.record(st)
             s["event"] = ev
 
+    def _pool(self, ef: int) -> int:
+        """Pool entries of a query's walk: max(ef, S) rounded up to 64."""
+        return (max(int(ef), self.S) + 63) // 64 * 64
+
     def ready(self, slot: int) -> bool:
         return self.slots[slot]["event"].query()
 
@@ -240,11 +273,10 @@ class GpuEngine:
 
     def deliver(self, slot: int, batch: List[Request]):
         s = self.slots[slot]
-        rec = s.get("rec")
-        if rec is not None:
-            rec["stats"] = s["h_stats"][:rec["n"]].numpy().copy()
+        for rec in s.get("recs", []):
+            rec["stats"] = s["h_stats"][rec["row0"]:rec["row0"] + rec["n"]].numpy().copy()
         n = 0
-        for r in batch:
+        for r in s["batch"]:  # the order the launch laid the requests out in
             r.ids = s["h_ids"][n:n + r.size].numpy().copy()
             r.dist = s["h_d"][n:n + r.size].numpy().copy()
             n += r.size

@@ -8,11 +8,13 @@ from paper_1804_09996_amd import serve
 pytestmark = pytest.mark.gpu
 
 
-@pytest.mark.parametrize("precision,efs", [("f16", (16, 32, 64)), ("f32", (16, 32, 64)),
-                                           ("f16", (16, 64, 160, 256))])
-def test_results_same_alone_and_in_the_mix(c1_build, precision, efs):
+@pytest.mark.parametrize("precision,efs,split", [("f16", (16, 32, 64), True), ("f32", (16, 32, 64), True),
+                                                 ("f16", (16, 64, 160, 256), True),
+                                                 ("f16", (16, 64, 160, 256), False)])
+def test_results_same_alone_and_in_the_mix(c1_build, precision, efs, split):
     # each launch is sized by its batch's largest ef (pools up to 128 in
-    # registers, larger in LDS); results never depend on it
+    # registers, larger in LDS), or split into the two classes walked
+    # concurrently; results never depend on it
     import torch
 
     import paper_1804_09996_amd as lc
@@ -20,7 +22,8 @@ def test_results_same_alone_and_in_the_mix(c1_build, precision, efs):
     gix = lc.Index.from_index(ix)
     S, K, ef_max = 32, 10, max(efs)
     reqs = serve.poisson_requests(w.d, q, rate_rps=4000.0, n_requests=40, seed=5, efs=efs, max_batch=48)
-    eng = serve.GpuEngine(gix, n_slots=3, slot_queries=128, ef_max=ef_max, S=S, K=K, precision=precision)
+    eng = serve.GpuEngine(gix, n_slots=3, slot_queries=128, ef_max=ef_max, S=S, K=K, precision=precision,
+                          split=split, record_walks=True)
     sch = serve.Scheduler(3, 128, mem_budget=200 * serve.query_bytes(w.m, S, K, w.d), bytes_per_query=
                           serve.query_bytes(w.m, S, K, w.d))
     stats = serve.serve(eng, sch, reqs)
@@ -31,6 +34,9 @@ def test_results_same_alone_and_in_the_mix(c1_build, precision, efs):
         ids, d, _ = gix.query(torch.from_numpy(r.queries), ef=r.ef, ef_max=ef_max, S=S, K=K, precision=precision)
         assert np.array_equal(r.ids, ids.cpu().numpy()), r.rid
         assert np.array_equal(r.dist.view(np.uint32), d.cpu().numpy().view(np.uint32)), r.rid
+    # the recorded walk launches cover every query once, with its (E, D)
+    assert sum(x["n"] for x in eng.walk_log) == sum(r.size for r in reqs)
+    assert all(x["stats"].shape == (x["n"], 2) and (x["stats"][:, 0] >= 1).all() for x in eng.walk_log)
     print(f"{precision}: {stats}")
 
 
