@@ -412,6 +412,12 @@ def bench_serve(args):
             "build_lut_f16": timed(lambda: gix.build_lut(qp, lc.LC_LUT_F16, projected=True)),
             "build_lut_f32": timed(lambda: gix.build_lut(qp, lc.LC_LUT_F32, projected=True)),
             "walk_f16": walk_ms}
+    for hb in (10, 11, 12):  # the walk's visited-table sizes (same results; LDS per slot against capacity)
+        sc_ = lc.schedule(hash_bits=hb)
+        wsh = gix.workspace(nq, int(mix_ef.max()), S, sc_)
+        kern[f"walk_f16_hash_bits_{hb}"] = timed(lambda: gix.search(lut16, sc16, ef=ef_t, ef_max=int(mix_ef.max()),
+                                                                    S=S, stats=False, sched=sc_, ws=wsh))
+        del wsh
     lut32, _ = gix.build_lut(qp, lc.LC_LUT_F32, projected=True)
     kern["walk_f32"] = timed(lambda: gix.search(lut32, None, ef=ef_t, ef_max=int(mix_ef.max()), S=S, stats=False,
                                                 ws=ws1))
@@ -496,11 +502,19 @@ def bench_serve(args):
             tot += r.size
         return hit1 / tot, hit10 / tot
 
-    def backlog(efs, n_req, seed):
+    def backlog(efs, n_req, seed, timing=None):
+        """n_req requests present at t = 0, served to completion; `timing`
+        receives the wall time of the loop alone (requests drawn before it,
+        recall taken after it)."""
         reqs = serve.poisson_requests(w.d, pool, 1e9, n_req, seed, efs=efs)
         for r in reqs:
             r.arrival = 0.0
+        torch.cuda.synchronize()
+        t_b = time.perf_counter()
         res = serve.serve(eng, serve.Scheduler(n_slots, slot_q, budget, bpq), reqs)
+        torch.cuda.synchronize()
+        if timing is not None:
+            timing.append(time.perf_counter() - t_b)
         res["R@1"], res["R@10"] = served_recall(reqs)
         return res, reqs
 
@@ -517,11 +531,9 @@ def bench_serve(args):
     if args.warmup:
         backlog(SERVE_MIX, args.warmup * args.step_requests, w.seed + 100)
     eng.walk_log.clear()
-    torch.cuda.synchronize()
-    t_ = time.perf_counter()
-    res_t, all_reqs = backlog(SERVE_MIX, args.steps * args.step_requests, w.seed + 200)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t_
+    tw = []
+    res_t, all_reqs = backlog(SERVE_MIX, args.steps * args.step_requests, w.seed + 200, timing=tw)
+    wall = tw[0]
     served_q = res_t["queries"]
     value = served_q / wall
     r1_head, r10_head = res_t["R@1"], res_t["R@10"]

@@ -68,7 +68,7 @@ class BatchedSearcher:
         torch = gix.torch
         self.torch, self.gix = torch, gix
         self.nq, self.ef_max, self.S, self.K = nq, ef_max, S, K
-        self.lut_dtype = LC_LUT_F16 if precision == "f16" else LC_LUT_F32
+        self.lut_dtype = LC_LUT_F16 if precision in ("f16", "f16+bf16") else LC_LUT_F32
         self.refine_p = gix.refine_mode(precision)
         dev = gix.device
         # the batch in (class, longest ef first) order, and the map back to query order

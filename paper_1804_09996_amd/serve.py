@@ -136,14 +136,14 @@ class GpuEngine:
         # split: a batch's queries whose pool fits registers (<= 128 entries) are walked by their own launch,
         # concurrently with the larger pools' launch (each with its own workspace)
         self.split = split
-        self.lut_dtype = lc.LC_LUT_F16 if precision == "f16" else lc.LC_LUT_F32
+        self.lut_dtype = lc.LC_LUT_F16 if precision in ("f16", "f16+bf16") else lc.LC_LUT_F32
         self.refine_p = gix.refine_mode(precision) if refine is None else int(refine)
         dev = gix.device
         Q, d, m = slot_queries, gix.d, gix.m
         # an index with a projection projects each batch once, for the tables and the refinement, as
         # Index.query does: the same rounding whatever the batch, so results never depend on it
         self.projected = gix.has_projection
-        lut_t = torch.float16 if precision == "f16" else torch.float32
+        lut_t = torch.float16 if precision in ("f16", "f16+bf16") else torch.float32
         self.slots = []
         for _ in range(n_slots):
             # launches are sized by their batch's largest ef: smaller pools fit
@@ -159,7 +159,7 @@ class GpuEngine:
                 "q": torch.empty((Q, d), dtype=torch.float32, device=dev),
                 "qp": torch.empty((Q, gix.d_pad) if self.projected else (1,), dtype=torch.float32, device=dev),
                 "ef": torch.empty(Q, dtype=torch.int32, device=dev),
-                "lut": torch.empty(((Q, gix.lut_stride_f16 if precision == "f16" else gix.lut_stride) if gix.coarse_k
+                "lut": torch.empty(((Q, gix.lut_stride_f16 if precision in ("f16", "f16+bf16") else gix.lut_stride) if gix.coarse_k
                                     else (Q, m, 256)), dtype=lut_t, device=dev),
                 "scale": torch.empty((Q, m), dtype=torch.float32, device=dev),
                 "cand_ids": torch.empty((Q, S), dtype=torch.int32, device=dev),

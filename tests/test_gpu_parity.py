@@ -300,12 +300,13 @@ def test_precision_refine_rescores_exactly(c1, torch):
     assert same >= 0.95 * w.nq
 
 
-def test_precision_path_recall_close_to_plain(c1, torch):
+@pytest.mark.parametrize("precision", ["f16", "f16+bf16"])
+def test_precision_path_recall_close_to_plain(c1, torch, precision):
     w, ix, gix, db, q = c1
     qt = torch.from_numpy(q)
     gt = np.argmin(((q[:, None, :].astype(np.float64) - db[None].astype(np.float64)) ** 2).sum(-1), 1)
     i32, _, _ = gix.query(qt, ef=w.ef, ef_max=w.ef, S=w.shortlist, K=w.topk)
-    i16, d16, _ = gix.query(qt, ef=w.ef, ef_max=w.ef, S=w.shortlist, K=w.topk, precision="f16")
+    i16, d16, _ = gix.query(qt, ef=w.ef, ef_max=w.ef, S=w.shortlist, K=w.topk, precision=precision)
     r32 = parity.recall_at(i32.cpu().numpy(), gt, 10)
     r16 = parity.recall_at(i16.cpu().numpy(), gt, 10)
     print(f"R@10 fp32 {r32:.3f} fp16/bf16 {r16:.3f}")

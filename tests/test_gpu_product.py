@@ -125,7 +125,7 @@ def test_generic_kernel_block_counts(torch, m, mb):
     _check(ixp, q, w, torch, precisions=("f32",))
     gix = lc.Index.from_index(ixp)
     with pytest.raises(lc.LCError):
-        gix.query(torch.from_numpy(q), ef=w.ef, ef_max=w.ef, S=w.shortlist, K=w.topk, precision="f16")
+        gix.query(torch.from_numpy(q), ef=w.ef, ef_max=w.ef, S=w.shortlist, K=w.topk, precision="f16+bf16")
     gix.close()
 
 
