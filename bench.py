@@ -183,13 +183,13 @@ def bench_batched(args):
 
     import datagen
     import paper_1804_09996_amd as lc
-    from paper_1804_09996_amd import builder
+    from paper_1804_09996_amd import gpu_build
     from paper_1804_09996_amd.batched import BatchedSearcher
 
     w = datagen.WORKLOADS[args.workload if args.workload not in ("C2-1M", "C5-20M") else "C4-10M"]
     dev = torch.device("cuda:0")
     t0 = time.time()
-    ix, db, q = builder.build_workload(w, cache_dir=args.cache, log=log)
+    ix, db, q = gpu_build.build_workload_gpu(w, device=dev, log=log)
     log(f"index ready in {time.time() - t0:.1f}s (n={ix.n}, max_level={ix.max_level})")
     gix = lc.Index.from_index(ix, device=dev)
     nq, K = q.shape[0], w.topk
@@ -200,7 +200,12 @@ def bench_batched(args):
     prec = "f16" if args.precision != "f32" else "f32"
     bs = BatchedSearcher(gix, nq, ef_max=ef_max, S=S, K=K, precision=prec)
     bs.set_inputs(q, ef)
-    sched = bs.tune(cache_path=None, log=log)
+    if args.no_tune:  # the default schedule, one class: every step is one walk launch of one kernel
+        import paper_1804_09996_amd as lc_
+        sched = lc_.schedule()
+        bs.sched, bs.table = sched, []
+    else:
+        sched = bs.tune(cache_path=None, log=log)
     bs.capture()
     for _ in range(args.warmup):
         bs.run()
@@ -676,6 +681,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="oracle baseline work (serving form)")
     ap.add_argument("--cache", default=os.environ.get("LC_INDEX_CACHE", os.path.join("/tmp", "lc_index_cache")))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="batched form: the default walk schedule and one ef class (no autotuning)")
     ap.add_argument("--streams", type=int, default=3,
                     help="streams that consecutive steps alternate on (1 = each step runs alone)")
     ap.add_argument("--precision", choices=("f32", "f16", "f16+bf16"), default="f32",
@@ -736,7 +743,11 @@ def main():
         w = dataclasses.replace(w, coarse_k=args.coarse_k)
     dev = torch.device("cuda:0")
     t0 = time.time()
-    ix, db, q = builder.build_workload(w, cache_dir=args.cache, log=log)
+    if w.coarse_k:  # the 2-level codec is built on the host
+        ix, db, q = builder.build_workload(w, cache_dir=args.cache, log=log)
+    else:
+        from paper_1804_09996_amd import gpu_build
+        ix, db, q = gpu_build.build_workload_gpu(w, device=dev, log=log)
     log(f"index ready in {time.time() - t0:.1f}s (n={ix.n}, max_level={ix.max_level})")
     gix = lc.Index.from_index(ix, device=dev)
     qd = torch.from_numpy(q).to(dev)
@@ -914,7 +925,8 @@ def main():
                                 f"and outputs), so one batch's walk tail overlaps the next batch" if args.streams > 1
                                 else "each step runs alone"),
                    "queries_per_step": nq, "ef": head["ef"], "shortlist": S_h, "streams": args.streams,
-                   "index": f"built on the host by liblc_build from seed {w.seed}"},
+                   "index": f"built from seed {w.seed} by " + ("liblc_build (host)" if w.coarse_k
+                                                                  else "gpu_build (GPU steps, the host builder's arrays)")},
         "roofline": {"bound": "hbm", "achieved": wb / (wm * 1e-3) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": wb / (wm * 1e-3) / 1e9 / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": walk_kernel_name(w.m, head["precision"], head["ef"], S_h, bool(w.coarse_k)),

@@ -174,7 +174,8 @@ int lc_search(const lc_index *ix, const void *lut, int lut_dtype, const float *l
  *   hash_bits     log2 of the per-query LDS table of the visited set, in
  *                 4-byte words (9..14; 0 = automatic: 9 for visited mode 1,
  *                 else the largest table of 2^10..2^12 words that leaves 8
- *                 query slots per compute unit, or 2^10).
+ *                 query slots per compute unit; 2^12 when the query's
+ *                 distance table alone leaves fewer than 8; else 2^10).
  *   prefetch      visited mode 0 only: 1 = at the start of every step, load
  *                 the adjacency rows of the two unexpanded entries that follow
  *                 the two being expanded (used at the next step when they

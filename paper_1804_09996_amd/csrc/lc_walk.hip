@@ -1512,11 +1512,16 @@ int table_tag_bits(int32_t n, int hash_bits) {
 // The visited table is sized by LDS: the largest narrow table of 2^10..2^12
 // words that leaves 8 query slots per CU (a full bucket sends ids to the
 // global bitset, which the longest walks pay for at every step, so capacity
-// beats residency down to about 8 slots); else 2^10 words.
+// beats residency down to about 8 slots).  When the query's table alone keeps
+// a CU below 8 slots (m * 256 entries of 28 KB and more), the largest table,
+// 2^12 words: one slot fewer per CU costs less than the overflow (measured on
+// the 20M-vector, 56-sub-space workload: 3.66 ms per 10k queries with 2^12
+// words and 3 slots per CU, 4.30 ms with 2^10 words and 4).
 template <int M>
 int auto_hash_bits(int w_cap, int32_t n, int lut_bytes, int lds_per_cu, bool reg) {
   for (int hb = 12; hb >= 10; --hb)
     if (table_tag_bits(n, hb) && lds_per_cu / lds_bytes_for<M>(w_cap, hb, lut_bytes, reg) >= 8) return hb;
+  if (lds_per_cu / lds_bytes_for<M>(w_cap, 10, lut_bytes, reg) < 8) return 12;
   return table_tag_bits(n, 10) || !table_tag_bits(n, 11) ? 10 : 11;
 }
 
