@@ -189,7 +189,7 @@ def bench_batched(args):
     w = datagen.WORKLOADS[args.workload if args.workload not in ("C2-1M", "C5-20M") else "C4-10M"]
     dev = torch.device("cuda:0")
     t0 = time.time()
-    ix, db, q = gpu_build.build_workload_gpu(w, device=dev, log=log)
+    ix, db, q = gpu_build.build_workload_gpu(w, device=dev, log=log, cache_dir=args.gpu_index_cache or None)
     log(f"index ready in {time.time() - t0:.1f}s (n={ix.n}, max_level={ix.max_level})")
     gix = lc.Index.from_index(ix, device=dev)
     nq, K = q.shape[0], w.topk
@@ -362,7 +362,8 @@ def bench_serve(args):
     # (1) the index: data-parallel build steps on the GPU
     t0 = time.time()
     build_t = {}
-    ix, db, _ = gpu_build.build_workload_gpu(w, device=dev, log=log, timings=build_t)
+    ix, db, _ = gpu_build.build_workload_gpu(w, device=dev, log=log, timings=build_t,
+                                             cache_dir=args.gpu_index_cache or None)
     build_t["data_and_build_s"] = time.time() - t0
     pool = datagen.vectors(dataclasses.replace(w, nq=args.pool), "query")
     # (2) ground truth of every pool query
@@ -680,6 +681,9 @@ def main():
     ap.add_argument("--parity-queries", type=int, default=600, help="oracle parity sample (serving form)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="oracle baseline work (serving form)")
     ap.add_argument("--cache", default=os.environ.get("LC_INDEX_CACHE", os.path.join("/tmp", "lc_index_cache")))
+    ap.add_argument("--gpu-index-cache", default="",
+                    help="serving and batched forms: save the GPU-built index here, or load it if a build of the "
+                         "same workload is there (the line then reports no build time)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-tune", action="store_true",
                     help="batched form: the default walk schedule and one ef class (no autotuning)")
@@ -747,7 +751,7 @@ def main():
         ix, db, q = builder.build_workload(w, cache_dir=args.cache, log=log)
     else:
         from paper_1804_09996_amd import gpu_build
-        ix, db, q = gpu_build.build_workload_gpu(w, device=dev, log=log)
+        ix, db, q = gpu_build.build_workload_gpu(w, device=dev, log=log, cache_dir=args.gpu_index_cache or None)
     log(f"index ready in {time.time() - t0:.1f}s (n={ix.n}, max_level={ix.max_level})")
     gix = lc.Index.from_index(ix, device=dev)
     qd = torch.from_numpy(q).to(dev)

@@ -40,34 +40,52 @@ constexpr int kCounters = 256;  // [0] groups, [1] overflowing groups
 
 __device__ __forceinline__ uint32_t byte_of(const uint32_t *w, int s) { return (w[s >> 2] >> (8 * (s & 3))) & 0xFFu; }
 
-// ||C[s][a] - C[s][b]||^2 as a sequential float loop.
+// ||C[s][a] - C[s][b]||^2 as a sequential float loop.  DSUB > 0: the
+// sub-vector length known at compile time (the loops unrolled, so a
+// candidate's independent look-ups issue back to back); 0: dsub at run time.
+template <int DSUB>
 __device__ __forceinline__ float cent_dist(const float *cent, int dsub, int s, uint32_t a, uint32_t b) {
-  const float *ca = cent + (size_t(s) * 256 + a) * dsub;
-  const float *cb = cent + (size_t(s) * 256 + b) * dsub;
+  const int ds = DSUB > 0 ? DSUB : dsub;
+  const float *ca = cent + (size_t(s) * 256 + a) * ds;
+  const float *cb = cent + (size_t(s) * 256 + b) * ds;
   float e = 0.f;
-  for (int u = 0; u < dsub; ++u) {
+#pragma unroll(DSUB > 0 ? DSUB : 1)
+  for (int u = 0; u < (DSUB > 0 ? DSUB : dsub); ++u) {
     const float df = ca[u] - cb[u];
     e += df * df;
   }
   return e;
 }
 
-// d(e, s) = sum over sub-spaces of ||C[t][e_t] - C[t][s_t]||^2, ascending t.
-template <int M>
+// d(e, s) = sum over sub-spaces of ||C[t][e_t] - C[t][s_t]||^2, ascending t:
+// the terms are independent (eight at a time, their look-ups issued
+// together), only their sum runs in order.
+template <int M, int DSUB>
 __device__ __forceinline__ float rec_rec(const float *cent, int dsub, const uint32_t *ca, const uint32_t *cb) {
+  constexpr int CH = DSUB > 0 ? 8 : 1;  // a run-time dsub keeps one term in flight (registers)
   float acc = 0.f;
-  for (int s = 0; s < M; ++s) acc += cent_dist(cent, dsub, s, byte_of(ca, s), byte_of(cb, s));
+#pragma unroll
+  for (int s0 = 0; s0 < M; s0 += CH) {
+    float e[CH];
+#pragma unroll
+    for (int j = 0; j < CH; ++j) e[j] = cent_dist<DSUB>(cent, dsub, s0 + j, byte_of(ca, s0 + j), byte_of(cb, s0 + j));
+#pragma unroll
+    for (int j = 0; j < CH; ++j) acc += e[j];
+  }
   return acc;
 }
 
 // ||v - q(y)||^2 over all coordinates in order (v the raw projected vector).
-template <int M>
+template <int M, int DSUB>
 __device__ __forceinline__ float raw_rec(const float *v, const float *cent, int dsub, const uint32_t *cy) {
+  const int ds = DSUB > 0 ? DSUB : dsub;
   float acc = 0.f;
+#pragma unroll(DSUB > 0 ? M : 1)
   for (int s = 0; s < M; ++s) {
-    const float *c = cent + (size_t(s) * 256 + byte_of(cy, s)) * dsub;
-    for (int u = 0; u < dsub; ++u) {
-      const float df = v[s * dsub + u] - c[u];
+    const float *c = cent + (size_t(s) * 256 + byte_of(cy, s)) * ds;
+#pragma unroll(DSUB > 0 ? DSUB : 1)
+    for (int u = 0; u < (DSUB > 0 ? DSUB : dsub); ++u) {
+      const float df = v[s * ds + u] - c[u];
       acc += df * df;
     }
   }
@@ -94,7 +112,7 @@ __device__ __forceinline__ float readlane_f(float v, int l) {
 // 0..nc-1, nc <= 64): returns the lanes of the kept links and of the filled
 // slots (at most cap).  Candidate i is tested against every link kept so far;
 // each kept lane computes its own d(i, s).
-template <int M>
+template <int M, int DSUB>
 __device__ uint64_t shrink_lanes(float dist, const uint32_t *code, int nc, int cap, const float *cent, int dsub,
                                  int lane) {
   uint64_t kept = 0;
@@ -105,7 +123,7 @@ __device__ uint64_t shrink_lanes(float dist, const uint32_t *code, int nc, int c
 #pragma unroll
     for (int k = 0; k < M / 4; ++k) ci[k] = uint32_t(__builtin_amdgcn_readlane(int(code[k]), i));
     bool fail = false;
-    if ((kept >> lane) & 1ull) fail = !(di < rec_rec<M>(cent, dsub, ci, code));
+    if ((kept >> lane) & 1ull) fail = !(di < rec_rec<M, DSUB>(cent, dsub, ci, code));
     if (__ballot(fail) == 0ull) {
       kept |= 1ull << i;
       ++nk;
@@ -189,7 +207,7 @@ __device__ __forceinline__ void note_link(const InsertArgs &a, int32_t tgt) {
 }
 
 // 2. Each new node's own list from its short-list, and its reverse links.
-template <int M>
+template <int M, int DSUB>
 __global__ __launch_bounds__(1024) void select_kernel(InsertArgs a) {
   extern __shared__ float lcent[];
   stage_cent(lcent, a.cent, a.m * 256 * a.dsub);
@@ -202,7 +220,7 @@ __global__ __launch_bounds__(1024) void select_kernel(InsertArgs a) {
   const float dist = lane < nc ? a.cand_adc[size_t(b) * a.efc + lane] : 0.f;
   uint32_t code[M / 4];
   load_codes<M>(a.codes, a.cs, id, code);
-  const uint64_t out = shrink_lanes<M>(dist, code, nc, a.deg0, lcent, a.dsub, lane);
+  const uint64_t out = shrink_lanes<M, DSUB>(dist, code, nc, a.deg0, lcent, a.dsub, lane);
   const bool mine = (out >> lane) & 1ull;
   const int pos = __builtin_amdgcn_mbcnt_hi(uint32_t(out >> 32), __builtin_amdgcn_mbcnt_lo(uint32_t(out), 0u));
   const int w = __popcll(out);
@@ -267,7 +285,7 @@ __device__ __forceinline__ void close_group(const InsertArgs &a, int g, int32_t 
 }
 
 // 5. A target's merge when its list and new links fit one wave (<= 64).
-template <int M>
+template <int M, int DSUB>
 __global__ __launch_bounds__(1024) void merge_kernel(InsertArgs a) {
   extern __shared__ float lds[];
   float *lcent = lds;
@@ -292,7 +310,7 @@ __global__ __launch_bounds__(1024) void merge_kernel(InsertArgs a) {
     const int32_t id = lane < have ? r : (lane < nc ? a.srcs[a.group_off[g] + lane - have] : -1);
     uint32_t code[M / 4];
     load_codes<M>(a.codes, a.cs, id, code);
-    const float dist = id >= 0 ? raw_rec<M>(vbuf, lcent, a.dsub, code) : 0.f;
+    const float dist = id >= 0 ? raw_rec<M, DSUB>(vbuf, lcent, a.dsub, code) : 0.f;
     uint64_t key = id >= 0 ? make_key(dist, id) : kKeyMax;
     key = sort64(key, lane);
     const int32_t sid = key == kKeyMax ? -1 : key_id(key);
@@ -300,7 +318,7 @@ __global__ __launch_bounds__(1024) void merge_kernel(InsertArgs a) {
       if (lane < a.deg0) row[lane] = lane < nc ? sid : -1;
     } else {
       load_codes<M>(a.codes, a.cs, sid, code);
-      const uint64_t out = shrink_lanes<M>(key_dist(key), code, nc, a.deg0, lcent, a.dsub, lane);
+      const uint64_t out = shrink_lanes<M, DSUB>(key_dist(key), code, nc, a.deg0, lcent, a.dsub, lane);
       const int pos = __builtin_amdgcn_mbcnt_hi(uint32_t(out >> 32), __builtin_amdgcn_mbcnt_lo(uint32_t(out), 0u));
       const int w = __popcll(out);
       if ((out >> lane) & 1ull) row[pos] = sid;
@@ -313,7 +331,7 @@ __global__ __launch_bounds__(1024) void merge_kernel(InsertArgs a) {
 
 // 6. A target with more than 64 candidates: keys sorted in LDS, the rule run
 // over them with the kept links' codes in lanes 0..deg0-1.
-template <int M>
+template <int M, int DSUB>
 __global__ __launch_bounds__(64) void merge_large_kernel(InsertArgs a, int kcap) {
   extern __shared__ uint64_t keys[];  // [kcap], then kcap flag bytes, then d_pad floats
   uint8_t *flag = reinterpret_cast<uint8_t *>(keys + kcap);
@@ -337,7 +355,7 @@ __global__ __launch_bounds__(64) void merge_large_kernel(InsertArgs a, int kcap)
         const int32_t id = j < have ? row[j] : a.srcs[a.group_off[g] + j - have];
         uint32_t code[M / 4];
         load_codes<M>(a.codes, a.cs, id, code);
-        key = make_key(raw_rec<M>(vbuf, a.cent, a.dsub, code), id);
+        key = make_key(raw_rec<M, DSUB>(vbuf, a.cent, a.dsub, code), id);
       }
       keys[j] = key;
       flag[j] = 0;
@@ -370,7 +388,7 @@ __global__ __launch_bounds__(64) void merge_large_kernel(InsertArgs a, int kcap)
       uint32_t ci[M / 4];
       load_codes<M>(a.codes, a.cs, id, ci);
       bool fail = false;
-      if (lane < nk) fail = !(key_dist(ki) < rec_rec<M>(a.cent, a.dsub, ci, mine));
+      if (lane < nk) fail = !(key_dist(ki) < rec_rec<M, DSUB>(a.cent, a.dsub, ci, mine));
       if (__ballot(fail) == 0ull) {
         if (lane == nk) {
 #pragma unroll
@@ -496,7 +514,7 @@ InsertLayout insert_layout(const lc_index *ix, int32_t max_count, int32_t efc) {
   return L;
 }
 
-template <int M>
+template <int M, int DSUB>
 int insert_m(const lc_index *ix, InsertArgs &a, const InsertLayout &L, char *ws, int32_t max_count,
              hipStream_t st) {
   const int cent_bytes = a.m * 256 * a.dsub * 4;
@@ -510,22 +528,22 @@ int insert_m(const lc_index *ix, InsertArgs &a, const InsertLayout &L, char *ws,
                           lc_walk_workspace_bytes(ix, max_count, a.efc, a.efc, nullptr), nullptr, st);
   if (rc != LC_OK) return rc;
   const int wpb = 16;  // waves per block sharing the staged centroids
-  const void *sel = reinterpret_cast<const void *>(&select_kernel<M>);
+  const void *sel = reinterpret_cast<const void *>(&select_kernel<M, DSUB>);
   if (hipFuncSetAttribute(sel, hipFuncAttributeMaxDynamicSharedMemorySize, cent_bytes) != hipSuccess) return LC_EHIP;
-  hipLaunchKernelGGL((select_kernel<M>), dim3(ceil_div(a.count, wpb)), dim3(64 * wpb), cent_bytes, st, a);
+  hipLaunchKernelGGL((select_kernel<M, DSUB>), dim3(ceil_div(a.count, wpb)), dim3(64 * wpb), cent_bytes, st, a);
   hipLaunchKernelGGL(scan_kernel, dim3(1), dim3(1024), 0, st, a);
   hipLaunchKernelGGL(scatter_kernel, dim3(ceil_div(int64_t(a.count) * a.deg0, 256)), dim3(256), 0, st, a);
   const int merge_lds = cent_bytes + wpb * a.d_pad * 4;
-  const void *mk = reinterpret_cast<const void *>(&merge_kernel<M>);
+  const void *mk = reinterpret_cast<const void *>(&merge_kernel<M, DSUB>);
   if (hipFuncSetAttribute(mk, hipFuncAttributeMaxDynamicSharedMemorySize, merge_lds) != hipSuccess) return LC_EHIP;
   // groups are at most count * deg0; a grid of a block per compute unit loops over them
-  hipLaunchKernelGGL((merge_kernel<M>), dim3(ix->num_cus), dim3(64 * wpb), merge_lds, st, a);
+  hipLaunchKernelGGL((merge_kernel<M, DSUB>), dim3(ix->num_cus), dim3(64 * wpb), merge_lds, st, a);
   int kcap = 64;
   while (kcap < a.deg0 + max_count) kcap <<= 1;
   const int large_lds = kcap * 9 + a.d_pad * 4;
-  const void *lk = reinterpret_cast<const void *>(&merge_large_kernel<M>);
+  const void *lk = reinterpret_cast<const void *>(&merge_large_kernel<M, DSUB>);
   if (hipFuncSetAttribute(lk, hipFuncAttributeMaxDynamicSharedMemorySize, large_lds) != hipSuccess) return LC_EHIP;
-  hipLaunchKernelGGL((merge_large_kernel<M>), dim3(ix->num_cus), dim3(64), large_lds, st, a, kcap);
+  hipLaunchKernelGGL((merge_large_kernel<M, DSUB>), dim3(ix->num_cus), dim3(64), large_lds, st, a, kcap);
   hipLaunchKernelGGL(reset_kernel, dim3(1), dim3(64), 0, st, a.counters);
   return hipGetLastError() == hipSuccess ? LC_OK : LC_EHIP;
 }
@@ -607,13 +625,20 @@ int lc_graph_insert(const lc_index *ix, int32_t *adj0, const float *xp, const in
   a.ovf = reinterpret_cast<int32_t *>(w + L.ovf);
   a.counters = reinterpret_cast<uint32_t *>(w);
   hipStream_t st = static_cast<hipStream_t>(stream);
+  // sub-vector lengths of the usual shapes unrolled at compile time, any other at run time
+#define CASE_D(MM)                                                  \
+  case MM:                                                          \
+    switch (a.dsub) {                                               \
+      case 2: return insert_m<MM, 2>(ix, a, L, w, max_count, st);   \
+      case 4: return insert_m<MM, 4>(ix, a, L, w, max_count, st);   \
+      case 6: return insert_m<MM, 6>(ix, a, L, w, max_count, st);   \
+      default: return insert_m<MM, 0>(ix, a, L, w, max_count, st);  \
+    }
   switch (ix->v.m) {
-#define CASE(MM) \
-  case MM: return insert_m<MM>(ix, a, L, w, max_count, st);
-    CASE(8) CASE(16) CASE(24) CASE(32) CASE(40) CASE(48) CASE(56) CASE(64)
-#undef CASE
+    CASE_D(8) CASE_D(16) CASE_D(24) CASE_D(32) CASE_D(40) CASE_D(48) CASE_D(56) CASE_D(64)
     default: return LC_ENOTSUP;
   }
+#undef CASE_D
 }
 
 }  // extern "C"

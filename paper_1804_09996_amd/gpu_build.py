@@ -167,13 +167,31 @@ def build_index_gpu(w, db, train, proj, level_u, pq_init, beta_ids, beta_init, d
     return ix
 
 
-def build_workload_gpu(w, device="cuda", nthreads: Optional[int] = None, log=None, timings: Optional[dict] = None):
-    """(index, db, queries) for a workload from its seed, built by build_index_gpu."""
+def build_workload_gpu(w, device="cuda", nthreads: Optional[int] = None, log=None, timings: Optional[dict] = None,
+                       cache_dir: Optional[str] = None):
+    """(index, db, queries) for a workload from its seed, built by build_index_gpu
+    (or loaded from ``cache_dir``, where a build of the same workload fields was
+    saved; ``timings`` then holds ``{"cached": 1}`` only)."""
+    import os
+
     import datagen
     db = datagen.vectors(w, "db")
     q = datagen.vectors(w, "query")
+    path = None
+    if cache_dir:
+        os.makedirs(cache_dir, exist_ok=True)
+        path = os.path.join(cache_dir, f"{w.name}-{w.key()}-gpu.npz")
+        if os.path.exists(path):
+            if timings is not None:
+                timings["cached"] = 1
+            if log:
+                log(f"index loaded from {path}")
+            return hb.BuiltIndex.load(path), db, q
     train = datagen.vectors(w, "train")
     ix = build_index_gpu(w, db, train, datagen.projection(w), datagen.level_uniforms(w),
                          datagen.pq_init_ids(w, train.shape[0]), datagen.beta_train_ids(w),
                          datagen.beta_init_ids(w, min(w.n, w.n_beta_train)), device, nthreads, log, timings)
+    if path:
+        ix.save(path + ".tmp.npz")
+        os.replace(path + ".tmp.npz", path)
     return ix, db, q
