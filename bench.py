@@ -40,14 +40,14 @@ def walk_bytes(w, E, D, S):
     return float(nq * (4 * w.m * 256 + 8 * S + 12) + 4 * w.deg0 * E.sum() + per_node * D.sum())
 
 
-def walk_kernel_name(m, precision, ef, S, coarse=False):
-    """The walk kernel the default schedule launches: the pool in registers up
-    to 128 entries, in LDS beyond."""
-    t = "half" if precision != "f32" else "float"
-    if coarse:
-        t = "rhalf" if precision != "f32" else "rfloat"  # the 2-level codec's table types
-    w_cap = -(-max(ef, S) // 64) * 64
-    return f"walk_reg_kernel<{m},{t},2,false>" if w_cap <= 128 else f"walk_kernel<{m},{t},false>"
+def walk_kernel_name(gix, nq, ef_max, S, precision, sched=None):
+    """The walk kernel the library launches for this batch (lc_walk_describe),
+    with its grid and LDS plan."""
+    import paper_1804_09996_amd as lc
+    dt = lc.LC_LUT_F32 if precision == "f32" else lc.LC_LUT_F16
+    p = gix.walk_plan(nq, ef_max, S, dt, sched)
+    return (f"{p['kernel']} ({p['grid']} slots, {p['slots_per_cu']} per CU, {p['lds_bytes']} B of LDS each, "
+            f"visited table 2^{p['hash_bits']} words)")
 
 
 def refine_bytes(w, cand_n, K):
@@ -254,7 +254,8 @@ def bench_batched(args):
                       "ef_classes": [{"rows": r1 - r0, "ef_max": efm} for r0, r1, efm in bs.ranges]},
            "roofline": {"bound": "hbm", "achieved": wb / (kms[1] * 1e-3) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                         "frac": wb / (kms[1] * 1e-3) / 1e9 / HBM_PEAK_GBS, "traffic": None,
-                        "kernel": "walk phase: " + ", ".join(walk_kernel_name(w.m, prec, efm, S) for _, _, efm in bs.ranges),
+                        "kernel": "walk phase: " + "; ".join(walk_kernel_name(gix, r1 - r0, efm, S, prec, sched)
+                                                             for r0, r1, efm in bs.ranges),
                         "algorithmic_bytes_per_launch": wb},
            "kernels_ms": dict(zip(("build_lut", "walk", "refine"), kms)),
            "step_ms_p50": float(np.percentile(step_ms, 50)), "step_ms_p99": float(np.percentile(step_ms, 99)),
@@ -398,7 +399,7 @@ def bench_serve(args):
     E1, D1 = st1[:, 0].astype(np.int64), st1[:, 1].astype(np.int64)
     wb = serve_walk_bytes(m, S, E1, D1)
     walk_ms = float(np.mean(durs))
-    kname = walk_kernel_name(m, "f16", int(mix_ef.max()), S)
+    kname = walk_kernel_name(gix, nq, int(mix_ef.max()), S, "f16")
     log(f"walk alone: {kname} {walk_ms:.3f} ms for {nq} queries, {wb / (walk_ms * 1e-3) / 1e9:.0f} GB/s algorithmic")
 
     # every kernel of the path on the same batch, one stream (median of reps)
@@ -933,7 +934,7 @@ def main():
                                                                   else "gpu_build (GPU steps, the host builder's arrays)")},
         "roofline": {"bound": "hbm", "achieved": wb / (wm * 1e-3) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": wb / (wm * 1e-3) / 1e9 / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": walk_kernel_name(w.m, head["precision"], head["ef"], S_h, bool(w.coarse_k)),
+                     "kernel": walk_kernel_name(gix, nq, head["ef"], S_h, head["precision"]),
                      "algorithmic_bytes_per_launch": wb},
         "kernels_ms": head["kernels_ms"],
         "kernels_GBps_algorithmic": {"build_lut": lb / (head["kernels_ms"]["build_lut"] * 1e-3) / 1e9,

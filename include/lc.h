@@ -154,7 +154,9 @@ size_t lc_search_workspace_bytes(const lc_index *ix, int64_t nq, int32_t ef_max,
  *      (sum of LUT[s][code[s]]), keep the best ef_eff; stop when every entry
  *      of W has been expanded;
  *   3. short-list = the min(S, |W|) best entries of W.
- * lut:       as written by lc_build_lut (lut_scale for F16, else NULL).
+ * lut:       as written by lc_build_lut (lut_scale for F16, else NULL); an
+ *            F16 node key is the float32 sum, in sub-space order, of its
+ *            entries times their row scales (each product exact).
  * ef:        i32 [nq] per-query efSearch, or NULL for ef_max everywhere;
  *            a query with ef[q] < 1 or ef[q] > ef_max is not searched and
  *            gets cand_n[q] = -1.
@@ -203,12 +205,38 @@ int lc_search(const lc_index *ix, const void *lut, int lut_dtype, const float *l
  *                 is when n <= 2^(hash_bits + 13).
  *   pool          visited mode 0 only: 0 = the pool W lives in registers when
  *                 it has at most 128 entries (max(ef_max, S) <= 128; the scan
- *                 is a ballot, kept keys are merged by bitonic networks), in
- *                 LDS otherwise; 1 = always in LDS.
- * The default schedule (sched = NULL, and lc_search) is {0, 1, 0, 1, 0, 0, 0}. */
+ *                 is a ballot, kept keys are merged by bitonic networks) and
+ *                 the table is not in registers, in LDS otherwise; 1 = always
+ *                 in LDS.
+ *   table         visited mode 0 only: where an fp16 table of the one-level
+ *                 codec lives during the walk.  1 = LDS; 2 = the wave's
+ *                 registers (2m words per lane, m <= 56; read by cross-lane
+ *                 permutes, so that a slot's LDS holds only the row scales,
+ *                 the pool and the visited table, and a CU keeps up to 8
+ *                 slots), with the pool in LDS whatever `pool` says; 0 =
+ *                 registers when the table in LDS would leave a CU 4 slots or
+ *                 fewer (m = 56), else LDS.  Same results either way; float32
+ *                 tables and the 2-level codec's stay in LDS.
+ *   codes         visited mode 0 only: 0 = each step fetches the codes of all
+ *                 the links it probes while the visited table is probed (a
+ *                 link found visited reads its code for nothing: more HBM
+ *                 traffic, a shorter dependent chain); 1 = only the codes of
+ *                 links the table does not hold, once it has answered.
+ * The default schedule (sched = NULL, and lc_search) is {0, 1, 0, 1, 0, 0, 0, 0, 0}. */
 typedef struct {
-  int32_t hash_bits, prefetch, waves_per_cu, queue, visited, wide, pool;
+  int32_t hash_bits, prefetch, waves_per_cu, queue, visited, wide, pool, table, codes;
 } lc_schedule;
+
+/* The walk that lc_search_sched would launch for these sizes, table type and
+ * schedule (NULL = default), without launching it or touching the device: a
+ * NUL-terminated line "<kernel> grid=<slots> slots_per_cu=<k> hash_bits=<b>
+ * lds_bytes=<bytes>" written to buf (len bytes, truncated to fit).  The
+ * kernel is named as a profiler lists it, without its namespace (the
+ * variant that counts distance evaluations, used when max_evals > 0, ends in
+ * "true" instead of "false").  LC_EINVAL for bad sizes, dtype or schedule;
+ * LC_ENOTSUP for an m the walk does not take. */
+int lc_walk_describe(const lc_index *ix, int64_t nq, int32_t ef_max, int32_t S, int lut_dtype,
+                     const lc_schedule *sched, char *buf, size_t len);
 
 /* Workspace bytes for lc_search_sched with schedule `sched` (NULL = default). */
 size_t lc_search_workspace_bytes_sched(const lc_index *ix, int64_t nq, int32_t ef_max, int32_t S,

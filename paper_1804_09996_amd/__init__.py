@@ -50,19 +50,21 @@ class Schedule(C.Structure):
     """Launch schedule of the walk (lc_schedule); every schedule gives the
     same results."""
     _fields_ = [("hash_bits", C.c_int32), ("prefetch", C.c_int32), ("waves_per_cu", C.c_int32),
-                ("queue", C.c_int32), ("visited", C.c_int32), ("wide", C.c_int32), ("pool", C.c_int32)]
+                ("queue", C.c_int32), ("visited", C.c_int32), ("wide", C.c_int32), ("pool", C.c_int32),
+                ("table", C.c_int32), ("codes", C.c_int32)]
 
     def __repr__(self):
         return (f"Schedule(hash_bits={self.hash_bits}, prefetch={self.prefetch}, "
                 f"waves_per_cu={self.waves_per_cu}, queue={self.queue}, visited={self.visited}, wide={self.wide}, "
-                f"pool={self.pool})")
+                f"pool={self.pool}, table={self.table}, codes={self.codes})")
 
     def as_dict(self):
         return {k: int(getattr(self, k)) for k, _ in self._fields_}
 
 
-def schedule(hash_bits=0, prefetch=1, waves_per_cu=0, queue=1, visited=0, wide=0, pool=0) -> Schedule:
-    return Schedule(hash_bits, prefetch, waves_per_cu, queue, visited, wide, pool)
+def schedule(hash_bits=0, prefetch=1, waves_per_cu=0, queue=1, visited=0, wide=0, pool=0, table=0,
+             codes=0) -> Schedule:
+    return Schedule(hash_bits, prefetch, waves_per_cu, queue, visited, wide, pool, table, codes)
 
 
 def lib():
@@ -87,6 +89,7 @@ def lib():
         L.lc_index_release.restype = None
         L.lc_build_lut.argtypes = [p, p, i64, C.c_int, p, p, p]
         L.lc_search_workspace_bytes.argtypes = [p, i64, i32, i32]
+        L.lc_walk_describe.argtypes = [p, i64, i32, i32, C.c_int, p, C.c_char_p, sz]
         L.lc_search_workspace_bytes.restype = sz
         L.lc_search.argtypes = [p, p, C.c_int, p, i64, p, i32, i32, p, p, p, p, p, sz, p]
         L.lc_search_workspace_bytes_sched.argtypes = [p, i64, i32, i32, C.POINTER(Schedule)]
@@ -116,7 +119,7 @@ def exported_symbols():
             "lc_search", "lc_refine", "lc_search_workspace_bytes_sched", "lc_search_sched", "lc_search_budget",
             "lc_assign_beta", "lc_project_queries", "lc_build_lut_projected", "lc_refine_projected", "lc_lut_stride",
             "lc_search_noalloc", "lc_project_exact", "lc_pq_encode", "lc_graph_insert_workspace_bytes",
-            "lc_graph_insert"]
+            "lc_graph_insert", "lc_walk_describe"]
 
 
 def _check(rc: int, where: str):
@@ -289,6 +292,20 @@ class Index:
     def workspace_bytes(self, nq: int, ef_max: int, S: int, sched: Optional[Schedule] = None) -> int:
         return int(lib().lc_search_workspace_bytes_sched(self.handle, max(nq, 1), ef_max, S,
                                                          None if sched is None else C.byref(sched)))
+
+    def walk_plan(self, nq: int, ef_max: int, S: int, lut_dtype: int = None, sched: Optional[Schedule] = None) -> dict:
+        """The walk lc_search_sched would launch (lc_walk_describe): kernel
+        name, grid, slots per CU, visited-table bits and LDS bytes per slot."""
+        buf = C.create_string_buffer(256)
+        dt = LC_LUT_F32 if lut_dtype is None else lut_dtype
+        _check(lib().lc_walk_describe(self.handle, max(nq, 1), ef_max, S, dt,
+                                      None if sched is None else C.byref(sched), buf, 256), "lc_walk_describe")
+        kernel, _, rest = buf.value.decode().partition(">")
+        out = {"kernel": kernel + ">"}
+        for kv in rest.split():
+            k, v = kv.split("=")
+            out[k] = int(v)
+        return out
 
     def workspace(self, nq: int, ef_max: int, S: int, sched: Optional[Schedule] = None):
         torch = self.torch

@@ -19,10 +19,12 @@ from . import Schedule, schedule
 DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "lc_autotune.json")
 
 
-def candidates(ef_max: int, S: int) -> list:
+def candidates(ef_max: int, S: int, f16: bool = False) -> list:
     """Grid of schedules: where the visited set lives (LDS table, or workspace
     bitset behind an LDS cache), the LDS table size and id width, prefetch,
-    the pool in registers or in LDS (pools up to 128 entries); always the
+    the pool in registers or in LDS (pools up to 128 entries), the codes of
+    every probed link or only of those the visited table does not hold, and
+    (fp16 tables) the query's table in LDS or in registers; always the
     queue."""
     out = [schedule(hash_bits=0, prefetch=1, waves_per_cu=0, queue=1, visited=0)]  # the library's own choice
     if max(ef_max, S) <= 128:
@@ -32,6 +34,10 @@ def candidates(ef_max: int, S: int) -> list:
     out.append(schedule(hash_bits=11, prefetch=0, waves_per_cu=0, queue=1, visited=0))
     out.append(schedule(hash_bits=12, prefetch=1, waves_per_cu=0, queue=1, visited=0, wide=1))
     out.append(schedule(hash_bits=9, prefetch=0, waves_per_cu=0, queue=1, visited=1))
+    out.append(schedule(hash_bits=0, prefetch=1, waves_per_cu=0, queue=1, visited=0, codes=1))
+    if f16:
+        for t in (1, 2):
+            out.append(schedule(hash_bits=0, prefetch=1, waves_per_cu=0, queue=1, visited=0, table=t))
     return out
 
 
@@ -39,7 +45,7 @@ def _key(gix, nq: int, ef_max: int, S: int, table: str = "f32") -> str:
     torch = gix.torch
     name = torch.cuda.get_device_properties(gix.device).name
     bucket = 1 << max(0, (int(nq) - 1).bit_length())
-    return f"{name}|n={gix.n}|m={gix.m}|ef={ef_max}|S={S}|nq~{bucket}|table={table}"
+    return f"{name}|n={gix.n}|m={gix.m}|ef={ef_max}|S={S}|nq~{bucket}|table={table}|schedule-fields=9"
 
 
 def load_cache(path: str) -> dict:
@@ -85,7 +91,7 @@ def tune(gix, lut, ef=None, ef_max: int = 64, S: int = 64, cands: Optional[Itera
     if key in cache:
         return schedule(**cache[key]["schedule"]), cache[key]["table"]
     table = []
-    for sc in (cands or candidates(ef_max, S)):
+    for sc in (cands or candidates(ef_max, S, f16=scale is not None)):
         ms = time_schedule(gix, lut, ef, ef_max, S, sc, reps, scale=scale)
         table.append({"schedule": sc.as_dict(), "ms": ms})
         if log:

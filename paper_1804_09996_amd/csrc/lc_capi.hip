@@ -131,6 +131,12 @@ size_t lc_search_workspace_bytes(const lc_index *ix, int64_t nq, int32_t ef_max,
   return lc_search_workspace_bytes_sched(ix, nq, ef_max, S, nullptr);
 }
 
+int lc_walk_describe(const lc_index *ix, int64_t nq, int32_t ef_max, int32_t S, int lut_dtype,
+                     const lc_schedule *sched, char *buf, size_t len) {
+  if (!ix || nq < 1 || ef_max < 1 || S < 1 || !buf || len < 1) return LC_EINVAL;
+  return lc_describe_walk(ix, nq, ef_max, S, lut_dtype, sched, buf, len);
+}
+
 int lc_search_budget(const lc_index *ix, const void *lut, int lut_dtype, const float *lut_scale, int64_t nq,
                      const int32_t *ef, int32_t ef_max, int32_t S, int32_t max_evals, const int32_t *order,
                      int32_t *cand_ids, float *cand_adc, int32_t *cand_n, int32_t *stats, void *ws,

@@ -97,6 +97,8 @@ int lc_launch_lut(const lc_index *ix, const float *q, int64_t nq, int dtype, voi
                   hipStream_t st);
 size_t lc_walk_workspace_bytes(const lc_index *ix, int64_t nq, int32_t ef_max, int32_t S,
                                const lc_schedule *sched);
+int lc_describe_walk(const lc_index *ix, int64_t nq, int32_t ef_max, int32_t S, int dtype, const lc_schedule *sched,
+                     char *buf, size_t len);
 int lc_launch_assign(const lc_index *ix, const float *x, int64_t n0, int64_t count, uint8_t *out, hipStream_t st);
 int lc_launch_walk(const lc_index *ix, const void *lut, int dtype, const float *scale, int64_t nq,
                    const int32_t *ef, int32_t ef_max, int32_t S, int32_t max_d, const int32_t *order, int32_t *cand_ids,

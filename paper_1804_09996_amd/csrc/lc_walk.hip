@@ -33,6 +33,7 @@
 // still the next two unexpanded entries.
 #include <hip/hip_fp16.h>
 
+#include <cstdio>
 #include <type_traits>
 
 #include "lc_internal.h"
@@ -56,6 +57,7 @@ struct WalkArgs {
   int32_t w_cap, hash_bits, prefetch, queue, vmode, list_cap;
   int32_t tag_bits;    // walk_kernel's table: 16-bit tags of this many bits, 0 = 32-bit ids
   int32_t max_d;       // budget T on distance evaluations (Sec. 3.1), 0 = none
+  int32_t late_codes;  // 1: a step fetches only the codes of links the visited table does not hold
   uint32_t *counters;  // [0] next query, [1] finished slots (queue mode)
   uint32_t *bits;
   int32_t *vlists;     // [slots][list_cap] ids whose bit is set (visited mode 1)
@@ -98,6 +100,55 @@ __device__ __forceinline__ float lut_at(const rhalf *lut, const float *sc, int s
 template <typename T>
 constexpr bool kRes = std::is_same<T, rfloat>::value || std::is_same<T, rhalf>::value;
 
+// Table entries read together before they are summed (m is a multiple of 8).
+constexpr int kAdcGroup = 8;
+
+// Where a walk reads the query's table from.  LdsTab: the table staged in LDS,
+// one load per entry, on any set of lanes.
+template <typename T>
+struct LdsTab {
+  static constexpr bool kWaveWide = false;
+  static constexpr int kGroup = kAdcGroup;  // entries read together
+  const T *lut;
+  __device__ __forceinline__ float at(const float *sc, int s, uint32_t c) const { return lut_at(lut, sc, s, c); }
+};
+
+// RegTab: an fp16 table spread over the wave's registers, 2m words per lane
+// (2m <= 128): word 2s + j of lane l holds entries 128j + 2l (low half) and
+// 128j + 2l + 1 (high half) of row s.  An entry is read with two cross-lane
+// permutes, one per word of its row, so every lane of the wave takes part in
+// each read: callers evaluate keys on all 64 lanes and discard the ones they
+// do not need.  Each entry's value is that of lut_at (the fp16 entry times its
+// row's power-of-two scale), so keys are identical to the LDS table's.
+template <int M>
+struct RegTab {
+  static constexpr bool kWaveWide = true;
+  static constexpr int kGroup = 4;  // entries read together (two permutes each)
+  uint32_t r[2 * M];
+  __device__ __forceinline__ void load(const __half *row, int lane) {
+    const uint32_t *w = reinterpret_cast<const uint32_t *>(row);
+#pragma unroll
+    for (int i = 0; i < 2 * M; ++i) r[i] = w[i * 64 + lane];
+  }
+  __device__ __forceinline__ float at(const float *sc, int s, uint32_t c) const {
+    const int addr = int((c >> 1) & 63u) << 2;
+    const uint32_t w0 = uint32_t(__builtin_amdgcn_ds_bpermute(addr, int(r[2 * s])));
+    const uint32_t w1 = uint32_t(__builtin_amdgcn_ds_bpermute(addr, int(r[2 * s + 1])));
+    const uint32_t wd = (c & 128u) ? w1 : w0;
+    const unsigned short h = (unsigned short)((c & 1u) ? (wd >> 16) : (wd & 0xFFFFu));
+    return __half2float(__ushort_as_half(h)) * sc[s];
+  }
+};
+
+// Stage the query's table into LDS, 16 bytes per lane and pass.
+template <typename T, int M>
+__device__ __forceinline__ void stage_table(T *dst, const T *src, int lane) {
+  constexpr int kChunks = M * 256 * int(sizeof(T)) / 16;
+  const float4 *s4 = reinterpret_cast<const float4 *>(src);
+  float4 *d4 = reinterpret_cast<float4 *>(dst);
+  for (int i = lane; i < kChunks; i += 64) d4[i] = s4[i];
+}
+
 // First-level entries of node id plus its stored term (2-level codec).
 __device__ __forceinline__ float coarse_term(const WalkArgs &a, const float *ctab, int32_t id) {
   const uint32_t c = a.ccodes[id];
@@ -108,25 +159,18 @@ __device__ __forceinline__ float coarse_term(const WalkArgs &a, const float *cta
 template <int M, typename T>
 __device__ __forceinline__ float adc_full(const T *lut, const float *sc, const uint8_t *codes, int cs,
                                           int32_t id) {
+  static_assert(M % 8 == 0, "m must be a multiple of 8");
   const uint8_t *row = codes + size_t(id) * cs;
   float acc = 0.f;
-  if constexpr (M % 16 == 0) {
 #pragma unroll
-    for (int i = 0; i < M / 16; ++i) {
-      const uint4 w = reinterpret_cast<const uint4 *>(row)[i];
-      const uint32_t ws[4] = {w.x, w.y, w.z, w.w};
+  for (int i = 0; i < M / 8; ++i) {
+    const uint2 w = reinterpret_cast<const uint2 *>(row)[i];
+    const uint32_t ws[2] = {w.x, w.y};
+    float v[8];
 #pragma unroll
-      for (int t = 0; t < 16; ++t) acc += lut_at(lut, sc, i * 16 + t, (ws[t >> 2] >> (8 * (t & 3))) & 0xFFu);
-    }
-  } else {
-    static_assert(M % 8 == 0, "m must be a multiple of 8");
+    for (int t = 0; t < 8; ++t) v[t] = lut_at(lut, sc, i * 8 + t, (ws[t >> 2] >> (8 * (t & 3))) & 0xFFu);
 #pragma unroll
-    for (int i = 0; i < M / 8; ++i) {
-      const uint2 w = reinterpret_cast<const uint2 *>(row)[i];
-      const uint32_t ws[2] = {w.x, w.y};
-#pragma unroll
-      for (int t = 0; t < 8; ++t) acc += lut_at(lut, sc, i * 8 + t, (ws[t >> 2] >> (8 * (t & 3))) & 0xFFu);
-    }
+    for (int t = 0; t < 8; ++t) acc += v[t];
   }
   return acc;
 }
@@ -159,11 +203,27 @@ struct CodeRegs {
   __device__ __forceinline__ void load_coarse(const WalkArgs &a, const float *ctab, int32_t id) {
     extra = coarse_term(a, ctab, id);
   }
-  template <typename T>
-  __device__ __forceinline__ float adc(const T *lut, const float *sc) const {
+  // the sum of the m entries (sub-space order) from either table view
+  // The sum of the m entries (sub-space order) from either table view.  The
+  // entries are read in groups of 8 before they are added, so that a group's
+  // reads are in flight together rather than one LDS round trip per entry.
+  template <typename Tab>
+  __device__ __forceinline__ float adc_sum(const Tab &tab, const float *sc) const {
+    constexpr int G = Tab::kGroup;
     float acc = 0.f;
 #pragma unroll
-    for (int s = 0; s < M; ++s) acc += lut_at(lut, sc, s, (w[s >> 2] >> (8 * (s & 3))) & 0xFFu);
+    for (int s0 = 0; s0 < M; s0 += G) {
+      float v[G];
+#pragma unroll
+      for (int g = 0; g < G; ++g) v[g] = tab.at(sc, s0 + g, (w[(s0 + g) >> 2] >> (8 * ((s0 + g) & 3))) & 0xFFu);
+#pragma unroll
+      for (int g = 0; g < G; ++g) acc += v[g];
+    }
+    return acc;
+  }
+  template <typename T>
+  __device__ __forceinline__ float adc(const T *lut, const float *sc) const {
+    float acc = adc_sum(LdsTab<T>{lut}, sc);
     if constexpr (kRes<T>) acc = clamp0(acc + extra);
     return acc;
   }
@@ -678,11 +738,18 @@ __device__ __forceinline__ void reg_merge_sorted(Pool &p, uint64_t kv, int efe, 
 // (Fetching every link's upper row index with its code saves one dependent
 // load per move but reads a cache line per link for it: more HBM traffic and
 // no measurable time, so the winner's row index is read after the move.)
-template <int M, typename T>
-__device__ __forceinline__ void greedy_descent(const WalkArgs &a, const T *lut, const float *sc, int lane,
+template <int M, typename T, typename Tab>
+__device__ __forceinline__ void greedy_descent(const WalkArgs &a, const Tab &tab, const float *sc, int lane,
                                                int32_t &cur, uint64_t &curkey, const float *ctab) {
   auto dist = [&](int32_t id) {
-    float v = adc_full<M, T>(lut, sc, a.codes, a.code_stride, id);
+    float v;
+    if constexpr (Tab::kWaveWide) {
+      CodeRegs<M> cr;
+      cr.load(a.codes, a.code_stride, id);
+      v = cr.adc_sum(tab, sc);
+    } else {
+      v = adc_full<M, T>(tab.lut, sc, a.codes, a.code_stride, id);
+    }
     if constexpr (kRes<T>) v = clamp0(v + coarse_term(a, ctab, id));
     return v;
   };
@@ -694,7 +761,13 @@ __device__ __forceinline__ void greedy_descent(const WalkArgs &a, const T *lut, 
       int32_t nb = -1;
       if (lane < a.deg_up && row >= 0 && row < a.n_up_rows) nb = a.adj_up[row * a.deg_up + lane];
       if (nb >= a.n) nb = -1;  // a malformed link is ignored rather than followed
-      const uint64_t k = nb >= 0 ? make_key(dist(nb), nb) : kKeyMax;
+      uint64_t k;
+      if constexpr (Tab::kWaveWide) {  // every lane evaluates (a missing link: the current node's code)
+        const float v = dist(nb >= 0 ? nb : cur);
+        k = nb >= 0 ? make_key(v, nb) : kKeyMax;
+      } else {
+        k = nb >= 0 ? make_key(dist(nb), nb) : kKeyMax;
+      }
       const uint64_t mn = wave_min64(k);
       if (mn < curkey) {
         curkey = mn;
@@ -735,11 +808,22 @@ __device__ __forceinline__ uint64_t budget_cut(uint64_t m, int D, int max_d, boo
   return kept;
 }
 
-template <int M, typename T, bool BUDGET>
+template <int M, typename T, bool BUDGET, typename Tab>
 __device__ __forceinline__ StepOut expand_links(const WalkArgs &a, const VTable &vt, uint32_t *bits, int32_t *vlist,
-                                                const T *lut, const float *sc, int32_t nb, const CodeRegs<M> &cr,
-                                                bool lo, bool two, uint64_t pk, int lane, int &D, int &E,
-                                                int &vcount) {
+                                                const Tab &tab, const float *sc, int32_t nb, int32_t cid,
+                                                const float *ctab, bool lo, bool two, uint64_t pk, int lane, int &D,
+                                                int &E, int &vcount) {
+  // The links' codes: by default every link's, fetched while the visited set
+  // is probed (a link that turns out visited reads its code for nothing);
+  // with late_codes only those of links the table does not hold, once the
+  // probe has answered (the other lanes read the expanded node's own code,
+  // one shared line).
+  CodeRegs<M> cr;
+  const bool late = a.late_codes != 0;
+  if (!late) {
+    cr.load(a.codes, a.code_stride, nb >= 0 ? nb : cid);
+    if constexpr (kRes<T>) cr.load_coarse(a, ctab, nb >= 0 ? nb : cid);
+  }
   // lanes 0..31 test-and-set c's links; lanes 32..63 look p's links up.
   // One bucket read and at most one CAS settle almost every link; a full
   // bucket or a lost CAS goes round the general path.
@@ -751,6 +835,11 @@ __device__ __forceinline__ StepOut expand_links(const WalkArgs &a, const VTable 
   int e;
   vt_inspect(vt, s4, tag, hit, e);
   hit = hit & act;
+  if (late) {
+    const int32_t src = act && !hit ? nb : cid;
+    cr.load(a.codes, a.code_stride, src);
+    if constexpr (kRes<T>) cr.load_coarse(a, ctab, src);
+  }
   const bool ins = act & lo & !hit & (e >= 0);
   bool ok = false;
   if (ins) ok = vt_try_store(vt, b, e, tag, s4);
@@ -776,7 +865,12 @@ __device__ __forceinline__ StepOut expand_links(const WalkArgs &a, const VTable 
 
   // ADC keys of both halves' candidates, from the codes loaded at the start of the step
   o.k = kKeyMax;
-  if (cand) o.k = make_key(cr.adc(lut, sc), nb);
+  if constexpr (Tab::kWaveWide) {  // every lane evaluates, candidates keep theirs
+    const float v = cr.adc_sum(tab, sc);
+    if (cand) o.k = make_key(v, nb);
+  } else {
+    if (cand) o.k = make_key(cr.adc(tab.lut, sc), nb);
+  }
 
   // p is the next expansion of the sequential walk iff no fresh key of c is below it
   o.dual = (!BUDGET || !o.stop) && two && __ballot(lo && cand && o.k < pk) == 0ull;
@@ -815,19 +909,24 @@ __device__ __forceinline__ StepOut expand_links(const WalkArgs &a, const VTable 
 
 // Level-0 walk with the visited set in an LDS table (and the bitset for ids
 // whose home bucket is full), two expansions per step when the sequential
-// order allows it.
-template <int M, typename T, bool BUDGET>
-__global__ __launch_bounds__(64) void walk_kernel(WalkArgs a) {
+// order allows it; the query's table in LDS, or (RL) an fp16 table in
+// registers.
+template <int M, typename T, bool BUDGET, bool RL>
+__device__ __forceinline__ void walk_body(const WalkArgs &a) {
+  static_assert(!RL || std::is_same<T, __half>::value, "registers hold fp16 tables only");
   extern __shared__ __align__(16) unsigned char smem[];
   const int lane = threadIdx.x;
   const int l32 = lane & 31;
   const bool lo = lane < 32;
-  constexpr int kLutBytes = M * 256 * int(sizeof(T));
+  constexpr int kLutBytes = RL ? 0 : M * 256 * int(sizeof(T));
   constexpr int kScaleBytes = sizeof(T) == 2 ? (M * 4 + 15) / 16 * 16 : 0;
   T *lut = reinterpret_cast<T *>(smem);
   float *sc = reinterpret_cast<float *>(smem + kLutBytes);
   uint64_t *W = reinterpret_cast<uint64_t *>(smem + kLutBytes + kScaleBytes);
   uint64_t *Ks = W + a.w_cap;  // merge scratch: the kept keys (compacted, then sorted)
+  using Tab = std::conditional_t<RL, RegTab<M>, LdsTab<T>>;
+  Tab tab;
+  if constexpr (!RL) tab.lut = lut;
   uint32_t *hash = reinterpret_cast<uint32_t *>(Ks + kMergeScratch);
   const int H = 1 << a.hash_bits;  // table words
   VTable vt;
@@ -870,11 +969,14 @@ __global__ __launch_bounds__(64) void walk_kernel(WalkArgs a) {
       const int efe = efq > a.S ? efq : a.S;
 
       // stage the table (and its row scales), clear the visited table
-      const float4 *src = reinterpret_cast<const float4 *>(static_cast<const T *>(a.lut) + q * a.lut_stride);
+      const T *src = static_cast<const T *>(a.lut) + q * a.lut_stride;
       [[maybe_unused]] const float *ctab =
           kRes<T> ? reinterpret_cast<const float *>(static_cast<const T *>(a.lut) + q * a.lut_stride + M * 256)
                   : nullptr;
-      for (int i = lane; i < kLutBytes / 16; i += 64) reinterpret_cast<float4 *>(lut)[i] = src[i];
+      if constexpr (RL)
+        tab.load(src, lane);
+      else
+        stage_table<T, M>(lut, src, lane);
       if (sizeof(T) == 2)
         for (int i = lane; i < M; i += 64) sc[i] = a.scale[q * M + i];
       for (int i = lane; i < H; i += 64) hash[i] = kEmpty;
@@ -883,7 +985,7 @@ __global__ __launch_bounds__(64) void walk_kernel(WalkArgs a) {
       // greedy descent on levels max_level .. 1
       int32_t cur;
       uint64_t curkey;
-      greedy_descent<M, T>(a, lut, sc, lane, cur, curkey, ctab);
+      greedy_descent<M, T>(a, tab, sc, lane, cur, curkey, ctab);
 
       // best-first walk on level 0
       if (lane == 0) {
@@ -912,13 +1014,8 @@ __global__ __launch_bounds__(64) void walk_kernel(WalkArgs a) {
         const bool two = pidx >= 0;
         if (lane == 0) W[fu] = ck | kExpanded;
         const int32_t nb = col_ok && (lo || two) ? row : -1;
-        // the codes of every link, fetched while the visited set is probed (a
-        // link that is not fresh reads its code for nothing)
-        CodeRegs<M> cr;
-        cr.load(a.codes, a.code_stride, nb >= 0 ? nb : cid);
-        if constexpr (kRes<T>) cr.load_coarse(a, ctab, nb >= 0 ? nb : cid);
-
-        const StepOut o = expand_links<M, T, BUDGET>(a, vt, bits, vlist, lut, sc, nb, cr, lo, two, pk, lane, D, E, vcount);
+        const StepOut o = expand_links<M, T, BUDGET>(a, vt, bits, vlist, tab, sc, nb, cid, ctab, lo, two, pk, lane, D,
+                                                     E, vcount);
         const bool dual = o.dual;
         const bool fresh = o.fresh;
         const uint64_t k = o.k;
@@ -1073,6 +1170,20 @@ __global__ __launch_bounds__(64) void walk_kernel(WalkArgs a) {
   }
 }
 
+template <int M, typename T, bool BUDGET>
+__global__ __launch_bounds__(64) void walk_kernel(WalkArgs a) {
+  walk_body<M, T, BUDGET, false>(a);
+}
+
+// The same walk with the fp16 table in registers (RegTab): a slot's LDS holds
+// the row scales, the pool and the visited table only, so that a CU keeps up
+// to 8 slots (two waves per SIMD) where the table in LDS keeps it to 3 or 4
+// (m >= 48); the register budget is held to 256 for those two waves.
+template <int M, bool BUDGET>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void walk_rl_kernel(WalkArgs a) {
+  walk_body<M, __half, BUDGET, true>(a);
+}
+
 // The same walk with the pool in registers (pools of up to 64 R entries, R <= 2):
 // the scan for the next unexpanded entries is a ballot per chunk, one kept key
 // moves the entries above it up one lane, and several kept keys are sorted
@@ -1132,11 +1243,11 @@ __global__ __launch_bounds__(64) void walk_reg_kernel(WalkArgs a) {
       const int efe = efq > a.S ? efq : a.S;
 
       // stage the table, take its row scales into registers, clear the visited table
-      const float4 *src = reinterpret_cast<const float4 *>(static_cast<const T *>(a.lut) + q * a.lut_stride);
+      const T *src = static_cast<const T *>(a.lut) + q * a.lut_stride;
       [[maybe_unused]] const float *ctab =
           kRes<T> ? reinterpret_cast<const float *>(static_cast<const T *>(a.lut) + q * a.lut_stride + M * 256)
                   : nullptr;
-      for (int i = lane; i < kLutBytes / 16; i += 64) reinterpret_cast<float4 *>(lut)[i] = src[i];
+      stage_table<T, M>(lut, src, lane);
       float scr[sizeof(T) == 2 ? M : 1];
 #pragma unroll
       for (int i = 0; i < (sizeof(T) == 2 ? M : 1); ++i) scr[i] = sizeof(T) == 2 ? a.scale[q * M + i] : 1.f;
@@ -1147,7 +1258,7 @@ __global__ __launch_bounds__(64) void walk_reg_kernel(WalkArgs a) {
       // greedy descent on levels max_level .. 1
       int32_t cur;
       uint64_t curkey;
-      greedy_descent<M, T>(a, lut, sc, lane, cur, curkey, ctab);
+      greedy_descent<M, T>(a, LdsTab<T>{lut}, sc, lane, cur, curkey, ctab);
 
       // best-first walk on level 0
       if (lane == 0) {
@@ -1177,13 +1288,8 @@ __global__ __launch_bounds__(64) void walk_reg_kernel(WalkArgs a) {
         const bool two = pidx >= 0;
         mark_expanded<R>(wr, fu, lane);
         const int32_t nb = col_ok && (lo || two) ? row : -1;
-        // the codes of every link, fetched while the visited set is probed (a
-        // link that is not fresh reads its code for nothing)
-        CodeRegs<M> cr;
-        cr.load(a.codes, a.code_stride, nb >= 0 ? nb : cid);
-        if constexpr (kRes<T>) cr.load_coarse(a, ctab, nb >= 0 ? nb : cid);
-
-        const StepOut o = expand_links<M, T, BUDGET>(a, vt, bits, vlist, lut, sc, nb, cr, lo, two, pk, lane, D, E, vcount);
+        const StepOut o = expand_links<M, T, BUDGET>(a, vt, bits, vlist, LdsTab<T>{lut}, sc, nb, cid, ctab, lo, two,
+                                                     pk, lane, D, E, vcount);
         const bool dual = o.dual;
         const uint64_t k = o.k;
         if (dual) mark_expanded<R>(wr, pidx, lane);
@@ -1342,11 +1448,11 @@ __global__ __launch_bounds__(64) void walk_cache_kernel(WalkArgs a) {
     } else {
       const int efe = efq > a.S ? efq : a.S;
 
-      const float4 *src = reinterpret_cast<const float4 *>(static_cast<const T *>(a.lut) + q * a.lut_stride);
+      const T *src = static_cast<const T *>(a.lut) + q * a.lut_stride;
       [[maybe_unused]] const float *ctab =
           kRes<T> ? reinterpret_cast<const float *>(static_cast<const T *>(a.lut) + q * a.lut_stride + M * 256)
                   : nullptr;
-      for (int i = lane; i < kLutBytes / 16; i += 64) reinterpret_cast<float4 *>(lut)[i] = src[i];
+      stage_table<T, M>(lut, src, lane);
       if (sizeof(T) == 2)
         for (int i = lane; i < M; i += 64) sc[i] = a.scale[q * M + i];
       for (int i = lane; i < H; i += 64) hash[i] = kEmpty;
@@ -1355,7 +1461,7 @@ __global__ __launch_bounds__(64) void walk_cache_kernel(WalkArgs a) {
       // greedy descent on levels max_level .. 1
       int32_t cur;
       uint64_t curkey;
-      greedy_descent<M, T>(a, lut, sc, lane, cur, curkey, ctab);
+      greedy_descent<M, T>(a, LdsTab<T>{lut}, sc, lane, cur, curkey, ctab);
 
       if (lane == 0) {
         W[0] = curkey;
@@ -1484,7 +1590,13 @@ __global__ __launch_bounds__(64) void walk_cache_kernel(WalkArgs a) {
 struct WalkPlan {
   int w_cap, hash_bits, lds_bytes, grid;
   int reg_chunks;  // > 0: the pool lives in registers, this many chunks of 64 (walk_reg_kernel)
+  bool reg_lut;    // the fp16 table lives in registers (walk_rl_kernel)
 };
+
+// Slots per CU of walk_rl_kernel: its register budget (256 of a SIMD's 512) keeps two waves per SIMD.
+constexpr int kRegLutSlotsPerCu = 8;
+// Largest m whose table registers hold within that budget (m = 64 spills).
+constexpr int kRegLutMaxM = 56;
 
 // Largest pool held in registers: two chunks (four chunks were measured
 // slower than the LDS pool: their merge networks cost more than they save).
@@ -1493,10 +1605,11 @@ constexpr int kRegPoolMax = 128;
 constexpr size_t kHeaderBytes = 256;  // two queue counters, padded
 
 template <int M>
-int lds_bytes_for(int w_cap, int hash_bits, int lut_bytes, bool reg) {
+int lds_bytes_for(int w_cap, int hash_bits, int lut_bytes, bool reg, bool rl = false) {
   const int scale_bytes = lut_bytes == 2 ? (M * 4 + 15) / 16 * 16 : 0;
   if (reg) return M * 256 * lut_bytes + (1 << hash_bits) * 4;  // table and visited table only
-  return M * 256 * lut_bytes + scale_bytes + w_cap * 8 + kMergeScratch * 8 + (1 << hash_bits) * 4;
+  const int table = rl ? 0 : M * 256 * lut_bytes;                // rl: the table is in registers
+  return table + scale_bytes + w_cap * 8 + kMergeScratch * 8 + (1 << hash_bits) * 4;
 }
 
 // Tag width of a narrow visited table with 2^(hash_bits-2) buckets for ids
@@ -1518,28 +1631,39 @@ int table_tag_bits(int32_t n, int hash_bits) {
 // the 20M-vector, 56-sub-space workload: 3.66 ms per 10k queries with 2^12
 // words and 3 slots per CU, 4.30 ms with 2^10 words and 4).
 template <int M>
-int auto_hash_bits(int w_cap, int32_t n, int lut_bytes, int lds_per_cu, bool reg) {
+int auto_hash_bits(int w_cap, int32_t n, int lut_bytes, int lds_per_cu, bool reg, bool rl) {
   for (int hb = 12; hb >= 10; --hb)
-    if (table_tag_bits(n, hb) && lds_per_cu / lds_bytes_for<M>(w_cap, hb, lut_bytes, reg) >= 8) return hb;
-  if (lds_per_cu / lds_bytes_for<M>(w_cap, 10, lut_bytes, reg) < 8) return 12;
+    if (table_tag_bits(n, hb) && lds_per_cu / lds_bytes_for<M>(w_cap, hb, lut_bytes, reg, rl) >= 8) return hb;
+  if (lds_per_cu / lds_bytes_for<M>(w_cap, 10, lut_bytes, reg, rl) < 8) return 12;
   return table_tag_bits(n, 10) || !table_tag_bits(n, 11) ? 10 : 11;
 }
 
+// plain_f16: the table is the one-level codec's fp16 table (the only one registers can hold)
 template <int M>
 WalkPlan plan_for(const lc_index *ix, int64_t nq, int32_t ef_max, int32_t S, const lc_schedule *sc,
-                  int lut_bytes) {
+                  int lut_bytes, bool plain_f16) {
   WalkPlan p;
   int ef_eff = ef_max > S ? ef_max : S;
   p.w_cap = (ef_eff + 63) / 64 * 64;
-  const bool reg = sc->visited == 0 && sc->pool == 0 && p.w_cap <= kRegPoolMax;
+  // The table in registers (fp16 tables of the walk with the visited table): when asked for, or (auto) when
+  // the table in LDS leaves a CU at most half the register form's slots.  That walk keeps its pool in LDS:
+  // at m = 56 it beats the register pool with the table in LDS at every pool size (8 slots per CU against 3;
+  // measured on the 20M-vector, 56-sub-space workload: 1.36 against 1.82 ms at ef 64, 2.22 against 2.83 at
+  // ef 128, per 10k queries).
+  const bool rl_ok = plain_f16 && sc->visited == 0 && M <= kRegLutMaxM;
+  p.reg_lut = rl_ok && (sc->table == 2 ||
+                        (sc->table == 0 && ix->lds_per_cu / lds_bytes_for<M>(p.w_cap, 10, lut_bytes, false) <=
+                                               kRegLutSlotsPerCu / 2));
+  const bool reg = !p.reg_lut && sc->visited == 0 && sc->pool == 0 && p.w_cap <= kRegPoolMax;
   p.reg_chunks = reg ? 2 : 0;
   // visited mode 1 keeps only a small LDS cache; mode 0 sizes its table from the pool
   p.hash_bits = sc->hash_bits ? sc->hash_bits
               : (sc->visited == 1 ? 9
                                   : auto_hash_bits<M>(p.w_cap, sc->wide ? INT32_MAX : ix->v.n, lut_bytes,
-                                                      ix->lds_per_cu, reg));
-  p.lds_bytes = lds_bytes_for<M>(p.w_cap, p.hash_bits, lut_bytes, reg);
+                                                      ix->lds_per_cu, reg, p.reg_lut));
+  p.lds_bytes = lds_bytes_for<M>(p.w_cap, p.hash_bits, lut_bytes, reg, p.reg_lut);
   int per_cu = ix->lds_per_cu / p.lds_bytes;
+  if (p.reg_lut && per_cu > kRegLutSlotsPerCu) per_cu = kRegLutSlotsPerCu;
   if (sc && sc->waves_per_cu > 0 && sc->waves_per_cu < per_cu) per_cu = sc->waves_per_cu;
   if (per_cu < 1) per_cu = 1;
   if (per_cu > 32) per_cu = 32;
@@ -1556,10 +1680,11 @@ bool valid_schedule(const lc_schedule *sc) {
   if (sc->prefetch < 0 || sc->prefetch > 1 || sc->queue < 0 || sc->queue > 1 || sc->waves_per_cu < 0) return false;
   if (sc->visited < 0 || sc->visited > 1 || sc->wide < 0 || sc->wide > 1 || sc->pool < 0 || sc->pool > 1)
     return false;
+  if (sc->table < 0 || sc->table > 2 || sc->codes < 0 || sc->codes > 1) return false;
   return true;
 }
 
-const lc_schedule kDefaultSchedule = {0, 1, 0, 1, 0, 0, 0};
+const lc_schedule kDefaultSchedule = {0, 1, 0, 1, 0, 0, 0, 0, 0};
 
 int list_cap_for(int w_cap) { return 16 * w_cap > 4096 ? 16 * w_cap : 4096; }
 
@@ -1572,15 +1697,27 @@ template <int M>
 size_t ws_bytes_m(const lc_index *ix, int64_t nq, int32_t ef_max, int32_t S, const lc_schedule *sc) {
   // enough for either table type
   const int64_t words = (int64_t(ix->v.n) + 31) / 32;
-  const size_t a = ws_need(plan_for<M>(ix, nq, ef_max, S, sc, 2), words);
-  const size_t b = ws_need(plan_for<M>(ix, nq, ef_max, S, sc, 4), words);
-  return a > b ? a : b;
+  const size_t a = ws_need(plan_for<M>(ix, nq, ef_max, S, sc, 2, true), words);
+  const size_t b = ws_need(plan_for<M>(ix, nq, ef_max, S, sc, 4, false), words);
+  const size_t c = ws_need(plan_for<M>(ix, nq, ef_max, S, sc, 2, false), words);
+  const size_t ab = a > b ? a : b;
+  return ab > c ? ab : c;
 }
 
 // The kernel the plan picks; with a budget on distance evaluations, its
 // variant that counts them (the kernels without one carry no such test).
 template <int M, typename T, bool BUDGET>
 int launch_kernel(const WalkPlan &p, const lc_schedule *sc, const WalkArgs &a, hipStream_t st) {
+  if constexpr (std::is_same<T, __half>::value && M <= kRegLutMaxM) {
+    if (p.reg_lut) {
+      const void *fr = reinterpret_cast<const void *>(&walk_rl_kernel<M, BUDGET>);
+      if (hipFuncSetAttribute(fr, hipFuncAttributeMaxDynamicSharedMemorySize, p.lds_bytes) != hipSuccess)
+        return LC_EHIP;
+      hipLaunchKernelGGL((walk_rl_kernel<M, BUDGET>), dim3(p.grid), dim3(64), p.lds_bytes, st, a);
+      return hipGetLastError() == hipSuccess ? LC_OK : LC_EHIP;
+    }
+  }
+  if (p.reg_lut) return LC_EINVAL;  // the plan gives registers fp16 tables only
   const void *fn = sc->visited == 1 ? reinterpret_cast<const void *>(&walk_cache_kernel<M, T, BUDGET>)
                    : p.reg_chunks  ? reinterpret_cast<const void *>(&walk_reg_kernel<M, T, 2, BUDGET>)
                                    : reinterpret_cast<const void *>(&walk_kernel<M, T, BUDGET>);
@@ -1600,7 +1737,7 @@ int launch_m(const lc_index *ix, const void *lut, const float *scale, int64_t nq
              int32_t ef_max, int32_t S, int32_t max_d, const int32_t *order, int32_t *cand_ids, float *cand_adc,
              int32_t *cand_n, int32_t *stats, void *ws, size_t ws_bytes, const lc_schedule *sc, hipStream_t st,
              bool fit_ws) {
-  WalkPlan p = plan_for<M>(ix, nq, ef_max, S, sc, int(sizeof(T)));
+  WalkPlan p = plan_for<M>(ix, nq, ef_max, S, sc, int(sizeof(T)), std::is_same<T, __half>::value);
   const int64_t words = (int64_t(ix->v.n) + 31) / 32;
   if (fit_ws) {
     // as many resident slots as the workspace holds (results do not depend on the slot count)
@@ -1623,6 +1760,7 @@ int launch_m(const lc_index *ix, const void *lut, const float *scale, int64_t nq
   a.ef_max = ef_max;
   a.S = S;
   a.max_d = max_d;
+  a.late_codes = sc->codes;
   a.nq = nq;
   a.n = ix->v.n;
   a.n_up_rows = ix->v.n_up_rows;
@@ -1654,6 +1792,28 @@ int launch_m(const lc_index *ix, const void *lut, const float *scale, int64_t nq
   return max_d > 0 ? launch_kernel<M, T, true>(p, sc, a, st) : launch_kernel<M, T, false>(p, sc, a, st);
 }
 
+
+// The kernel and plan launch_m would use (lc_walk_describe).
+template <int M, typename T>
+int describe_m(const lc_index *ix, int64_t nq, int32_t ef_max, int32_t S, const lc_schedule *sc, char *buf,
+               size_t len) {
+  const WalkPlan p = plan_for<M>(ix, nq, ef_max, S, sc, int(sizeof(T)), std::is_same<T, __half>::value);
+  const char *t = std::is_same<T, float>::value ? "float" : std::is_same<T, __half>::value ? "__half"
+                  : std::is_same<T, rfloat>::value ? "rfloat" : "rhalf";
+  char kname[96];
+  if (p.reg_lut)
+    snprintf(kname, sizeof kname, "walk_rl_kernel<%d, %s>", M, "false");
+  else if (sc->visited == 1)
+    snprintf(kname, sizeof kname, "walk_cache_kernel<%d, %s, %s>", M, t, "false");
+  else if (p.reg_chunks)
+    snprintf(kname, sizeof kname, "walk_reg_kernel<%d, %s, 2, %s>", M, t, "false");
+  else
+    snprintf(kname, sizeof kname, "walk_kernel<%d, %s, %s>", M, t, "false");
+  const int slots = int((p.grid + ix->num_cus - 1) / ix->num_cus);
+  snprintf(buf, len, "%s grid=%d slots_per_cu=%d hash_bits=%d lds_bytes=%d", kname, p.grid, slots, p.hash_bits,
+           p.lds_bytes);
+  return LC_OK;
+}
 
 }  // namespace
 
@@ -1700,6 +1860,25 @@ int lc_launch_walk(const lc_index *ix, const void *lut, int dtype, const float *
                                                      cand_ids, cand_adc, cand_n, stats, ws, ws_bytes, sc, st, fit_ws) \
                                : launch_m<MM, __half>(ix, lut, scale, nq, ef, ef_max, S, max_d, order,       \
                                                       cand_ids, cand_adc, cand_n, stats, ws, ws_bytes, sc, st, fit_ws);
+    LC_FOR_EACH_M(CASE)
+#undef CASE
+    default: return LC_ENOTSUP;
+  }
+}
+
+int lc_describe_walk(const lc_index *ix, int64_t nq, int32_t ef_max, int32_t S, int dtype, const lc_schedule *sched,
+                     char *buf, size_t len) {
+  if (dtype != LC_LUT_F32 && dtype != LC_LUT_F16) return LC_EINVAL;
+  if (!valid_schedule(sched)) return LC_EINVAL;
+  const lc_schedule *sc = sched ? sched : &kDefaultSchedule;
+  const bool f32 = dtype == LC_LUT_F32, res = ix->v.coarse_k > 0;
+  switch (ix->v.m) {
+#define CASE(MM)                                                                                    \
+  case MM:                                                                                          \
+    return res ? (f32 ? describe_m<MM, rfloat>(ix, nq, ef_max, S, sc, buf, len)                    \
+                      : describe_m<MM, rhalf>(ix, nq, ef_max, S, sc, buf, len))                    \
+               : (f32 ? describe_m<MM, float>(ix, nq, ef_max, S, sc, buf, len)                     \
+                      : describe_m<MM, __half>(ix, nq, ef_max, S, sc, buf, len));
     LC_FOR_EACH_M(CASE)
 #undef CASE
     default: return LC_ENOTSUP;

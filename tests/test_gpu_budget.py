@@ -19,7 +19,8 @@ pytestmark = pytest.mark.gpu
 SCHEDULES = [None,
              dict(hash_bits=0, prefetch=1, waves_per_cu=0, queue=1, visited=0, pool=1),
              dict(hash_bits=9, prefetch=0, waves_per_cu=0, queue=1, visited=1),
-             dict(hash_bits=9, prefetch=0, waves_per_cu=0, queue=0, visited=0)]
+             dict(hash_bits=9, prefetch=0, waves_per_cu=0, queue=0, visited=0),
+             dict(hash_bits=9, prefetch=1, waves_per_cu=0, queue=1, visited=0, codes=1)]
 BUDGETS = [1, 2, 31, 32, 33, 100, 517, 4000]
 
 

@@ -191,7 +191,9 @@ SCHEDULES = [dict(hash_bits=9, prefetch=0, waves_per_cu=0, queue=0, visited=0), 
              dict(hash_bits=0, prefetch=1, waves_per_cu=0, queue=1, visited=0, pool=1),   # pool in LDS
              dict(hash_bits=9, prefetch=0, waves_per_cu=0, queue=0, visited=0, pool=1),
              dict(hash_bits=9, prefetch=0, waves_per_cu=0, queue=1, visited=1),   # bitset + LDS cache
-             dict(hash_bits=10, prefetch=1, waves_per_cu=0, queue=0, visited=1)]
+             dict(hash_bits=10, prefetch=1, waves_per_cu=0, queue=0, visited=1),
+             dict(hash_bits=0, prefetch=1, waves_per_cu=0, queue=1, visited=0, codes=1),   # codes after the probe
+             dict(hash_bits=9, prefetch=0, waves_per_cu=0, queue=1, visited=0, pool=1, codes=1)]
 
 
 def test_every_schedule_gives_identical_results(c1, c1_oracle, torch):
