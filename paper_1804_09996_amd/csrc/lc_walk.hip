@@ -114,29 +114,49 @@ struct LdsTab {
 };
 
 // RegTab: an fp16 table spread over the wave's registers, 2m words per lane
-// (2m <= 128): word 2s + j of lane l holds entries 128j + 2l (low half) and
-// 128j + 2l + 1 (high half) of row s.  An entry is read with two cross-lane
-// permutes, one per word of its row, so every lane of the wave takes part in
-// each read: callers evaluate keys on all 64 lanes and discard the ones they
-// do not need.  Each entry's value is that of lut_at (the fp16 entry times its
-// row's power-of-two scale), so keys are identical to the LDS table's.
+// (m <= 56): word 2s + j of lane l holds entries 128j + 2l (low half) and
+// 128j + 2l + 1 (high half) of row s, so that entry c sits at lane
+// (c >> 1) & 63, in word 2s + (c >> 7), half c & 1.  A read fetches both
+// words of the row from that lane with two cross-lane permutes and picks the
+// half with a byte permute whose selector comes from the code's bits 7 and
+// 0; four entries' lane addresses and selectors come from their code word
+// with a few packed operations.  Every lane of the wave takes part in each
+// permute, so callers evaluate keys on all 64 lanes and discard the ones
+// they do not need.  Each entry's value is that of lut_at (the fp16 entry
+// times its row's power-of-two scale), so keys are identical to the LDS
+// table's.
 template <int M>
 struct RegTab {
   static constexpr bool kWaveWide = true;
-  static constexpr int kGroup = 4;  // entries read together (two permutes each)
+  static constexpr int kGroup = 4;  // entries read together: one code word
   uint32_t r[2 * M];
   __device__ __forceinline__ void load(const __half *row, int lane) {
     const uint32_t *w = reinterpret_cast<const uint32_t *>(row);
 #pragma unroll
     for (int i = 0; i < 2 * M; ++i) r[i] = w[i * 64 + lane];
   }
-  __device__ __forceinline__ float at(const float *sc, int s, uint32_t c) const {
-    const int addr = int((c >> 1) & 63u) << 2;
-    const uint32_t w0 = uint32_t(__builtin_amdgcn_ds_bpermute(addr, int(r[2 * s])));
-    const uint32_t w1 = uint32_t(__builtin_amdgcn_ds_bpermute(addr, int(r[2 * s + 1])));
-    const uint32_t wd = (c & 128u) ? w1 : w0;
-    const unsigned short h = (unsigned short)((c & 1u) ? (wd >> 16) : (wd & 0xFFFFu));
-    return __half2float(__ushort_as_half(h)) * sc[s];
+  // acc plus the entries of rows s0 .. s0 + 3 at the four codes of word cw
+  // (row s0 in its low byte), added in row order
+  __device__ __forceinline__ float sum4(const float *sc, int s0, uint32_t cw, float acc) const {
+    const uint32_t addr4 = (cw << 1) & 0xFCFCFCFCu;  // per byte: lane ((c >> 1) & 63) times 4
+    // per byte: 2q, the first byte of half q = 2 (c >> 7) + (c & 1) within the two words, and 2q + 1
+    const uint32_t q2 = ((cw >> 5) & 0x04040404u) | ((cw << 1) & 0x02020202u);
+    const uint32_t q2b = q2 | 0x01010101u;
+    uint32_t w0[4], w1[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int addr = int((addr4 >> (8 * t)) & 0xFFu);
+      w0[t] = uint32_t(__builtin_amdgcn_ds_bpermute(addr, int(r[2 * (s0 + t)])));
+      w1[t] = uint32_t(__builtin_amdgcn_ds_bpermute(addr, int(r[2 * (s0 + t) + 1])));
+    }
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      // selector: bytes 2q and 2q + 1 of (w1:w0) into the low half (byte values 0-3: w0, 4-7: w1)
+      const uint32_t sel = __builtin_amdgcn_perm(q2b, q2, uint32_t(t) | (uint32_t(4 + t) << 8) | 0x0C0C0000u);
+      const uint32_t v = __builtin_amdgcn_perm(w1[t], w0[t], sel);
+      acc += __half2float(__ushort_as_half((unsigned short)(v & 0xFFFFu))) * sc[s0 + t];
+    }
+    return acc;
   }
 };
 
@@ -211,13 +231,18 @@ struct CodeRegs {
   __device__ __forceinline__ float adc_sum(const Tab &tab, const float *sc) const {
     constexpr int G = Tab::kGroup;
     float acc = 0.f;
+    if constexpr (Tab::kWaveWide) {
 #pragma unroll
-    for (int s0 = 0; s0 < M; s0 += G) {
-      float v[G];
+      for (int i = 0; i < M / 4; ++i) acc = tab.sum4(sc, 4 * i, w[i], acc);
+    } else {
 #pragma unroll
-      for (int g = 0; g < G; ++g) v[g] = tab.at(sc, s0 + g, (w[(s0 + g) >> 2] >> (8 * ((s0 + g) & 3))) & 0xFFu);
+      for (int s0 = 0; s0 < M; s0 += G) {
+        float v[G];
 #pragma unroll
-      for (int g = 0; g < G; ++g) acc += v[g];
+        for (int g = 0; g < G; ++g) v[g] = tab.at(sc, s0 + g, (w[(s0 + g) >> 2] >> (8 * ((s0 + g) & 3))) & 0xFFu);
+#pragma unroll
+        for (int g = 0; g < G; ++g) acc += v[g];
+      }
     }
     return acc;
   }
