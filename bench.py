@@ -62,20 +62,20 @@ def lut_bytes(w, nq):
     return float(nq) * (4 * w.d + 4 * (w.m * 256 + 2 * w.coarse_k))
 
 
-def traffic_from_profiles(kernel_src, precision, ef, S):
-    """HBM bytes per walk launch from the committed counter summary, valid
-    only while the kernel source is unchanged and for the same configuration."""
+def traffic_from_profiles(config):
+    """HBM bytes per walk launch (FETCH_SIZE + WRITE_SIZE, each scaled by the
+    calibration copy) from the committed counter summary
+    profiles/walk_traffic.json, for the entry whose configuration equals
+    `config`; valid only while the walk's source is the one the counters were
+    taken on (its sha1), else None."""
     path = os.path.join(ROOT, "profiles", "walk_traffic.json")
     if not os.path.exists(path):
         return None
-    t = json.load(open(path))
-    sha = hashlib.sha1(open(kernel_src, "rb").read()).hexdigest()
-    c = t.get("config", {})
-    # the walk depends on the table type only (the refinement precision does not enter it)
-    table = precision.split("+")[0]
-    if t.get("kernel_sha1") != sha or (c.get("precision"), c.get("ef"), c.get("S")) != (table, ef, S):
-        return None
-    return t.get("bytes_per_launch")
+    sha = hashlib.sha1(open(os.path.join(ROOT, "paper_1804_09996_amd", "csrc", "lc_walk.hip"), "rb").read()).hexdigest()
+    for e in json.load(open(path)).get("entries", []):
+        if e.get("kernel_sha1") == sha and e.get("config") == config:
+            return e.get("bytes_per_launch")
+    return None
 
 
 def ground_truth(torch, db, q, dev, q_chunk=512, db_chunk=1 << 21):
@@ -234,6 +234,33 @@ def bench_batched(args):
     torch.cuda.synchronize()
     kms = [e[j].elapsed_time(e[j + 1]) for j in range(3)]
     st = bs.res.stats.cpu().numpy()
+    # the walk alone (one launch over the whole batch, longest ef first) with other schedules and table types:
+    # the codes fetched after the visited probe, fp16 tables in LDS and in registers (same walk results per
+    # table type)
+    variants = {}
+    qx_all = torch.from_numpy(q).to(dev)
+    ef_all = torch.from_numpy(ef).to(dev)
+    order = torch.argsort(-ef_all, stable=True).to(torch.int32)
+    l32, _ = gix.build_lut(qx_all, lc.LC_LUT_F32)
+    l16, s16 = gix.build_lut(qx_all, lc.LC_LUT_F16)
+    for name, lut_v, sc_v, sch in (("f32", l32, None, lc.schedule()), ("f32_codes_after_probe", l32, None,
+                                                                        lc.schedule(codes=1)),
+                                   ("f16_table_in_lds", l16, s16, lc.schedule(table=1)),
+                                   ("f16_table_in_registers", l16, s16, lc.schedule(table=2))):
+        wsv = gix.workspace(nq, ef_max, S, sch)
+        ts = []
+        for k in range(3):
+            a_, b_ = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a_.record()
+            gix.search(lut_v, sc_v, ef=ef_all, ef_max=ef_max, S=S, stats=False, sched=sch, ws=wsv, order=order)
+            b_.record()
+            b_.synchronize()
+            ts.append(a_.elapsed_time(b_))
+        plan = gix.walk_plan(nq, ef_max, S, lc.LC_LUT_F32 if sc_v is None else lc.LC_LUT_F16, sch)
+        variants[name] = {"ms": float(np.median(ts[1:])), "kernel": plan["kernel"],
+                          "slots_per_cu": plan["slots_per_cu"]}
+        del wsv
+    del l32, l16, s16
     E, D = st[:, 0].astype(np.int64), st[:, 1].astype(np.int64)
     wb = walk_bytes(w, E, D, S)
     if prec == "f16":
@@ -253,13 +280,18 @@ def bench_batched(args):
                                   f"graph",
                       "ef_classes": [{"rows": r1 - r0, "ef_max": efm} for r0, r1, efm in bs.ranges]},
            "roofline": {"bound": "hbm", "achieved": wb / (kms[1] * 1e-3) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                        "frac": wb / (kms[1] * 1e-3) / 1e9 / HBM_PEAK_GBS, "traffic": None,
+                        "frac": wb / (kms[1] * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                        "traffic": traffic_from_profiles({"form": "batched", "workload": w.name, "table": prec,
+                                                          "schedule": "default" if args.no_tune else "autotuned",
+                                                          "S": S}) if args.no_tune else None,
+                        "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, calibrated)",
                         "kernel": "walk phase: " + "; ".join(walk_kernel_name(gix, r1 - r0, efm, S, prec, sched)
                                                              for r0, r1, efm in bs.ranges),
                         "algorithmic_bytes_per_launch": wb},
            "kernels_ms": dict(zip(("build_lut", "walk", "refine"), kms)),
            "step_ms_p50": float(np.percentile(step_ms, 50)), "step_ms_p99": float(np.percentile(step_ms, 99)),
            "recall_10k_sample": rec, "walk_mean_E": float(E.mean()), "walk_mean_D": float(D.mean()),
+           "walk_variants_one_launch": variants,
            "autotune_table": bs.table}
     print(json.dumps(out), flush=True)
 
@@ -384,13 +416,15 @@ def bench_serve(args):
     qp = gix.project(qd)
     lut16, sc16 = gix.build_lut(qp, lc.LC_LUT_F16, projected=True)
     ef_t = torch.from_numpy(mix_ef).to(dev)
+    # slots take the queries longest ef first, as the serving engine lays out each launch
+    ord_t = torch.argsort(ef_t, descending=True, stable=True).to(torch.int32)
     ws1 = gix.workspace(nq, int(mix_ef.max()), S)
     reps = max(5, args.steps // 2)
     durs = []
     for k in range(reps + 1):
         a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         a.record()
-        r1 = gix.search(lut16, sc16, ef=ef_t, ef_max=int(mix_ef.max()), S=S, stats=True, ws=ws1)
+        r1 = gix.search(lut16, sc16, ef=ef_t, ef_max=int(mix_ef.max()), S=S, stats=True, ws=ws1, order=ord_t)
         b.record()
         b.synchronize()
         if k:
@@ -423,11 +457,17 @@ def bench_serve(args):
         sc_ = lc.schedule(hash_bits=hb)
         wsh = gix.workspace(nq, int(mix_ef.max()), S, sc_)
         kern[f"walk_f16_hash_bits_{hb}"] = timed(lambda: gix.search(lut16, sc16, ef=ef_t, ef_max=int(mix_ef.max()),
-                                                                    S=S, stats=False, sched=sc_, ws=wsh))
+                                                                    S=S, stats=False, sched=sc_, ws=wsh, order=ord_t))
+        del wsh
+    for name, sc_ in (("walk_f16_codes_after_probe", lc.schedule(codes=1)),
+                      ("walk_f16_table_in_lds", lc.schedule(table=1, pool=1))):
+        wsh = gix.workspace(nq, int(mix_ef.max()), S, sc_)
+        kern[name] = timed(lambda: gix.search(lut16, sc16, ef=ef_t, ef_max=int(mix_ef.max()), S=S, stats=False,
+                                              sched=sc_, ws=wsh, order=ord_t))
         del wsh
     lut32, _ = gix.build_lut(qp, lc.LC_LUT_F32, projected=True)
     kern["walk_f32"] = timed(lambda: gix.search(lut32, None, ef=ef_t, ef_max=int(mix_ef.max()), S=S, stats=False,
-                                                ws=ws1))
+                                                ws=ws1, order=ord_t))
     for name, prec in (("refine_f32", lc.LC_REFINE_F32), ("refine_bf16_rescore", lc.LC_REFINE_BF16_RESCORE)):
         kern[name] = timed(lambda: gix.refine(qp, r1.cand_ids, r1.cand_n, K, prec, projected=True))
     served_refine = args.serve_refine
@@ -607,11 +647,15 @@ def bench_serve(args):
                           "offered_load_frac": loads[-1]["offered_load_frac"]} if loads else None,
            "loads": loads,
            "roofline": {"bound": "hbm", "achieved": wb / (walk_ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,
-                        "unit": "GB/s", "frac": wb / (walk_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, "traffic": None,
+                        "unit": "GB/s", "frac": wb / (walk_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                        "traffic": traffic_from_profiles({"form": "serve", "workload": w.name, "table": "f16",
+                                                          "ef_mix": list(SERVE_MIX), "S": S, "queries": nq}),
+                        "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, calibrated)",
                         "kernel": kname, "algorithmic_bytes_per_launch": wb, "launch_ms": walk_ms,
                         "launches": reps, "queries_per_launch": nq,
-                        "measured": "one stream, the walk alone on the query pool with the workload's ef mix "
-                                    "(these are the process's first launches of this kernel after one warm-up)",
+                        "measured": "one stream, the walk alone on the query pool with the workload's ef mix, "
+                                    "slots taking queries longest ef first (these are the process's first "
+                                    "launches of this kernel after one warm-up)",
                         "walk_mean_E": float(E1.mean()), "walk_mean_D": float(D1.mean())},
            "served_walk_launches": served_walk,
            "one_stream_kernels_ms": kern,
@@ -902,8 +946,8 @@ def main():
         walk_bytes(w, E, D, S_h) - nq * 2 * w.m * 256 + nq * 4 * w.m  # fp16 table + scales
     rb = refine_bytes(w, head["cand_n"], K)
     lb = lut_bytes(w, nq) if not f16 else float(nq) * (4 * w.d + 2 * w.m * 256 + 4 * w.m)
-    traffic = traffic_from_profiles(os.path.join(ROOT, "paper_1804_09996_amd", "csrc", "lc_walk.hip"),
-                                    head["precision"], head["ef"], S_h)
+    traffic = traffic_from_profiles({"form": "plain", "workload": w.name, "table": head["precision"].split("+")[0],
+                                     "ef": head["ef"], "S": S_h})
     form = {"f32": "plain fp32 path",
             "f16": "fp16 tables in the walk, fp32 refinement",
             "f16+bf16": "precision form: fp16 tables, bf16 refinement, exact fp32 re-score of the best 2K"}[head["precision"]]
