@@ -624,7 +624,10 @@ def bench_serve(args):
                                   f"gpu_build; requests of round(exp(U(0, ln1024))) queries, efSearch uniform over "
                                   f"{list(SERVE_MIX)}, short-list {S}, top-{K}; served by continuous batching "
                                   f"({n_slots} slots x {slot_q} queries, each on its own stream, memory budget "
-                                  f"{budget} B = 75 % of the slots' capacity) with fp16 tables and the "
+                                  f"{budget} B = 75 % of the slots' capacity; each batch's walk "
+                                  + ("split into its register-pool and LDS-pool classes on two streams" if eng.split
+                                     else "one launch, queries longest ef first") +
+                                  f") with fp16 tables and the "
                                   f"{served_refine} refinement; a step = {args.step_requests} requests; the K "
                                   f"timed steps' requests are present at t = 0 and served back to back",
                       "n": w.n, "queries_per_step": served_q / args.steps, "requests_per_step": args.step_requests,

@@ -10,7 +10,8 @@ pytestmark = pytest.mark.gpu
 
 @pytest.mark.parametrize("precision,efs,split", [("f16", (16, 32, 64), True), ("f32", (16, 32, 64), True),
                                                  ("f16", (16, 64, 160, 256), True),
-                                                 ("f16", (16, 64, 160, 256), False)])
+                                                 ("f16", (16, 64, 160, 256), False),
+                                                 ("f16", (16, 64, 160, 256), None)])
 def test_results_same_alone_and_in_the_mix(c1_build, precision, efs, split):
     # each launch is sized by its batch's largest ef (pools up to 128 in
     # registers, larger in LDS), or split into the two classes walked
