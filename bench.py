@@ -486,6 +486,8 @@ def bench_serve(args):
         per_q = not np.isscalar(ef_)
         ef_top = int(np.max(ef_)) if per_q else int(ef_)
         ef_dev = torch.from_numpy(np.asarray(ef_, np.int32)).to(dev) if per_q else None
+        # per-query ef: slots take the queries longest ef first, as the served form's launches do
+        ord_dev = torch.argsort(ef_dev, descending=True, stable=True).to(torch.int32) if per_q else None
         lanes = []
         for i, st_ in enumerate(side):
             nb = gix.workspace_bytes(nq, max(ef_top, S), S)
@@ -499,7 +501,7 @@ def bench_serve(args):
             with torch.cuda.stream(st_):
                 qx = gix.project(qd)
                 lut, _ = gix.build_lut(qx, lc.LC_LUT_F32, projected=True)
-                r = gix.search(lut, None, ef=ef_dev, ef_max=ef_top, S=S, stats=False, ws=ws_)
+                r = gix.search(lut, None, ef=ef_dev, ef_max=ef_top, S=S, stats=False, ws=ws_, order=ord_dev)
                 return gix.refine(qx, r.cand_ids, r.cand_n, K, lc.LC_REFINE_F32, projected=True)
 
         for k in range(len(lanes)):
@@ -637,8 +639,8 @@ def bench_serve(args):
            "plain_fp32": {"qps_at_same_R@1": q_plain_r1, "qps_at_same_R@10": q_plain_r10,
                           "form": "plain float32 path (tables, walk, refinement, fp32) on fixed batches of the "
                                   f"{nq}-query pool, each query with its request's ef (the workload's mix, scaled "
-                                  f"x{list(scales)} for the curve), short-list {S}, consecutive batches over three "
-                                  "streams",
+                                  f"x{list(scales)} for the curve; slots take them longest ef first), short-list {S}, "
+                                  "consecutive batches over three streams",
                           "curve": plain_curve,
                           "one_ef_for_all": {"qps_at_same_R@1": q_unif_r1, "curve": uniform_curve,
                                              "note": "every query with the same ef: a different workload (no "
