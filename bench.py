@@ -197,7 +197,7 @@ def bench_batched(args):
     S, ef_max = K, 512
     # --precision f16: fp16 tables in the walk (the refinement stays fp32 at this short-list: K = S leaves
     # nothing for a bf16 first pass to skip)
-    prec = "f16" if args.precision != "f32" else "f32"
+    prec = "f32" if args.precision == "f32" else "f16"
     bs = BatchedSearcher(gix, nq, ef_max=ef_max, S=S, K=K, precision=prec)
     bs.set_inputs(q, ef)
     if args.no_tune:  # the default schedule, one class: every step is one walk launch of one kernel
@@ -739,8 +739,9 @@ def main():
                     help="batched form: the default walk schedule and one ef class (no autotuning)")
     ap.add_argument("--streams", type=int, default=3,
                     help="streams that consecutive steps alternate on (1 = each step runs alone)")
-    ap.add_argument("--precision", choices=("f32", "f16", "f16+bf16"), default="f32",
-                    help="form timed by --form plain (default: the plain fp32 path)")
+    ap.add_argument("--precision", choices=("f32", "f16", "f16+bf16"), default=None,
+                    help="form timed by --form plain (default: the plain fp32 path) and --form batched (default: "
+                         "fp16 tables, the precision form)")
     ap.add_argument("--ef", type=int, default=0, help="efSearch for --form plain (default: the workload's)")
     ap.add_argument("--shortlist", type=int, default=0, help="short-list size for --form plain (default: the workload's)")
     ap.add_argument("--m-beta", type=int, default=1,
@@ -757,6 +758,8 @@ def main():
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="also run one device-to-device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
+    if args.precision is None:  # per form: fp16 tables for the batched form, the plain fp32 path otherwise
+        args.precision = "f16" if args.form == "batched" else "f32"
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on exactly one GPU: the search shards over GPUs by query "
                                    "slices or by database shards, each GPU running this path on its share",

@@ -1618,10 +1618,37 @@ struct WalkPlan {
   bool reg_lut;    // the fp16 table lives in registers (walk_rl_kernel)
 };
 
-// Slots per CU of walk_rl_kernel: its register budget (256 of a SIMD's 512) keeps two waves per SIMD.
+// Slots per CU of walk_rl_kernel when its register count cannot be read: two waves per SIMD (its register
+// budget is 256 of a SIMD's 512).
 constexpr int kRegLutSlotsPerCu = 8;
 // Largest m whose table registers hold within that budget (m = 64 spills).
 constexpr int kRegLutMaxM = 56;
+
+// Slots per CU that walk_rl_kernel<M>'s registers allow: four SIMDs times the waves that fit a SIMD's 512
+// registers per lane (its register count, either budget variant, rounded up to the allocation granule of 8),
+// at most 8 per SIMD.  m = 16 takes 155 registers, so three waves per SIMD; m = 56 takes 243, so two.
+template <int M>
+int rl_slots_cap() {
+  if constexpr (M > kRegLutMaxM) {
+    return 0;
+  } else {
+    static const int cap = [] {
+      int regs = 0;
+      for (const void *fn : {reinterpret_cast<const void *>(&walk_rl_kernel<M, false>),
+                             reinterpret_cast<const void *>(&walk_rl_kernel<M, true>)}) {
+        hipFuncAttributes at;
+        if (hipFuncGetAttributes(&at, fn) != hipSuccess || at.numRegs <= 0) return kRegLutSlotsPerCu;
+        if (at.numRegs > regs) regs = at.numRegs;
+      }
+      regs = (regs + 7) / 8 * 8;
+      int waves = 512 / regs;
+      if (waves > 8) waves = 8;
+      if (waves < 1) waves = 1;
+      return 4 * waves;
+    }();
+    return cap;
+  }
+}
 
 // Largest pool held in registers: two chunks (four chunks were measured
 // slower than the LDS pool: their merge networks cost more than they save).
@@ -1671,24 +1698,34 @@ WalkPlan plan_for(const lc_index *ix, int64_t nq, int32_t ef_max, int32_t S, con
   int ef_eff = ef_max > S ? ef_max : S;
   p.w_cap = (ef_eff + 63) / 64 * 64;
   // The table in registers (fp16 tables of the walk with the visited table): when asked for, or (auto) when
-  // the table in LDS leaves a CU at most half the register form's slots.  That walk keeps its pool in LDS:
-  // at m = 56 it beats the register pool with the table in LDS at every pool size (8 slots per CU against 3;
-  // measured on the 20M-vector, 56-sub-space workload: 1.36 against 1.82 ms at ef 64, 2.22 against 2.83 at
-  // ef 128, per 10k queries).
+  // it keeps at least 1.3 times the slots per CU of the table in LDS (a slot's step costs more with the table
+  // in registers: two permutes per entry).  That walk keeps its pool in LDS: at m = 56 it beats the register
+  // pool with the table in LDS at every pool size (8 slots per CU against 3; measured on the 20M-vector,
+  // 56-sub-space workload: 1.36 against 1.82 ms at ef 64, 2.22 against 2.83 at ef 128, per 10k queries).
   const bool rl_ok = plain_f16 && sc->visited == 0 && M <= kRegLutMaxM;
-  p.reg_lut = rl_ok && (sc->table == 2 ||
-                        (sc->table == 0 && ix->lds_per_cu / lds_bytes_for<M>(p.w_cap, 10, lut_bytes, false) <=
-                                               kRegLutSlotsPerCu / 2));
+  const int32_t n_tags = sc->wide ? INT32_MAX : ix->v.n;
+  if (rl_ok && sc->table == 0) {
+    const bool reg_alt = sc->pool == 0 && p.w_cap <= kRegPoolMax;  // the kernel the table in LDS would take
+    const int hb_alt = sc->hash_bits ? sc->hash_bits
+                                     : auto_hash_bits<M>(p.w_cap, n_tags, lut_bytes, ix->lds_per_cu, reg_alt, false);
+    const int slots_alt = ix->lds_per_cu / lds_bytes_for<M>(p.w_cap, hb_alt, lut_bytes, reg_alt, false);
+    const int hb_rl = sc->hash_bits ? sc->hash_bits
+                                    : auto_hash_bits<M>(p.w_cap, n_tags, lut_bytes, ix->lds_per_cu, false, true);
+    int slots_rl = ix->lds_per_cu / lds_bytes_for<M>(p.w_cap, hb_rl, lut_bytes, false, true);
+    if (slots_rl > rl_slots_cap<M>()) slots_rl = rl_slots_cap<M>();
+    p.reg_lut = 10 * slots_rl >= 13 * slots_alt;
+  } else {
+    p.reg_lut = rl_ok && sc->table == 2;
+  }
   const bool reg = !p.reg_lut && sc->visited == 0 && sc->pool == 0 && p.w_cap <= kRegPoolMax;
   p.reg_chunks = reg ? 2 : 0;
   // visited mode 1 keeps only a small LDS cache; mode 0 sizes its table from the pool
   p.hash_bits = sc->hash_bits ? sc->hash_bits
               : (sc->visited == 1 ? 9
-                                  : auto_hash_bits<M>(p.w_cap, sc->wide ? INT32_MAX : ix->v.n, lut_bytes,
-                                                      ix->lds_per_cu, reg, p.reg_lut));
+                                  : auto_hash_bits<M>(p.w_cap, n_tags, lut_bytes, ix->lds_per_cu, reg, p.reg_lut));
   p.lds_bytes = lds_bytes_for<M>(p.w_cap, p.hash_bits, lut_bytes, reg, p.reg_lut);
   int per_cu = ix->lds_per_cu / p.lds_bytes;
-  if (p.reg_lut && per_cu > kRegLutSlotsPerCu) per_cu = kRegLutSlotsPerCu;
+  if (p.reg_lut && per_cu > rl_slots_cap<M>()) per_cu = rl_slots_cap<M>();
   if (sc && sc->waves_per_cu > 0 && sc->waves_per_cu < per_cu) per_cu = sc->waves_per_cu;
   if (per_cu < 1) per_cu = 1;
   if (per_cu > 32) per_cu = 32;
