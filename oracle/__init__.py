@@ -77,6 +77,7 @@ def _declare(L):
     L.orc_search.argtypes = [C.POINTER(OrcIndex), _p, _i64, _p, C.c_int32, C.c_int32, _i, _p, _p, _p, _p, _p, _p]
     L.orc_search_capped.argtypes = [C.POINTER(OrcIndex), _p, _i64, _p, C.c_int32, C.c_int32, C.c_int32, _i, _p, _p,
                                     _p, _p, _p, _p]
+    L.orc_walk_tables.argtypes = [C.POINTER(OrcIndex), _p, _i64, _p, C.c_int32, _i, _p, _p, _p, _p]
     L.orc_refined_distance.argtypes = [C.POINTER(OrcIndex), _p, C.c_int32]
     L.orc_refined_distance.restype = C.c_double
     L.orc_walk_trace.argtypes = [C.POINTER(OrcIndex), _p, C.c_int32, _p, C.c_int32]
@@ -400,6 +401,23 @@ class Index:
         y = _c(y, np.float32)
         nt = _load().orc_walk_trace(C.byref(s), _ptr(y), int(ef_eff), _ptr(out), cap)
         return out[:nt].copy()
+
+    def walk_tables(self, tables: np.ndarray, ef, S: int, nthreads: Optional[int] = None) -> dict:
+        """The search's first stage (descent, level-0 walk, short-list) on the
+        given ADC tables [nq][m][ksub] (float64) instead of the queries' own."""
+        t = _c(tables, np.float64)
+        nq = t.shape[0]
+        assert t.shape[1:] == (self.m, 256)
+        ef_arr = _c(np.broadcast_to(np.asarray(ef, dtype=np.int32), (nq,)), np.int32)
+        out = {"cand_ids": np.empty((nq, S), np.int32), "cand_adc": np.empty((nq, S), np.float64),
+               "cand_n": np.empty(nq, np.int32), "stats": np.empty((nq, 2), np.int32)}
+        s = self._struct()
+        rc = _load().orc_walk_tables(C.byref(s), _ptr(t), nq, _ptr(ef_arr), S, nthreads or default_threads(),
+                                     _ptr(out["cand_ids"]), _ptr(out["cand_adc"]), _ptr(out["cand_n"]),
+                                     _ptr(out["stats"]))
+        if rc != 0:
+            raise ValueError(f"orc_walk_tables failed ({rc})")
+        return out
 
     def search(self, q: np.ndarray, ef, S: int, K: int, nthreads: Optional[int] = None, max_evals: int = 0) -> dict:
         """Full search; ``max_evals`` > 0 is the budget T on level-0 distance

@@ -1324,6 +1324,54 @@ int orc_search_capped(const orc_index *ix, const float *q, int64_t nq, const int
   return 0;
 }
 
+typedef struct {
+  const orc_index *ix;
+  const double *tables;
+  const int32_t *ef;
+  int32_t S;
+  int32_t *cand_ids, *cand_n, *stats;
+  double *cand_adc;
+  int32_t **stamp;
+  int32_t *sv;
+} wt_ctx;
+
+static void walk_tables_one(int64_t qi, int tid, void *vctx) {
+  wt_ctx *c = (wt_ctx *)vctx;
+  const orc_index *ix = c->ix;
+  const double *lut = c->tables + qi * (int64_t)ix->m * ix->ksub;
+  okey ep = greedy_upper(ix, lut);
+  int ef = c->ef[qi] > c->S ? c->ef[qi] : c->S;
+  okey *W = (okey *)malloc(sizeof(okey) * (size_t)(ef + 2));
+  int32_t E, D;
+  int nw = walk0(ix, lut, ep, ef, c->stamp[tid], ++c->sv[tid], W, &E, &D, NULL, 0, NULL, 0);
+  int ns = nw < c->S ? nw : c->S;
+  for (int i = 0; i < c->S; i++) {
+    if (c->cand_ids) c->cand_ids[qi * c->S + i] = i < ns ? W[i].id : -1;
+    if (c->cand_adc) c->cand_adc[qi * c->S + i] = i < ns ? W[i].d : INFINITY;
+  }
+  if (c->cand_n) c->cand_n[qi] = ns;
+  if (c->stats) {
+    c->stats[qi * 2] = E;
+    c->stats[qi * 2 + 1] = D;
+  }
+  free(W);
+}
+
+int orc_walk_tables(const orc_index *ix, const double *tables, int64_t nq, const int32_t *ef, int32_t S,
+                    int nthreads, int32_t *cand_ids, double *cand_adc, int32_t *cand_n, int32_t *stats) {
+  if (nq < 0 || S < 1 || ix->n < 1 || ix->coarse.k > 0 || !tables) return -1;
+  if (nthreads < 1) nthreads = 1;
+  wt_ctx c = {ix, tables, ef, S, cand_ids, cand_n, stats, cand_adc, NULL, NULL};
+  c.stamp = (int32_t **)malloc(sizeof(int32_t *) * nthreads);
+  c.sv = (int32_t *)calloc((size_t)nthreads, sizeof(int32_t));
+  for (int t = 0; t < nthreads; t++) c.stamp[t] = (int32_t *)calloc((size_t)ix->n, sizeof(int32_t));
+  orc_parallel_for(nq, nthreads, walk_tables_one, &c);
+  for (int t = 0; t < nthreads; t++) free(c.stamp[t]);
+  free(c.stamp);
+  free(c.sv);
+  return 0;
+}
+
 int orc_search(const orc_index *ix, const float *q, int64_t nq, const int32_t *ef, int32_t S,
                int32_t K, int nthreads, int32_t *out_ids, double *out_d, int32_t *cand_ids,
                double *cand_adc, int32_t *cand_n, int32_t *stats) {

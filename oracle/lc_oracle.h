@@ -180,6 +180,15 @@ int orc_search_capped(const orc_index *ix, const float *q, int64_t nq, const int
                       int32_t K, int32_t max_d, int nthreads, int32_t *out_ids, double *out_d,
                       int32_t *cand_ids, double *cand_adc, int32_t *cand_n, int32_t *stats);
 
+/* The search's first stage (Sec. 2: greedy descent on the upper levels, then
+ * the best-first walk on level 0 with W bounded by ef_eff = max(ef_q, S),
+ * and the S-entry short-list) with the caller's ADC tables in place of
+ * orc_lut's: tables double [nq][m][ksub], a node's key being the sum of its
+ * codes' entries.  One-level codec only (-1 for a 2-level index); outputs as
+ * orc_search's first-stage outputs. */
+int orc_walk_tables(const orc_index *ix, const double *tables, int64_t nq, const int32_t *ef, int32_t S,
+                    int nthreads, int32_t *cand_ids, double *cand_adc, int32_t *cand_n, int32_t *stats);
+
 /* Refined squared distance ||y' - x~_i||^2 for any id, x~_i = sum_j beta_j q(g_j(i))
  * block by block (Eq. 5, Eq. 9). */
 double orc_refined_distance(const orc_index *ix, const float *y, int32_t i);

@@ -45,11 +45,12 @@ __device__ __forceinline__ uint32_t byte_of(const uint32_t *w, int s) { return (
 // candidate's independent look-ups issue back to back); 0: dsub at run time.
 template <int DSUB>
 __device__ __forceinline__ float cent_dist(const float *cent, int dsub, int s, uint32_t a, uint32_t b) {
+  constexpr int kUnrollU = DSUB > 0 ? DSUB : 1;
   const int ds = DSUB > 0 ? DSUB : dsub;
   const float *ca = cent + (size_t(s) * 256 + a) * ds;
   const float *cb = cent + (size_t(s) * 256 + b) * ds;
   float e = 0.f;
-#pragma unroll(DSUB > 0 ? DSUB : 1)
+#pragma unroll kUnrollU
   for (int u = 0; u < (DSUB > 0 ? DSUB : dsub); ++u) {
     const float df = ca[u] - cb[u];
     e += df * df;
@@ -78,12 +79,13 @@ __device__ __forceinline__ float rec_rec(const float *cent, int dsub, const uint
 // ||v - q(y)||^2 over all coordinates in order (v the raw projected vector).
 template <int M, int DSUB>
 __device__ __forceinline__ float raw_rec(const float *v, const float *cent, int dsub, const uint32_t *cy) {
+  constexpr int kUnrollS = DSUB > 0 ? M : 1, kUnrollU = DSUB > 0 ? DSUB : 1;
   const int ds = DSUB > 0 ? DSUB : dsub;
   float acc = 0.f;
-#pragma unroll(DSUB > 0 ? M : 1)
+#pragma unroll kUnrollS
   for (int s = 0; s < M; ++s) {
     const float *c = cent + (size_t(s) * 256 + byte_of(cy, s)) * ds;
-#pragma unroll(DSUB > 0 ? DSUB : 1)
+#pragma unroll kUnrollU
     for (int u = 0; u < (DSUB > 0 ? DSUB : dsub); ++u) {
       const float df = v[s * ds + u] - c[u];
       acc += df * df;

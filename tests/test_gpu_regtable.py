@@ -4,7 +4,8 @@ table = 2, walk_rl_kernel) against the same walk with the table in LDS
 E and D), on the pool sizes, sub-space counts, per-query ef, budgets and
 overflow cases of the LDS-pool walk, with the workspace left zero-filled;
 also with the codes fetched after the visited probe (codes = 1); the fp16
-keys against their definition; the plan lc_walk_describe reports."""
+keys against their definition; the fp16 walks against the oracle's walk on
+the same table values; the plan lc_walk_describe reports."""
 import numpy as np
 import pytest
 
@@ -154,4 +155,38 @@ def test_walk_plan_names_the_kernel(torch):
     assert gix.walk_plan(5, 256, 32, f16)["grid"] == 5  # never more slots than queries
     with pytest.raises(lc.LCError):
         gix.walk_plan(10, 64, 32, f16, lc.schedule(table=3))
+    gix.close()
+
+
+def _oracle_view(ix):
+    import oracle
+    return oracle.Index(n=ix.n, d=ix.d, d_pad=ix.d_pad, m=ix.m, deg0=ix.deg0, deg_up=ix.deg_up, k_reg=ix.k_reg,
+                        n_beta=ix.n_beta, entry=ix.entry, max_level=ix.max_level, proj=ix.proj, centroids=ix.centroids,
+                        codes=ix.codes, adj0=ix.adj0, level=ix.level, up_base=ix.up_base, adj_up=ix.adj_up,
+                        beta=ix.beta, beta_idx=ix.beta_idx, m_beta=ix.m_beta)
+
+
+@pytest.mark.parametrize("m,table", [(16, 1), (16, 2), (56, 1), (56, 2), (56, 0)])
+def test_fp16_walk_is_the_walk_on_its_table(torch, m, table):
+    # the fp16 walk against the oracle's walk (Sec. 2: descent, best-first walk, short-list) on the same table
+    # values (each fp16 entry times its row scale, exact in float64): short-lists, their lengths, E and D
+    # identical on every query; keys within the float32 rounding of their m-term sums
+    import paper_1804_09996_amd as lc
+    w, ix, q = _index(m)
+    gix = lc.Index.from_index(ix)
+    lut, sc = gix.build_lut(torch.from_numpy(q), lc.LC_LUT_F16)
+    tabs = (lut.cpu().numpy().view(np.float16).reshape(q.shape[0], m, 256).astype(np.float64)
+            * sc.cpu().numpy().astype(np.float64)[:, :, None])
+    oix = _oracle_view(ix)
+    rng = np.random.default_rng(m + table)
+    for ef, S in ((16, 16), (64, 16), (200, 32), (rng.integers(1, 257, q.shape[0]).astype(np.int32), 32)):
+        ef_max = int(np.max(ef))
+        o = oix.walk_tables(tabs, ef, S, nthreads=8)
+        r = gix.search(lut, sc, ef=ef, ef_max=ef_max, S=S, sched=lc.schedule(table=table))
+        ids, adc = r.cand_ids.cpu().numpy(), r.cand_adc.cpu().numpy().astype(np.float64)
+        assert np.array_equal(ids, o["cand_ids"]), (ef_max, S)
+        assert np.array_equal(r.cand_n.cpu().numpy(), o["cand_n"]) and np.array_equal(r.stats.cpu().numpy(), o["stats"])
+        ok = ids >= 0
+        bound = m * 2.0 ** -24 * np.abs(o["cand_adc"][ok]) + 1e-30
+        assert np.all(np.abs(adc[ok] - o["cand_adc"][ok]) <= bound), (ef_max, S)
     gix.close()

@@ -302,6 +302,37 @@ def test_walk_with_ef_at_least_n_is_exhaustive(tiny_build):
         np.testing.assert_allclose(adc[order], r["cand_adc"][qi], rtol=1e-12)
 
 
+def test_walk_on_given_tables(tiny_build):
+    # the first stage on caller-given tables (used to hold the fp16 walks to the paper's walk on their own
+    # table values): (i) the queries' own tables give the search's first stage; (ii) tables scaled by a power
+    # of two give the same walk with keys scaled exactly; (iii) on a Hamming table (entry 0 where the code
+    # equals a target node's, else 1) the exhaustive walk's short-list is the brute-force order of
+    # (Hamming distance to the target's code, id)
+    w, ix, db, q = tiny_build
+    n, m = ix.n, ix.m
+    tabs = np.stack([ix.lut(y) for y in q[:6]]).reshape(6, m, 256)
+    r = ix.search(q[:6], w.ef, w.shortlist, 5, nthreads=3)
+    t = ix.walk_tables(tabs, w.ef, w.shortlist, nthreads=3)
+    for k in ("cand_ids", "cand_adc", "cand_n", "stats"):
+        assert np.array_equal(t[k], r[k]), k
+    t4 = ix.walk_tables(tabs * 4.0, w.ef, w.shortlist, nthreads=3)
+    assert np.array_equal(t4["cand_ids"], t["cand_ids"]) and np.array_equal(t4["stats"], t["stats"])
+    assert np.array_equal(t4["cand_adc"], t["cand_adc"] * 4.0)
+    codes = np.asarray(ix.codes)[:, :m]
+    rng = np.random.default_rng(3)
+    targets = rng.choice(n, 4, replace=False)
+    ham = np.ones((4, m, 256))
+    for j, tg in enumerate(targets):
+        ham[j, np.arange(m), codes[tg]] = 0.0
+    th = ix.walk_tables(ham, n, n, nthreads=2)
+    for j, tg in enumerate(targets):
+        hd = (codes != codes[tg][None, :]).sum(1)
+        order = np.lexsort((np.arange(n), hd))
+        assert th["cand_n"][j] == n and th["stats"][j][1] == n - 1
+        assert np.array_equal(th["cand_ids"][j], order)
+        assert np.array_equal(th["cand_adc"][j], hd[order].astype(np.float64))
+
+
 def test_search_outputs_consistent(tiny_build):
     w, ix, db, q = tiny_build
     r = ix.search(q, w.ef, w.shortlist, w.shortlist + 3)
