@@ -8,8 +8,9 @@ builder's: tests/test_gpu_build.py).
   and 256, longest ef first, replayed from a HIP graph), 600 sampled queries.
 * 20M vectors, d 96 -> 112 through the projection, PQ 56, k = 32: the plain
   float32 path on a 10k-query batch (ef 128, short-list 32, top-10), 600
-  sampled queries, and the served fp16 form's requests against the path run
-  alone.
+  sampled queries; the fp16 walk of the served form (table in registers) on
+  the sample against the oracle's walk on the same fp16 table values; and the
+  served fp16 form's requests against the path run alone.
 
 Bars: top-K EXACT on every sampled query, every distance within 1e-5
 relative of the oracle's float64 value, (E, D) identical on at least 99.5 %
@@ -96,6 +97,21 @@ def test_serving_workload_at_20M_against_oracle_sample():
     print(f"20M plain fp32: EXACT {s['exact_frac']:.4f} (E,D) identical {walk_same:.4f} max rel err "
           f"{s['max_rel_err']:.2e}")
     assert s["exact_frac"] == 1.0 and walk_same >= WALK_BAR and s["max_rel_err"] <= 1e-5
+    # the fp16 walk the served form runs (the default schedule: the table in registers) against the oracle's
+    # walk on the same table values, on the sample with the serving ef mix (R34: near-ties of float32 sums)
+    mix = np.asarray((32, 64, 128, 256))[np.random.default_rng(8).integers(0, 4, len(samp))].astype(np.int32)
+    qp = gix.project(torch.from_numpy(pool[samp]).cuda())
+    lut, sc = gix.build_lut(qp, lc.LC_LUT_F16, projected=True)
+    r16 = gix.search(lut, sc, ef=mix, ef_max=256, S=S)
+    tabs = (lut.cpu().numpy().view(np.float16).reshape(len(samp), w.m, 256).astype(np.float64)
+            * sc.cpu().numpy().astype(np.float64)[:, :, None])
+    o16 = oix.walk_tables(tabs, mix, S, nthreads=16)
+    ids16 = r16.cand_ids.cpu().numpy()
+    same16 = np.mean([np.array_equal(ids16[i], o16["cand_ids"][i]) and
+                      np.array_equal(r16.stats.cpu().numpy()[i], o16["stats"][i]) for i in range(len(samp))])
+    print(f"20M fp16 walk ({gix.walk_plan(len(samp), 256, S, lc.LC_LUT_F16)['kernel']}): short-list and (E,D) "
+          f"identical to the oracle's walk on the same tables on {same16:.4f} of the sample")
+    assert same16 >= WALK_BAR
     # the served fp16 form: every request as the path gives it alone
     reqs = serve.poisson_requests(w.d, pool, 1e9, 60, 9, efs=(32, 64, 128, 256))
     for q_ in reqs:
