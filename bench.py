@@ -210,6 +210,10 @@ def bench_batched(args):
     for _ in range(args.warmup):
         bs.run()
     torch.cuda.synchronize()
+    t_w = time.time()  # the device at its working clocks before the timed steps
+    while time.time() - t_w < args.warm_seconds:
+        bs.run()
+        torch.cuda.synchronize()
     evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
     t0 = time.perf_counter()
     for a, b in evs:
@@ -412,7 +416,6 @@ def bench_serve(args):
     mix_ef = np.asarray(SERVE_MIX)[datagen.rng(w.seed, "EF").integers(0, len(SERVE_MIX), nq)].astype(np.int32)
 
     # (3) the dominant kernel alone: fp16-table walk over the pool with the workload's ef mix, one stream.
-    # These are the first launches of this kernel in the process (the build's walks use float32 tables).
     qp = gix.project(qd)
     lut16, sc16 = gix.build_lut(qp, lc.LC_LUT_F16, projected=True)
     ef_t = torch.from_numpy(mix_ef).to(dev)
@@ -420,34 +423,39 @@ def bench_serve(args):
     ord_t = torch.argsort(ef_t, descending=True, stable=True).to(torch.int32)
     ws1 = gix.workspace(nq, int(mix_ef.max()), S)
     reps = max(5, args.steps // 2)
-    durs = []
-    for k in range(reps + 1):
+
+    def walk1():
+        return gix.search(lut16, sc16, ef=ef_t, ef_max=int(mix_ef.max()), S=S, stats=True, ws=ws1, order=ord_t)
+
+    # the device at its working clocks first: walks back to back for a second (a launch right after the
+    # host-side build and ground truth has been measured up to 35 % slower than the same launch later)
+    t_w = time.time()
+    while time.time() - t_w < args.warm_seconds:
+        walk1()
+        torch.cuda.synchronize()
+
+    def back_to_back(fn, n):
+        """Mean time per launch of n launches queued back to back on the current stream (events around the
+        whole run, so host-side launch gaps are not counted while the queue is fed)."""
+        fn()
         a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         a.record()
-        r1 = gix.search(lut16, sc16, ef=ef_t, ef_max=int(mix_ef.max()), S=S, stats=True, ws=ws1, order=ord_t)
+        for _ in range(n):
+            out = fn()
         b.record()
         b.synchronize()
-        if k:
-            durs.append(a.elapsed_time(b))
+        return a.elapsed_time(b) / n, out
+
+    walk_ms, r1 = back_to_back(walk1, reps)
     st1 = r1.stats.cpu().numpy()
     E1, D1 = st1[:, 0].astype(np.int64), st1[:, 1].astype(np.int64)
     wb = serve_walk_bytes(m, S, E1, D1)
-    walk_ms = float(np.mean(durs))
     kname = walk_kernel_name(gix, nq, int(mix_ef.max()), S, "f16")
     log(f"walk alone: {kname} {walk_ms:.3f} ms for {nq} queries, {wb / (walk_ms * 1e-3) / 1e9:.0f} GB/s algorithmic")
 
-    # every kernel of the path on the same batch, one stream (median of reps)
-    def timed(fn, reps_=5):
-        ts = []
-        for k in range(reps_ + 1):
-            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            a.record()
-            fn()
-            b.record()
-            b.synchronize()
-            if k:
-                ts.append(a.elapsed_time(b))
-        return float(np.median(ts))
+    # every kernel of the path on the same batch, one stream (mean of launches queued back to back)
+    def timed(fn, reps_=10):
+        return back_to_back(fn, reps_)[0]
 
     kern = {"project": timed(lambda: gix.project(qd)),
             "build_lut_f16": timed(lambda: gix.build_lut(qp, lc.LC_LUT_F16, projected=True)),
@@ -659,8 +667,8 @@ def bench_serve(args):
                         "kernel": kname, "algorithmic_bytes_per_launch": wb, "launch_ms": walk_ms,
                         "launches": reps, "queries_per_launch": nq,
                         "measured": "one stream, the walk alone on the query pool with the workload's ef mix, "
-                                    "slots taking queries longest ef first (these are the process's first "
-                                    "launches of this kernel after one warm-up)",
+                                    "slots taking queries longest ef first; launches queued back to back after "
+                                    f"{args.warm_seconds:g} s of warm-up walks, mean per launch",
                         "walk_mean_E": float(E1.mean()), "walk_mean_D": float(D1.mean())},
            "served_walk_launches": served_walk,
            "one_stream_kernels_ms": kern,
@@ -715,6 +723,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=30)
     ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--warm-seconds", type=float, default=1.0,
+                    help="walks run back to back before the walk alone is timed (the device at working clocks)")
     ap.add_argument("--workload", default="C5-20M")
     ap.add_argument("--form", choices=("serve", "both", "plain", "batched", "assign"), default="serve")
     ap.add_argument("--n", type=int, default=0, help="override the database size (serving form; named in the line)")

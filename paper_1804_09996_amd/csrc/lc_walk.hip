@@ -114,38 +114,43 @@ struct LdsTab {
 };
 
 // RegTab: an fp16 table spread over the wave's registers, 2m words per lane
-// (m <= 56): word 2s + j of lane l holds entries 128j + 2l (low half) and
-// 128j + 2l + 1 (high half) of row s, so that entry c sits at lane
-// (c >> 1) & 63, in word 2s + (c >> 7), half c & 1.  A read fetches both
-// words of the row from that lane with two cross-lane permutes and picks the
-// half with a byte permute whose selector comes from the code's bits 7 and
-// 0; four entries' lane addresses and selectors come from their code word
-// with a few packed operations.  Every lane of the wave takes part in each
-// permute, so callers evaluate keys on all 64 lanes and discard the ones
-// they do not need.  Each entry's value is that of lut_at (the fp16 entry
-// times its row's power-of-two scale), so keys are identical to the LDS
-// table's.
+// (m <= 56): lane l holds entries 4l .. 4l + 3 of every row s, in word 2s
+// (entries 4l, 4l + 1 as low and high half) and word 2s + 1 (4l + 2,
+// 4l + 3), so that entry c sits at lane c >> 2, at byte 2 (c & 3) of the
+// lane's two words.  A read fetches both words from that lane with two
+// cross-lane permutes, whose byte address is the code byte itself (the lane
+// is the address over 4), and picks the entry with a byte permute whose
+// selector comes from the code's two low bits; the four entries of a code
+// word share the few operations that form their addresses and selectors.
+// Every lane of the wave takes part in each permute, so callers evaluate
+// keys on all 64 lanes and discard the ones they do not need.  Each entry's
+// value is that of lut_at (the fp16 entry times its row's power-of-two
+// scale), so keys are identical to the LDS table's.
 template <int M>
 struct RegTab {
   static constexpr bool kWaveWide = true;
   static constexpr int kGroup = 4;  // entries read together: one code word
   uint32_t r[2 * M];
+  // row s of the table is 64 pairs of words; lane l takes pair l
   __device__ __forceinline__ void load(const __half *row, int lane) {
-    const uint32_t *w = reinterpret_cast<const uint32_t *>(row);
+    const uint2 *w = reinterpret_cast<const uint2 *>(row);
 #pragma unroll
-    for (int i = 0; i < 2 * M; ++i) r[i] = w[i * 64 + lane];
+    for (int s = 0; s < M; ++s) {
+      const uint2 v = w[s * 64 + lane];
+      r[2 * s] = v.x;
+      r[2 * s + 1] = v.y;
+    }
   }
   // acc plus the entries of rows s0 .. s0 + 3 at the four codes of word cw
   // (row s0 in its low byte), added in row order
   __device__ __forceinline__ float sum4(const float *sc, int s0, uint32_t cw, float acc) const {
-    const uint32_t addr4 = (cw << 1) & 0xFCFCFCFCu;  // per byte: lane ((c >> 1) & 63) times 4
-    // per byte: 2q, the first byte of half q = 2 (c >> 7) + (c & 1) within the two words, and 2q + 1
-    const uint32_t q2 = ((cw >> 5) & 0x04040404u) | ((cw << 1) & 0x02020202u);
+    // per byte: 2 (c & 3), the entry's first byte within the two words, and the byte after it
+    const uint32_t q2 = (cw << 1) & 0x06060606u;
     const uint32_t q2b = q2 | 0x01010101u;
     uint32_t w0[4], w1[4];
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
-      const int addr = int((addr4 >> (8 * t)) & 0xFFu);
+      const int addr = int((cw >> (8 * t)) & 0xFFu);  // byte address 4 (c >> 2) + (c & 3)
       w0[t] = uint32_t(__builtin_amdgcn_ds_bpermute(addr, int(r[2 * (s0 + t)])));
       w1[t] = uint32_t(__builtin_amdgcn_ds_bpermute(addr, int(r[2 * (s0 + t) + 1])));
     }
