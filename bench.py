@@ -429,10 +429,11 @@ def bench_serve(args):
 
     # the device at its working clocks first: walks back to back for a second (a launch right after the
     # host-side build and ground truth has been measured up to 35 % slower than the same launch later)
-    t_w = time.time()
+    t_w, n_warm = time.time(), 0
     while time.time() - t_w < args.warm_seconds:
         walk1()
         torch.cuda.synchronize()
+        n_warm += 1
 
     def back_to_back(fn, n):
         """Mean time per launch of n launches queued back to back on the current stream (events around the
@@ -666,6 +667,8 @@ def bench_serve(args):
                         "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, calibrated)",
                         "kernel": kname, "algorithmic_bytes_per_launch": wb, "launch_ms": walk_ms,
                         "launches": reps, "queries_per_launch": nq,
+                        # launches of this walk before the timed ones: the warm-up, then one untimed
+                        "launches_before": n_warm + 1,
                         "measured": "one stream, the walk alone on the query pool with the workload's ef mix, "
                                     "slots taking queries longest ef first; launches queued back to back after "
                                     f"{args.warm_seconds:g} s of warm-up walks, mean per launch",
