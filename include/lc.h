@@ -136,7 +136,7 @@ int64_t lc_lut_stride(const lc_index *ix, int lut_dtype);
  * [2][coarse_k] float32 entries ||z^h - C1[h][c]||^2, then zero padding;
  * lc_search adds a node's two first-level entries and its coarse_norm to the
  * sum over its codes, and clamps the result at 0.
- * nq == 0 is a no-op. */
+ * lut must be 16-byte aligned (LC_EINVAL otherwise).  nq == 0 is a no-op. */
 int lc_build_lut(const lc_index *ix, const float *q, int64_t nq, int lut_dtype, void *lut,
                  float *lut_scale, void *stream);
 

@@ -88,6 +88,7 @@ int build_lut(const lc_index *ix, const float *q, int64_t nq, int lut_dtype, voi
   if (lut_dtype != LC_LUT_F32 && lut_dtype != LC_LUT_F16) return LC_EINVAL;
   if (nq == 0) return LC_OK;
   if (!q || !lut) return LC_EINVAL;
+  if (reinterpret_cast<uintptr_t>(lut) % 16) return LC_EINVAL;  // rows are written 8 or 16 bytes per lane
   if (lut_dtype == LC_LUT_F16 && !lut_scale) return LC_EINVAL;
   return lc_launch_lut(ix, q, nq, lut_dtype, lut, lut_scale, projected, static_cast<hipStream_t>(stream));
 }

@@ -8,8 +8,9 @@
 // cancellation of the expansion small.  The cross term for a tile of 16
 // queries x 16 centroids is one v_mfma_f32_16x16x4_f32 per 4 sub-dimensions.
 //
-// One wavefront per (16 queries, sub-space); the write of the table (m*256
-// floats per query) dominates, so the kernel is bound by HBM writes.
+// One wavefront per (sub-space, a run of 16-query groups); the write of the
+// table (m*256 entries per query) dominates, so the kernel is bound by HBM
+// writes.
 #include <hip/hip_fp16.h>
 
 #include <type_traits>
@@ -22,12 +23,14 @@ typedef float floatx4 __attribute__((ext_vector_type(4)));
 
 // OUT = float: the table itself.  OUT = __half: the table divided by a
 // power-of-two scale per (query, sub-space) row that maps the row's largest
-// entry to at most 2^15 (scale written to `scale`).
+// entry to at most 2^15 (scale written to `scale`).  A block stages the
+// sub-space's centred centroids once and then takes `groups` consecutive
+// groups of 16 queries.
 template <int DSUB, typename OUT>
 __global__ __launch_bounds__(64) void lut_kernel(const float *__restrict__ q, int64_t nq, int d,
                                                   const float *__restrict__ proj, int m,
                                                   const float *__restrict__ cent, OUT *__restrict__ lut,
-                                                  float *__restrict__ scale) {
+                                                  float *__restrict__ scale, int groups) {
   constexpr int KS = (DSUB + 3) / 4;  // MFMA K steps
   constexpr int DP = KS * 4;          // sub-dimension padded to the MFMA K
   __shared__ float cc[256 * DP];      // centred centroids, zero padded
@@ -37,7 +40,6 @@ __global__ __launch_bounds__(64) void lut_kernel(const float *__restrict__ q, in
   __shared__ float ny[16];
   const int lane = threadIdx.x;
   const int s = blockIdx.y;
-  const int64_t q0 = int64_t(blockIdx.x) * 16;
   const float *cs = cent + size_t(s) * 256 * DSUB;
 
   if (lane < DP) {
@@ -57,124 +59,138 @@ __global__ __launch_bounds__(64) void lut_kernel(const float *__restrict__ q, in
     }
     nc[c] = nrm;
   }
-  if (proj) {
-    // the sub-space's DSUB rows of P y for the 16 queries: four lanes per query,
-    // each over a quarter of the inputs (contiguous runs of the query and of
-    // every row of P, the rows shared by all queries), summed over the four
-    const int i = lane >> 2, part = lane & 3;
-    const int64_t qi = q0 + i;
-    const int span = (d + 3) / 4, u0 = part * span, u1 = u0 + span < d ? u0 + span : d;
-    float acc[DSUB];
-#pragma unroll
-    for (int t = 0; t < DSUB; ++t) acc[t] = 0.f;
-    if (qi < nq) {
-      const float *y = q + qi * d;
-      for (int u = u0; u < u1; ++u) {
-        const float yu = y[u];
-#pragma unroll
-        for (int t = 0; t < DSUB; ++t) acc[t] += proj[size_t(s * DSUB + t) * d + u] * yu;
-      }
-    }
-#pragma unroll
-    for (int t = 0; t < DSUB; ++t) {
-      acc[t] += __shfl_xor(acc[t], 1);
-      acc[t] += __shfl_xor(acc[t], 2);
-    }
-    if (part == 0) {
-#pragma unroll
-      for (int t = 0; t < DP; ++t) ya[i * DP + t] = qi < nq && t < DSUB ? acc[t < DSUB ? t : 0] - mu[t] : 0.f;
-    }
-  } else {
-    for (int e = lane; e < 16 * DP; e += 64) {
-      const int i = e / DP, t = e % DP;
-      const int64_t qi = q0 + i;
-      float v = 0.f;
-      if (qi < nq && t < DSUB) v = q[qi * d + s * DSUB + t] - mu[t];
-      ya[e] = v;
-    }
-  }
-  __syncthreads();
-  if (lane < 16) {
-    float a = 0.f;
-#pragma unroll
-    for (int t = 0; t < DP; ++t) a += ya[lane * DP + t] * ya[lane * DP + t];
-    ny[lane] = a;
-  }
-  __syncthreads();
 
   // v_mfma_f32_16x16x4_f32 operand layout: lane l supplies A[l % 16][l / 16]
   // and B[l / 16][l % 16]; it receives D[4 (l / 16) + r][l % 16], r = 0..3.
+  // A is a tile of 16 centroids, B the 16 queries: lane l holds centroids
+  // 4 (l / 16) .. 4 (l / 16) + 3 of the tile for query l % 16, contiguous in
+  // that query's table row.
   const int col = lane & 15, kg = lane >> 4;
-  float a[KS];
-#pragma unroll
-  for (int ks = 0; ks < KS; ++ks) a[ks] = ya[col * DP + ks * 4 + kg];
-  if constexpr (std::is_same<OUT, float>::value) {
-    for (int tile = 0; tile < 16; ++tile) {
-      floatx4 acc = {0.f, 0.f, 0.f, 0.f};
-      const int c = tile * 16 + col;
-#pragma unroll
-      for (int ks = 0; ks < KS; ++ks)
-        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[ks], cc[c * DP + ks * 4 + kg], acc, 0, 0, 0);
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int i = kg * 4 + r;
-        const int64_t qi = q0 + i;
-        if (qi < nq) lut[(qi * m + s) * 256 + c] = lc::clamp0(ny[i] + nc[c] - 2.f * acc[r]);
-      }
-    }
-  } else {
-    float vals[16][4];
-    float mx[4] = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-    for (int tile = 0; tile < 16; ++tile) {
-      floatx4 acc = {0.f, 0.f, 0.f, 0.f};
-      const int c = tile * 16 + col;
-#pragma unroll
-      for (int ks = 0; ks < KS; ++ks)
-        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[ks], cc[c * DP + ks * 4 + kg], acc, 0, 0, 0);
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        vals[tile][r] = lc::clamp0(ny[kg * 4 + r] + nc[c] - 2.f * acc[r]);
-        mx[r] = fmaxf(mx[r], vals[tile][r]);
-      }
-    }
-    // row maxima across the 16 lanes that share a row group
-#pragma unroll
-    for (int r = 0; r < 4; ++r)
-      for (int o = 1; o < 16; o <<= 1) mx[r] = fmaxf(mx[r], __shfl_xor(mx[r], o));
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int i = kg * 4 + r;
+  for (int g = 0; g < groups; ++g) {
+    const int64_t q0 = (int64_t(blockIdx.x) * groups + g) * 16;
+    if (q0 >= nq) break;
+    __syncthreads();  // the previous group's queries are no longer read
+    if (proj) {
+      // the sub-space's DSUB rows of P y for the 16 queries: four lanes per query,
+      // each over a quarter of the inputs (contiguous runs of the query and of
+      // every row of P, the rows shared by all queries), summed over the four
+      const int i = lane >> 2, part = lane & 3;
       const int64_t qi = q0 + i;
-      if (qi >= nq) continue;
+      const int span = (d + 3) / 4, u0 = part * span, u1 = u0 + span < d ? u0 + span : d;
+      float acc[DSUB];
+#pragma unroll
+      for (int t = 0; t < DSUB; ++t) acc[t] = 0.f;
+      if (qi < nq) {
+        const float *y = q + qi * d;
+        for (int u = u0; u < u1; ++u) {
+          const float yu = y[u];
+#pragma unroll
+          for (int t = 0; t < DSUB; ++t) acc[t] += proj[size_t(s * DSUB + t) * d + u] * yu;
+        }
+      }
+#pragma unroll
+      for (int t = 0; t < DSUB; ++t) {
+        acc[t] += __shfl_xor(acc[t], 1);
+        acc[t] += __shfl_xor(acc[t], 2);
+      }
+      if (part == 0) {
+#pragma unroll
+        for (int t = 0; t < DP; ++t) ya[i * DP + t] = qi < nq && t < DSUB ? acc[t < DSUB ? t : 0] - mu[t] : 0.f;
+      }
+    } else {
+      for (int e = lane; e < 16 * DP; e += 64) {
+        const int i = e / DP, t = e % DP;
+        const int64_t qi = q0 + i;
+        float v = 0.f;
+        if (qi < nq && t < DSUB) v = q[qi * d + s * DSUB + t] - mu[t];
+        ya[e] = v;
+      }
+    }
+    __syncthreads();
+    if (lane < 16) {
+      float a = 0.f;
+#pragma unroll
+      for (int t = 0; t < DP; ++t) a += ya[lane * DP + t] * ya[lane * DP + t];
+      ny[lane] = a;
+    }
+    __syncthreads();
+
+    float b[KS];
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) b[ks] = ya[col * DP + ks * 4 + kg];
+    const float nq_ = ny[col];
+    const int64_t qi = q0 + col;  // this lane's query
+    OUT *row = lut + (qi * m + s) * 256 + 4 * kg;
+    float vals[16][4];
+    float mx = 0.f;
+#pragma unroll
+    for (int tile = 0; tile < 16; ++tile) {
+      floatx4 acc = {0.f, 0.f, 0.f, 0.f};
+      const int c = tile * 16 + col;
+#pragma unroll
+      for (int ks = 0; ks < KS; ++ks)
+        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(cc[c * DP + ks * 4 + kg], b[ks], acc, 0, 0, 0);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        vals[tile][r] = lc::clamp0(nq_ + nc[tile * 16 + 4 * kg + r] - 2.f * acc[r]);
+        if constexpr (!std::is_same<OUT, float>::value) mx = fmaxf(mx, vals[tile][r]);
+      }
+      if constexpr (std::is_same<OUT, float>::value) {
+        if (qi < nq) *reinterpret_cast<float4 *>(row + tile * 16) = make_float4(vals[tile][0], vals[tile][1],
+                                                                                vals[tile][2], vals[tile][3]);
+      }
+    }
+    if constexpr (!std::is_same<OUT, float>::value) {
+      // the row maximum across the four lanes that share the query
+      mx = fmaxf(mx, __shfl_xor(mx, 16));
+      mx = fmaxf(mx, __shfl_xor(mx, 32));
       int e = 0;
-      if (mx[r] > 0.f) {
-        frexpf(mx[r] * (1.f / 32768.f), &e);  // mx / 2^15 = f * 2^e, f in [0.5, 1)
+      if (mx > 0.f) {
+        frexpf(mx * (1.f / 32768.f), &e);  // mx / 2^15 = f * 2^e, f in [0.5, 1)
         e = e < -100 ? -100 : (e > 100 ? 100 : e);
       }
-      const float sc = ldexpf(1.f, e);
       const float inv = ldexpf(1.f, -e);
-      if (col == 0) scale[qi * m + s] = sc;
+      if (qi < nq) {
+        if (kg == 0) scale[qi * m + s] = ldexpf(1.f, e);
 #pragma unroll
-      for (int tile = 0; tile < 16; ++tile)
-        lut[(qi * m + s) * 256 + tile * 16 + col] = __float2half_rn(vals[tile][r] * inv);
+        for (int tile = 0; tile < 16; ++tile) {
+          const uint32_t h0 = __half_as_ushort(__float2half_rn(vals[tile][0] * inv));
+          const uint32_t h1 = __half_as_ushort(__float2half_rn(vals[tile][1] * inv));
+          const uint32_t h2 = __half_as_ushort(__float2half_rn(vals[tile][2] * inv));
+          const uint32_t h3 = __half_as_ushort(__float2half_rn(vals[tile][3] * inv));
+          *reinterpret_cast<uint2 *>(row + tile * 16) = make_uint2(h0 | (h1 << 16), h2 | (h3 << 16));
+        }
+      }
     }
   }
+}
+
+// Query groups per block: as many as keep at least 4096 blocks in the grid
+// (up to 8), so that the centroid staging is shared without idling CUs; one
+// when the kernel projects the queries itself (that projection, not the
+// staging, then dominates a group, and more blocks run it in parallel).
+inline int lut_groups(int64_t nq, int m, bool projects) {
+  if (projects) return 1;
+  const int64_t g16 = lc::ceil_div(nq, 16);
+  int g = 1;
+  while (g < 8 && lc::ceil_div(g16, 2 * g) * m >= 4096) g *= 2;
+  return g;
 }
 
 template <int DSUB>
 hipError_t launch_dsub(const lc_index *ix, const float *q, int64_t nq, int dtype, void *lut, float *scale,
                        bool projected, hipStream_t st) {
-  dim3 grid(lc::ceil_div(nq, 16), ix->v.m);
   // projected queries [nq][d_pad] need no projection
   const float *proj = projected ? nullptr : ix->v.proj;
+  const int groups = lut_groups(nq, ix->v.m, proj != nullptr);
+  dim3 grid(lc::ceil_div(lc::ceil_div(nq, 16), groups), ix->v.m);
   const int d = projected ? ix->v.d_pad : ix->v.d;
   if (dtype == LC_LUT_F32)
     hipLaunchKernelGGL((lut_kernel<DSUB, float>), grid, dim3(64), 0, st, q, nq, d, proj, ix->v.m,
-                       ix->v.centroids, static_cast<float *>(lut), scale);
+                       ix->v.centroids, static_cast<float *>(lut), scale, groups);
   else
     hipLaunchKernelGGL((lut_kernel<DSUB, __half>), grid, dim3(64), 0, st, q, nq, d, proj, ix->v.m,
-                       ix->v.centroids, static_cast<__half *>(lut), scale);
+                       ix->v.centroids, static_cast<__half *>(lut), scale, groups);
   return hipGetLastError();
 }
 
