@@ -24,7 +24,8 @@
 // builder with the same inputs.
 //
 // Reverse links are grouped by target on the device (an atomic count per
-// node, one group per target, a scan, a scatter); a group's candidates are
+// node, one group per target, a range of the link list per group taken by
+// atomics, a scatter); a group's candidates are
 // ordered by their keys, so the order in which its links arrive does not
 // matter.  A group of at most 64 candidates is handled in registers (one per
 // lane), a larger one in LDS.
@@ -36,7 +37,7 @@ namespace {
 
 using namespace lc;
 
-constexpr int kCounters = 256;  // [0] groups, [1] overflowing groups
+constexpr int kCounters = 256;  // [0] groups, [1] overflowing groups, [2] links placed
 
 __device__ __forceinline__ uint32_t byte_of(const uint32_t *w, int s) { return (w[s >> 2] >> (8 * (s & 3))) & 0xFFu; }
 
@@ -239,31 +240,29 @@ __global__ __launch_bounds__(1024) void select_kernel(InsertArgs a) {
   }
 }
 
-// 3. Offsets of the groups' link lists (one block: a scan over the groups).
-__global__ __launch_bounds__(1024) void scan_kernel(InsertArgs a) {
-  __shared__ int32_t part[1024];
-  __shared__ int32_t carry;
+// 3. Each group's range of the link list: a wave sums its groups' counts and
+// takes its ranges with one atomic add.  Groups are independent and a group's
+// links are ordered by key before they are used, so where a range lies does
+// not change the graph.
+__global__ __launch_bounds__(256) void offsets_kernel(InsertArgs a) {
   const int ng = int(a.counters[0]);
-  if (threadIdx.x == 0) carry = 0;
-  __syncthreads();
-  for (int base = 0; base < ng; base += 1024) {
-    const int g = base + threadIdx.x;
+  const int lane = threadIdx.x & 63;
+  for (int base = blockIdx.x * blockDim.x + (threadIdx.x & ~63); base < ng; base += gridDim.x * blockDim.x) {
+    const int g = base + lane;
     const int32_t c = g < ng ? a.inbox[a.group_tgt[g]] : 0;
-    part[threadIdx.x] = c;
-    __syncthreads();
-    for (int off = 1; off < 1024; off <<= 1) {  // inclusive scan
-      const int32_t add = threadIdx.x >= off ? part[threadIdx.x - off] : 0;
-      __syncthreads();
-      part[threadIdx.x] += add;
-      __syncthreads();
+    int32_t incl = c;  // inclusive sum over the wave's lanes
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const int32_t t = __shfl_up(incl, o);
+      if (lane >= o) incl += t;
     }
+    int32_t start = 0;
+    if (lane == 63) start = int32_t(atomicAdd(a.counters + 2, uint32_t(incl)));
+    start = __shfl(start, 63);
     if (g < ng) {
       a.group_cnt[g] = c;
-      a.group_off[g] = carry + part[threadIdx.x] - c;
+      a.group_off[g] = start + incl - c;
     }
-    __syncthreads();
-    if (threadIdx.x == 1023) carry += part[1023];
-    __syncthreads();
   }
 }
 
@@ -428,7 +427,7 @@ __global__ __launch_bounds__(64) void merge_large_kernel(InsertArgs a, int kcap)
 }
 
 __global__ void reset_kernel(uint32_t *counters) {
-  if (threadIdx.x < 2) counters[threadIdx.x] = 0u;
+  if (threadIdx.x < 3) counters[threadIdx.x] = 0u;
 }
 
 // -- projection and encoding ------------------------------------------------
@@ -533,7 +532,7 @@ int insert_m(const lc_index *ix, InsertArgs &a, const InsertLayout &L, char *ws,
   const void *sel = reinterpret_cast<const void *>(&select_kernel<M, DSUB>);
   if (hipFuncSetAttribute(sel, hipFuncAttributeMaxDynamicSharedMemorySize, cent_bytes) != hipSuccess) return LC_EHIP;
   hipLaunchKernelGGL((select_kernel<M, DSUB>), dim3(ceil_div(a.count, wpb)), dim3(64 * wpb), cent_bytes, st, a);
-  hipLaunchKernelGGL(scan_kernel, dim3(1), dim3(1024), 0, st, a);
+  hipLaunchKernelGGL(offsets_kernel, dim3(ceil_div(int64_t(a.count) * a.deg0, 256)), dim3(256), 0, st, a);
   hipLaunchKernelGGL(scatter_kernel, dim3(ceil_div(int64_t(a.count) * a.deg0, 256)), dim3(256), 0, st, a);
   const int merge_lds = cent_bytes + wpb * a.d_pad * 4;
   const void *mk = reinterpret_cast<const void *>(&merge_kernel<M, DSUB>);
