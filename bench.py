@@ -279,7 +279,7 @@ def bench_batched(args):
            "config": {"workload": f"{w.name}: N={w.n} d={w.d} Gaussian mixture ({w.n_comp} components), PQ {w.m}x256, "
                                   f"k={w.k_reg}, {nq} queries in one step, efSearch per query round(exp(U(ln16, "
                                   f"ln512))), pool max(ef, {S}), short-list {S}, top-{K}, longest ef first, "
-                                  f"autotuned schedule {sched.as_dict()} and ef classes (pool limits "
+                                  f"{'default' if args.no_tune else 'autotuned'} schedule {sched.as_dict()} and ef classes (pool limits "
                                   f"{bs.limits}: one concurrent walk launch per class), step replayed from a HIP "
                                   f"graph",
                       "ef_classes": [{"rows": r1 - r0, "ef_max": efm} for r0, r1, efm in bs.ranges]},
