@@ -111,23 +111,65 @@ __device__ __forceinline__ float readlane_f(float v, int l) {
   return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
 }
 
+// Every test of the shrinking rule for candidates held one per lane in key
+// order (lanes 0..nc-1, nc <= 64): lane i returns the lanes s < i whose link
+// candidate i does not beat, d(x, i) >= d(i, s).  Whether i beats s does not
+// depend on which links end up kept, so the nc (nc - 1) / 2 pairs are spread
+// over the lanes, 64 at a time (pair p = i (i - 1) / 2 + s on lane p mod 64),
+// each lane fetching both candidates' codes from their lanes and summing
+// d(i, s) exactly as rec_rec does; the lanes of one candidate's pairs are
+// contiguous, so its mask is a slice of the round's ballot.
+template <int M, int DSUB>
+__device__ uint64_t pair_fails(float dist, const uint32_t *code, int nc, const float *cent, int dsub, int lane) {
+  uint64_t fails = 0;
+  const int np = nc * (nc - 1) / 2;
+  const int first = lane * (lane - 1) / 2;  // this lane's pairs as candidate i: [first, first + lane)
+  for (int p0 = 0; p0 < np; p0 += 64) {
+    const int p = p0 + lane;
+    const bool act = p < np;
+    // i = floor((1 + sqrt(1 + 8p)) / 2): exact in float for p < 2016, checked anyway
+    int i = act ? int((1.f + __builtin_sqrtf(float(1 + 8 * p))) * 0.5f) : 1;
+    if (act) {
+      if (i * (i - 1) / 2 > p) --i;
+      if (i * (i + 1) / 2 <= p) ++i;
+    }
+    const int sidx = act ? p - i * (i - 1) / 2 : 0;
+    uint32_t ci[M / 4], cs[M / 4];
+#pragma unroll
+    for (int k = 0; k < M / 4; ++k) {
+      ci[k] = uint32_t(__builtin_amdgcn_ds_bpermute(i << 2, int(code[k])));
+      cs[k] = uint32_t(__builtin_amdgcn_ds_bpermute(sidx << 2, int(code[k])));
+    }
+    const float di = __int_as_float(__builtin_amdgcn_ds_bpermute(i << 2, __float_as_int(dist)));
+    const bool fail = act && !(di < rec_rec<M, DSUB>(cent, dsub, ci, cs));
+    const uint64_t b = __ballot(fail);
+    // this lane's pairs that fall in the round
+    const int lo = first > p0 ? first : p0;
+    const int hi = first + lane < p0 + 64 ? first + lane : p0 + 64;
+    if (lo < hi) {
+      const int len = hi - lo;
+      const uint64_t bits = (b >> (lo - p0)) & (len >= 64 ? ~0ull : ((1ull << len) - 1ull));
+      fails |= bits << (lo - first);
+    }
+  }
+  return fails;
+}
+
 // The shrinking rule over candidates held one per lane in key order (lanes
 // 0..nc-1, nc <= 64): returns the lanes of the kept links and of the filled
-// slots (at most cap).  Candidate i is tested against every link kept so far;
-// each kept lane computes its own d(i, s).
+// slots (at most cap).  Candidate i is kept when d(x, i) < d(i, s) for every
+// link s kept before it, candidates taken in order until cap are kept; when
+// fewer are, the nearest rejected ones fill the free slots.
 template <int M, int DSUB>
 __device__ uint64_t shrink_lanes(float dist, const uint32_t *code, int nc, int cap, const float *cent, int dsub,
                                  int lane) {
+  const uint64_t fails = pair_fails<M, DSUB>(dist, code, nc, cent, dsub, lane);
   uint64_t kept = 0;
   int nk = 0;
   for (int i = 0; i < nc && nk < cap; ++i) {
-    const float di = readlane_f(dist, i);
-    uint32_t ci[M / 4];
-#pragma unroll
-    for (int k = 0; k < M / 4; ++k) ci[k] = uint32_t(__builtin_amdgcn_readlane(int(code[k]), i));
-    bool fail = false;
-    if ((kept >> lane) & 1ull) fail = !(di < rec_rec<M, DSUB>(cent, dsub, ci, code));
-    if (__ballot(fail) == 0ull) {
+    const uint64_t f = (uint64_t(uint32_t(__builtin_amdgcn_readlane(int(uint32_t(fails >> 32)), i))) << 32) |
+                       uint32_t(__builtin_amdgcn_readlane(int(uint32_t(fails)), i));
+    if ((f & kept) == 0ull) {
       kept |= 1ull << i;
       ++nk;
     }
