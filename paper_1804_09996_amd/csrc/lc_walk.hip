@@ -1704,9 +1704,12 @@ WalkPlan plan_for(const lc_index *ix, int64_t nq, int32_t ef_max, int32_t S, con
   p.w_cap = (ef_eff + 63) / 64 * 64;
   // The table in registers (fp16 tables of the walk with the visited table): when asked for, or (auto) when
   // it keeps at least 1.3 times the slots per CU of the table in LDS (a slot's step costs more with the table
-  // in registers: two permutes per entry).  That walk keeps its pool in LDS: at m = 56 it beats the register
-  // pool with the table in LDS at every pool size (8 slots per CU against 3; measured on the 20M-vector,
-  // 56-sub-space workload: 1.36 against 1.82 ms at ef 64, 2.22 against 2.83 at ef 128, per 10k queries).
+  // in registers: two permutes per entry), or as many slots with a larger visited table (the LDS the table
+  // no longer takes; a full bucket sends ids to the global bitset).  That walk keeps its pool in LDS: at
+  // m = 56 it beats the register pool with the table in LDS at every pool size (8 slots per CU against 3;
+  // measured on the 20M-vector, 56-sub-space workload: 1.36 against 1.82 ms at ef 64, 2.22 against 2.83 at
+  // ef 128, per 10k queries); at m = 32 and a pool of 128 both keep 8 slots, with 2^12 visited words against
+  // 2^10 (1M 128-d integer vectors, ef 144 and 128, short-list 128: 3.44M against 2.54M queries/s).
   const bool rl_ok = plain_f16 && sc->visited == 0 && M <= kRegLutMaxM;
   const int32_t n_tags = sc->wide ? INT32_MAX : ix->v.n;
   if (rl_ok && sc->table == 0) {
@@ -1718,7 +1721,7 @@ WalkPlan plan_for(const lc_index *ix, int64_t nq, int32_t ef_max, int32_t S, con
                                     : auto_hash_bits<M>(p.w_cap, n_tags, lut_bytes, ix->lds_per_cu, false, true);
     int slots_rl = ix->lds_per_cu / lds_bytes_for<M>(p.w_cap, hb_rl, lut_bytes, false, true);
     if (slots_rl > rl_slots_cap<M>()) slots_rl = rl_slots_cap<M>();
-    p.reg_lut = 10 * slots_rl >= 13 * slots_alt;
+    p.reg_lut = 10 * slots_rl >= 13 * slots_alt || (slots_rl >= slots_alt && hb_rl > hb_alt);
   } else {
     p.reg_lut = rl_ok && sc->table == 2;
   }

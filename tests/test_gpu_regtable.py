@@ -156,6 +156,15 @@ def test_walk_plan_names_the_kernel(torch):
     with pytest.raises(lc.LCError):
         gix.walk_plan(10, 64, 32, f16, lc.schedule(table=3))
     gix.close()
+    # m = 32, pool 128: the register pool with the table in LDS keeps 8 slots per CU only with a 2^10-word
+    # visited table; the table in registers keeps as many with 2^12 words and is taken
+    w, ix, q = _index(32)
+    gix = lc.Index.from_index(ix)
+    p = gix.walk_plan(10_000, 128, 32, f16)
+    assert p["kernel"] == "walk_rl_kernel<32, false>" and p["hash_bits"] == 12 and p["slots_per_cu"] == 8, p
+    p = gix.walk_plan(10_000, 128, 32, f16, lc.schedule(table=1))
+    assert p["kernel"] == "walk_reg_kernel<32, __half, 2, false>" and p["hash_bits"] == 10, p
+    gix.close()
 
 
 def _oracle_view(ix):
