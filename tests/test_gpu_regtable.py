@@ -175,7 +175,7 @@ def _oracle_view(ix):
                         beta=ix.beta, beta_idx=ix.beta_idx, m_beta=ix.m_beta)
 
 
-@pytest.mark.parametrize("m,table", [(16, 1), (16, 2), (56, 1), (56, 2), (56, 0)])
+@pytest.mark.parametrize("m,table", [(16, 1), (16, 2), (32, 0), (56, 1), (56, 2), (56, 0)])
 def test_fp16_walk_is_the_walk_on_its_table(torch, m, table):
     # the fp16 walk against the oracle's walk (Sec. 2: descent, best-first walk, short-list) on the same table
     # values (each fp16 entry times its row scale, exact in float64): short-lists, their lengths, E and D
