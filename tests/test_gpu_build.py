@@ -47,7 +47,9 @@ def _compare(w, torch, log=print):
 @pytest.mark.parametrize("kw", [dict(name="gb-small", n=3000, d=32, m=8),
                                 dict(name="gb-pad", n=3000, d=28, m=8, d_pad=32),
                                 dict(name="gb-m56", n=4000, d=96, m=56, d_pad=112, k_reg=32, n_beta=32),
-                                dict(name="gb-m16", n=5000, d=96, m=16, k_reg=16, n_beta=64, ef_construction=64)])
+                                dict(name="gb-m16", n=5000, d=96, m=16, k_reg=16, n_beta=64, ef_construction=64),
+                                # sub-space width 8: the kernels with the width known only at run time
+                                dict(name="gb-dsub8", n=3000, d=64, m=8)])
 def test_gpu_build_equals_host_build(torch, kw):
     base = dict(nq=8, n_train=4096, n_beta_train=3000, pq_iters=6, beta_kmeans_iters=4, em_iters=3)
     base.update(kw)
