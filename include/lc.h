@@ -210,13 +210,16 @@ int lc_search(const lc_index *ix, const void *lut, int lut_dtype, const float *l
  *                 in LDS.
  *   table         visited mode 0 only: where an fp16 table of the one-level
  *                 codec lives during the walk.  1 = LDS; 2 = the wave's
- *                 registers (2m words per lane, m <= 56; read by cross-lane
- *                 permutes, so that a slot's LDS holds only the row scales,
- *                 the pool and the visited table, and a CU keeps up to 8
- *                 slots), with the pool in LDS whatever `pool` says; 0 =
- *                 registers when the table in LDS would leave a CU 4 slots or
- *                 fewer (m = 56), else LDS.  Same results either way; float32
- *                 tables and the 2-level codec's stay in LDS.
+ *                 registers (2m words per lane, four entries per lane,
+ *                 m <= 56; read by cross-lane permutes, so that a slot's LDS
+ *                 holds only the row scales, the pool and the visited table,
+ *                 and a CU keeps up to 8 slots, 12 at m <= 24), with the pool
+ *                 in LDS whatever `pool` says; 0 = registers when they keep at
+ *                 least 1.3 times the slots per CU of the table in LDS, or as
+ *                 many with a larger visited table (m = 24..56, and m = 16
+ *                 beyond a pool of 128 entries), else LDS.  Same results
+ *                 either way; float32 tables and the 2-level codec's stay in
+ *                 LDS.
  *   codes         visited mode 0 only: 0 = each step fetches the codes of all
  *                 the links it probes while the visited table is probed (a
  *                 link found visited reads its code for nothing: more HBM
