@@ -173,7 +173,7 @@ inline int lut_groups(int64_t nq, int m, bool projects) {
   if (projects) return 1;
   const int64_t g16 = lc::ceil_div(nq, 16);
   int g = 1;
-  while (g < 8 && lc::ceil_div(g16, 2 * g) * m >= 4096) g *= 2;
+  while (g < 8 && int64_t(lc::ceil_div(g16, 2 * g)) * m >= 4096) g *= 2;
   return g;
 }
 
