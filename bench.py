@@ -736,8 +736,8 @@ def main():
     ap.add_argument("--step-requests", type=int, default=250, help="requests per timed step (serving form)")
     ap.add_argument("--pool", type=int, default=10_000, help="query pool with exact neighbours (serving form)")
     ap.add_argument("--serve-shortlist", type=int, default=32, help="short-list size (serving form)")
-    ap.add_argument("--slots", type=int, default=6, help="serving slots (each with its own streams; serving form)")
-    ap.add_argument("--slot-queries", type=int, default=4096, help="queries per serving slot (serving form)")
+    ap.add_argument("--slots", type=int, default=3, help="serving slots (each with its own streams; serving form)")
+    ap.add_argument("--slot-queries", type=int, default=16384, help="queries per serving slot (serving form)")
     ap.add_argument("--serve-refine", choices=("auto", "f32", "bf16"), default="auto",
                     help="served refinement: fp32, bf16 with the fp32 re-score, or the faster of the two on the "
                          "one-stream measurement (serving form)")
