@@ -112,16 +112,19 @@ def test_serving_workload_at_20M_against_oracle_sample():
     print(f"20M fp16 walk ({gix.walk_plan(len(samp), 256, S, lc.LC_LUT_F16)['kernel']}): short-list and (E,D) "
           f"identical to the oracle's walk on the same tables on {same16:.4f} of the sample")
     assert same16 >= WALK_BAR
-    # the served fp16 form: every request as the path gives it alone
-    reqs = serve.poisson_requests(w.d, pool, 1e9, 60, 9, efs=(32, 64, 128, 256))
-    for q_ in reqs:
-        q_.arrival = 0.0
+    # the served fp16 form: every request as the path gives it alone, with small slots and with the
+    # benchmark's (3 slots of 16384 queries, 150 requests at once so that batches fill them)
     bpq = serve.query_bytes(w.m, S, K, w.d, d_proj=w.d_pad)
-    eng = serve.GpuEngine(gix, n_slots=4, slot_queries=2048, ef_max=256, S=S, K=K, precision="f16")
-    serve.serve(eng, serve.Scheduler(4, 2048, 6144 * bpq, bpq), reqs)
-    torch.cuda.synchronize()
-    for q_ in reqs[:20]:
-        i1, d1, _ = gix.query(torch.from_numpy(q_.queries), ef=q_.ef, ef_max=256, S=S, K=K, precision="f16")
-        assert np.array_equal(q_.ids, i1.cpu().numpy()) and np.array_equal(q_.dist.view(np.uint32),
-                                                                           d1.cpu().numpy().view(np.uint32))
+    for n_slots, slot_q, n_req in ((4, 2048, 60), (3, 16384, 150)):
+        reqs = serve.poisson_requests(w.d, pool, 1e9, n_req, 9, efs=(32, 64, 128, 256))
+        for q_ in reqs:
+            q_.arrival = 0.0
+        eng = serve.GpuEngine(gix, n_slots=n_slots, slot_queries=slot_q, ef_max=256, S=S, K=K, precision="f16")
+        serve.serve(eng, serve.Scheduler(n_slots, slot_q, int(0.75 * n_slots * slot_q) * bpq, bpq), reqs)
+        torch.cuda.synchronize()
+        for q_ in reqs[:: max(1, n_req // 20)]:
+            i1, d1, _ = gix.query(torch.from_numpy(q_.queries), ef=q_.ef, ef_max=256, S=S, K=K, precision="f16")
+            assert np.array_equal(q_.ids, i1.cpu().numpy()) and np.array_equal(q_.dist.view(np.uint32),
+                                                                               d1.cpu().numpy().view(np.uint32))
+        del eng
     gix.close()
