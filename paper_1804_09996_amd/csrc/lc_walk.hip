@@ -1695,6 +1695,20 @@ int auto_hash_bits(int w_cap, int32_t n, int lut_bytes, int lds_per_cu, bool reg
   return table_tag_bits(n, 10) || !table_tag_bits(n, 11) ? 10 : 11;
 }
 
+// The visited table of the walk with its table in registers: the largest that
+// keeps every slot its registers allow (12 per CU at m <= 24, 8 beyond), else
+// the rule above.  At m = 16 the larger register budget outweighs a larger
+// table: on 1M vectors, pools of 192 and 256, 1.91 and 2.44 ms per 10k
+// queries with 2^11 words and 12 slots per CU, against 2.10 and 2.66 with
+// 2^12 words and 8 (and 1.07 against 1.17 at a pool of 128).
+template <int M>
+int rl_hash_bits(int w_cap, int32_t n, int lut_bytes, int lds_per_cu) {
+  const int cap = rl_slots_cap<M>();
+  for (int hb = 12; hb >= 10; --hb)
+    if (table_tag_bits(n, hb) && lds_per_cu / lds_bytes_for<M>(w_cap, hb, lut_bytes, false, true) >= cap) return hb;
+  return auto_hash_bits<M>(w_cap, n, lut_bytes, lds_per_cu, false, true);
+}
+
 // plain_f16: the table is the one-level codec's fp16 table (the only one registers can hold)
 template <int M>
 WalkPlan plan_for(const lc_index *ix, int64_t nq, int32_t ef_max, int32_t S, const lc_schedule *sc,
@@ -1728,9 +1742,12 @@ WalkPlan plan_for(const lc_index *ix, int64_t nq, int32_t ef_max, int32_t S, con
   const bool reg = !p.reg_lut && sc->visited == 0 && sc->pool == 0 && p.w_cap <= kRegPoolMax;
   p.reg_chunks = reg ? 2 : 0;
   // visited mode 1 keeps only a small LDS cache; mode 0 sizes its table from the pool
+  // (the choice above compares the register table at its largest visited table leaving 8 slots; once
+  // taken, it gets the table that keeps all the slots its registers allow)
   p.hash_bits = sc->hash_bits ? sc->hash_bits
-              : (sc->visited == 1 ? 9
-                                  : auto_hash_bits<M>(p.w_cap, n_tags, lut_bytes, ix->lds_per_cu, reg, p.reg_lut));
+              : sc->visited == 1 ? 9
+              : p.reg_lut        ? rl_hash_bits<M>(p.w_cap, n_tags, lut_bytes, ix->lds_per_cu)
+                                 : auto_hash_bits<M>(p.w_cap, n_tags, lut_bytes, ix->lds_per_cu, reg, false);
   p.lds_bytes = lds_bytes_for<M>(p.w_cap, p.hash_bits, lut_bytes, reg, p.reg_lut);
   int per_cu = ix->lds_per_cu / p.lds_bytes;
   if (p.reg_lut && per_cu > rl_slots_cap<M>()) per_cu = rl_slots_cap<M>();

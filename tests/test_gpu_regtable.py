@@ -165,6 +165,16 @@ def test_walk_plan_names_the_kernel(torch):
     p = gix.walk_plan(10_000, 128, 32, f16, lc.schedule(table=1))
     assert p["kernel"] == "walk_reg_kernel<32, __half, 2, false>" and p["hash_bits"] == 10, p
     gix.close()
+    # m = 16: the register pool with the table in LDS up to a pool of 128; beyond, the table in registers with
+    # the visited table that keeps all 12 slots its registers allow (2^11 words)
+    w, ix, q = _index(16)
+    gix = lc.Index.from_index(ix)
+    assert gix.walk_plan(10_000, 128, 32, f16)["kernel"] == "walk_reg_kernel<16, __half, 2, false>"
+    p = gix.walk_plan(10_000, 256, 32, f16)
+    assert p["kernel"] == "walk_rl_kernel<16, false>" and p["hash_bits"] == 11 and p["slots_per_cu"] == 12, p
+    p = gix.walk_plan(10_000, 128, 32, f16, lc.schedule(table=2))
+    assert p["hash_bits"] == 11 and p["slots_per_cu"] == 12, p
+    gix.close()
 
 
 def _oracle_view(ix):
