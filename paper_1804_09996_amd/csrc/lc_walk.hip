@@ -486,30 +486,60 @@ __device__ __forceinline__ int shr1(int v, int fill) {
 
 // Merge of 2..32 kept keys (one per lane with `keep` in km, all unique, none
 // in W, each below the largest key of W when W is full) into the sorted pool
-// W[0..nw), keeping the best efe; nw is updated.  The kept keys are ranked
-// (broadcast one by one) and stored sorted in Ks.  Chunks of 64 entries move
+// W[0..nw), keeping the best efe; nw is updated.  The kept keys are packed
+// into Ks in lane order, every lane reads them back and ranks its own key by
+// counting the smaller ones, and each key is then stored at its rank, so that
+// Ks holds them sorted.  Chunks of 64 entries move
 // from the top down: an entry moves up by the number of kept keys below it,
 // and the kept keys of ranks [below entry i-1, below entry i) land just
 // below entry i (slot nw acts as +inf).  Each chunk's counts come with the
 // next-lower chunk read one step ahead, whose top lane gives lane 0 its
 // predecessor's count; the walk stops below the smallest kept key.
 // Returns the slot of the smallest kept key.
+template <bool Ahead>
 __device__ __forceinline__ int merge_keys(uint64_t *W, uint64_t *Ks, int &nw, int efe, uint64_t k, bool keep,
                                           uint64_t km, int lane) {
   const int nn = __popcll(km);
-  int rank = 0;
-  for (uint64_t mm = km; mm; mm &= mm - 1) {
-    const uint64_t kj = readlane64(k, __ffsll((unsigned long long)mm) - 1);
-    rank += kj < k ? 1 : 0;
-  }
+  const bool mid = nn > 8, more = nn > 16;
+  // packed in lane order (slots past nn keep the largest key, which never counts as smaller)
+  const int packed = int(__builtin_amdgcn_mbcnt_hi(uint32_t(km >> 32), __builtin_amdgcn_mbcnt_lo(uint32_t(km), 0u)));
   if (lane < 32) Ks[lane] = kKeyMax;
   wave_sync();
-  if (keep) Ks[rank] = k;
+  if (keep) Ks[packed] = k;
   wave_sync();
   uint64_t kv[16];
 #pragma unroll
   for (int j = 0; j < 16; ++j) kv[j] = Ks[j];
-  const bool mid = nn > 8, more = nn > 16;
+  int rank;
+  {
+    int r0 = 0, r1 = 0, r2 = 0, r3 = 0;
+#pragma unroll
+    for (int j = 0; j < 16; j += 4) {
+      r0 += kv[j] < k ? 1 : 0;
+      r1 += kv[j + 1] < k ? 1 : 0;
+      r2 += kv[j + 2] < k ? 1 : 0;
+      r3 += kv[j + 3] < k ? 1 : 0;
+    }
+    if (more) {
+#pragma unroll
+      for (int j = 16; j < 32; j += 4) {
+        r0 += Ks[j] < k ? 1 : 0;
+        r1 += Ks[j + 1] < k ? 1 : 0;
+        r2 += Ks[j + 2] < k ? 1 : 0;
+        r3 += Ks[j + 3] < k ? 1 : 0;
+      }
+    }
+    rank = (r0 + r1) + (r2 + r3);
+  }
+  wave_sync();  // every read of the packed keys comes before the sorted store
+  if (keep) Ks[rank] = k;
+  wave_sync();
+  // below() counts over kv and, past 16 keys, over Ks[16 .. 32): the two must
+  // then be the sorted halves; up to 16 keys kv holds them all in packed order
+  if (more) {
+#pragma unroll
+    for (int j = 0; j < 16; ++j) kv[j] = Ks[j];
+  }
   // number of kept keys below x (the padding never counts), in four
   // independent sums so that the compares overlap
   auto below = [&](uint64_t x) {
@@ -544,17 +574,21 @@ __device__ __forceinline__ int merge_keys(uint64_t *W, uint64_t *Ks, int &nw, in
   int c = nw >> 6;
   int idx = (c << 6) + lane;
   uint64_t v = idx < nw ? W[idx] : kKeyMax;
+  // lower chunks lie wholly below nw and no chunk's writes reach below it, so
+  // with Ahead each is read one step before its turn (two more registers)
+  uint64_t vl = Ahead && c > 0 ? W[idx - 64] : 0;
   int cnt = idx < nw ? below(pure_key(v)) : nn;
   int pos_min = efe;
   for (; c >= 0; --c) {
-    // the next-lower chunk lies wholly below nw, and this chunk's writes never reach it
     int cl = 0;
-    uint64_t vl = 0;
     const int il = ((c - 1) << 6) + lane;
-    if (c > 0) {
+    uint64_t vll = 0;
+    if constexpr (Ahead) {
+      if (c > 1) vll = W[il - 64];
+    } else if (c > 0) {
       vl = W[il];
-      cl = below(pure_key(vl));
     }
+    if (c > 0) cl = below(pure_key(vl));
     const int fill = c > 0 ? __builtin_amdgcn_readlane(cl, 63) : 0;
     const int cprev = shr1(cnt, fill);
     wave_sync();  // reads of this chunk and the one below come before any write
@@ -569,10 +603,19 @@ __device__ __forceinline__ int merge_keys(uint64_t *W, uint64_t *Ks, int &nw, in
     }
     idx = il;
     v = vl;
+    if constexpr (Ahead) vl = vll;
     cnt = cl;
   }
   nw = nw + nn < efe ? nw + nn : efe;
   return pos_min;
+}
+
+// Merge of 1..32 kept keys (as merge_keys), a single one by merge_one.
+template <bool Ahead>
+__device__ __forceinline__ int merge_few(uint64_t *W, uint64_t *Ks, int &nw, int efe, uint64_t k, bool keep,
+                                         uint64_t km, int lane) {
+  if (__popcll(km) == 1) return merge_one(W, nw, efe, k, __ffsll((unsigned long long)km) - 1, lane);
+  return merge_keys<Ahead>(W, Ks, nw, efe, k, keep, km, lane);
 }
 
 // ---------------------------------------------------------------------------
@@ -955,6 +998,9 @@ __device__ __forceinline__ void walk_body(const WalkArgs &a) {
   uint64_t *W = reinterpret_cast<uint64_t *>(smem + kLutBytes + kScaleBytes);
   uint64_t *Ks = W + a.w_cap;  // merge scratch: the kept keys (compacted, then sorted)
   using Tab = std::conditional_t<RL, RegTab<M>, LdsTab<T>>;
+  // the merge's read-ahead, except where its two registers would cost the
+  // register-table kernel its third wave per SIMD (m <= 24)
+  constexpr bool kAhead = !RL || M > 24;
   Tab tab;
   if constexpr (!RL) tab.lut = lut;
   uint32_t *hash = reinterpret_cast<uint32_t *>(Ks + kMergeScratch);
@@ -1058,13 +1104,20 @@ __device__ __forceinline__ void walk_body(const WalkArgs &a) {
         if (km) {
           const int nn = __popcll(km);
           int pos_min;
-          if (nn == 1) {
-            pos_min = merge_one(W, nw, efe, k, __ffsll((unsigned long long)km) - 1, lane);
-          } else if (nn <= 32) {
-            pos_min = merge_keys(W, Ks, nw, efe, k, keep, km, lane);
+          if (nn <= 32) {
+            pos_min = merge_few<kAhead>(W, Ks, nw, efe, k, keep, km, lane);
           } else {
-            int before_ck = 0;
-            pos_min = merge_kept(W, nw, efe, k, keep, km, ck, lane, before_ck);
+            // more than 32 (the first steps of a walk): c's links, then p's, which are filtered
+            // again by the pool's largest key once c's have filled it
+            pos_min = merge_few<kAhead>(W, Ks, nw, efe, k, keep && lo, km & 0xFFFFFFFFull, lane);
+            wave_sync();
+            const uint64_t wm = nw == efe ? pure_key(W[nw - 1]) : kKeyMax;
+            const bool keep2 = keep && !lo && k < wm;
+            const uint64_t km2 = __ballot(keep2);
+            if (km2) {
+              const int pos2 = merge_few<kAhead>(W, Ks, nw, efe, k, keep2, km2, lane);
+              pos_min = pos2 < pos_min ? pos2 : pos_min;
+            }
           }
           // unexpanded entries were at or above fu and only move up; new ones sit at or above pos_min
           p0 = fu < pos_min ? fu : pos_min;
@@ -1208,9 +1261,11 @@ __global__ __launch_bounds__(64) void walk_kernel(WalkArgs a) {
 // The same walk with the fp16 table in registers (RegTab): a slot's LDS holds
 // the row scales, the pool and the visited table only, so that a CU keeps up
 // to 8 slots (two waves per SIMD) where the table in LDS keeps it to 3 or 4
-// (m >= 48); the register budget is held to 256 for those two waves.
+// (m >= 48); the register budget is held to 256 for those two waves, and to
+// 168 for three at m <= 24 (12 slots; at m = 24 a few registers spill).
 template <int M, bool BUDGET>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void walk_rl_kernel(WalkArgs a) {
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(M <= 24 ? 3 : 2))) void walk_rl_kernel(
+    WalkArgs a) {
   walk_body<M, __half, BUDGET, true>(a);
 }
 
